@@ -1,0 +1,178 @@
+/*
+ * locpir.h -- C ABI of the MI355X gate-bootstrapping library for LocPIR
+ * ("Fast Private Location-based Information Retrieval over the Torus").
+ *
+ * Scope: TFHE gate bootstrapping (blind rotation by CMux external products,
+ * sample extraction, LWE key switching) for every gate of the paper's
+ * bounding-box circuit (Algorithms 2-5), on one GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Torus32: a torus value t is the uint32 round(t * 2^32) mod 2^32; sums wrap.
+ * LWE ciphertext ("TLWE sample" in the paper, Sec. 2.3): n+1 little-endian
+ *   uint32 words, mask a[0..n) then body b.  Arrays of ciphertexts are
+ *   [count][n+1], densely packed.  Bit encoding f(m) = m/4 - 1/8, i.e. the
+ *   plaintext of bit 1 is +2^29 and of bit 0 is -2^29.
+ * Extracted ("big") LWE sample: N+1 words under the ring key.
+ * Pointers named d_* are device pointers (HIP global memory of the device the
+ *   key lives on); all others are host pointers.  The caller owns every
+ *   buffer it passes in; the library owns the opaque handles and frees them
+ *   with the matching *_free call.
+ * stream: a hipStream_t passed as void* (NULL = the null stream).  Device
+ *   calls are asynchronous on that stream unless stated otherwise; they may
+ *   allocate device memory with the stream-ordered allocator.
+ * Errors: every call returns lp_status (0 on success, negative on error) and
+ *   never throws; lp_last_error() gives a thread-local message for the last
+ *   failing call of the calling thread.
+ * Thread safety: handles are immutable after creation except for the query
+ *   plan cache inside an lp_device_key, which is internally locked.  Calls
+ *   that share an lp_device_key on different streams may run concurrently.
+ */
+#ifndef LOCPIR_H
+#define LOCPIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lp_status;
+#define LP_OK 0
+#define LP_EINVAL (-1)       /* bad argument, size or parameter set      */
+#define LP_ENOMEM (-2)       /* host or device allocation failed          */
+#define LP_EDEVICE (-3)      /* a HIP call failed                         */
+#define LP_EUNSUPPORTED (-4) /* parameters the GPU kernels do not handle  */
+#define LP_EBUDGET (-5)      /* server admission beyond the memory budget */
+
+/* TFHE parameters.  n, lwe_sigma: LWE dimension and noise of gate
+ * ciphertexts (KeyGen outputs n and sigma, Sec. 2.3).  N, k: ring degree and
+ * TRLWE dimension of the accumulator; bg_bit, l: gadget base 2^bg_bit and
+ * levels; bk_sigma: noise of the bootstrapping key; ks_base_bit, ks_t:
+ * key-switching base 2^ks_base_bit and digit count.  The GPU kernels support
+ * N = 1024, k = 1, bg_bit = 7, l = 3, any n <= 1024, any ks_base_bit*ks_t <= 31. */
+typedef struct {
+  uint32_t n, N, k, bg_bit, l, ks_base_bit, ks_t;
+  double lwe_sigma, bk_sigma;
+} lp_params;
+
+typedef struct lp_secret_key lp_secret_key; /* client: LWE key s, ring key S     */
+typedef struct lp_cloud_key lp_cloud_key;   /* PK = {bootstrapping key, KS key}  */
+typedef struct lp_device_key lp_device_key; /* PK resident on one GPU            */
+
+/* Gates (Sec. 2.3 EvalGate; the paper's HomAND, HomXNOR, HomMUX, HomXOR,
+ * HomNOT, plus the other two-input gates of the same construction).
+ * MUX(in0 = select, in1 = if one, in2 = if zero).  NOT and COPY do not
+ * bootstrap. */
+typedef enum {
+  LP_GATE_NAND = 0, LP_GATE_AND = 1, LP_GATE_OR = 2, LP_GATE_XOR = 3,
+  LP_GATE_XNOR = 4, LP_GATE_NOR = 5, LP_GATE_MUX = 6, LP_GATE_NOT = 7,
+  LP_GATE_COPY = 8
+} lp_gate;
+
+const char* lp_last_error(void);
+const char* lp_version(void);
+
+/* Default parameters: n = 630, lwe_sigma = 2^-15, N = 1024, k = 1,
+ * bg_bit = 7, l = 3, bk_sigma = 2^-25, ks_base_bit = 2, ks_t = 8. */
+lp_status lp_params_default(lp_params* out);
+
+/* ---- client side (host) -------------------------------------------------- */
+
+/* KeyGen(lambda) of Sec. 2.3 with the parameters given: a binary LWE key s,
+ * a binary ring key S, PK = {BSK, KSK}.  Deterministic in seed (SplitMix64
+ * counter-based draws).  BSK_i is a TGSW encryption of s_i: 2l TRLWE rows,
+ * row (p, j) = TRLWE_S(0) + s_i/Bg^(j+1) on component p.  KSK[i][j][v-1]
+ * (v = 1..base-1) is LWE_s(v * S_i / base^(j+1)).  Host only; no GPU needed. */
+lp_status lp_keygen(const lp_params* P, uint64_t seed, lp_secret_key** sk, lp_cloud_key** ck);
+
+/* Raw key material.  s: n bytes in {0,1}; S: N bytes in {0,1}.
+ * bsk: [n][2l][2][N] uint32 (row r = p*l + j; component 0 = mask polynomial,
+ *   1 = body polynomial).  ksk: [N][ks_t][base-1][n+1] uint32.
+ * Import copies the arrays; export writes into caller arrays of these sizes. */
+lp_status lp_secret_key_import(const lp_params* P, const uint8_t* s, const uint8_t* S, lp_secret_key** sk);
+lp_status lp_secret_key_export(const lp_secret_key* sk, uint8_t* s, uint8_t* S);
+lp_status lp_cloud_key_import(const lp_params* P, const uint32_t* bsk, const uint32_t* ksk, lp_cloud_key** ck);
+lp_status lp_cloud_key_export(const lp_cloud_key* ck, uint32_t* bsk, uint32_t* ksk);
+lp_status lp_cloud_key_params(const lp_cloud_key* ck, lp_params* out);
+size_t lp_bsk_words(const lp_params* P);
+size_t lp_ksk_words(const lp_params* P);
+
+/* Encrypt(m, K, n, sigma) of Sec. 2.3, bit by bit (Sec. 4.1): ct[k] =
+ * (a, <a,s> + f(bits[k]) + e), a uniform, e ~ N(0, lwe_sigma), drawn from
+ * (seed, first_index + k).  ct: cnt*(n+1) uint32, host. */
+lp_status lp_encrypt_bits(const lp_secret_key* sk, const uint8_t* bits, size_t cnt, uint64_t seed,
+                          uint64_t first_index, uint32_t* ct);
+/* Decrypt(ct, K) of Sec. 2.3: bit = sign of the phase b - <a,s>.  phase may
+ * be NULL; otherwise it receives the signed phase (int32 Torus32). */
+lp_status lp_decrypt_bits(const lp_secret_key* sk, const uint32_t* ct, size_t cnt, uint8_t* bits,
+                          int32_t* phase);
+
+/* ---- cloud side (device) ------------------------------------------------- */
+
+/* Upload PK to the current HIP device and transform the bootstrapping key to
+ * the NTT domain there (about 62 MB of BSK plus 62 MB of KSK per key). */
+lp_status lp_device_key_create(const lp_cloud_key* ck, void* stream, lp_device_key** dk);
+lp_status lp_device_key_bytes(const lp_device_key* dk, size_t* bytes);
+
+/* cnt gates of one kind on device ciphertexts: d_out[k] = gate(d_in0[k],
+ * d_in1[k], d_in2[k]).  d_in1 is ignored for NOT/COPY; d_in2 is used by MUX
+ * only.  All arrays are cnt*(n+1) uint32 on the key's device.  Every
+ * bootstrapped gate runs the blind rotation, sample extraction and key
+ * switching (MUX: two blind rotations, one key switch).  cnt = 0 is a no-op. */
+lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                             const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
+                             uint32_t* d_out, void* stream);
+
+/* Key switching alone: d_in holds cnt extracted samples of N+1 words under
+ * the ring key; d_out receives cnt samples of n+1 words under s. */
+lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,
+                             uint32_t* d_out, void* stream);
+
+/* The bounding-box query of Algorithm 3 (LocPIR): four ripple comparators
+ * per box (Algorithm 2, HomCompS and HomCompLE = NOT HomCompS with swapped
+ * arguments), the validation ANDs, bitwiseAND with the box's service bits
+ * (Algorithm 4) and the XOR sum over boxes (Algorithm 5, as a balanced tree).
+ * Bits are LSB first.  is_signed = 1 applies the MSB flip of Algorithm 2
+ * (two's-complement coordinates); 0 compares unsigned codes.  Boxes are
+ * half-open: x1 <= x < x2 and y1 <= y < y2.
+ *   d_x, d_y:    l ciphertexts each
+ *   d_bounds:    n_boxes x {x1, x2, y1, y2} x l ciphertexts
+ *   d_payload:   n_boxes x m ciphertexts
+ * d_out receives m ciphertexts.  The circuit is cut into depth levels; each
+ * level is one batched bootstrap launch plus one key-switch launch. */
+typedef struct {
+  uint32_t l, n_boxes, m;
+  int32_t is_signed;
+  const uint32_t* d_x;
+  const uint32_t* d_y;
+  const uint32_t* d_bounds;
+  const uint32_t* d_payload;
+} lp_bbox_query;
+lp_status lp_eval_bbox_query(const lp_device_key* dk, const lp_bbox_query* q, uint32_t* d_out,
+                             void* stream);
+/* Bootstraps, key switches and depth levels of that circuit. */
+lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,
+                         uint32_t* n_levels);
+
+/* ---- diagnostics (device) ------------------------------------------------ */
+
+/* Exact negacyclic products mod 2^32 of cnt pairs (digit polynomial,
+ * Torus32 polynomial) of degree < 1024, by the library's NTT.  d_digits:
+ * cnt*1024 int32 with |d| <= 64; d_poly, d_out: cnt*1024 uint32. */
+lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint32_t* d_poly, size_t cnt,
+                                  uint32_t* d_out, void* stream);
+/* Blind rotation of cnt LWE_n samples over their first `steps` key bits
+ * (steps >= n: all); d_acc receives cnt accumulators of [2][N] uint32. */
+lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,
+                                uint32_t steps, uint32_t* d_acc, void* stream);
+
+void lp_secret_key_free(lp_secret_key* sk);
+void lp_cloud_key_free(lp_cloud_key* ck);
+void lp_device_key_free(lp_device_key* dk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

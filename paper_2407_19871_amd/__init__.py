@@ -1,0 +1,304 @@
+"""LocPIR gate bootstrapping on MI355X (gfx950): Python binding of liblocpir.
+
+Argument marshalling only: every step of the path runs in the native library
+(include/locpir.h).  Device buffers are torch tensors on a ROCm device
+(uint32 stored as int32, since torch has no uint32 arithmetic we rely on);
+streams are torch streams.  The library is built by ``_build.py``; if it is
+missing, every call raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblocpir.so")
+_LIB = None
+
+GATES = {"NAND": 0, "AND": 1, "OR": 2, "XOR": 3, "XNOR": 4, "NOR": 5, "MUX": 6, "NOT": 7, "COPY": 8}
+
+
+class LocpirError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"locpir error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("N", C.c_uint32), ("k", C.c_uint32), ("bg_bit", C.c_uint32),
+                ("l", C.c_uint32), ("ks_base_bit", C.c_uint32), ("ks_t", C.c_uint32),
+                ("lwe_sigma", C.c_double), ("bk_sigma", C.c_double)]
+
+    def __repr__(self):
+        return (f"Params(n={self.n}, N={self.N}, k={self.k}, bg_bit={self.bg_bit}, l={self.l}, "
+                f"ks_base_bit={self.ks_base_bit}, ks_t={self.ks_t}, lwe_sigma={self.lwe_sigma}, "
+                f"bk_sigma={self.bk_sigma})")
+
+
+class BBoxQuery(C.Structure):
+    _fields_ = [("l", C.c_uint32), ("n_boxes", C.c_uint32), ("m", C.c_uint32), ("is_signed", C.c_int32),
+                ("d_x", C.c_void_p), ("d_y", C.c_void_p), ("d_bounds", C.c_void_p), ("d_payload", C.c_void_p)]
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(_LIB_PATH):
+        raise LocpirError(-100, f"{_LIB_PATH} is not built (run __graft_entry__.build())")
+    # torch ships its own HIP runtime with the same soname; loading torch
+    # first makes liblocpir bind to that one runtime instead of a second copy
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = C.CDLL(_LIB_PATH)
+    vp, sz, u32, u64, i32 = C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint64, C.c_int32
+    PP = C.POINTER(Params)
+    sig = {
+        "lp_last_error": (C.c_char_p, []),
+        "lp_version": (C.c_char_p, []),
+        "lp_params_default": (i32, [PP]),
+        "lp_keygen": (i32, [PP, u64, C.POINTER(vp), C.POINTER(vp)]),
+        "lp_secret_key_import": (i32, [PP, vp, vp, C.POINTER(vp)]),
+        "lp_secret_key_export": (i32, [vp, vp, vp]),
+        "lp_cloud_key_import": (i32, [PP, vp, vp, C.POINTER(vp)]),
+        "lp_cloud_key_export": (i32, [vp, vp, vp]),
+        "lp_cloud_key_params": (i32, [vp, PP]),
+        "lp_bsk_words": (sz, [PP]),
+        "lp_ksk_words": (sz, [PP]),
+        "lp_encrypt_bits": (i32, [vp, vp, sz, u64, u64, vp]),
+        "lp_decrypt_bits": (i32, [vp, vp, sz, vp, vp]),
+        "lp_device_key_create": (i32, [vp, vp, C.POINTER(vp)]),
+        "lp_device_key_bytes": (i32, [vp, C.POINTER(sz)]),
+        "lp_bootstrap_batch": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
+        "lp_keyswitch_batch": (i32, [vp, vp, sz, vp, vp]),
+        "lp_eval_bbox_query": (i32, [vp, C.POINTER(BBoxQuery), vp, vp]),
+        "lp_bbox_counts": (i32, [u32, u32, u32, C.POINTER(u64), C.POINTER(u64), C.POINTER(u32)]),
+        "lp_debug_negacyclic_mul": (i32, [vp, vp, sz, vp, vp]),
+        "lp_debug_blind_rotate": (i32, [vp, vp, sz, u32, vp, vp]),
+        "lp_secret_key_free": (None, [vp]),
+        "lp_cloud_key_free": (None, [vp]),
+        "lp_device_key_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(code: int):
+    if code != 0:
+        raise LocpirError(code, lib().lp_last_error().decode(errors="replace"))
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ------------------------------------------------------------------ params
+def params_default() -> Params:
+    p = Params()
+    _check(lib().lp_params_default(C.byref(p)))
+    return p
+
+
+def bsk_words(p: Params) -> int:
+    return int(lib().lp_bsk_words(C.byref(p)))
+
+
+def ksk_words(p: Params) -> int:
+    return int(lib().lp_ksk_words(C.byref(p)))
+
+
+# ------------------------------------------------------------------ keys
+class SecretKey:
+    def __init__(self, handle, params: Params):
+        self._h = handle
+        self.params = params
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            try:
+                _LIB.lp_secret_key_free(h)
+            except Exception:  # interpreter shutdown
+                pass
+
+    @classmethod
+    def from_arrays(cls, params: Params, s, S):
+        s = np.ascontiguousarray(s, np.uint8)
+        S = np.ascontiguousarray(S, np.uint8)
+        h = C.c_void_p()
+        _check(lib().lp_secret_key_import(C.byref(params), _np_ptr(s), _np_ptr(S), C.byref(h)))
+        return cls(h, params)
+
+    def export(self):
+        s = np.zeros(self.params.n, np.uint8)
+        S = np.zeros(self.params.N, np.uint8)
+        _check(lib().lp_secret_key_export(self._h, _np_ptr(s), _np_ptr(S)))
+        return s, S
+
+    def encrypt_bits(self, bits, seed: int, first_index: int = 0) -> np.ndarray:
+        bits = np.ascontiguousarray(np.asarray(bits, np.uint8).reshape(-1))
+        ct = np.zeros((len(bits), self.params.n + 1), np.uint32)
+        _check(lib().lp_encrypt_bits(self._h, _np_ptr(bits), len(bits), seed, first_index, _np_ptr(ct)))
+        return ct
+
+    def decrypt_bits(self, ct):
+        ct = np.ascontiguousarray(np.asarray(ct).view(np.uint32) if np.asarray(ct).dtype == np.int32
+                                  else np.asarray(ct, np.uint32)).reshape(-1, self.params.n + 1)
+        bits = np.zeros(len(ct), np.uint8)
+        ph = np.zeros(len(ct), np.int32)
+        _check(lib().lp_decrypt_bits(self._h, _np_ptr(ct), len(ct), _np_ptr(bits), _np_ptr(ph)))
+        return bits, ph
+
+
+class CloudKey:
+    def __init__(self, handle, params: Params):
+        self._h = handle
+        self.params = params
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            try:
+                _LIB.lp_cloud_key_free(h)
+            except Exception:  # interpreter shutdown
+                pass
+
+    @classmethod
+    def from_arrays(cls, params: Params, bsk, ksk):
+        bsk = np.ascontiguousarray(bsk, np.uint32)
+        ksk = np.ascontiguousarray(ksk, np.uint32)
+        if bsk.size != bsk_words(params) or ksk.size != ksk_words(params):
+            raise LocpirError(-1, "key array sizes do not match the parameters")
+        h = C.c_void_p()
+        _check(lib().lp_cloud_key_import(C.byref(params), _np_ptr(bsk), _np_ptr(ksk), C.byref(h)))
+        return cls(h, params)
+
+    def export(self):
+        bsk = np.zeros(bsk_words(self.params), np.uint32)
+        ksk = np.zeros(ksk_words(self.params), np.uint32)
+        _check(lib().lp_cloud_key_export(self._h, _np_ptr(bsk), _np_ptr(ksk)))
+        return bsk, ksk
+
+
+def keygen(params: Params | None, seed: int):
+    params = params or params_default()
+    sk, ck = C.c_void_p(), C.c_void_p()
+    _check(lib().lp_keygen(C.byref(params), seed, C.byref(sk), C.byref(ck)))
+    return SecretKey(sk, params), CloudKey(ck, params)
+
+
+def bbox_counts(l: int, n_boxes: int, m: int):
+    br, ks, lv = C.c_uint64(), C.c_uint64(), C.c_uint32()
+    _check(lib().lp_bbox_counts(l, n_boxes, m, C.byref(br), C.byref(ks), C.byref(lv)))
+    return int(br.value), int(ks.value), int(lv.value)
+
+
+# ------------------------------------------------------------------ device side
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise LocpirError(-1, "device buffers must be contiguous GPU tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def to_device(arr, device="cuda"):
+    """Host uint32 array -> int32 GPU tensor holding the same bits."""
+    torch = _torch()
+    a = np.ascontiguousarray(np.asarray(arr, np.uint32)).view(np.int32)
+    return torch.from_numpy(a.copy()).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+class DeviceKey:
+    """PK resident on the current GPU (BSK in the NTT domain + KSK)."""
+
+    def __init__(self, cloud_key: CloudKey, stream=None):
+        self.params = cloud_key.params
+        h = C.c_void_p()
+        _check(lib().lp_device_key_create(cloud_key._h, _stream_ptr(stream), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            try:
+                _LIB.lp_device_key_free(h)
+            except Exception:  # interpreter shutdown
+                pass
+
+    @property
+    def bytes(self) -> int:
+        b = C.c_size_t()
+        _check(lib().lp_device_key_bytes(self._h, C.byref(b)))
+        return int(b.value)
+
+
+def bootstrap_batch(dk: DeviceKey, gate: str, in0, in1=None, in2=None, out=None, stream=None):
+    torch = _torch()
+    cnt = in0.shape[0]
+    if out is None:
+        out = torch.empty((cnt, dk.params.n + 1), dtype=torch.int32, device=in0.device)
+    _check(lib().lp_bootstrap_batch(dk._h, GATES[gate], _dev_ptr(in0), _dev_ptr(in1), _dev_ptr(in2), cnt,
+                                    _dev_ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def keyswitch_batch(dk: DeviceKey, big, out=None, stream=None):
+    torch = _torch()
+    cnt = big.shape[0]
+    if out is None:
+        out = torch.empty((cnt, dk.params.n + 1), dtype=torch.int32, device=big.device)
+    _check(lib().lp_keyswitch_batch(dk._h, _dev_ptr(big), cnt, _dev_ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def eval_bbox_query(dk: DeviceKey, l, n_boxes, m, is_signed, x, y, bounds, payload, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty((m, dk.params.n + 1), dtype=torch.int32, device=x.device)
+    q = BBoxQuery(l, n_boxes, m, int(bool(is_signed)), _dev_ptr(x), _dev_ptr(y), _dev_ptr(bounds),
+                  _dev_ptr(payload))
+    _check(lib().lp_eval_bbox_query(dk._h, C.byref(q), _dev_ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def debug_negacyclic_mul(digits, poly, out=None, stream=None):
+    torch = _torch()
+    cnt = digits.shape[0]
+    if out is None:
+        out = torch.empty((cnt, 1024), dtype=torch.int32, device=digits.device)
+    _check(lib().lp_debug_negacyclic_mul(_dev_ptr(digits), _dev_ptr(poly), cnt, _dev_ptr(out),
+                                         _stream_ptr(stream)))
+    return out
+
+
+def debug_blind_rotate(dk: DeviceKey, ct, steps: int, out=None, stream=None):
+    torch = _torch()
+    cnt = ct.shape[0]
+    if out is None:
+        out = torch.empty((cnt, 2 * dk.params.N), dtype=torch.int32, device=ct.device)
+    _check(lib().lp_debug_blind_rotate(dk._h, _dev_ptr(ct), cnt, steps, _dev_ptr(out), _stream_ptr(stream)))
+    return out

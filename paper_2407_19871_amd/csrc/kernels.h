@@ -1,0 +1,52 @@
+// Launchers of the gfx950 kernels (C++ linkage, internal to liblocpir).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "jobs.h"
+
+namespace lp {
+
+// Twiddle tables of the 32 x 32 NTT (each 1024 u64, see ntt32.h):
+//   tw_f[i*32 + l] = psi^((2 brv5(i) + 1) l)
+//   tw_i[m*32 + l] = psi^(-(2 brv5(l) + 1) m) / 1024
+struct Twiddles {
+  const uint64_t* fwd;
+  const uint64_t* inv;
+};
+
+// Torus32 polynomials [npoly][1024] -> NTT domain [npoly][16 slot pairs][32 lanes][2].
+hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, Twiddles tw,
+                             hipStream_t s);
+
+// Blind rotation + sample extraction (or raw accumulator output) of njobs
+// jobs.  ex: extract buffer, N+1 words per slot (2N per slot when raw_acc).
+hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
+                               const uint64_t* const* d_bsk_tab, int n_lwe, int steps, int raw_acc,
+                               Twiddles tw, int waves_per_block, hipStream_t s);
+
+// Key switching of njobs jobs (tiles of consecutive jobs share one key).
+hipError_t launch_keyswitch(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
+                            const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t,
+                            int ks_base_bit, int tile, hipStream_t s);
+
+// Descriptors of cnt equal gates on arrays in0/in1/in2 (bases 0, 1, 2).
+// nbr = 1: one blind rotation per gate with (cst, c0*in0 + c1*in1);
+// nbr = 2 (MUX): rotations (sel AND t) and (NOT sel AND f), one key switch
+// of their sum plus 1/8.
+hipError_t launch_make_batch_jobs(int nbr, uint32_t cst, int32_t c0, int32_t c1, int has_in1,
+                                  size_t cnt, BrJob* d_br, KsJob* d_ks, hipStream_t s);
+
+// out[k] = sign * in[k] over cnt samples of `words` words (NOT, COPY).
+hipError_t launch_lwe_scale(const uint32_t* d_in, uint32_t* d_out, size_t words, int32_t sign,
+                            hipStream_t s);
+
+// out[j] = src[ref[j]] for cnt LWE_n samples.
+hipError_t launch_gather(const uint32_t* d_refs, int cnt, const SrcBases& src, uint32_t* d_out,
+                         int n_lwe, hipStream_t s);
+
+// cnt exact negacyclic products (digits x NTT-domain polynomial) mod 2^32.
+hipError_t launch_debug_polymul(const int32_t* d_digits, const uint64_t* d_poly_ntt, uint32_t* d_out,
+                                int cnt, Twiddles tw, hipStream_t s);
+
+}  // namespace lp

@@ -1,0 +1,460 @@
+// gfx950 kernels of the gate bootstrap: NTT-domain key conversion, the
+// blind rotation (CMux external products) with sample extraction, key
+// switching, and small helpers.
+//
+// Blind rotation layout (one 64-lane wave per bootstrap):
+//   half-wave h = lane / 32 owns accumulator component h (0 = mask A,
+//   1 = body B); lane l = lane % 32 holds coefficients l + 32 m, m < 32, of
+//   that component in registers.  Each step i:
+//     1. D_h = X^{a_i} ACC_h - ACC_h via this half's LDS block;
+//     2. for each gadget level j: digits of D_h -> forward NTT (first stage
+//        fused with the digit extraction) -> multiply by BSK_i[(h, j)][q]
+//        for q = h and q = 1-h; the q = 1-h products cross to the other
+//        half (lane ^ 32) so half h accumulates output component q = h;
+//     3. inverse NTT of the accumulated component, centred lift mod 2^32,
+//        ACC_h += result.
+//   The bootstrapping key is streamed from global memory in the NTT
+//   domain, laid out [i][row][q][slot pair][lane][2] so that each half-wave
+//   reads 512 contiguous bytes per 16-byte load.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gl64.h"
+#include "jobs.h"
+#include "kernels.h"
+#include "ntt32.h"
+
+namespace lp {
+
+constexpr int RING_N = 1024;
+constexpr int ROW = 33;             // padded LDS row (u64) of a 32 x 32 transpose
+constexpr int LDS_HALF = 32 * ROW;  // u64 per half-wave block
+constexpr int MAX_LWE = 1024;
+
+// Orders this wave's LDS accesses (DS operations of one wave execute in
+// program order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The value held by lane ^ 32.
+__device__ __forceinline__ uint64_t from_other_half(uint64_t v, int lane) {
+  const int addr = (lane ^ 32) << 2;
+  uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// 32 x 32 transpose through a half-wave LDS block: on entry lane l holds
+// row l (a[i] = (l, i)); on exit lane l holds column l (a[m] = (m, l)).
+// Rows are padded to 33 words so both phases are bank-conflict free.
+__device__ __forceinline__ void transpose32(uint64_t (&a)[32], uint64_t* buf, int l) {
+#pragma unroll
+  for (int i = 0; i < 32; ++i) buf[l * ROW + i] = a[i];
+  wave_fence();
+#pragma unroll
+  for (int m = 0; m < 32; ++m) a[m] = buf[m * ROW + l];
+  wave_fence();
+}
+
+// Twist between the passes: slot i of lane l times psi^((2 brv5(i)+1) l).
+__device__ __forceinline__ void twist_fwd(uint64_t (&f)[32], const uint64_t* __restrict__ tw, int l) {
+#pragma unroll
+  for (int i = 0; i < 32; ++i) f[i] = gl_mul(f[i], tw[i * 32 + l]);
+}
+
+// Forward negacyclic NTT of one polynomial per half-wave.  In: lane l,
+// slot m = coefficient l + 32 m.  Out: lane l -> ka = brv5(l), slot i ->
+// kb = brv5(i).
+__device__ __forceinline__ void ntt_fwd(uint64_t (&f)[32], uint64_t* buf, const uint64_t* __restrict__ tw_f,
+                                        int l) {
+  fwd1(f);
+  twist_fwd(f, tw_f, l);
+  transpose32(f, buf, l);
+  fwd2(f);
+}
+
+// The same for small signed digits, first butterfly stage fused.
+__device__ __forceinline__ void ntt_fwd_digits(const int32_t (&d)[32], uint64_t (&f)[32], uint64_t* buf,
+                                               const uint64_t* __restrict__ tw_f, int l) {
+  fwd1_first_stage_digits(d, f);
+  fwd1_rest(f);
+  twist_fwd(f, tw_f, l);
+  transpose32(f, buf, l);
+  fwd2(f);
+}
+
+// Inverse of ntt_fwd including the 1/1024 scaling.
+__device__ __forceinline__ void ntt_inv(uint64_t (&f)[32], uint64_t* buf, const uint64_t* __restrict__ tw_i,
+                                        int l) {
+  inv2(f);
+#pragma unroll
+  for (int m = 0; m < 32; ++m) f[m] = gl_mul(f[m], tw_i[m * 32 + l]);
+  transpose32(f, buf, l);
+  inv1(f);
+}
+
+// Offset of (slot s, lane l) inside one NTT-domain polynomial.
+__device__ __forceinline__ int ntt_pos(int s, int l) { return (s >> 1) * 64 + l * 2 + (s & 1); }
+
+// ---------------------------------------------------------------------------
+// Bootstrapping key -> NTT domain.  One polynomial per half-wave.
+__global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restrict__ src,
+                                                        uint64_t* __restrict__ dst, int npoly,
+                                                        const uint64_t* __restrict__ tw_f) {
+  __shared__ uint64_t s_buf[2][LDS_HALF];
+  const int lane = threadIdx.x, h = lane >> 5, l = lane & 31;
+  const int poly = blockIdx.x * 2 + h;
+  const bool live = poly < npoly;
+  uint64_t f[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) f[m] = live ? (uint64_t)src[(size_t)poly * RING_N + l + 32 * m] : 0ull;
+  ntt_fwd(f, s_buf[h], tw_f, l);
+  if (live) {
+    uint64_t* d = dst + (size_t)poly * RING_N;
+#pragma unroll
+    for (int s = 0; s < 32; ++s) d[ntt_pos(s, l)] = f[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blind rotation.
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void blind_rotate_kernel(
+    const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
+    const uint64_t* const* __restrict__ bsk_tab, int n_lwe, int steps, int raw_acc,
+    const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
+  __shared__ uint64_t s_buf[WPB][2][LDS_HALF];
+  __shared__ uint16_t s_abar[WPB][MAX_LWE + 4];
+
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  const int job = blockIdx.x * WPB + wave;
+  if (job >= njobs) return;
+
+  const BrJob J = jobs[job];
+  uint64_t* buf = s_buf[wave][h];
+  uint16_t* abar = s_abar[wave];
+
+  // modulus switch of the combined input (0, cst) + c0 in0 + c1 in1
+  {
+    const uint32_t* in0 = J.in0 == REF_NONE ? nullptr
+                                            : src.p[J.in0 >> REF_SHIFT] + (size_t)(J.in0 & REF_INDEX_MASK) * (n_lwe + 1);
+    const uint32_t* in1 = J.in1 == REF_NONE ? nullptr
+                                            : src.p[J.in1 >> REF_SHIFT] + (size_t)(J.in1 & REF_INDEX_MASK) * (n_lwe + 1);
+    for (int c = lane; c <= n_lwe; c += 64) {
+      uint32_t v = (c == n_lwe) ? J.cst : 0u;
+      if (in0) v += (uint32_t)J.c0 * in0[c];
+      if (in1) v += (uint32_t)J.c1 * in1[c];
+      abar[c] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
+    }
+  }
+  wave_fence();
+
+  // ACC = (0, X^{-b} v), v = sum_j (1/8) X^j: coefficient j of X^{-b} v is
+  // +1/8 when (j + b) mod 2N < N, else -1/8
+  const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)abar[n_lwe]);
+  uint32_t acc[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) {
+    const uint32_t j = (uint32_t)(l + 32 * m);
+    acc[m] = h == 0 ? 0u : ((((j + bbar) & 2047u) < 1024u) ? 0x20000000u : 0xE0000000u);
+  }
+
+  const uint64_t* __restrict__ bsk = bsk_tab[J.key];
+  uint32_t* abuf = reinterpret_cast<uint32_t*>(buf);
+  const int nsteps = steps < n_lwe ? steps : n_lwe;
+
+  for (int i = 0; i < nsteps; ++i) {
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)abar[i]);
+    if (a == 0) continue;  // X^0 ACC - ACC = 0 decomposes to zero digits
+
+    // D = X^a ACC_h - ACC_h
+#pragma unroll
+    for (int m = 0; m < 32; ++m) abuf[l + 32 * m] = acc[m];
+    wave_fence();
+    uint32_t D[32];
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+      const uint32_t e = ((uint32_t)(l + 32 * m) - a) & 2047u;
+      const uint32_t v = abuf[e & 1023u];
+      D[m] = ((e & 1024u) ? (0u - v) : v) - acc[m];
+    }
+    wave_fence();
+
+    uint64_t outv[32];
+    const uint64_t* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+#pragma nounroll
+    for (int jj = 0; jj < 3; ++jj) {
+      // signed digit of level jj+1: ((D + 0x81020400) >> (25 - 7 jj)) & 127) - 64
+      const int sh = 25 - 7 * jj;
+      int32_t dg[32];
+#pragma unroll
+      for (int m = 0; m < 32; ++m) dg[m] = (int32_t)(((D[m] + 0x81020400u) >> sh) & 127u) - 64;
+      uint64_t f[32];
+      ntt_fwd_digits(dg, f, buf, tw_f, l);
+
+      const int row = h * 3 + jj;
+      const uint64_t* k_own = step_key + (size_t)(row * 2 + h) * RING_N;
+      const uint64_t* k_oth = step_key + (size_t)(row * 2 + (1 - h)) * RING_N;
+#pragma unroll
+      for (int sp = 0; sp < 16; ++sp) {
+        const ulonglong2 ko = *reinterpret_cast<const ulonglong2*>(k_own + sp * 64 + l * 2);
+        const ulonglong2 kt = *reinterpret_cast<const ulonglong2*>(k_oth + sp * 64 + l * 2);
+        const uint64_t x0 = gl_mul(f[2 * sp], ko.x), x1 = gl_mul(f[2 * sp + 1], ko.y);
+        const uint64_t y0 = gl_mul(f[2 * sp], kt.x), y1 = gl_mul(f[2 * sp + 1], kt.y);
+        const uint64_t t0 = gl_add(x0, from_other_half(y0, lane));
+        const uint64_t t1 = gl_add(x1, from_other_half(y1, lane));
+        outv[2 * sp] = jj == 0 ? t0 : gl_add(outv[2 * sp], t0);
+        outv[2 * sp + 1] = jj == 0 ? t1 : gl_add(outv[2 * sp + 1], t1);
+      }
+    }
+
+    ntt_inv(outv, buf, tw_i, l);
+#pragma unroll
+    for (int m = 0; m < 32; ++m) acc[m] += gl_lift_u32(outv[m]);
+  }
+
+  if (raw_acc) {
+    uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + h * RING_N;
+#pragma unroll
+    for (int m = 0; m < 32; ++m) o[l + 32 * m] = acc[m];
+  } else {
+    // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
+    uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
+    if (h == 0) {
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const int j = l + 32 * m;
+        if (j == 0) o[0] = acc[m];
+        else o[RING_N - j] = 0u - acc[m];
+      }
+    } else if (l == 0) {
+      o[RING_N] = acc[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Key switching: a tile of T jobs x 64 output columns per wave.  For every
+// (i, j) the wave reads the base-1 KSK rows of that digit position once and
+// each job of the tile subtracts the row its digit selects.
+template <int T, int BB>
+__global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__ jobs, int njobs,
+                                                       const uint32_t* __restrict__ ex, DstBases dst,
+                                                       const uint32_t* const* __restrict__ ksk_tab,
+                                                       int n_lwe, int N, int ks_t) {
+  constexpr int NROWS = (1 << BB) - 1;
+  const int lane = threadIdx.x;
+  const int col = blockIdx.x * 64 + lane;
+  const int j0 = blockIdx.y * T;
+  const bool colok = col <= n_lwe;
+  const int w = n_lwe + 1;
+  const uint32_t* __restrict__ ksk = ksk_tab[jobs[j0].key];
+  const uint32_t prec = 1u << (31 - BB * ks_t);
+
+  uint32_t accv[T];
+  const uint32_t* e0[T];
+  const uint32_t* e1[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int jb = j0 + t;
+    e0[t] = nullptr;
+    e1[t] = nullptr;
+    accv[t] = 0u;
+    if (jb < njobs) {
+      const KsJob K = jobs[jb];
+      e0[t] = ex + (size_t)K.ex0 * (N + 1);
+      e1[t] = K.ex1 == REF_NONE ? nullptr : ex + (size_t)K.ex1 * (N + 1);
+      if (col == n_lwe) accv[t] = K.cst + e0[t][N] + (e1[t] ? e1[t][N] : 0u);
+    }
+  }
+
+  for (int i0 = 0; i0 < N; i0 += 64) {
+    uint32_t av[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      uint32_t v = 0u;
+      if (e0[t]) v = e0[t][i0 + lane] + (e1[t] ? e1[t][i0 + lane] : 0u) + prec;
+      av[t] = v;
+    }
+    for (int ii = 0; ii < 64; ++ii) {
+      const int i = i0 + ii;
+      uint32_t asc[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) asc[t] = (uint32_t)__builtin_amdgcn_readlane((int)av[t], ii);
+      for (int j = 0; j < ks_t; ++j) {
+        const uint32_t* rowp = ksk + ((size_t)(i * ks_t + j) * NROWS) * w + col;
+        uint32_t r[NROWS + 1];
+        r[0] = 0u;
+#pragma unroll
+        for (int v = 0; v < NROWS; ++v) r[v + 1] = colok ? rowp[(size_t)v * w] : 0u;
+        const int shift = 32 - (j + 1) * BB;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const uint32_t d = (asc[t] >> shift) & (uint32_t)NROWS;
+          uint32_t sub = 0u;
+#pragma unroll
+          for (int v = 1; v <= NROWS; ++v) sub = (d == (uint32_t)v) ? r[v] : sub;
+          accv[t] -= sub;
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int jb = j0 + t;
+    if (jb < njobs && colok) {
+      const uint32_t o = jobs[jb].out;
+      dst.p[o >> REF_SHIFT][(size_t)(o & REF_INDEX_MASK) * w + col] = accv[t];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void make_batch_jobs_kernel(int nbr, uint32_t cst, int32_t c0, int32_t c1, int has_in1,
+                                       size_t cnt, BrJob* __restrict__ br, KsJob* __restrict__ ks) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cnt) return;
+  const uint32_t kk = (uint32_t)k;
+  if (nbr == 1) {
+    br[k] = BrJob{make_ref(0, kk), has_in1 ? make_ref(1, kk) : REF_NONE, c0, c1, cst, kk, 0u, 0u};
+    ks[k] = KsJob{kk, REF_NONE, 0u, make_ref(0, kk), 0u, {0u, 0u, 0u}};
+  } else {
+    // MUX(sel = in0, t = in1, f = in2): (sel AND t), (NOT sel AND f)
+    br[2 * k] = BrJob{make_ref(0, kk), make_ref(1, kk), 1, 1, 0xE0000000u, 2 * kk, 0u, 0u};
+    br[2 * k + 1] = BrJob{make_ref(0, kk), make_ref(2, kk), -1, 1, 0xE0000000u, 2 * kk + 1, 0u, 0u};
+    ks[k] = KsJob{2 * kk, 2 * kk + 1, 0x20000000u, make_ref(0, kk), 0u, {0u, 0u, 0u}};
+  }
+}
+
+__global__ void lwe_scale_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, size_t words,
+                                 int32_t sign) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < words) out[k] = (uint32_t)sign * in[k];
+}
+
+__global__ void gather_kernel(const uint32_t* __restrict__ refs, int cnt, SrcBases src,
+                              uint32_t* __restrict__ out, int n_lwe) {
+  const int j = blockIdx.x;
+  if (j >= cnt) return;
+  const uint32_t r = refs[j];
+  const uint32_t* s = src.p[r >> REF_SHIFT] + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
+  for (int c = threadIdx.x; c <= n_lwe; c += blockDim.x) out[(size_t)j * (n_lwe + 1) + c] = s[c];
+}
+
+__global__ __launch_bounds__(64) void debug_polymul_kernel(const int32_t* __restrict__ digits,
+                                                           const uint64_t* __restrict__ poly,
+                                                           uint32_t* __restrict__ out, int cnt,
+                                                           const uint64_t* __restrict__ tw_f,
+                                                           const uint64_t* __restrict__ tw_i) {
+  __shared__ uint64_t s_buf[2][LDS_HALF];
+  const int lane = threadIdx.x, h = lane >> 5, l = lane & 31;
+  const int p = blockIdx.x;
+  if (p >= cnt) return;
+  int32_t dg[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) dg[m] = digits[(size_t)p * RING_N + l + 32 * m];
+  uint64_t f[32];
+  ntt_fwd_digits(dg, f, s_buf[h], tw_f, l);
+  const uint64_t* b = poly + (size_t)p * RING_N;
+#pragma unroll
+  for (int s = 0; s < 32; ++s) f[s] = gl_mul(f[s], b[ntt_pos(s, l)]);
+  ntt_inv(f, s_buf[h], tw_i, l);
+  if (h == 0) {
+#pragma unroll
+    for (int m = 0; m < 32; ++m) out[(size_t)p * RING_N + l + 32 * m] = gl_lift_u32(f[m]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, Twiddles tw, hipStream_t s) {
+  if (npoly <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bsk_to_ntt_kernel, dim3((npoly + 1) / 2), dim3(64), 0, s, d_src, d_dst, npoly, tw.fwd);
+  return hipGetLastError();
+}
+
+hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
+                               const uint64_t* const* d_bsk_tab, int n_lwe, int steps, int raw_acc, Twiddles tw,
+                               int waves_per_block, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  switch (waves_per_block) {
+    case 1:
+      hipLaunchKernelGGL(blind_rotate_kernel<1>, dim3(njobs), dim3(64), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
+                         n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+      break;
+    case 2:
+      hipLaunchKernelGGL(blind_rotate_kernel<2>, dim3((njobs + 1) / 2), dim3(128), 0, s, d_jobs, njobs, src, d_ex,
+                         d_bsk_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+      break;
+    case 4:
+      hipLaunchKernelGGL(blind_rotate_kernel<4>, dim3((njobs + 3) / 4), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
+                         d_bsk_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int T>
+static hipError_t launch_ks_t(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
+                              const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t, int bb, hipStream_t s) {
+  dim3 grid((n_lwe + 1 + 63) / 64, (njobs + T - 1) / T);
+  switch (bb) {
+    case 1: hipLaunchKernelGGL((keyswitch_kernel<T, 1>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
+    case 2: hipLaunchKernelGGL((keyswitch_kernel<T, 2>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
+    case 3: hipLaunchKernelGGL((keyswitch_kernel<T, 3>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
+    case 4: hipLaunchKernelGGL((keyswitch_kernel<T, 4>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_keyswitch(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
+                            const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t, int ks_base_bit,
+                            int tile, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  switch (tile) {
+    case 1: return launch_ks_t<1>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
+    case 4: return launch_ks_t<4>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
+    case 8: return launch_ks_t<8>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
+    case 16: return launch_ks_t<16>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_make_batch_jobs(int nbr, uint32_t cst, int32_t c0, int32_t c1, int has_in1, size_t cnt, BrJob* d_br,
+                                  KsJob* d_ks, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+  hipLaunchKernelGGL(make_batch_jobs_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, nbr, cst, c0, c1,
+                     has_in1, cnt, d_br, d_ks);
+  return hipGetLastError();
+}
+
+hipError_t launch_lwe_scale(const uint32_t* d_in, uint32_t* d_out, size_t words, int32_t sign, hipStream_t s) {
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(lwe_scale_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, d_in, d_out, words, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint32_t* d_refs, int cnt, const SrcBases& src, uint32_t* d_out, int n_lwe,
+                         hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3(cnt), dim3(256), 0, s, d_refs, cnt, src, d_out, n_lwe);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_polymul(const int32_t* d_digits, const uint64_t* d_poly_ntt, uint32_t* d_out, int cnt,
+                                Twiddles tw, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(debug_polymul_kernel, dim3(cnt), dim3(64), 0, s, d_digits, d_poly_ntt, d_out, cnt, tw.fwd,
+                     tw.inv);
+  return hipGetLastError();
+}
+
+}  // namespace lp

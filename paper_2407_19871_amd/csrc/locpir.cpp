@@ -1,0 +1,914 @@
+// Host side of liblocpir: the C ABI declared in include/locpir.h.
+//
+//   * client operations (KeyGen, Encrypt, Decrypt of Sec. 2.3) on the host;
+//   * device keys: upload and NTT-domain conversion of the bootstrapping key;
+//   * gate batches and key-switch batches on the GPU;
+//   * the bounding-box circuit of Algorithms 2-5 compiled to a level plan
+//     (a DAG cut into depth levels; each level = one blind-rotation launch
+//     plus one key-switch launch over every gate of that level).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../../include/locpir.h"
+#include "jobs.h"
+#include "kernels.h"
+
+using lp::BrJob;
+using lp::KsJob;
+
+// ---------------------------------------------------------------- errors
+namespace {
+thread_local std::string g_err;
+
+lp_status fail(lp_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(LP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool params_ok(const lp_params* P, std::string* why) {
+  if (!P) { *why = "null params"; return false; }
+  if (P->n == 0 || P->n > 4096) { *why = "n out of range"; return false; }
+  if (P->N < 2 || P->N > 4096 || (P->N & (P->N - 1))) { *why = "N must be a power of two"; return false; }
+  if (P->k != 1) { *why = "only k = 1 is supported"; return false; }
+  if (P->bg_bit == 0 || P->l == 0 || P->bg_bit * P->l > 31) { *why = "bad gadget"; return false; }
+  if (P->ks_base_bit == 0 || P->ks_base_bit > 8 || P->ks_t == 0 || P->ks_base_bit * P->ks_t > 31) {
+    *why = "bad key-switching base/digits";
+    return false;
+  }
+  if (!(P->lwe_sigma >= 0) || !(P->bk_sigma >= 0)) { *why = "bad sigma"; return false; }
+  return true;
+}
+
+bool gpu_params_ok(const lp_params& P, std::string* why) {
+  if (P.N != 1024 || P.k != 1 || P.bg_bit != 7 || P.l != 3) {
+    *why = "GPU kernels need N = 1024, k = 1, bg_bit = 7, l = 3";
+    return false;
+  }
+  if (P.n > 1024) { *why = "GPU kernels need n <= 1024"; return false; }
+  if (P.ks_base_bit > 4) { *why = "GPU key switching needs ks_base_bit <= 4"; return false; }
+  return true;
+}
+
+// ---------------------------------------------------------------- random
+// SplitMix64 (Steele, Lea, Flood 2014).  The k-th output (k from 0) of a
+// generator started at state x is finalize(x + (k+1) * 0x9E3779B97F4A7C15).
+// A draw is addressed by (seed, stream, index): the stream's key is output
+// `stream` of SplitMix64(seed), the draw is output `index` of
+// SplitMix64(key).  Counter addressing lets rows be generated in parallel.
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+inline uint64_t finalize64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return x;
+}
+
+struct Stream {
+  uint64_t key;
+  Stream(uint64_t seed, uint64_t id) : key(finalize64(seed + (id + 1) * kGolden)) {}
+  uint64_t u64(uint64_t idx) const { return finalize64(key + (idx + 1) * kGolden); }
+  uint32_t u32(uint64_t idx) const { return (uint32_t)(u64(idx) >> 32); }
+  uint8_t bit(uint64_t idx) const { return (uint8_t)(u64(idx) >> 63); }
+  // centred Gaussian in Torus32 units, std sigma (torus): Box-Muller, cosine
+  // branch, from draws 2 idx and 2 idx + 1; rounded half away from zero
+  uint32_t gauss(uint64_t idx, double sigma) const {
+    const double u1 = (double)((u64(2 * idx) >> 11) + 1) * 0x1p-53;
+    const double u2 = (double)(u64(2 * idx + 1) >> 11) * 0x1p-53;
+    const double radius = std::sqrt(-2.0 * std::log(u1));
+    const double z = radius * std::cos(6.283185307179586 * u2);
+    const double scaled = z * (sigma * 4294967296.0);
+    return (uint32_t)(uint64_t)std::llround(scaled);
+  }
+};
+
+enum : uint64_t { kStLweKey = 0, kStRingKey = 1, kStBskMask = 2, kStBskNoise = 3, kStKskMask = 4,
+                  kStKskNoise = 5, kStEncMask = 6, kStEncNoise = 7 };
+
+void parallel_rows(size_t rows, const std::function<void(size_t)>& fn) {
+  unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (rows < 64 || hw == 1) {
+    for (size_t r = 0; r < rows; ++r) fn(r);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < hw; ++t)
+    th.emplace_back([&, t] {
+      for (size_t r = t; r < rows; r += hw) fn(r);
+    });
+  for (auto& x : th) x.join();
+}
+}  // namespace
+
+// ---------------------------------------------------------------- handles
+struct lp_secret_key {
+  lp_params P;
+  std::vector<uint8_t> s;  // LWE key, n bits
+  std::vector<uint8_t> S;  // ring key, N bits
+};
+
+struct lp_cloud_key {
+  lp_params P;
+  std::vector<uint32_t> bsk;  // [n][2l][2][N]
+  std::vector<uint32_t> ksk;  // [N][t][base-1][n+1]
+};
+
+namespace {
+struct Plan;
+}
+
+struct lp_device_key {
+  lp_params P;
+  int device = 0;
+  uint64_t* bsk_ntt = nullptr;             // [n][2l][2][N] NTT domain
+  uint32_t* ksk = nullptr;                 // [N][t][base-1][n+1]
+  const uint64_t** bsk_tab = nullptr;      // device array {bsk_ntt}
+  const uint32_t** ksk_tab = nullptr;      // device array {ksk}
+  lp::Twiddles tw{};
+  size_t bytes = 0;
+  std::mutex mu;
+  std::map<std::tuple<uint32_t, uint32_t, uint32_t, int>, std::shared_ptr<Plan>> plans;
+};
+
+extern "C" size_t lp_bsk_words(const lp_params* P) {
+  return P ? (size_t)P->n * 2 * P->l * 2 * P->N : 0;
+}
+extern "C" size_t lp_ksk_words(const lp_params* P) {
+  return P ? (size_t)P->N * P->ks_t * ((1u << P->ks_base_bit) - 1) * (P->n + 1) : 0;
+}
+
+extern "C" const char* lp_last_error(void) { return g_err.c_str(); }
+extern "C" const char* lp_version(void) { return "locpir-mi355x 0.1"; }
+
+extern "C" lp_status lp_params_default(lp_params* out) {
+  if (!out) return fail(LP_EINVAL, "null output");
+  *out = lp_params{630, 1024, 1, 7, 3, 2, 8, std::ldexp(1.0, -15), std::ldexp(1.0, -25)};
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------- KeyGen
+// B = A * S in Z_{2^32}[X]/(X^N + 1) for a binary S: B[j] = sum over set
+// bits t of S of (X^t A)[j].  With the sign-extended table
+// W[y] = -A[y] (y < N), A[y - N] (y >= N), (X^t A)[j] = W[N + j - t].
+static void ring_times_binary(uint32_t N, const uint32_t* A, const uint8_t* S, uint32_t* B) {
+  std::vector<uint32_t> W(2 * N);
+  for (uint32_t y = 0; y < N; ++y) {
+    W[y] = 0u - A[y];
+    W[N + y] = A[y];
+  }
+  std::fill(B, B + N, 0u);
+  for (uint32_t t = 0; t < N; ++t) {
+    if (!S[t]) continue;
+    const uint32_t* w = W.data() + (N - t);
+    for (uint32_t j = 0; j < N; ++j) B[j] += w[j];
+  }
+}
+
+// LWE sample of torus value mu under binary key s (dimension n)
+static void lwe_sample(uint32_t n, const uint8_t* s, uint32_t mu, const Stream& mask, const Stream& noise,
+                       uint64_t idx, double sigma, uint32_t* out) {
+  uint32_t dot = 0;
+  for (uint32_t c = 0; c < n; ++c) {
+    out[c] = mask.u32(idx * n + c);
+    if (s[c]) dot += out[c];
+  }
+  out[n] = dot + mu + noise.gauss(idx, sigma);
+}
+
+extern "C" lp_status lp_keygen(const lp_params* P, uint64_t seed, lp_secret_key** sk, lp_cloud_key** ck) {
+  std::string why;
+  if (!params_ok(P, &why)) return fail(LP_EINVAL, "lp_keygen: %s", why.c_str());
+  if (!sk || !ck) return fail(LP_EINVAL, "lp_keygen: null output");
+  try {
+    auto s = std::make_unique<lp_secret_key>();
+    auto c = std::make_unique<lp_cloud_key>();
+    s->P = c->P = *P;
+    const uint32_t n = P->n, N = P->N, l = P->l, rows = 2 * l;
+    const Stream st_s(seed, kStLweKey), st_S(seed, kStRingKey);
+    s->s.resize(n);
+    s->S.resize(N);
+    for (uint32_t i = 0; i < n; ++i) s->s[i] = st_s.bit(i);
+    for (uint32_t i = 0; i < N; ++i) s->S[i] = st_S.bit(i);
+
+    // bootstrapping key: BSK_i = TGSW_S(s_i), row r = (p, j) with p = r / l
+    c->bsk.resize(lp_bsk_words(P));
+    const Stream st_a(seed, kStBskMask), st_e(seed, kStBskNoise);
+    parallel_rows((size_t)n * rows, [&](size_t row) {
+      const uint32_t i = (uint32_t)(row / rows), r = (uint32_t)(row % rows);
+      uint32_t* A = c->bsk.data() + row * 2 * N;
+      uint32_t* B = A + N;
+      for (uint32_t k = 0; k < N; ++k) A[k] = st_a.u32(row * N + k);
+      ring_times_binary(N, A, s->S.data(), B);
+      for (uint32_t k = 0; k < N; ++k) B[k] += st_e.gauss(row * N + k, P->bk_sigma);
+      if (s->s[i]) {
+        const uint32_t p = r / l, j = r % l;
+        const uint32_t g = 1u << (32 - P->bg_bit * (j + 1));  // 1/Bg^(j+1)
+        (p == 0 ? A : B)[0] += g;
+      }
+    });
+
+    // key-switching key: KSK[i][j][v-1] = LWE_s(v S_i / base^(j+1))
+    const uint32_t nv = (1u << P->ks_base_bit) - 1;
+    c->ksk.resize(lp_ksk_words(P));
+    const Stream st_ka(seed, kStKskMask), st_ke(seed, kStKskNoise);
+    parallel_rows((size_t)N * P->ks_t, [&](size_t ij) {
+      const uint32_t i = (uint32_t)(ij / P->ks_t), j = (uint32_t)(ij % P->ks_t);
+      for (uint32_t v = 1; v <= nv; ++v) {
+        const uint64_t row = ij * nv + (v - 1);
+        const uint32_t msg = s->S[i] ? v << (32 - P->ks_base_bit * (j + 1)) : 0u;
+        lwe_sample(n, s->s.data(), msg, st_ka, st_ke, row, P->lwe_sigma, c->ksk.data() + row * (n + 1));
+      }
+    });
+    *sk = s.release();
+    *ck = c.release();
+    return LP_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(LP_ENOMEM, "lp_keygen: out of host memory");
+  }
+}
+
+extern "C" lp_status lp_secret_key_import(const lp_params* P, const uint8_t* s, const uint8_t* S,
+                                          lp_secret_key** sk) {
+  std::string why;
+  if (!params_ok(P, &why)) return fail(LP_EINVAL, "lp_secret_key_import: %s", why.c_str());
+  if (!s || !S || !sk) return fail(LP_EINVAL, "lp_secret_key_import: null argument");
+  auto k = std::make_unique<lp_secret_key>();
+  k->P = *P;
+  k->s.assign(s, s + P->n);
+  k->S.assign(S, S + P->N);
+  for (auto& b : k->s) if (b > 1) return fail(LP_EINVAL, "lp_secret_key_import: key bits must be 0/1");
+  for (auto& b : k->S) if (b > 1) return fail(LP_EINVAL, "lp_secret_key_import: key bits must be 0/1");
+  *sk = k.release();
+  return LP_OK;
+}
+
+extern "C" lp_status lp_secret_key_export(const lp_secret_key* sk, uint8_t* s, uint8_t* S) {
+  if (!sk) return fail(LP_EINVAL, "lp_secret_key_export: null key");
+  if (s) std::memcpy(s, sk->s.data(), sk->s.size());
+  if (S) std::memcpy(S, sk->S.data(), sk->S.size());
+  return LP_OK;
+}
+
+extern "C" lp_status lp_cloud_key_import(const lp_params* P, const uint32_t* bsk, const uint32_t* ksk,
+                                         lp_cloud_key** ck) {
+  std::string why;
+  if (!params_ok(P, &why)) return fail(LP_EINVAL, "lp_cloud_key_import: %s", why.c_str());
+  if (!bsk || !ksk || !ck) return fail(LP_EINVAL, "lp_cloud_key_import: null argument");
+  try {
+    auto k = std::make_unique<lp_cloud_key>();
+    k->P = *P;
+    k->bsk.assign(bsk, bsk + lp_bsk_words(P));
+    k->ksk.assign(ksk, ksk + lp_ksk_words(P));
+    *ck = k.release();
+    return LP_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(LP_ENOMEM, "lp_cloud_key_import: out of host memory");
+  }
+}
+
+extern "C" lp_status lp_cloud_key_export(const lp_cloud_key* ck, uint32_t* bsk, uint32_t* ksk) {
+  if (!ck) return fail(LP_EINVAL, "lp_cloud_key_export: null key");
+  if (bsk) std::memcpy(bsk, ck->bsk.data(), ck->bsk.size() * 4);
+  if (ksk) std::memcpy(ksk, ck->ksk.data(), ck->ksk.size() * 4);
+  return LP_OK;
+}
+
+extern "C" lp_status lp_cloud_key_params(const lp_cloud_key* ck, lp_params* out) {
+  if (!ck || !out) return fail(LP_EINVAL, "lp_cloud_key_params: null argument");
+  *out = ck->P;
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------- Encrypt / Decrypt
+extern "C" lp_status lp_encrypt_bits(const lp_secret_key* sk, const uint8_t* bits, size_t cnt, uint64_t seed,
+                                     uint64_t first_index, uint32_t* ct) {
+  if (!sk || (cnt && (!bits || !ct))) return fail(LP_EINVAL, "lp_encrypt_bits: null argument");
+  const uint32_t n = sk->P.n;
+  const Stream mask(seed, kStEncMask), noise(seed, kStEncNoise);
+  for (size_t k = 0; k < cnt; ++k) {
+    if (bits[k] > 1) return fail(LP_EINVAL, "lp_encrypt_bits: bits must be 0/1");
+    const uint32_t mu = bits[k] ? 0x20000000u : 0xE0000000u;  // f(m) = m/4 - 1/8
+    lwe_sample(n, sk->s.data(), mu, mask, noise, first_index + k, sk->P.lwe_sigma, ct + k * (n + 1));
+  }
+  return LP_OK;
+}
+
+extern "C" lp_status lp_decrypt_bits(const lp_secret_key* sk, const uint32_t* ct, size_t cnt, uint8_t* bits,
+                                     int32_t* phase) {
+  if (!sk || (cnt && (!ct || !bits))) return fail(LP_EINVAL, "lp_decrypt_bits: null argument");
+  const uint32_t n = sk->P.n;
+  for (size_t k = 0; k < cnt; ++k) {
+    const uint32_t* c = ct + k * (n + 1);
+    uint32_t dot = 0;
+    for (uint32_t i = 0; i < n; ++i)
+      if (sk->s[i]) dot += c[i];
+    const int32_t ph = (int32_t)(c[n] - dot);
+    bits[k] = ph > 0 ? 1 : 0;
+    if (phase) phase[k] = ph;
+  }
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------- twiddles
+namespace {
+constexpr uint64_t kP = 0xFFFFFFFF00000001ull;
+
+uint64_t mulmod_p(uint64_t a, uint64_t b) { return (uint64_t)(((unsigned __int128)a * b) % kP); }
+uint64_t powmod_p(uint64_t b, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = mulmod_p(r, b);
+    b = mulmod_p(b, b);
+    e >>= 1;
+  }
+  return r;
+}
+int bit_reverse5(int x) {
+  int r = 0;
+  for (int b = 0; b < 5; ++b) r |= ((x >> b) & 1) << (4 - b);
+  return r;
+}
+
+// psi: a primitive 2048th root of unity with psi^32 = 8.  7 generates Z_p^*
+// (checked against every prime factor of p - 1 = 2^32 3 5 17 257 65537).
+// g = 7^((p-1)/2048) is a primitive 2048th root; g^32 is a primitive 64th
+// root, i.e. 8^c for some odd c, and psi = g^e with (g^32)^e = 8.
+bool make_twiddles(std::vector<uint64_t>& fwd, std::vector<uint64_t>& inv) {
+  for (uint64_t f : {2ull, 3ull, 5ull, 17ull, 257ull, 65537ull})
+    if (powmod_p(7, (kP - 1) / f) == 1) return false;
+  const uint64_t g = powmod_p(7, (kP - 1) / 2048);
+  const uint64_t g32 = powmod_p(g, 32);
+  uint64_t e = 0;
+  for (uint64_t c = 1; c < 64; c += 2)
+    if (powmod_p(g32, c) == 8) { e = c; break; }
+  if (!e) return false;
+  const uint64_t psi = powmod_p(g, e);
+  if (powmod_p(psi, 32) != 8 || powmod_p(psi, 1024) != kP - 1) return false;
+  const uint64_t psi_inv = powmod_p(psi, 2047);
+  const uint64_t n_inv = powmod_p(1024, kP - 2);
+  fwd.assign(1024, 0);
+  inv.assign(1024, 0);
+  for (int i = 0; i < 32; ++i)
+    for (int l = 0; l < 32; ++l) {
+      const uint64_t ex = (uint64_t)(2 * bit_reverse5(i) + 1) * l;
+      fwd[i * 32 + l] = powmod_p(psi, ex % 2048);
+    }
+  for (int m = 0; m < 32; ++m)
+    for (int l = 0; l < 32; ++l) {
+      const uint64_t ex = (uint64_t)(2 * bit_reverse5(l) + 1) * m;
+      inv[m * 32 + l] = mulmod_p(powmod_p(psi_inv, ex % 2048), n_inv);
+    }
+  return true;
+}
+
+struct DeviceTables {
+  uint64_t* fwd = nullptr;
+  uint64_t* inv = nullptr;
+};
+std::mutex g_tw_mu;
+std::map<int, DeviceTables> g_tw;
+
+// Twiddle tables of the current device, uploaded once and kept for the
+// process lifetime.
+lp_status device_twiddles(lp::Twiddles* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  auto it = g_tw.find(dev);
+  if (it == g_tw.end()) {
+    std::vector<uint64_t> f, i;
+    if (!make_twiddles(f, i)) return fail(LP_EDEVICE, "twiddle construction failed");
+    DeviceTables t;
+    HIP_TRY(hipMalloc(&t.fwd, 1024 * 8));
+    HIP_TRY(hipMalloc(&t.inv, 1024 * 8));
+    HIP_TRY(hipMemcpy(t.fwd, f.data(), 1024 * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t.inv, i.data(), 1024 * 8, hipMemcpyHostToDevice));
+    it = g_tw.emplace(dev, t).first;
+  }
+  out->fwd = it->second.fwd;
+  out->inv = it->second.inv;
+  return LP_OK;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+}  // namespace
+
+// ---------------------------------------------------------------- device keys
+extern "C" void lp_device_key_free(lp_device_key* dk);
+
+extern "C" lp_status lp_device_key_create(const lp_cloud_key* ck, void* stream, lp_device_key** dk) {
+  if (!ck || !dk) return fail(LP_EINVAL, "lp_device_key_create: null argument");
+  std::string why;
+  if (!gpu_params_ok(ck->P, &why)) return fail(LP_EUNSUPPORTED, "lp_device_key_create: %s", why.c_str());
+  hipStream_t s = as_stream(stream);
+  auto k = std::make_unique<lp_device_key>();
+  k->P = ck->P;
+  HIP_TRY(hipGetDevice(&k->device));
+  lp_status st = device_twiddles(&k->tw);
+  if (st != LP_OK) return st;
+  const size_t bw = ck->bsk.size(), kw = ck->ksk.size();
+  uint32_t* tmp = nullptr;
+  hipError_t e = hipMalloc(&k->bsk_ntt, bw * 8);
+  if (e == hipSuccess) e = hipMalloc(&k->ksk, kw * 4);
+  if (e == hipSuccess) e = hipMalloc(&tmp, bw * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&k->bsk_tab, sizeof(void*));
+  if (e == hipSuccess) e = hipMalloc((void**)&k->ksk_tab, sizeof(void*));
+  if (e != hipSuccess) {
+    if (tmp) (void)hipFree(tmp);
+    lp_device_key_free(k.release());
+    return fail(LP_ENOMEM, "lp_device_key_create: device allocation failed (%s)", hipGetErrorString(e));
+  }
+  e = hipMemcpyAsync(tmp, ck->bsk.data(), bw * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(k->ksk, ck->ksk.data(), kw * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(k->bsk_tab, &k->bsk_ntt, sizeof(void*), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(k->ksk_tab, &k->ksk, sizeof(void*), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = lp::launch_bsk_to_ntt(tmp, k->bsk_ntt, (int)(bw / 1024), k->tw, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    lp_device_key_free(k.release());
+    return fail(LP_EDEVICE, "lp_device_key_create: %s", hipGetErrorString(e));
+  }
+  k->bytes = bw * 8 + kw * 4;
+  *dk = k.release();
+  return LP_OK;
+}
+
+extern "C" lp_status lp_device_key_bytes(const lp_device_key* dk, size_t* bytes) {
+  if (!dk || !bytes) return fail(LP_EINVAL, "lp_device_key_bytes: null argument");
+  *bytes = dk->bytes;
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------- gate batches
+namespace {
+struct GateCombo {
+  int nbr;  // 0 = linear only, 1 = one blind rotation, 2 = MUX
+  uint32_t cst;
+  int32_t c0, c1;
+};
+
+// Linear pre-combination whose phase sign is the gate's value; HomAND =
+// Bootstrap((0, -1/8) + c1 + c2) (Sec. 2.3), the rest alike.
+bool gate_combo(lp_gate g, GateCombo* c) {
+  const uint32_t E = 0x20000000u, Qr = 0x40000000u;  // 1/8, 1/4
+  switch (g) {
+    case LP_GATE_NAND: *c = {1, E, -1, -1}; return true;
+    case LP_GATE_AND: *c = {1, 0u - E, 1, 1}; return true;
+    case LP_GATE_OR: *c = {1, E, 1, 1}; return true;
+    case LP_GATE_NOR: *c = {1, 0u - E, -1, -1}; return true;
+    case LP_GATE_XOR: *c = {1, Qr, 2, 2}; return true;
+    case LP_GATE_XNOR: *c = {1, 0u - Qr, -2, -2}; return true;
+    case LP_GATE_MUX: *c = {2, 0, 0, 0}; return true;
+    case LP_GATE_NOT: *c = {0, 0, -1, 0}; return true;
+    case LP_GATE_COPY: *c = {0, 0, 1, 0}; return true;
+  }
+  return false;
+}
+
+int pick_ks_tile(size_t njobs) { return njobs >= 4096 ? 16 : njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1; }
+int pick_br_wpb(size_t njobs) { (void)njobs; return 1; }
+
+struct ScopedDevice {
+  int prev = -1;
+  explicit ScopedDevice(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~ScopedDevice() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+}  // namespace
+
+extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                                        const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt, uint32_t* d_out,
+                                        void* stream) {
+  if (!dk) return fail(LP_EINVAL, "lp_bootstrap_batch: null key");
+  GateCombo gc;
+  if (!gate_combo(gate, &gc)) return fail(LP_EINVAL, "lp_bootstrap_batch: unknown gate %d", (int)gate);
+  if (cnt == 0) return LP_OK;
+  if (!d_in0 || !d_out) return fail(LP_EINVAL, "lp_bootstrap_batch: null buffer");
+  if (gc.nbr >= 1 && gate != LP_GATE_MUX && !d_in1) return fail(LP_EINVAL, "lp_bootstrap_batch: gate needs d_in1");
+  if (gate == LP_GATE_MUX && (!d_in1 || !d_in2)) return fail(LP_EINVAL, "lp_bootstrap_batch: MUX needs three inputs");
+  if (cnt > (size_t)(lp::REF_INDEX_MASK / 2)) return fail(LP_EINVAL, "lp_bootstrap_batch: batch too large");
+  ScopedDevice sd(dk->device);
+  hipStream_t s = as_stream(stream);
+  const uint32_t n = dk->P.n, N = dk->P.N;
+  if (gc.nbr == 0) {
+    HIP_TRY(lp::launch_lwe_scale(d_in0, d_out, cnt * (n + 1), gc.c0, s));
+    return LP_OK;
+  }
+  const size_t nbr = cnt * gc.nbr;
+  const size_t ex_bytes = nbr * (N + 1) * 4, br_bytes = nbr * sizeof(BrJob), ks_bytes = cnt * sizeof(KsJob);
+  char* scratch = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&scratch, ex_bytes + br_bytes + ks_bytes + 512, s));
+  uint32_t* ex = reinterpret_cast<uint32_t*>(scratch);
+  BrJob* br = reinterpret_cast<BrJob*>(scratch + ((ex_bytes + 255) & ~size_t(255)));
+  KsJob* ks = reinterpret_cast<KsJob*>(reinterpret_cast<char*>(br) + ((br_bytes + 255) & ~size_t(255)));
+  hipError_t e = lp::launch_make_batch_jobs(gc.nbr, gc.cst, gc.c0, gc.c1, d_in1 != nullptr, cnt, br, ks, s);
+  lp::SrcBases src{};
+  src.p[0] = d_in0;
+  src.p[1] = d_in1;
+  src.p[2] = d_in2;
+  lp::DstBases dst{};
+  dst.p[0] = d_out;
+  if (e == hipSuccess)
+    e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, (int)n, (int)n, 0, dk->tw, pick_br_wpb(nbr), s);
+  if (e == hipSuccess)
+    e = lp::launch_keyswitch(ks, (int)cnt, ex, dst, dk->ksk_tab, (int)n, (int)N, (int)dk->P.ks_t,
+                             (int)dk->P.ks_base_bit, pick_ks_tile(cnt), s);
+  hipError_t e2 = hipFreeAsync(scratch, s);
+  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e2));
+  return LP_OK;
+}
+
+extern "C" lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, uint32_t* d_out,
+                                        void* stream) {
+  if (!dk) return fail(LP_EINVAL, "lp_keyswitch_batch: null key");
+  if (cnt == 0) return LP_OK;
+  if (!d_in || !d_out) return fail(LP_EINVAL, "lp_keyswitch_batch: null buffer");
+  if (cnt > (size_t)lp::REF_INDEX_MASK) return fail(LP_EINVAL, "lp_keyswitch_batch: batch too large");
+  ScopedDevice sd(dk->device);
+  hipStream_t s = as_stream(stream);
+  std::vector<KsJob> jobs(cnt);
+  for (size_t k = 0; k < cnt; ++k) jobs[k] = KsJob{(uint32_t)k, lp::REF_NONE, 0u, lp::make_ref(0, (uint32_t)k), 0u, {0, 0, 0}};
+  KsJob* dj = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&dj, cnt * sizeof(KsJob), s));
+  hipError_t e = hipMemcpyAsync(dj, jobs.data(), cnt * sizeof(KsJob), hipMemcpyHostToDevice, s);
+  lp::DstBases dst{};
+  dst.p[0] = d_out;
+  if (e == hipSuccess)
+    e = lp::launch_keyswitch(dj, (int)cnt, d_in, dst, dk->ksk_tab, (int)dk->P.n, (int)dk->P.N, (int)dk->P.ks_t,
+                             (int)dk->P.ks_base_bit, pick_ks_tile(cnt), s);
+  // the host staging vector must outlive the copy
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipError_t e2 = hipFreeAsync(dj, s);
+  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_keyswitch_batch: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(LP_EDEVICE, "lp_keyswitch_batch: %s", hipGetErrorString(e2));
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------- bbox circuit
+namespace {
+// A ciphertext of the circuit: an input or gate-output slot, possibly
+// negated (HomNOT is free: it negates the sample), or the noiseless trivial
+// sample (0, v).
+struct CRef {
+  int32_t slot = -1;  // -1: trivial
+  bool neg = false;
+  uint32_t tval = 0;
+  int level = 0;
+};
+
+struct Gate {
+  int kind;  // LP_GATE_AND, LP_GATE_XNOR, LP_GATE_XOR or LP_GATE_MUX
+  CRef in[3];
+  int level;
+  int32_t out;
+};
+
+CRef cnot(CRef r) {
+  if (r.slot < 0) r.tval = 0u - r.tval;
+  else r.neg = !r.neg;
+  return r;
+}
+
+struct Circuit {
+  int32_t n_slots = 0;
+  std::vector<Gate> gates;
+  std::vector<CRef> outputs;
+
+  CRef input() {
+    CRef r;
+    r.slot = n_slots++;
+    return r;
+  }
+  CRef gate(int kind, CRef a, CRef b, CRef c = CRef()) {
+    Gate g;
+    g.kind = kind;
+    g.in[0] = a;
+    g.in[1] = b;
+    g.in[2] = c;
+    g.level = 1 + std::max({a.level, b.level, kind == LP_GATE_MUX ? c.level : 0});
+    g.out = n_slots++;
+    gates.push_back(g);
+    CRef r;
+    r.slot = g.out;
+    r.level = g.level;
+    return r;
+  }
+  // Algorithm 2 (HomCompS): Enc(1) iff a < b.  t0 starts as the trivial
+  // Enc(0) = (0, -1/8); signed inputs flip both MSBs first; then per bit from
+  // the LSB: t1 = XNOR(a_i, b_i), t0 = MUX(t1, t0, b_i).
+  CRef comp_s(std::vector<CRef> a, std::vector<CRef> b, bool is_signed) {
+    const size_t l = a.size();
+    if (is_signed) {
+      a[l - 1] = cnot(a[l - 1]);
+      b[l - 1] = cnot(b[l - 1]);
+    }
+    CRef t0;
+    t0.tval = 0xE0000000u;
+    for (size_t i = 0; i < l; ++i) {
+      CRef t1 = gate(LP_GATE_XNOR, a[i], b[i]);
+      t0 = gate(LP_GATE_MUX, t1, t0, b[i]);
+    }
+    return t0;
+  }
+};
+
+// Algorithms 3-5 for one query shape.
+Circuit build_bbox(uint32_t l, uint32_t N, uint32_t m, bool is_signed) {
+  Circuit C;
+  std::vector<CRef> X(l), Y(l);
+  for (auto& r : X) r = C.input();
+  for (auto& r : Y) r = C.input();
+  std::vector<std::vector<CRef>> B(4 * N, std::vector<CRef>(l));
+  for (auto& v : B)
+    for (auto& r : v) r = C.input();
+  std::vector<CRef> S((size_t)N * m);
+  for (auto& r : S) r = C.input();
+  std::vector<std::vector<CRef>> T(m);
+  for (uint32_t bi = 0; bi < N; ++bi) {
+    // x_l = HomCompLE(x1, x) = NOT HomCompS(x, x1);  x_r = HomCompS(x, x2)
+    CRef xl = cnot(C.comp_s(X, B[4 * bi + 0], is_signed));
+    CRef xr = C.comp_s(X, B[4 * bi + 1], is_signed);
+    CRef yl = cnot(C.comp_s(Y, B[4 * bi + 2], is_signed));
+    CRef yr = C.comp_s(Y, B[4 * bi + 3], is_signed);
+    CRef v1 = C.gate(LP_GATE_AND, xl, xr);
+    CRef v2 = C.gate(LP_GATE_AND, yl, yr);
+    CRef f = C.gate(LP_GATE_AND, v1, v2);
+    for (uint32_t j = 0; j < m; ++j) T[j].push_back(C.gate(LP_GATE_AND, f, S[(size_t)bi * m + j]));  // Alg. 4
+  }
+  // Algorithm 5 as a balanced XOR tree: pairs left to right, odd one carried
+  for (uint32_t j = 0; j < m; ++j) {
+    std::vector<CRef> cur = T[j];
+    while (cur.size() > 1) {
+      std::vector<CRef> nxt;
+      for (size_t k = 0; k + 1 < cur.size(); k += 2) nxt.push_back(C.gate(LP_GATE_XOR, cur[k], cur[k + 1]));
+      if (cur.size() & 1) nxt.push_back(cur.back());
+      cur.swap(nxt);
+    }
+    C.outputs.push_back(cur[0]);
+  }
+  return C;
+}
+
+struct Plan {
+  uint32_t l, N, m;
+  int is_signed;
+  uint32_t n_inputs = 0, n_slots = 0;
+  uint64_t n_br = 0, n_ks = 0;
+  std::vector<int> br_off, br_cnt, ks_off, ks_cnt;  // per level, into the job arrays
+  int max_br = 0;
+  BrJob* d_br = nullptr;
+  KsJob* d_ks = nullptr;
+  uint32_t* d_out_refs = nullptr;
+  int levels() const { return (int)br_cnt.size(); }
+  ~Plan() {
+    if (d_br) (void)hipFree(d_br);
+    if (d_ks) (void)hipFree(d_ks);
+    if (d_out_refs) (void)hipFree(d_out_refs);
+  }
+};
+
+// Host part of a plan: jobs grouped by level.
+void schedule(const Circuit& C, uint32_t n_inputs, Plan& P, std::vector<BrJob>& br, std::vector<KsJob>& ks,
+              std::vector<uint32_t>& out_refs) {
+  int depth = 0;
+  for (auto& g : C.gates) depth = std::max(depth, g.level);
+  std::vector<std::vector<const Gate*>> by_level(depth + 1);
+  for (auto& g : C.gates) by_level[g.level].push_back(&g);
+  P.n_inputs = n_inputs;
+  P.n_slots = (uint32_t)C.n_slots;
+  // operand (coef * ref) folded into a blind-rotation input
+  auto put = [](BrJob& j, int which, const CRef& r, int32_t coef) {
+    if (r.slot < 0) {
+      j.cst += (uint32_t)coef * r.tval;
+      return;
+    }
+    const uint32_t ref = lp::make_ref(0, (uint32_t)r.slot);
+    const int32_t c = r.neg ? -coef : coef;
+    if (which == 0) { j.in0 = ref; j.c0 = c; }
+    else { j.in1 = ref; j.c1 = c; }
+  };
+  for (int L = 1; L <= depth; ++L) {
+    P.br_off.push_back((int)br.size());
+    P.ks_off.push_back((int)ks.size());
+    int slot = 0;
+    for (const Gate* g : by_level[L]) {
+      BrJob j{lp::REF_NONE, lp::REF_NONE, 0, 0, 0u, 0u, 0u, 0u};
+      KsJob k{lp::REF_NONE, lp::REF_NONE, 0u, lp::make_ref(0, (uint32_t)g->out), 0u, {0, 0, 0}};
+      if (g->kind == LP_GATE_MUX) {
+        BrJob j1 = j, j2 = j;
+        j1.cst = j2.cst = 0xE0000000u;  // -1/8
+        put(j1, 0, g->in[0], 1);         // sel AND t
+        put(j1, 1, g->in[1], 1);
+        put(j2, 0, g->in[0], -1);        // NOT sel AND f
+        put(j2, 1, g->in[2], 1);
+        j1.out = (uint32_t)slot++;
+        j2.out = (uint32_t)slot++;
+        br.push_back(j1);
+        br.push_back(j2);
+        k.ex0 = j1.out;
+        k.ex1 = j2.out;
+        k.cst = 0x20000000u;             // + 1/8
+        P.n_br += 2;
+      } else {
+        GateCombo gc;
+        gate_combo((lp_gate)g->kind, &gc);
+        j.cst = gc.cst;
+        put(j, 0, g->in[0], gc.c0);
+        put(j, 1, g->in[1], gc.c1);
+        j.out = (uint32_t)slot++;
+        br.push_back(j);
+        k.ex0 = j.out;
+        P.n_br += 1;
+      }
+      ks.push_back(k);
+      P.n_ks += 1;
+    }
+    P.br_cnt.push_back((int)br.size() - P.br_off.back());
+    P.ks_cnt.push_back((int)ks.size() - P.ks_off.back());
+    P.max_br = std::max(P.max_br, slot);
+  }
+  for (auto& o : C.outputs) out_refs.push_back(lp::make_ref(0, (uint32_t)o.slot));
+}
+
+lp_status get_plan(lp_device_key* dk, uint32_t l, uint32_t N, uint32_t m, int is_signed, std::shared_ptr<Plan>* out) {
+  std::lock_guard<std::mutex> lk(dk->mu);
+  auto key = std::make_tuple(l, N, m, is_signed);
+  auto it = dk->plans.find(key);
+  if (it != dk->plans.end()) {
+    *out = it->second;
+    return LP_OK;
+  }
+  Circuit C = build_bbox(l, N, m, is_signed != 0);
+  auto P = std::make_shared<Plan>();
+  P->l = l;
+  P->N = N;
+  P->m = m;
+  P->is_signed = is_signed;
+  std::vector<BrJob> br;
+  std::vector<KsJob> ks;
+  std::vector<uint32_t> refs;
+  schedule(C, 2 * l + 4 * l * N + N * m, *P, br, ks, refs);
+  if (P->n_slots > lp::REF_INDEX_MASK) return fail(LP_EINVAL, "query too large");
+  HIP_TRY(hipMalloc(&P->d_br, std::max<size_t>(1, br.size()) * sizeof(BrJob)));
+  HIP_TRY(hipMalloc(&P->d_ks, std::max<size_t>(1, ks.size()) * sizeof(KsJob)));
+  HIP_TRY(hipMalloc(&P->d_out_refs, std::max<size_t>(1, refs.size()) * 4));
+  HIP_TRY(hipMemcpy(P->d_br, br.data(), br.size() * sizeof(BrJob), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P->d_ks, ks.data(), ks.size() * sizeof(KsJob), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P->d_out_refs, refs.data(), refs.size() * 4, hipMemcpyHostToDevice));
+  dk->plans[key] = P;
+  *out = P;
+  return LP_OK;
+}
+}  // namespace
+
+extern "C" lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,
+                                    uint32_t* n_levels) {
+  if (l == 0 || l > 64 || n_boxes == 0 || m == 0) return fail(LP_EINVAL, "lp_bbox_counts: empty shape");
+  Circuit C = build_bbox(l, n_boxes, m, true);
+  Plan P;
+  std::vector<BrJob> br;
+  std::vector<KsJob> ks;
+  std::vector<uint32_t> refs;
+  schedule(C, 0, P, br, ks, refs);
+  if (n_br) *n_br = P.n_br;
+  if (n_ks) *n_ks = P.n_ks;
+  if (n_levels) *n_levels = (uint32_t)P.levels();
+  return LP_OK;
+}
+
+extern "C" lp_status lp_eval_bbox_query(const lp_device_key* dkc, const lp_bbox_query* q, uint32_t* d_out,
+                                        void* stream) {
+  if (!dkc || !q || !d_out) return fail(LP_EINVAL, "lp_eval_bbox_query: null argument");
+  if (q->l == 0 || q->l > 64 || q->n_boxes == 0 || q->m == 0)
+    return fail(LP_EINVAL, "lp_eval_bbox_query: empty or oversized query shape");
+  if (!q->d_x || !q->d_y || !q->d_bounds || !q->d_payload) return fail(LP_EINVAL, "lp_eval_bbox_query: null input");
+  lp_device_key* dk = const_cast<lp_device_key*>(dkc);
+  ScopedDevice sd(dk->device);
+  std::shared_ptr<Plan> P;
+  lp_status st = get_plan(dk, q->l, q->n_boxes, q->m, q->is_signed ? 1 : 0, &P);
+  if (st != LP_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const uint32_t n = dk->P.n, w = n + 1, Nr = dk->P.N;
+  const size_t pool_bytes = (size_t)P->n_slots * w * 4, ex_bytes = (size_t)P->max_br * (Nr + 1) * 4;
+  uint32_t* pool = nullptr;
+  uint32_t* ex = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&pool, pool_bytes, s));
+  hipError_t e = hipMallocAsync((void**)&ex, std::max<size_t>(ex_bytes, 4), s);
+  const size_t l = q->l, Nb = q->n_boxes, m = q->m;
+  size_t off = 0;
+  auto put = [&](const uint32_t* src, size_t cts) {
+    if (e == hipSuccess) e = hipMemcpyAsync(pool + off * w, src, cts * w * 4, hipMemcpyDeviceToDevice, s);
+    off += cts;
+  };
+  put(q->d_x, l);
+  put(q->d_y, l);
+  put(q->d_bounds, 4 * l * Nb);
+  put(q->d_payload, Nb * m);
+  lp::SrcBases src{};
+  src.p[0] = pool;
+  lp::DstBases dst{};
+  dst.p[0] = pool;
+  for (int L = 0; L < P->levels() && e == hipSuccess; ++L) {
+    e = lp::launch_blind_rotate(P->d_br + P->br_off[L], P->br_cnt[L], src, ex, dk->bsk_tab, (int)n, (int)n, 0, dk->tw,
+                                pick_br_wpb(P->br_cnt[L]), s);
+    if (e == hipSuccess)
+      e = lp::launch_keyswitch(P->d_ks + P->ks_off[L], P->ks_cnt[L], ex, dst, dk->ksk_tab, (int)n, (int)Nr,
+                               (int)dk->P.ks_t, (int)dk->P.ks_base_bit, pick_ks_tile(P->ks_cnt[L]), s);
+  }
+  if (e == hipSuccess) e = lp::launch_gather(P->d_out_refs, (int)m, src, d_out, (int)n, s);
+  hipError_t e2 = hipFreeAsync(pool, s);
+  hipError_t e3 = ex ? hipFreeAsync(ex, s) : hipSuccess;
+  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_eval_bbox_query: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess || e3 != hipSuccess) return fail(LP_EDEVICE, "lp_eval_bbox_query: free failed");
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------- diagnostics
+extern "C" lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint32_t* d_poly, size_t cnt,
+                                             uint32_t* d_out, void* stream) {
+  if (cnt == 0) return LP_OK;
+  if (!d_digits || !d_poly || !d_out) return fail(LP_EINVAL, "lp_debug_negacyclic_mul: null buffer");
+  if (cnt > (1u << 20)) return fail(LP_EINVAL, "lp_debug_negacyclic_mul: too many products");
+  hipStream_t s = as_stream(stream);
+  lp::Twiddles tw;
+  lp_status st = device_twiddles(&tw);
+  if (st != LP_OK) return st;
+  uint64_t* tmp = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&tmp, cnt * 1024 * 8, s));
+  hipError_t e = lp::launch_bsk_to_ntt(d_poly, tmp, (int)cnt, tw, s);
+  if (e == hipSuccess) e = lp::launch_debug_polymul(d_digits, tmp, d_out, (int)cnt, tw, s);
+  hipError_t e2 = hipFreeAsync(tmp, s);
+  if (e != hipSuccess || e2 != hipSuccess) return fail(LP_EDEVICE, "lp_debug_negacyclic_mul: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  return LP_OK;
+}
+
+extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, uint32_t steps,
+                                           uint32_t* d_acc, void* stream) {
+  if (!dk) return fail(LP_EINVAL, "lp_debug_blind_rotate: null key");
+  if (cnt == 0) return LP_OK;
+  if (!d_in || !d_acc) return fail(LP_EINVAL, "lp_debug_blind_rotate: null buffer");
+  if (cnt > (size_t)lp::REF_INDEX_MASK) return fail(LP_EINVAL, "lp_debug_blind_rotate: batch too large");
+  ScopedDevice sd(dk->device);
+  hipStream_t s = as_stream(stream);
+  std::vector<BrJob> jobs(cnt);
+  for (size_t k = 0; k < cnt; ++k)
+    jobs[k] = BrJob{lp::make_ref(0, (uint32_t)k), lp::REF_NONE, 1, 0, 0u, (uint32_t)k, 0u, 0u};
+  BrJob* dj = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&dj, cnt * sizeof(BrJob), s));
+  hipError_t e = hipMemcpyAsync(dj, jobs.data(), cnt * sizeof(BrJob), hipMemcpyHostToDevice, s);
+  lp::SrcBases src{};
+  src.p[0] = d_in;
+  const int st = (int)std::min<uint32_t>(steps, dk->P.n);
+  if (e == hipSuccess)
+    e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, (int)dk->P.n, st, 1, dk->tw, 1, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipError_t e2 = hipFreeAsync(dj, s);
+  if (e != hipSuccess || e2 != hipSuccess) return fail(LP_EDEVICE, "lp_debug_blind_rotate: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  return LP_OK;
+}
+
+// ---------------------------------------------------------------- free
+extern "C" void lp_secret_key_free(lp_secret_key* sk) { delete sk; }
+extern "C" void lp_cloud_key_free(lp_cloud_key* ck) { delete ck; }
+extern "C" void lp_device_key_free(lp_device_key* dk) {
+  if (!dk) return;
+  ScopedDevice sd(dk->device);
+  dk->plans.clear();
+  if (dk->bsk_ntt) (void)hipFree(dk->bsk_ntt);
+  if (dk->ksk) (void)hipFree(dk->ksk);
+  if (dk->bsk_tab) (void)hipFree(dk->bsk_tab);
+  if (dk->ksk_tab) (void)hipFree(dk->ksk_tab);
+  delete dk;
+}

@@ -1,0 +1,148 @@
+// Register-resident 32-point transforms over the Goldilocks field: the two
+// passes of a 1024-point negacyclic NTT laid out as 32 lanes x 32 registers.
+//
+// The 1024-point negacyclic transform evaluates a(X) at psi^(2k+1),
+// k < 1024, where psi is a primitive 2048th root of unity chosen with
+// psi^32 = 8.  Writing j = j1 + 32*j2 and k = ka + 32*kb:
+//   pass 1 (per j1): B_j1(ka) = sum_j2 a_{j1+32 j2} rho^{j2 (2ka+1)},
+//                    rho = psi^32 = 8, a negacyclic 32-point DFT;
+//   twist:           C_j1(ka) = B_j1(ka) * psi^{(2ka+1) j1};
+//   pass 2 (per ka): A(ka + 32 kb) = sum_j1 C_j1(ka) omega^{kb j1},
+//                    omega = psi^64 = 64, a cyclic 32-point DFT.
+// rho and omega are powers of two, so both passes use shift twiddles
+// (gl_mul_pow2); only the twist needs general multiplications.
+//
+// Pass 1 runs merged Cooley-Tukey butterflies (natural order in, slot i
+// holds ka = brv5(i) out); pass 2 runs Gentleman-Sande butterflies (natural
+// in, slot i' holds kb = brv5(i') out).  The inverse passes undo them in the
+// opposite order; their factor 32 each is folded into the inverse twist.
+#pragma once
+#include <type_traits>
+
+#include "gl64.h"
+
+namespace lp {
+
+constexpr int brv5(int x) {
+  return ((x & 1) << 4) | ((x & 2) << 2) | (x & 4) | ((x & 8) >> 2) | ((x & 16) >> 4);
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// ---- pass 1, forward: merged negacyclic CT, root rho = 2^3 ----------------
+template <int LEN>
+__device__ __forceinline__ void fwd1_stage(uint64_t (&a)[32]) {
+  static_for<0, 32 / (2 * LEN)>([&](auto blk) {
+    constexpr int start = decltype(blk)::value * 2 * LEN;
+    constexpr int k = 32 / (2 * LEN) + start / (2 * LEN);
+    constexpr int z = 3 * brv5(k);
+    static_for<0, LEN>([&](auto jj) {
+      constexpr int j = start + decltype(jj)::value;
+      uint64_t t = gl_mul_pow2<z>(a[j + LEN]);
+      a[j + LEN] = gl_sub(a[j], t);
+      a[j] = gl_add(a[j], t);
+    });
+  });
+}
+
+// First stage on small signed integers (gadget digits, |d| <= 64): the
+// twiddle is rho^16 = 2^48 and a +- 2^48 b is exact in 64-bit integers.
+__device__ __forceinline__ void fwd1_first_stage_digits(const int32_t (&d)[32], uint64_t (&a)[32]) {
+  static_for<0, 16>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    int64_t lo = d[j], hi = (int64_t)d[j + 16] * (int64_t)(1ll << 48);
+    a[j] = gl_from_i64(lo + hi);
+    a[j + 16] = gl_from_i64(lo - hi);
+  });
+}
+
+__device__ __forceinline__ void fwd1_rest(uint64_t (&a)[32]) {
+  fwd1_stage<8>(a);
+  fwd1_stage<4>(a);
+  fwd1_stage<2>(a);
+  fwd1_stage<1>(a);
+}
+
+__device__ __forceinline__ void fwd1(uint64_t (&a)[32]) {
+  fwd1_stage<16>(a);
+  fwd1_rest(a);
+}
+
+// ---- pass 2, forward: cyclic GS DIF, root omega = 2^6 ---------------------
+template <int LEN>
+__device__ __forceinline__ void fwd2_stage(uint64_t (&a)[32]) {
+  static_for<0, 32 / (2 * LEN)>([&](auto blk) {
+    constexpr int start = decltype(blk)::value * 2 * LEN;
+    static_for<0, LEN>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      constexpr int e = 6 * (16 / LEN) * j; /* omega_{2 LEN}^j */
+      uint64_t u = a[start + j], v = a[start + j + LEN];
+      a[start + j] = gl_add(u, v);
+      a[start + j + LEN] = gl_mul_pow2<e>(gl_sub(u, v));
+    });
+  });
+}
+
+__device__ __forceinline__ void fwd2(uint64_t (&a)[32]) {
+  fwd2_stage<16>(a);
+  fwd2_stage<8>(a);
+  fwd2_stage<4>(a);
+  fwd2_stage<2>(a);
+  fwd2_stage<1>(a);
+}
+
+// ---- pass 2, inverse: cyclic CT DIT with omega^-1 (factor 32 left over) ---
+template <int LEN>
+__device__ __forceinline__ void inv2_stage(uint64_t (&a)[32]) {
+  static_for<0, 32 / (2 * LEN)>([&](auto blk) {
+    constexpr int start = decltype(blk)::value * 2 * LEN;
+    static_for<0, LEN>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      constexpr int e = (192 - 6 * (16 / LEN) * j) % 192;
+      uint64_t u = a[start + j];
+      uint64_t v = gl_mul_pow2<e>(a[start + j + LEN]);
+      a[start + j] = gl_add(u, v);
+      a[start + j + LEN] = gl_sub(u, v);
+    });
+  });
+}
+
+__device__ __forceinline__ void inv2(uint64_t (&a)[32]) {
+  inv2_stage<1>(a);
+  inv2_stage<2>(a);
+  inv2_stage<4>(a);
+  inv2_stage<8>(a);
+  inv2_stage<16>(a);
+}
+
+// ---- pass 1, inverse: GS butterflies with rho^-brv5(k) (factor 32 left) ---
+template <int LEN>
+__device__ __forceinline__ void inv1_stage(uint64_t (&a)[32]) {
+  static_for<0, 32 / (2 * LEN)>([&](auto blk) {
+    constexpr int start = decltype(blk)::value * 2 * LEN;
+    constexpr int k = 32 / (2 * LEN) + start / (2 * LEN);
+    constexpr int z = (192 - 3 * brv5(k)) % 192;
+    static_for<0, LEN>([&](auto jj) {
+      constexpr int j = start + decltype(jj)::value;
+      uint64_t t = a[j];
+      a[j] = gl_add(t, a[j + LEN]);
+      a[j + LEN] = gl_mul_pow2<z>(gl_sub(t, a[j + LEN]));
+    });
+  });
+}
+
+__device__ __forceinline__ void inv1(uint64_t (&a)[32]) {
+  inv1_stage<1>(a);
+  inv1_stage<2>(a);
+  inv1_stage<4>(a);
+  inv1_stage<8>(a);
+  inv1_stage<16>(a);
+}
+
+}  // namespace lp

@@ -1,0 +1,89 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-side
+client operations agree bit for bit with the oracle (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2407_19871_amd as lp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "locpir.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lp.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    assert lp.lib().lp_version().decode().startswith("locpir")
+
+
+def test_default_params():
+    p = lp.params_default()
+    assert (p.n, p.N, p.k, p.bg_bit, p.l, p.ks_base_bit, p.ks_t) == (630, 1024, 1, 7, 3, 2, 8)
+    assert p.lwe_sigma == 2.0**-15 and p.bk_sigma == 2.0**-25
+    assert lp.bsk_words(p) == O.DEFAULT.bsk_words
+    assert lp.ksk_words(p) == O.DEFAULT.ksk_words
+
+
+@pytest.fixture(scope="module")
+def pkeys():
+    return lp.keygen(None, 1)
+
+
+def test_keygen_matches_oracle_bit_for_bit(pkeys, okeys):
+    sk, ck = pkeys
+    s, S = sk.export()
+    bsk, ksk = ck.export()
+    assert (s == okeys.s_lwe).all() and (S == okeys.s_ring).all()
+    assert (bsk == okeys.bsk).all()
+    assert (ksk == okeys.ksk).all()
+
+
+def test_encrypt_matches_oracle_and_decrypts(pkeys, okeys):
+    sk, _ = pkeys
+    bits = np.random.default_rng(3).integers(0, 2, 300).astype(np.uint8)
+    ct = sk.encrypt_bits(bits, seed=77, first_index=5)
+    assert (ct == O.encrypt_bits(okeys, bits, seed=77, first_index=5)).all()
+    d, ph = sk.decrypt_bits(ct)
+    od, oph = O.decrypt_bits(okeys, ct)
+    assert (d == bits).all() and (d == od).all() and (ph == oph).all()
+
+
+def test_imported_keys_roundtrip(okeys):
+    p = lp.params_default()
+    sk = lp.SecretKey.from_arrays(p, okeys.s_lwe, okeys.s_ring)
+    s, S = sk.export()
+    assert (s == okeys.s_lwe).all() and (S == okeys.s_ring).all()
+    ck = lp.CloudKey.from_arrays(p, okeys.bsk, okeys.ksk)
+    b, k = ck.export()
+    assert (b == okeys.bsk).all() and (k == okeys.ksk).all()
+
+
+@pytest.mark.parametrize("l,N,m", [(8, 1, 8), (16, 16, 32), (16, 9, 9), (13, 9, 9), (32, 5, 3), (4, 7, 2)])
+def test_plan_counts_match_oracle_walk(l, N, m):
+    br, ks, depth = O.bbox_counts(l, N, m)
+    assert lp.bbox_counts(l, N, m) == (br, ks, depth)
+
+
+def test_error_paths_do_not_throw():
+    p = lp.params_default()
+    bad = lp.Params(p.n, 1000, 1, 7, 3, 2, 8, p.lwe_sigma, p.bk_sigma)  # N not a power of two
+    h1, h2 = ctypes.c_void_p(), ctypes.c_void_p()
+    assert lp.lib().lp_keygen(ctypes.byref(bad), 1, ctypes.byref(h1), ctypes.byref(h2)) == -1
+    assert "power of two" in lp.lib().lp_last_error().decode()
+    assert lp.lib().lp_bootstrap_batch(None, 0, None, None, None, 1, None, None) == -1
+    assert lp.lib().lp_eval_bbox_query(None, None, None, None) == -1
+    assert lp.lib().lp_bbox_counts(0, 1, 1, None, None, None) == -1
+    with pytest.raises(lp.LocpirError):
+        lp.SecretKey.from_arrays(p, np.full(p.n, 2, np.uint8), np.zeros(p.N, np.uint8))

@@ -1,0 +1,42 @@
+"""GPU parity of gate batches of the microbenchmark sizes (uniform random
+bits, NAND gates sharing one key) and of ragged sizes."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2407_19871_amd as lp
+from paper_2407_19871_amd import workloads as W
+
+from gpu_common import as_u32, bits_of, cuda_or_skip, device_key_from_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dkey(okeys):
+    cuda_or_skip()
+    return device_key_from_oracle(okeys)
+
+
+@pytest.mark.parametrize("B", [1, 64, 97, 1024])
+def test_nand_batch_parity(okeys, octx, dkey, B):
+    a = W.random_bits(1000 + B, B)
+    b = W.random_bits(2000 + B, B)
+    c1 = O.encrypt_bits(okeys, a, seed=3000 + B)
+    c2 = O.encrypt_bits(okeys, b, seed=4000 + B)
+    got = as_u32(lp.bootstrap_batch(dkey, "NAND", lp.to_device(c1), lp.to_device(c2)))
+    exp, _ = octx.gate_batch("NAND", c1, c2)
+    assert (got == exp).all()
+    d, ph = bits_of(okeys, got)
+    assert (d == 1 - (a & b)).all()
+    assert np.abs(np.abs(ph.astype(np.int64)) - 2**29).max() < 2**28
+
+
+def test_mux_batch_ragged(okeys, octx, dkey):
+    B = 37
+    s, t, f = (W.random_bits(k, B) for k in (1, 2, 3))
+    cs, ct, cf = (O.encrypt_bits(okeys, v, seed=90 + i) for i, v in enumerate((s, t, f)))
+    got = as_u32(lp.bootstrap_batch(dkey, "MUX", lp.to_device(cs), lp.to_device(ct), lp.to_device(cf)))
+    exp, _ = octx.gate_batch("MUX", cs, ct, cf)
+    assert (got == exp).all()
+    assert (bits_of(okeys, got)[0] == np.where(s == 1, t, f)).all()
