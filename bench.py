@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark: one encrypted bounding-box query per step on one MI355X.
+
+Workload: 16-bit signed fixed-point latitude/longitude (9 integer + 7
+fraction bits) against 16 encrypted boxes that tile a Korea-like region
+(random guillotine widths), 32-bit encrypted payload per box; TFHE Torus32
+parameters n=630, N=1024, k=1, Bg=2^7, l=3, key-switch base 2^2 with t=8.
+The circuit (Algorithms 2-5) has 4112 gate bootstraps and 3088 key
+switches in 24 depth levels.  Inputs and keys are resident on the GPU before
+the timed region; a step is one full query evaluation.
+
+Prints one JSON line: bootstraps/s (value), queries/s, p50/p99 latency, the
+roofline of the blind-rotation kernel (event-timed live), the CPU oracle's
+rate on a bounded sample of the same gate mix, and batched NAND throughput
+against one bootstrap per launch.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gate bootstraps/s; bbox queries/s; p50/p99 query latency on 1 MI355X"
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic integer work of one blind rotation in 32-bit VALU lane-cycles:
+# 630 CMux steps x (6 forward + 2 inverse radix-2 1024-point NTTs = 40960
+# butterflies, plus 12 x 1024 pointwise products) = 25.8 M butterflies and
+# 7.74 M products; a Goldilocks mulmod costs 4 quarter-rate 32x32 multiplies
+# (16 lane-cycles) + 12 ALU ops, an add or subtract mod p 6 ops, so a
+# butterfly is 40 and a pointwise multiply-accumulate 35 lane-cycles.
+ALG_LANE_CYCLES_PER_BR = 630 * ((6 + 2) * 5120 * 40 + 12 * 1024 * 35)
+KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd/csrc/ntt32.h",
+                  "paper_2407_19871_amd/csrc/gl64.h"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_bbox16x16_traffic.txt")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """Per-launch HBM bytes of the blind-rotation kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on this kernel."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    txt = open(TRAFFIC_SUMMARY).read()
+    m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", txt, re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d
+
+
+def cpu_baseline(seed: int):
+    """The oracle as it stands, on a bounded sample of the query's gate mix:
+    256 XNOR + 128 MUX gates (512 bootstraps, the comparator mix), OpenMP over
+    every host thread."""
+    import oracle as O
+    keys = O.keygen(seed)
+    ctx = O.Ctx(keys)
+    rng = np.random.default_rng(seed)
+    nx, nm = 256, 128
+    bits = rng.integers(0, 2, 2 * nx + 3 * nm).astype(np.uint8)
+    ct = O.encrypt_bits(keys, bits, seed=seed + 1)
+    t0 = time.perf_counter()
+    _, th1 = ctx.gate_batch("XNOR", ct[:nx], ct[nx:2 * nx])
+    o = 2 * nx
+    _, th2 = ctx.gate_batch("MUX", ct[o:o + nm], ct[o + nm:o + 2 * nm], ct[o + 2 * nm:o + 3 * nm])
+    dt = time.perf_counter() - t0
+    n_br = nx + 2 * nm
+    return {"value": round(n_br / dt, 2), "unit": "bootstraps/s", "cores": int(max(th1, th2)), "kind": "oracle",
+            "sample": f"{nx} XNOR + {nm} MUX gates = {n_br} bootstraps with key switching, "
+                      f"same parameters, {dt:.1f} s", "host_cpus": os.cpu_count()}
+
+
+def microbench(lp, torch, sk, dk, sizes=(1, 64, 1024, 16384)):
+    """Batched NAND bootstraps (one launch pair per batch) and the plain
+    one-bootstrap-per-launch path."""
+    res = {}
+    rng = np.random.default_rng(3)
+    for B in sizes:
+        bits = rng.integers(0, 2, 2 * B).astype(np.uint8)
+        ct = sk.encrypt_bits(bits, seed=30 + B)
+        c1, c2 = lp.to_device(ct[:B]), lp.to_device(ct[B:])
+        out = lp.bootstrap_batch(dk, "NAND", c1, c2)
+        torch.cuda.synchronize()
+        reps = 3 if B <= 1024 else 1
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = lp.bootstrap_batch(dk, "NAND", c1, c2)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        d, _ = sk.decrypt_bits(lp.to_host(out))
+        assert (d == 1 - (bits[:B] & bits[B:])).all()
+        res[str(B)] = round(B / dt, 1)
+    # one bootstrap per launch: 16 single-gate launches back to back
+    ct = sk.encrypt_bits(rng.integers(0, 2, 32).astype(np.uint8), seed=99)
+    cs = [(lp.to_device(ct[k:k + 1]), lp.to_device(ct[16 + k:17 + k])) for k in range(16)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in cs:
+        lp.bootstrap_batch(dk, "NAND", a, b)
+    torch.cuda.synchronize()
+    one = 16 / (time.perf_counter() - t0)
+    return {"batched_nand_bootstraps_per_s": res, "one_per_launch_bootstraps_per_s": round(one, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-micro", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run device copies of this many bytes (traffic calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the gate-bootstrap path here runs on a single MI355X "
+              f"and has no multi-GPU mode (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2407_19871_amd as lp
+    from oracle import plain
+    from paper_2407_19871_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    seed = 2
+    q = W.random_query(seed, 16, 16, 32, force_inside=True)
+    sk, ck = lp.keygen(None, seed)
+    xb, yb, bb, pb = q.plain_bits()
+    cts = sk.encrypt_bits(np.concatenate([xb, yb, bb, pb]), seed=seed)
+    l, N, m = q.l, q.n_boxes, q.m
+    d_x = lp.to_device(cts[:l])
+    d_y = lp.to_device(cts[l:2 * l])
+    d_b = lp.to_device(cts[2 * l:2 * l + 4 * l * N])
+    d_p = lp.to_device(cts[2 * l + 4 * l * N:])
+    dk = lp.DeviceKey(ck)
+    n_br, n_ks, levels = lp.bbox_counts(l, N, m)
+    out = torch.empty((m, 631), dtype=torch.int32, device="cuda")
+
+    def step():
+        lp.eval_bbox_query(dk, l, N, m, True, d_x, d_y, d_b, d_p, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    d, _ = sk.decrypt_bits(lp.to_host(out))
+    expect = plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, True)
+    correct = W.from_bits(d) == expect
+
+    lp.profile_enable(True)
+    lp.profile_collect()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        step()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = lp.profile_collect()
+    lp.profile_enable(False)
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+
+    br = stats.get("blind_rotate", {"launches": 0, "jobs": 0, "total_ms": 0.0})
+    ks = stats.get("keyswitch", {"launches": 0, "jobs": 0, "total_ms": 0.0})
+    achieved = ALG_LANE_CYCLES_PER_BR * br["jobs"] / (br["total_ms"] / 1e3) / 1e12 if br["total_ms"] else 0.0
+    traffic = load_traffic()
+    roofline = {
+        "bound": "alu", "kernel": "blind_rotate_kernel",
+        "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
+        "frac": round(achieved / VALU_PEAK_TOPS, 4),
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "avg_launch_ms": round(br["total_ms"] / max(1, br["launches"]), 3),
+        "bootstraps_per_launch": round(br["jobs"] / max(1, br["launches"]), 1),
+        "op_unit": "32-bit VALU lane-cycles, 1.30e9 per bootstrap (algorithmic count)",
+    }
+
+    res = {
+        "metric": METRIC,
+        "value": round(n_br * args.steps / wall, 1),
+        "unit": "bootstraps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "bbox query, 16-bit signed fixed-point point vs 16 encrypted boxes (guillotine "
+                               "tiling of a Korea-like region), 32-bit encrypted payloads; TFHE Torus32 n=630, "
+                               "N=1024, k=1, Bg=2^7, l=3, KS base 2^2 t=8",
+                   "bootstraps_per_query": n_br, "keyswitches_per_query": n_ks, "levels": levels, "seed": seed},
+        "queries_per_s": round(args.steps / wall, 3),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "correct_vs_predicate": bool(correct),
+        "kernels": {"blind_rotate_ms": round(br["total_ms"], 3), "keyswitch_ms": round(ks["total_ms"], 3),
+                    "launches": br["launches"] + ks["launches"]},
+        "roofline": roofline,
+    }
+    if not args.no_micro:
+        res["microbench"] = microbench(lp, torch, sk, dk)
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = args.copy_probe
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(seed)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

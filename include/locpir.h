@@ -51,7 +51,7 @@ typedef int32_t lp_status;
  * TRLWE dimension of the accumulator; bg_bit, l: gadget base 2^bg_bit and
  * levels; bk_sigma: noise of the bootstrapping key; ks_base_bit, ks_t:
  * key-switching base 2^ks_base_bit and digit count.  The GPU kernels support
- * N = 1024, k = 1, bg_bit = 7, l = 3, any n <= 1024, any ks_base_bit*ks_t <= 31. */
+ * N = 1024, k = 1, bg_bit = 7, l = 3, n <= 1024 and ks_base_bit <= 4. */
 typedef struct {
   uint32_t n, N, k, bg_bit, l, ks_base_bit, ks_t;
   double lwe_sigma, bk_sigma;
@@ -167,6 +167,24 @@ lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint32_t* d_pol
  * (steps >= n: all); d_acc receives cnt accumulators of [2][N] uint32. */
 lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,
                                 uint32_t steps, uint32_t* d_acc, void* stream);
+
+/* ---- profiling ----------------------------------------------------------- */
+
+/* Per-kernel statistics: when enabled, the library records a HIP event pair
+ * around every blind-rotation and key-switch launch on the launch stream.
+ * lp_profile_collect waits for the recorded events, writes one entry per
+ * kernel kind (at most *count entries; *count receives the number written)
+ * and clears the record.  name: static string ("blind_rotate",
+ * "keyswitch"); jobs: bootstraps or key switches launched; total_ms: sum of
+ * event-measured kernel durations. */
+typedef struct {
+  const char* name;
+  uint64_t launches;
+  uint64_t jobs;
+  double total_ms;
+} lp_kernel_stat;
+lp_status lp_profile_enable(int on);
+lp_status lp_profile_collect(lp_kernel_stat* stats, int* count);
 
 void lp_secret_key_free(lp_secret_key* sk);
 void lp_cloud_key_free(lp_cloud_key* ck);

@@ -37,6 +37,10 @@ class Params(C.Structure):
                 f"bk_sigma={self.bk_sigma})")
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64), ("jobs", C.c_uint64), ("total_ms", C.c_double)]
+
+
 class BBoxQuery(C.Structure):
     _fields_ = [("l", C.c_uint32), ("n_boxes", C.c_uint32), ("m", C.c_uint32), ("is_signed", C.c_int32),
                 ("d_x", C.c_void_p), ("d_y", C.c_void_p), ("d_bounds", C.c_void_p), ("d_payload", C.c_void_p)]
@@ -79,6 +83,8 @@ def lib() -> C.CDLL:
         "lp_bbox_counts": (i32, [u32, u32, u32, C.POINTER(u64), C.POINTER(u64), C.POINTER(u32)]),
         "lp_debug_negacyclic_mul": (i32, [vp, vp, sz, vp, vp]),
         "lp_debug_blind_rotate": (i32, [vp, vp, sz, u32, vp, vp]),
+        "lp_profile_enable": (i32, [i32]),
+        "lp_profile_collect": (i32, [C.POINTER(KernelStat), C.POINTER(C.c_int)]),
         "lp_secret_key_free": (None, [vp]),
         "lp_cloud_key_free": (None, [vp]),
         "lp_device_key_free": (None, [vp]),
@@ -302,3 +308,17 @@ def debug_blind_rotate(dk: DeviceKey, ct, steps: int, out=None, stream=None):
         out = torch.empty((cnt, 2 * dk.params.N), dtype=torch.int32, device=ct.device)
     _check(lib().lp_debug_blind_rotate(dk._h, _dev_ptr(ct), cnt, steps, _dev_ptr(out), _stream_ptr(stream)))
     return out
+
+
+# ------------------------------------------------------------------ profiling
+def profile_enable(on: bool = True):
+    _check(lib().lp_profile_enable(1 if on else 0))
+
+
+def profile_collect() -> dict:
+    """{kernel name: {"launches", "jobs", "total_ms"}} since the last collect."""
+    arr = (KernelStat * 8)()
+    cnt = C.c_int(8)
+    _check(lib().lp_profile_collect(arr, C.byref(cnt)))
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "jobs": int(arr[i].jobs),
+                                   "total_ms": float(arr[i].total_ms)} for i in range(cnt.value)}

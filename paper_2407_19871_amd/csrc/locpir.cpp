@@ -419,6 +419,79 @@ lp_status device_twiddles(lp::Twiddles* out) {
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 }  // namespace
 
+// ---------------------------------------------------------------- profiling
+namespace {
+enum ProfKind { kProfBR = 0, kProfKS = 1, kProfKinds = 2 };
+const char* kProfNames[kProfKinds] = {"blind_rotate", "keyswitch"};
+struct ProfRecord {
+  int kind;
+  uint64_t jobs;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  bool on = false;
+  ProfRecord rec{};
+  hipStream_t s;
+  ProfScope(int kind, uint64_t jobs, hipStream_t st) : s(st) {
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      on = g_prof_on;
+    }
+    if (!on || jobs == 0) { on = false; return; }
+    rec.kind = kind;
+    rec.jobs = jobs;
+    if (hipEventCreate(&rec.start) != hipSuccess) { on = false; return; }
+    if (hipEventCreate(&rec.stop) != hipSuccess) { (void)hipEventDestroy(rec.start); on = false; return; }
+    (void)hipEventRecord(rec.start, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.stop, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(rec);
+  }
+};
+}  // namespace
+
+extern "C" lp_status lp_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return LP_OK;
+}
+
+extern "C" lp_status lp_profile_collect(lp_kernel_stat* stats, int* count) {
+  if (!count) return fail(LP_EINVAL, "lp_profile_collect: null count");
+  std::vector<ProfRecord> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  lp_kernel_stat agg[kProfKinds];
+  for (int k = 0; k < kProfKinds; ++k) agg[k] = lp_kernel_stat{kProfNames[k], 0, 0, 0.0};
+  lp_status st = LP_OK;
+  for (auto& r : recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) st = fail(LP_EDEVICE, "lp_profile_collect: %s", hipGetErrorString(e));
+    agg[r.kind].launches += 1;
+    agg[r.kind].jobs += r.jobs;
+    agg[r.kind].total_ms += ms;
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  const int n = std::min(*count, (int)kProfKinds);
+  if (stats)
+    for (int k = 0; k < n; ++k) stats[k] = agg[k];
+  *count = stats ? n : 0;
+  return st;
+}
+
 // ---------------------------------------------------------------- device keys
 extern "C" void lp_device_key_free(lp_device_key* dk);
 
@@ -539,11 +612,15 @@ extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, c
   src.p[2] = d_in2;
   lp::DstBases dst{};
   dst.p[0] = d_out;
-  if (e == hipSuccess)
+  if (e == hipSuccess) {
+    ProfScope ps(kProfBR, nbr, s);
     e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, (int)n, (int)n, 0, dk->tw, pick_br_wpb(nbr), s);
-  if (e == hipSuccess)
+  }
+  if (e == hipSuccess) {
+    ProfScope ps(kProfKS, cnt, s);
     e = lp::launch_keyswitch(ks, (int)cnt, ex, dst, dk->ksk_tab, (int)n, (int)N, (int)dk->P.ks_t,
                              (int)dk->P.ks_base_bit, pick_ks_tile(cnt), s);
+  }
   hipError_t e2 = hipFreeAsync(scratch, s);
   if (e != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e2));
@@ -841,11 +918,16 @@ extern "C" lp_status lp_eval_bbox_query(const lp_device_key* dkc, const lp_bbox_
   lp::DstBases dst{};
   dst.p[0] = pool;
   for (int L = 0; L < P->levels() && e == hipSuccess; ++L) {
-    e = lp::launch_blind_rotate(P->d_br + P->br_off[L], P->br_cnt[L], src, ex, dk->bsk_tab, (int)n, (int)n, 0, dk->tw,
-                                pick_br_wpb(P->br_cnt[L]), s);
-    if (e == hipSuccess)
+    {
+      ProfScope ps(kProfBR, (uint64_t)P->br_cnt[L], s);
+      e = lp::launch_blind_rotate(P->d_br + P->br_off[L], P->br_cnt[L], src, ex, dk->bsk_tab, (int)n, (int)n, 0,
+                                  dk->tw, pick_br_wpb(P->br_cnt[L]), s);
+    }
+    if (e == hipSuccess) {
+      ProfScope ps(kProfKS, (uint64_t)P->ks_cnt[L], s);
       e = lp::launch_keyswitch(P->d_ks + P->ks_off[L], P->ks_cnt[L], ex, dst, dk->ksk_tab, (int)n, (int)Nr,
                                (int)dk->P.ks_t, (int)dk->P.ks_base_bit, pick_ks_tile(P->ks_cnt[L]), s);
+    }
   }
   if (e == hipSuccess) e = lp::launch_gather(P->d_out_refs, (int)m, src, d_out, (int)n, s);
   hipError_t e2 = hipFreeAsync(pool, s);
