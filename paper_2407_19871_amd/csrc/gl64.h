@@ -6,12 +6,15 @@
 // coefficient is a sum of 2*l*N = 6144 terms below 2^6 * 2^32, so it lies
 // in (-2^50.6, 2^50.6) and is recovered exactly from its residue mod p
 // (p/2 > 2^63).  The identities used for reduction are
-//   2^64 = 2^32 - 1 (mod p)  and  2^96 = -1 (mod p),
+//   2^64 = 2^32 - 1 = EPS (mod p)  and  2^96 = -1 (mod p),
 // so 2 is a 192nd root of unity and every 64th root of unity is a power of
 // two: the butterflies of 32-point transforms need only shifts.
 //
-// Representation: every value handed between these functions is canonical,
-// i.e. in [0, p).  Each function documents why its result stays canonical.
+// Representation ("lazy"): a residue is held as any 64-bit value x in
+// [0, 2^64) with x = residue (mod p); only gl_canon() maps to [0, p).
+// Every function is exact for all 64-bit inputs.  Carries come from the
+// overflow builtins, which gfx950 executes as v_add_co/v_addc_co (and the
+// subtract forms) with the carry in a scalar register.
 #pragma once
 #include <stdint.h>
 
@@ -24,55 +27,62 @@
 #define GL_INLINE inline
 #endif
 
-// a + b for a, b < p.  If the 64-bit sum carries, the true sum is s + 2^64
-// = s + EPS (mod p) and s + EPS < p because s < 2p - 2^64.  Otherwise the
-// sum is >= p exactly when s + EPS carries, and then s - p = s + EPS - 2^64.
+// a + b.  A carry means the true sum is s + 2^64 = s + EPS (mod p).  Adding
+// EPS can carry again only when s >= p; the wrapped value is then below EPS
+// and a second EPS cannot carry.
 GL_INLINE uint64_t gl_add(uint64_t a, uint64_t b) {
-  uint64_t s = a + b;
-  uint64_t t = s + GL_EPS;
-  bool c1 = s < a;
-  bool c2 = t < s;
-  return (c1 || c2) ? t : s;
+  uint64_t s;
+  const bool c1 = __builtin_add_overflow(a, b, &s);
+  const bool c2 = __builtin_add_overflow(s, c1 ? GL_EPS : 0ull, &s);
+  return s + (c2 ? GL_EPS : 0ull);
 }
 
-// a - b for a, b < p.  On borrow the wrapped difference is a - b + 2^64, and
-// subtracting EPS gives a - b + p, which lies in (EPS, p) -- no second wrap.
+// a - b.  A borrow means the true difference is d - 2^64 = d - EPS (mod p).
+// Subtracting EPS can borrow again only when d < EPS; the wrapped value is
+// then at least 2^64 - EPS and a second EPS cannot borrow.
 GL_INLINE uint64_t gl_sub(uint64_t a, uint64_t b) {
-  uint64_t d = a - b;
-  return (a < b) ? d - GL_EPS : d;
+  uint64_t d;
+  const bool b1 = __builtin_sub_overflow(a, b, &d);
+  const bool b2 = __builtin_sub_overflow(d, b1 ? GL_EPS : 0ull, &d);
+  return d - (b2 ? GL_EPS : 0ull);
 }
 
-GL_INLINE uint64_t gl_neg(uint64_t a) { return a == 0 ? 0 : GL_P - a; }
+// -a (mod p) as p - a, for a canonicalised first (a = 0 maps to 0)
+GL_INLINE uint64_t gl_canon(uint64_t a) {
+  uint64_t t;
+  const bool c = __builtin_add_overflow(a, GL_EPS, &t);  // carries iff a >= p
+  return c ? t : a;
+}
+GL_INLINE uint64_t gl_neg(uint64_t a) { return gl_sub(0ull, a); }
 
-// x = lo + 2^64 hi (any 128-bit value) reduced to [0, p):
-//   x = lo + 2^64 hl + 2^96 hh = lo - hh + (2^32 - 1) hl  (mod p).
-// t0 = lo - hh: on borrow lo < hh < 2^32, so the wrapped value is >= p and
-//   subtracting EPS keeps it in [0, 2^64).
-// t1 = hl * (2^32 - 1) < 2^64.  r = t0 + t1: on carry the wrapped sum is
-//   < 2^64 - 2^33 + 1 and adding EPS neither carries nor reaches p; without
-//   carry a final conditional subtraction of p makes r canonical.
+// x = lo + 2^64 hi (any 128-bit value) mod p:
+//   x = lo + 2^64 hl + 2^96 hh = lo - hh + EPS * hl   (mod p).
+// t0 = lo - hh: a borrow needs lo < hh < 2^32, so the wrapped value is at
+//   least p and subtracting EPS cannot borrow again.
+// t1 = hl * EPS = (hl << 32) - hl < 2^64.
+// t0 + t1: a carry leaves a wrapped sum below 2^64 - 2^33 + 1, so adding EPS
+//   cannot carry again.
 GL_INLINE uint64_t gl_reduce128(uint64_t lo, uint64_t hi) {
-  uint32_t hh = (uint32_t)(hi >> 32);
-  uint32_t hl = (uint32_t)hi;
-  uint64_t t0 = lo - hh;
-  if (lo < (uint64_t)hh) t0 -= GL_EPS;
-  uint64_t t1 = ((uint64_t)hl << 32) - hl;
-  uint64_t r = t0 + t1;
-  bool c = r < t0;
-  uint64_t u = r + GL_EPS;
-  bool c2 = u < r;
-  return (c || c2) ? u : r;
+  const uint32_t hh = (uint32_t)(hi >> 32);
+  const uint32_t hl = (uint32_t)hi;
+  uint64_t t0;
+  const bool b = __builtin_sub_overflow(lo, (uint64_t)hh, &t0);
+  t0 -= b ? GL_EPS : 0ull;
+  const uint64_t t1 = ((uint64_t)hl << 32) - hl;
+  uint64_t r;
+  const bool c = __builtin_add_overflow(t0, t1, &r);
+  return r + (c ? GL_EPS : 0ull);
 }
 
 // 64 x 64 -> 128-bit product from four 32 x 32 -> 64 multiply-adds; no
 // intermediate overflows because (2^32-1)^2 + 2*(2^32-1) < 2^64.
 GL_INLINE void gl_mul_wide(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi) {
-  uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-  uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-  uint64_t t = (uint64_t)a0 * b0;
-  uint64_t m1 = (uint64_t)a0 * b1 + (t >> 32);
-  uint64_t m2 = (uint64_t)a1 * b0 + (uint32_t)m1;
-  uint64_t h = (uint64_t)a1 * b1 + (m1 >> 32);
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t t = (uint64_t)a0 * b0;
+  const uint64_t m1 = (uint64_t)a0 * b1 + (t >> 32);
+  const uint64_t m2 = (uint64_t)a1 * b0 + (uint32_t)m1;
+  const uint64_t h = (uint64_t)a1 * b1 + (m1 >> 32);
   hi = h + (m2 >> 32);
   lo = (m2 << 32) | (uint32_t)t;
 }
@@ -83,9 +93,10 @@ GL_INLINE uint64_t gl_mul(uint64_t a, uint64_t b) {
   return gl_reduce128(lo, hi);
 }
 
-// x * 2^S mod p for a compile-time S.  2^96 = -1 folds S into [0, 96);
-// shifts below 64 produce a 128-bit value for gl_reduce128; shifts in
-// [64, 96) are done as two smaller shifts.
+// x * 2^S mod p for a compile-time S.  2^96 = -1 folds S into [0, 96).  For
+// 0 < s < 32 the product is w0 + 2^32 w1 + 2^64 w2 with w2 < 2^31, i.e.
+// (w1:w0) + EPS w2 (mod p); for 32 <= s < 64 the three high words are
+// reduced by gl_reduce128; s in [64, 96) is two smaller shifts.
 template <int S>
 GL_INLINE uint64_t gl_mul_pow2(uint64_t x) {
   constexpr int s = ((S % 192) + 192) % 192;
@@ -93,6 +104,13 @@ GL_INLINE uint64_t gl_mul_pow2(uint64_t x) {
     return x;
   } else if constexpr (s >= 96) {
     return gl_neg(gl_mul_pow2<s - 96>(x));
+  } else if constexpr (s < 32) {
+    const uint64_t low = x << s;
+    const uint32_t w2 = (uint32_t)(x >> (64 - s));
+    const uint64_t t = ((uint64_t)w2 << 32) - w2;  // EPS * w2 < 2^63
+    uint64_t r;
+    const bool c = __builtin_add_overflow(low, t, &r);
+    return r + (c ? GL_EPS : 0ull);
   } else if constexpr (s < 64) {
     return gl_reduce128(x << s, x >> (64 - s));
   } else {
@@ -100,12 +118,13 @@ GL_INLINE uint64_t gl_mul_pow2(uint64_t x) {
   }
 }
 
-// Canonical residue of a signed integer |v| < 2^63.
+// Residue of a signed integer |v| < 2^63.
 GL_INLINE uint64_t gl_from_i64(int64_t v) { return v < 0 ? (uint64_t)v + GL_P : (uint64_t)v; }
 
-// Centred lift of a canonical residue to the integers, reduced mod 2^32: a
+// Centred lift of a residue to the integers, reduced mod 2^32: the canonical
 // residue r > (p-1)/2 stands for r - p, whose low word is low32(r) - 1
 // because low32(p) = 1.
-GL_INLINE uint32_t gl_lift_u32(uint64_t r) {
+GL_INLINE uint32_t gl_lift_u32(uint64_t x) {
+  const uint64_t r = gl_canon(x);
   return (uint32_t)r - (r > (GL_P >> 1) ? 1u : 0u);
 }

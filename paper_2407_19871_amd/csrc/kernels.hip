@@ -27,8 +27,8 @@
 namespace lp {
 
 constexpr int RING_N = 1024;
-constexpr int ROW = 33;             // padded LDS row (u64) of a 32 x 32 transpose
-constexpr int LDS_HALF = 32 * ROW;  // u64 per half-wave block
+constexpr int ROW = 33;             // padded LDS row (32-bit words) of a 32 x 32 transpose
+constexpr int LDS_HALF = 32 * ROW;  // words per half-wave transpose block
 constexpr int MAX_LWE = 1024;
 
 // Orders this wave's LDS accesses (DS operations of one wave execute in
@@ -36,6 +36,15 @@ constexpr int MAX_LWE = 1024;
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// Hides a (uniform) pointer's value from the optimizer so that loads
+// through it stay inside the loop that uses them: hoisting the 64 twiddle
+// loads out of the step loop would pin 128 VGPRs for the whole kernel.
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
 }
 
 // The value held by lane ^ 32.
@@ -46,15 +55,23 @@ __device__ __forceinline__ uint64_t from_other_half(uint64_t v, int lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// 32 x 32 transpose through a half-wave LDS block: on entry lane l holds
-// row l (a[i] = (l, i)); on exit lane l holds column l (a[m] = (m, l)).
-// Rows are padded to 33 words so both phases are bank-conflict free.
-__device__ __forceinline__ void transpose32(uint64_t (&a)[32], uint64_t* buf, int l) {
+// 32 x 32 transpose through a half-wave LDS block of 32 x 33 words, in two
+// 32-bit passes (low words, then high words): on entry lane l holds row l
+// (a[i] = (l, i)); on exit lane l holds column l (a[m] = (m, l)).  Rows are
+// padded to 33 words so both phases are bank-conflict free.
+__device__ __forceinline__ void transpose32(uint64_t (&a)[32], uint32_t* buf, int l) {
+  uint32_t lo[32];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) buf[l * ROW + i] = a[i];
+  for (int i = 0; i < 32; ++i) buf[l * ROW + i] = (uint32_t)a[i];
   wave_fence();
 #pragma unroll
-  for (int m = 0; m < 32; ++m) a[m] = buf[m * ROW + l];
+  for (int m = 0; m < 32; ++m) lo[m] = buf[m * ROW + l];
+  wave_fence();
+#pragma unroll
+  for (int i = 0; i < 32; ++i) buf[l * ROW + i] = (uint32_t)(a[i] >> 32);
+  wave_fence();
+#pragma unroll
+  for (int m = 0; m < 32; ++m) a[m] = ((uint64_t)buf[m * ROW + l] << 32) | lo[m];
   wave_fence();
 }
 
@@ -67,7 +84,7 @@ __device__ __forceinline__ void twist_fwd(uint64_t (&f)[32], const uint64_t* __r
 // Forward negacyclic NTT of one polynomial per half-wave.  In: lane l,
 // slot m = coefficient l + 32 m.  Out: lane l -> ka = brv5(l), slot i ->
 // kb = brv5(i).
-__device__ __forceinline__ void ntt_fwd(uint64_t (&f)[32], uint64_t* buf, const uint64_t* __restrict__ tw_f,
+__device__ __forceinline__ void ntt_fwd(uint64_t (&f)[32], uint32_t* buf, const uint64_t* __restrict__ tw_f,
                                         int l) {
   fwd1(f);
   twist_fwd(f, tw_f, l);
@@ -76,7 +93,7 @@ __device__ __forceinline__ void ntt_fwd(uint64_t (&f)[32], uint64_t* buf, const 
 }
 
 // The same for small signed digits, first butterfly stage fused.
-__device__ __forceinline__ void ntt_fwd_digits(const int32_t (&d)[32], uint64_t (&f)[32], uint64_t* buf,
+__device__ __forceinline__ void ntt_fwd_digits(const int32_t (&d)[32], uint64_t (&f)[32], uint32_t* buf,
                                                const uint64_t* __restrict__ tw_f, int l) {
   fwd1_first_stage_digits(d, f);
   fwd1_rest(f);
@@ -86,7 +103,7 @@ __device__ __forceinline__ void ntt_fwd_digits(const int32_t (&d)[32], uint64_t 
 }
 
 // Inverse of ntt_fwd including the 1/1024 scaling.
-__device__ __forceinline__ void ntt_inv(uint64_t (&f)[32], uint64_t* buf, const uint64_t* __restrict__ tw_i,
+__device__ __forceinline__ void ntt_inv(uint64_t (&f)[32], uint32_t* buf, const uint64_t* __restrict__ tw_i,
                                         int l) {
   inv2(f);
 #pragma unroll
@@ -103,7 +120,7 @@ __device__ __forceinline__ int ntt_pos(int s, int l) { return (s >> 1) * 64 + l 
 __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restrict__ src,
                                                         uint64_t* __restrict__ dst, int npoly,
                                                         const uint64_t* __restrict__ tw_f) {
-  __shared__ uint64_t s_buf[2][LDS_HALF];
+  __shared__ uint32_t s_buf[2][LDS_HALF];
   const int lane = threadIdx.x, h = lane >> 5, l = lane & 31;
   const int poly = blockIdx.x * 2 + h;
   const bool live = poly < npoly;
@@ -119,23 +136,33 @@ __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Blind rotation.
-template <int WPB>
-__global__ __launch_bounds__(64 * WPB) void blind_rotate_kernel(
+// Blind rotation.  W waves cooperate on one bootstrap:
+//   W = 1: the wave runs the three gadget levels in turn (throughput mode:
+//          independent bootstraps fill the GPU);
+//   W = 3: wave w runs gadget level w; waves 1 and 2 hand their partial
+//          products to wave 0 through LDS, wave 0 runs the inverse NTT and
+//          updates the accumulator (latency mode for narrow circuit levels).
+// The accumulator lives in LDS ([component][coefficient] u32); each level
+// re-reads it to form X^a ACC - ACC.
+template <int W>
+__global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, int n_lwe, int steps, int raw_acc,
     const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
-  __shared__ uint64_t s_buf[WPB][2][LDS_HALF];
-  __shared__ uint16_t s_abar[WPB][MAX_LWE + 4];
+  constexpr int PART = (W > 1) ? (W - 1) * 32 * 64 : 1;
+  __shared__ uint32_t s_acc[2][RING_N];
+  __shared__ uint32_t s_tr[W][2][LDS_HALF];
+  __shared__ uint64_t s_part[PART];
+  __shared__ uint16_t s_abar[MAX_LWE + 4];
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
-  const int job = blockIdx.x * WPB + wave;
-  if (job >= njobs) return;
+  const int job = blockIdx.x;
+  if (job >= njobs) return;  // uniform over the block
 
   const BrJob J = jobs[job];
-  uint64_t* buf = s_buf[wave][h];
-  uint16_t* abar = s_abar[wave];
+  uint32_t* buf = s_tr[wave][h];
+  uint32_t* acc = s_acc[h];
 
   // modulus switch of the combined input (0, cst) + c0 in0 + c1 in1
   {
@@ -143,57 +170,49 @@ __global__ __launch_bounds__(64 * WPB) void blind_rotate_kernel(
                                             : src.p[J.in0 >> REF_SHIFT] + (size_t)(J.in0 & REF_INDEX_MASK) * (n_lwe + 1);
     const uint32_t* in1 = J.in1 == REF_NONE ? nullptr
                                             : src.p[J.in1 >> REF_SHIFT] + (size_t)(J.in1 & REF_INDEX_MASK) * (n_lwe + 1);
-    for (int c = lane; c <= n_lwe; c += 64) {
+    for (int c = threadIdx.x; c <= n_lwe; c += 64 * W) {
       uint32_t v = (c == n_lwe) ? J.cst : 0u;
       if (in0) v += (uint32_t)J.c0 * in0[c];
       if (in1) v += (uint32_t)J.c1 * in1[c];
-      abar[c] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
+      s_abar[c] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
     }
   }
-  wave_fence();
+  __syncthreads();
 
   // ACC = (0, X^{-b} v), v = sum_j (1/8) X^j: coefficient j of X^{-b} v is
   // +1/8 when (j + b) mod 2N < N, else -1/8
-  const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)abar[n_lwe]);
-  uint32_t acc[32];
-#pragma unroll
-  for (int m = 0; m < 32; ++m) {
-    const uint32_t j = (uint32_t)(l + 32 * m);
-    acc[m] = h == 0 ? 0u : ((((j + bbar) & 2047u) < 1024u) ? 0x20000000u : 0xE0000000u);
+  const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
+  for (int c = threadIdx.x; c < 2 * RING_N; c += 64 * W) {
+    const uint32_t j = (uint32_t)c & 1023u;
+    s_acc[c >> 10][j] = c < RING_N ? 0u : ((((j + bbar) & 2047u) < 1024u) ? 0x20000000u : 0xE0000000u);
   }
+  __syncthreads();
 
   const uint64_t* __restrict__ bsk = bsk_tab[J.key];
-  uint32_t* abuf = reinterpret_cast<uint32_t*>(buf);
   const int nsteps = steps < n_lwe ? steps : n_lwe;
 
   for (int i = 0; i < nsteps; ++i) {
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)abar[i]);
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
     if (a == 0) continue;  // X^0 ACC - ACC = 0 decomposes to zero digits
 
-    // D = X^a ACC_h - ACC_h
-#pragma unroll
-    for (int m = 0; m < 32; ++m) abuf[l + 32 * m] = acc[m];
-    wave_fence();
-    uint32_t D[32];
-#pragma unroll
-    for (int m = 0; m < 32; ++m) {
-      const uint32_t e = ((uint32_t)(l + 32 * m) - a) & 2047u;
-      const uint32_t v = abuf[e & 1023u];
-      D[m] = ((e & 1024u) ? (0u - v) : v) - acc[m];
-    }
-    wave_fence();
-
-    uint64_t outv[32];
     const uint64_t* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+    uint64_t outv[32];
 #pragma nounroll
-    for (int jj = 0; jj < 3; ++jj) {
-      // signed digit of level jj+1: ((D + 0x81020400) >> (25 - 7 jj)) & 127) - 64
+    for (int jj = (W == 1 ? 0 : wave); jj < (W == 1 ? 3 : wave + 1); ++jj) {
+      // signed digit of level jj+1 of D = X^a ACC_h - ACC_h:
+      // ((D + 0x81020400) >> (25 - 7 jj)) & 127) - 64
       const int sh = 25 - 7 * jj;
       int32_t dg[32];
 #pragma unroll
-      for (int m = 0; m < 32; ++m) dg[m] = (int32_t)(((D[m] + 0x81020400u) >> sh) & 127u) - 64;
+      for (int m = 0; m < 32; ++m) {
+        const uint32_t j = (uint32_t)(l + 32 * m);
+        const uint32_t e = (j - a) & 2047u;
+        const uint32_t v = acc[e & 1023u];
+        const uint32_t D = ((e & 1024u) ? (0u - v) : v) - acc[j];
+        dg[m] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+      }
       uint64_t f[32];
-      ntt_fwd_digits(dg, f, buf, tw_f, l);
+      ntt_fwd_digits(dg, f, buf, opaque(tw_f), l);
 
       const int row = h * 3 + jj;
       const uint64_t* k_own = step_key + (size_t)(row * 2 + h) * RING_N;
@@ -206,20 +225,48 @@ __global__ __launch_bounds__(64 * WPB) void blind_rotate_kernel(
         const uint64_t y0 = gl_mul(f[2 * sp], kt.x), y1 = gl_mul(f[2 * sp + 1], kt.y);
         const uint64_t t0 = gl_add(x0, from_other_half(y0, lane));
         const uint64_t t1 = gl_add(x1, from_other_half(y1, lane));
-        outv[2 * sp] = jj == 0 ? t0 : gl_add(outv[2 * sp], t0);
-        outv[2 * sp + 1] = jj == 0 ? t1 : gl_add(outv[2 * sp + 1], t1);
+        if (W == 1 && jj > 0) {
+          outv[2 * sp] = gl_add(outv[2 * sp], t0);
+          outv[2 * sp + 1] = gl_add(outv[2 * sp + 1], t1);
+        } else {
+          outv[2 * sp] = t0;
+          outv[2 * sp + 1] = t1;
+        }
       }
     }
 
-    ntt_inv(outv, buf, tw_i, l);
+    if constexpr (W > 1) {
+      if (wave > 0) {
+        uint64_t* part = s_part + (size_t)(wave - 1) * 32 * 64;
 #pragma unroll
-    for (int m = 0; m < 32; ++m) acc[m] += gl_lift_u32(outv[m]);
+        for (int s = 0; s < 32; ++s) part[s * 64 + lane] = outv[s];
+      }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int w = 1; w < W; ++w) {
+          const uint64_t* part = s_part + (size_t)(w - 1) * 32 * 64;
+#pragma unroll
+          for (int s = 0; s < 32; ++s) outv[s] = gl_add(outv[s], part[s * 64 + lane]);
+        }
+        ntt_inv(outv, buf, opaque(tw_i), l);
+#pragma unroll
+        for (int m = 0; m < 32; ++m) acc[l + 32 * m] += gl_lift_u32(outv[m]);
+      }
+      __syncthreads();
+    } else {
+      ntt_inv(outv, buf, opaque(tw_i), l);
+#pragma unroll
+      for (int m = 0; m < 32; ++m) acc[l + 32 * m] += gl_lift_u32(outv[m]);
+      wave_fence();
+    }
   }
 
+  if (wave != 0) return;
   if (raw_acc) {
     uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + h * RING_N;
 #pragma unroll
-    for (int m = 0; m < 32; ++m) o[l + 32 * m] = acc[m];
+    for (int m = 0; m < 32; ++m) o[l + 32 * m] = acc[l + 32 * m];
   } else {
     // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
     uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
@@ -227,8 +274,8 @@ __global__ __launch_bounds__(64 * WPB) void blind_rotate_kernel(
 #pragma unroll
       for (int m = 0; m < 32; ++m) {
         const int j = l + 32 * m;
-        if (j == 0) o[0] = acc[m];
-        else o[RING_N - j] = 0u - acc[m];
+        if (j == 0) o[0] = acc[0];
+        else o[RING_N - j] = 0u - acc[j];
       }
     } else if (l == 0) {
       o[RING_N] = acc[0];
@@ -239,7 +286,10 @@ __global__ __launch_bounds__(64 * WPB) void blind_rotate_kernel(
 // ---------------------------------------------------------------------------
 // Key switching: a tile of T jobs x 64 output columns per wave.  For every
 // (i, j) the wave reads the base-1 KSK rows of that digit position once and
-// each job of the tile subtracts the row its digit selects.
+// each job of the tile subtracts the row its digit selects.  With
+// gridDim.z > 1 the ring index i is split into gridDim.z ranges; each block
+// subtracts its partial sum atomically from an output that ks_init_kernel
+// set to (0, b') (u32 wrap-around addition is exact and order-free).
 template <int T, int BB>
 __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__ jobs, int njobs,
                                                        const uint32_t* __restrict__ ex, DstBases dst,
@@ -253,6 +303,8 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
   const int w = n_lwe + 1;
   const uint32_t* __restrict__ ksk = ksk_tab[jobs[j0].key];
   const uint32_t prec = 1u << (31 - BB * ks_t);
+  const int isplit = gridDim.z;
+  const int i_lo = (int)blockIdx.z * (N / isplit), i_hi = i_lo + N / isplit;
 
   uint32_t accv[T];
   const uint32_t* e0[T];
@@ -267,11 +319,11 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
       const KsJob K = jobs[jb];
       e0[t] = ex + (size_t)K.ex0 * (N + 1);
       e1[t] = K.ex1 == REF_NONE ? nullptr : ex + (size_t)K.ex1 * (N + 1);
-      if (col == n_lwe) accv[t] = K.cst + e0[t][N] + (e1[t] ? e1[t][N] : 0u);
+      if (col == n_lwe && isplit == 1) accv[t] = K.cst + e0[t][N] + (e1[t] ? e1[t][N] : 0u);
     }
   }
 
-  for (int i0 = 0; i0 < N; i0 += 64) {
+  for (int i0 = i_lo; i0 < i_hi; i0 += 64) {
     uint32_t av[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -308,8 +360,29 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
     const int jb = j0 + t;
     if (jb < njobs && colok) {
       const uint32_t o = jobs[jb].out;
-      dst.p[o >> REF_SHIFT][(size_t)(o & REF_INDEX_MASK) * w + col] = accv[t];
+      uint32_t* p = dst.p[o >> REF_SHIFT] + (size_t)(o & REF_INDEX_MASK) * w + col;
+      if (isplit == 1) *p = accv[t];
+      else atomicAdd(p, accv[t]);  // accv already holds minus the partial sum
     }
+  }
+}
+
+// Output of a split key switch before accumulation: (0, ..., 0, b'), with
+// b' = cst + b(ex0) (+ b(ex1)).
+__global__ void ks_init_kernel(const KsJob* __restrict__ jobs, int njobs, const uint32_t* __restrict__ ex,
+                               DstBases dst, int n_lwe, int N) {
+  const int jb = blockIdx.x;
+  if (jb >= njobs) return;
+  const KsJob K = jobs[jb];
+  const int w = n_lwe + 1;
+  uint32_t* o = dst.p[K.out >> REF_SHIFT] + (size_t)(K.out & REF_INDEX_MASK) * w;
+  for (int c = threadIdx.x; c < w; c += blockDim.x) {
+    uint32_t v = 0u;
+    if (c == n_lwe) {
+      v = K.cst + ex[(size_t)K.ex0 * (N + 1) + N];
+      if (K.ex1 != REF_NONE) v += ex[(size_t)K.ex1 * (N + 1) + N];
+    }
+    o[c] = v;
   }
 }
 
@@ -350,7 +423,7 @@ __global__ __launch_bounds__(64) void debug_polymul_kernel(const int32_t* __rest
                                                            uint32_t* __restrict__ out, int cnt,
                                                            const uint64_t* __restrict__ tw_f,
                                                            const uint64_t* __restrict__ tw_i) {
-  __shared__ uint64_t s_buf[2][LDS_HALF];
+  __shared__ uint32_t s_buf[2][LDS_HALF];
   const int lane = threadIdx.x, h = lane >> 5, l = lane & 31;
   const int p = blockIdx.x;
   if (p >= cnt) return;
@@ -380,20 +453,16 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
 
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                const uint64_t* const* d_bsk_tab, int n_lwe, int steps, int raw_acc, Twiddles tw,
-                               int waves_per_block, hipStream_t s) {
+                               int waves_per_job, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  switch (waves_per_block) {
+  switch (waves_per_job) {
     case 1:
       hipLaunchKernelGGL(blind_rotate_kernel<1>, dim3(njobs), dim3(64), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
-    case 2:
-      hipLaunchKernelGGL(blind_rotate_kernel<2>, dim3((njobs + 1) / 2), dim3(128), 0, s, d_jobs, njobs, src, d_ex,
-                         d_bsk_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
-      break;
-    case 4:
-      hipLaunchKernelGGL(blind_rotate_kernel<4>, dim3((njobs + 3) / 4), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
-                         d_bsk_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+    case 3:
+      hipLaunchKernelGGL(blind_rotate_kernel<3>, dim3(njobs), dim3(192), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
+                         n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
     default:
       return hipErrorInvalidValue;
@@ -403,8 +472,14 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
 
 template <int T>
 static hipError_t launch_ks_t(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
-                              const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t, int bb, hipStream_t s) {
-  dim3 grid((n_lwe + 1 + 63) / 64, (njobs + T - 1) / T);
+                              const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t, int bb, int isplit,
+                              hipStream_t s) {
+  dim3 grid((n_lwe + 1 + 63) / 64, (njobs + T - 1) / T, isplit);
+  if (isplit > 1) {
+    hipLaunchKernelGGL(ks_init_kernel, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, d_ex, dst, n_lwe, N);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   switch (bb) {
     case 1: hipLaunchKernelGGL((keyswitch_kernel<T, 1>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
     case 2: hipLaunchKernelGGL((keyswitch_kernel<T, 2>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
@@ -417,13 +492,14 @@ static hipError_t launch_ks_t(const KsJob* d_jobs, int njobs, const uint32_t* d_
 
 hipError_t launch_keyswitch(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
                             const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t, int ks_base_bit,
-                            int tile, hipStream_t s) {
+                            int tile, int isplit, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
+  if (isplit < 1 || N % (64 * isplit) != 0) return hipErrorInvalidValue;
   switch (tile) {
-    case 1: return launch_ks_t<1>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
-    case 4: return launch_ks_t<4>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
-    case 8: return launch_ks_t<8>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
-    case 16: return launch_ks_t<16>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, s);
+    case 1: return launch_ks_t<1>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
+    case 4: return launch_ks_t<4>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
+    case 8: return launch_ks_t<8>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
+    case 16: return launch_ks_t<16>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -565,8 +566,31 @@ bool gate_combo(lp_gate g, GateCombo* c) {
   return false;
 }
 
-int pick_ks_tile(size_t njobs) { return njobs >= 4096 ? 16 : njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1; }
-int pick_br_wpb(size_t njobs) { (void)njobs; return 1; }
+// Launch shapes.  Defaults come from measurements on MI355X; the
+// environment variables LOCPIR_BR_WAVES, LOCPIR_BR_WIDE_MAX, LOCPIR_KS_TILE
+// and LOCPIR_KS_SPLIT override them (for the autotuner).
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? std::atoi(v) : dflt;
+}
+int pick_ks_tile(size_t njobs) {
+  const int t = env_int("LOCPIR_KS_TILE", 0);
+  if (t == 1 || t == 4 || t == 8 || t == 16) return t;
+  return njobs >= 4096 ? 16 : njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1;
+}
+int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
+  const int forced = env_int("LOCPIR_KS_SPLIT", 0);
+  if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
+  const size_t blocks = ((n_lwe + 64) / 64) * ((njobs + tile - 1) / tile);
+  int sp = 1;
+  while (sp < 16 && blocks * sp < 2048) sp *= 2;
+  return sp;
+}
+int pick_br_wpb(size_t njobs) {
+  const int forced = env_int("LOCPIR_BR_WAVES", 0);
+  if (forced == 1 || forced == 3) return forced;
+  return (int)njobs <= env_int("LOCPIR_BR_WIDE_MAX", 512) ? 3 : 1;
+}
 
 struct ScopedDevice {
   int prev = -1;
@@ -618,8 +642,9 @@ extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, c
   }
   if (e == hipSuccess) {
     ProfScope ps(kProfKS, cnt, s);
+    const int tile = pick_ks_tile(cnt);
     e = lp::launch_keyswitch(ks, (int)cnt, ex, dst, dk->ksk_tab, (int)n, (int)N, (int)dk->P.ks_t,
-                             (int)dk->P.ks_base_bit, pick_ks_tile(cnt), s);
+                             (int)dk->P.ks_base_bit, tile, pick_ks_split(cnt, tile, n), s);
   }
   hipError_t e2 = hipFreeAsync(scratch, s);
   if (e != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e));
@@ -642,9 +667,11 @@ extern "C" lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t*
   hipError_t e = hipMemcpyAsync(dj, jobs.data(), cnt * sizeof(KsJob), hipMemcpyHostToDevice, s);
   lp::DstBases dst{};
   dst.p[0] = d_out;
-  if (e == hipSuccess)
+  if (e == hipSuccess) {
+    const int tile = pick_ks_tile(cnt);
     e = lp::launch_keyswitch(dj, (int)cnt, d_in, dst, dk->ksk_tab, (int)dk->P.n, (int)dk->P.N, (int)dk->P.ks_t,
-                             (int)dk->P.ks_base_bit, pick_ks_tile(cnt), s);
+                             (int)dk->P.ks_base_bit, tile, pick_ks_split(cnt, tile, dk->P.n), s);
+  }
   // the host staging vector must outlive the copy
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipError_t e2 = hipFreeAsync(dj, s);
@@ -925,8 +952,9 @@ extern "C" lp_status lp_eval_bbox_query(const lp_device_key* dkc, const lp_bbox_
     }
     if (e == hipSuccess) {
       ProfScope ps(kProfKS, (uint64_t)P->ks_cnt[L], s);
+      const int tile = pick_ks_tile(P->ks_cnt[L]);
       e = lp::launch_keyswitch(P->d_ks + P->ks_off[L], P->ks_cnt[L], ex, dst, dk->ksk_tab, (int)n, (int)Nr,
-                               (int)dk->P.ks_t, (int)dk->P.ks_base_bit, pick_ks_tile(P->ks_cnt[L]), s);
+                               (int)dk->P.ks_t, (int)dk->P.ks_base_bit, tile, pick_ks_split(P->ks_cnt[L], tile, n), s);
     }
   }
   if (e == hipSuccess) e = lp::launch_gather(P->d_out_refs, (int)m, src, d_out, (int)n, s);
@@ -974,7 +1002,8 @@ extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32
   src.p[0] = d_in;
   const int st = (int)std::min<uint32_t>(steps, dk->P.n);
   if (e == hipSuccess)
-    e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, (int)dk->P.n, st, 1, dk->tw, 1, s);
+    e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, (int)dk->P.n, st, 1, dk->tw,
+                                pick_br_wpb(cnt), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipError_t e2 = hipFreeAsync(dj, s);
   if (e != hipSuccess || e2 != hipSuccess) return fail(LP_EDEVICE, "lp_debug_blind_rotate: %s", hipGetErrorString(e != hipSuccess ? e : e2));
