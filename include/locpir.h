@@ -152,6 +152,18 @@ typedef struct {
 } lp_bbox_query;
 lp_status lp_eval_bbox_query(const lp_device_key* dk, const lp_bbox_query* q, uint32_t* d_out,
                              void* stream);
+/* Several queries, each under its own device key (keys[k], queries[k],
+ * d_outs[k] for k < nq), evaluated together: depth level L of every query
+ * runs in one fused blind-rotation launch and one fused key-switch launch,
+ * each job selecting its query's key.  All keys must live on one device with
+ * equal n, ks_base_bit and ks_t.  The compiled program (job lists, ciphertext
+ * pool, one graph per level for the blind rotations and one for the key
+ * switches) is cached per (stream, keys, query shapes) and replayed; calls
+ * that share a stream and a program are serialised by the library.  Set the
+ * environment variable LOCPIR_GRAPHS=0 to launch the kernels directly. */
+lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
+                             uint32_t* const* d_outs, void* stream);
+
 /* Bootstraps, key switches and depth levels of that circuit. */
 lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,
                          uint32_t* n_levels);

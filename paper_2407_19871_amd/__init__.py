@@ -80,6 +80,7 @@ def lib() -> C.CDLL:
         "lp_bootstrap_batch": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
         "lp_keyswitch_batch": (i32, [vp, vp, sz, vp, vp]),
         "lp_eval_bbox_query": (i32, [vp, C.POINTER(BBoxQuery), vp, vp]),
+        "lp_eval_bbox_batch": (i32, [C.POINTER(vp), C.POINTER(BBoxQuery), sz, C.POINTER(vp), vp]),
         "lp_bbox_counts": (i32, [u32, u32, u32, C.POINTER(u64), C.POINTER(u64), C.POINTER(u32)]),
         "lp_debug_negacyclic_mul": (i32, [vp, vp, sz, vp, vp]),
         "lp_debug_blind_rotate": (i32, [vp, vp, sz, u32, vp, vp]),
@@ -289,6 +290,24 @@ def eval_bbox_query(dk: DeviceKey, l, n_boxes, m, is_signed, x, y, bounds, paylo
                   _dev_ptr(payload))
     _check(lib().lp_eval_bbox_query(dk._h, C.byref(q), _dev_ptr(out), _stream_ptr(stream)))
     return out
+
+
+def eval_bbox_batch(keys, queries, outs=None, stream=None):
+    """queries: sequence of (l, n_boxes, m, is_signed, x, y, bounds, payload)
+    with device tensors; keys: one DeviceKey per query.  Returns the outputs."""
+    torch = _torch()
+    nq = len(queries)
+    if len(keys) != nq:
+        raise LocpirError(-1, "one key per query")
+    if outs is None:
+        outs = [torch.empty((q[2], k.params.n + 1), dtype=torch.int32, device=q[4].device)
+                for k, q in zip(keys, queries)]
+    qarr = (BBoxQuery * nq)(*[BBoxQuery(q[0], q[1], q[2], int(bool(q[3])), _dev_ptr(q[4]), _dev_ptr(q[5]),
+                                        _dev_ptr(q[6]), _dev_ptr(q[7])) for q in queries])
+    karr = (C.c_void_p * nq)(*[k._h for k in keys])
+    oarr = (C.c_void_p * nq)(*[_dev_ptr(o) for o in outs])
+    _check(lib().lp_eval_bbox_batch(karr, qarr, nq, oarr, _stream_ptr(stream)))
+    return outs
 
 
 def debug_negacyclic_mul(digits, poly, out=None, stream=None):

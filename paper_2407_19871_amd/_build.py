@@ -19,11 +19,11 @@ HIP_FLAGS = [
 def build(verbose: bool = False, extra=()) -> str:
     objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in ("kernels.hip", "locpir.cpp"):
+    for src in ("kernels.hip", "locpir.cpp", "sched.cpp"):
         obj = os.path.join(HERE, "_build", src + ".o")
         cmd = ["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = ["hipcc", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
+            cmd = ["hipcc", f"--offload-arch={ARCH}", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
                    "-Wall", "-Wno-unused-result", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -1,0 +1,142 @@
+// Internal declarations shared by the host sources of liblocpir: handle
+// layouts, error reporting, launch-shape selection, device scoping and the
+// per-launch event profiler.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
+
+#include "../../include/locpir.h"
+#include "kernels.h"
+
+struct lp_secret_key {
+  lp_params P;
+  std::vector<uint8_t> s;  // LWE key, n bits
+  std::vector<uint8_t> S;  // ring key, N bits
+};
+
+struct lp_cloud_key {
+  lp_params P;
+  std::vector<uint32_t> bsk;  // [n][2l][2][N]
+  std::vector<uint32_t> ksk;  // [N][t][base-1][n+1]
+};
+
+struct lp_device_key {
+  lp_params P;
+  int device = 0;
+  uint64_t* bsk_ntt = nullptr;         // [n][2l][2][N] NTT domain
+  uint32_t* ksk = nullptr;             // [N][t][base-1][n+1]
+  const uint64_t** bsk_tab = nullptr;  // device array {bsk_ntt}
+  const uint32_t** ksk_tab = nullptr;  // device array {ksk}
+  lp::Twiddles tw{};
+  size_t bytes = 0;
+};
+
+namespace lp {
+
+// Records a message for lp_last_error() and returns code.
+lp_status fail(lp_status code, const char* fmt, ...);
+
+#define LP_HIP_TRY(expr)                                                                          \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return ::lp::fail(LP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Twiddle tables of the current device (uploaded once per device).
+lp_status device_twiddles(Twiddles* out);
+
+// Drops every cached query program that references dk.
+void sched_forget_key(const lp_device_key* dk);
+
+// ---- launch shapes ---------------------------------------------------------
+// Defaults come from measurements on MI355X; LOCPIR_BR_WAVES,
+// LOCPIR_BR_WIDE_MAX, LOCPIR_KS_TILE and LOCPIR_KS_SPLIT override them (the
+// autotuner sets them while it sweeps).
+inline int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? std::atoi(v) : dflt;
+}
+inline int pick_ks_tile(size_t njobs) {
+  const int t = env_int("LOCPIR_KS_TILE", 0);
+  if (t == 1 || t == 4 || t == 8 || t == 16) return t;
+  return njobs >= 4096 ? 16 : njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1;
+}
+inline int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
+  const int forced = env_int("LOCPIR_KS_SPLIT", 0);
+  if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
+  const size_t blocks = ((n_lwe + 64) / 64) * ((njobs + tile - 1) / tile);
+  int sp = 1;
+  while (sp < 16 && blocks * sp < 2048) sp *= 2;
+  return sp;
+}
+// Waves per bootstrap: 3 (latency mode) for narrow launches, else 1.
+inline int pick_br_wpb(size_t njobs) {
+  const int forced = env_int("LOCPIR_BR_WAVES", 0);
+  if (forced == 1 || forced == 3) return forced;
+  return (int)njobs <= env_int("LOCPIR_BR_WIDE_MAX", 512) ? 3 : 1;
+}
+
+struct ScopedDevice {
+  int prev = -1;
+  explicit ScopedDevice(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~ScopedDevice() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// ---- profiling -------------------------------------------------------------
+enum ProfKind { kProfBR = 0, kProfKS = 1, kProfKinds = 2 };
+struct ProfRecord {
+  int kind;
+  uint64_t jobs;
+  hipEvent_t start, stop;
+};
+extern std::mutex g_prof_mu;
+extern bool g_prof_on;
+extern std::vector<ProfRecord> g_prof;
+
+// Brackets one launch (or one graph launch) with events when profiling is on.
+struct ProfScope {
+  bool on = false;
+  ProfRecord rec{};
+  hipStream_t s;
+  ProfScope(int kind, uint64_t jobs, hipStream_t st) : s(st) {
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      on = g_prof_on;
+    }
+    if (!on || jobs == 0) {
+      on = false;
+      return;
+    }
+    rec.kind = kind;
+    rec.jobs = jobs;
+    if (hipEventCreate(&rec.start) != hipSuccess) {
+      on = false;
+      return;
+    }
+    if (hipEventCreate(&rec.stop) != hipSuccess) {
+      (void)hipEventDestroy(rec.start);
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(rec.start, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.stop, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(rec);
+  }
+};
+
+}  // namespace lp

@@ -27,7 +27,8 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
                                Twiddles tw, int waves_per_job, hipStream_t s);
 
 // Key switching of njobs jobs (tiles of `tile` consecutive jobs share one
-// key); the ring index is split into `isplit` ranges (N divisible by 64 isplit).
+// key; jobs with ex0 == REF_NONE are padding and skipped); the ring index is
+// split into `isplit` ranges (N divisible by 64 isplit).
 hipError_t launch_keyswitch(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
                             const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t,
                             int ks_base_bit, int tile, int isplit, hipStream_t s);
@@ -43,9 +44,9 @@ hipError_t launch_make_batch_jobs(int nbr, uint32_t cst, int32_t c0, int32_t c1,
 hipError_t launch_lwe_scale(const uint32_t* d_in, uint32_t* d_out, size_t words, int32_t sign,
                             hipStream_t s);
 
-// out[j] = src[ref[j]] for cnt LWE_n samples.
-hipError_t launch_gather(const uint32_t* d_refs, int cnt, const SrcBases& src, uint32_t* d_out,
-                         int n_lwe, hipStream_t s);
+// out[j] = src[ref[j] + index_offset] for cnt LWE_n samples.
+hipError_t launch_gather(const uint32_t* d_refs, int cnt, const SrcBases& src, uint32_t index_offset,
+                         uint32_t* d_out, int n_lwe, hipStream_t s);
 
 // cnt exact negacyclic products (digits x NTT-domain polynomial) mod 2^32.
 hipError_t launch_debug_polymul(const int32_t* d_digits, const uint64_t* d_poly_ntt, uint32_t* d_out,

@@ -140,8 +140,10 @@ __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restri
 //   W = 1: the wave runs the three gadget levels in turn (throughput mode:
 //          independent bootstraps fill the GPU);
 //   W = 3: wave w runs gadget level w; waves 1 and 2 hand their partial
-//          products to wave 0 through LDS, wave 0 runs the inverse NTT and
-//          updates the accumulator (latency mode for narrow circuit levels).
+//          products to wave 0 through their own transpose blocks, 16 slots
+//          at a time; wave 0 runs the inverse NTT and updates the
+//          accumulator (latency mode for narrow circuit levels; 35 KB of LDS,
+//          so four bootstraps fit one CU).
 // The accumulator lives in LDS ([component][coefficient] u32); each level
 // re-reads it to form X^a ACC - ACC.
 template <int W>
@@ -149,10 +151,8 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, int n_lwe, int steps, int raw_acc,
     const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
-  constexpr int PART = (W > 1) ? (W - 1) * 32 * 64 : 1;
   __shared__ uint32_t s_acc[2][RING_N];
-  __shared__ uint32_t s_tr[W][2][LDS_HALF];
-  __shared__ uint64_t s_part[PART];
+  __shared__ __align__(16) uint32_t s_tr[W][2][LDS_HALF];
   __shared__ uint16_t s_abar[MAX_LWE + 4];
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -236,19 +236,27 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     }
 
     if constexpr (W > 1) {
-      if (wave > 0) {
-        uint64_t* part = s_part + (size_t)(wave - 1) * 32 * 64;
+      // hand-off of 16 slots at a time through the helpers' transpose blocks
+      // (2 x 1056 words >= 16 slots x 64 lanes x 2 words)
 #pragma unroll
-        for (int s = 0; s < 32; ++s) part[s * 64 + lane] = outv[s];
-      }
-      __syncthreads();
-      if (wave == 0) {
+      for (int half = 0; half < 2; ++half) {
+        if (wave > 0) {
+          uint64_t* part = reinterpret_cast<uint64_t*>(s_tr[wave][0]);
 #pragma unroll
-        for (int w = 1; w < W; ++w) {
-          const uint64_t* part = s_part + (size_t)(w - 1) * 32 * 64;
-#pragma unroll
-          for (int s = 0; s < 32; ++s) outv[s] = gl_add(outv[s], part[s * 64 + lane]);
+          for (int s = 0; s < 16; ++s) part[s * 64 + lane] = outv[half * 16 + s];
         }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+          for (int w = 1; w < W; ++w) {
+            const uint64_t* part = reinterpret_cast<const uint64_t*>(s_tr[w][0]);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) outv[half * 16 + s] = gl_add(outv[half * 16 + s], part[s * 64 + lane]);
+          }
+        }
+        __syncthreads();
+      }
+      if (wave == 0) {
         ntt_inv(outv, buf, opaque(tw_i), l);
 #pragma unroll
         for (int m = 0; m < 32; ++m) acc[l + 32 * m] += gl_lift_u32(outv[m]);
@@ -315,7 +323,7 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
     e0[t] = nullptr;
     e1[t] = nullptr;
     accv[t] = 0u;
-    if (jb < njobs) {
+    if (jb < njobs && jobs[jb].ex0 != REF_NONE) {
       const KsJob K = jobs[jb];
       e0[t] = ex + (size_t)K.ex0 * (N + 1);
       e1[t] = K.ex1 == REF_NONE ? nullptr : ex + (size_t)K.ex1 * (N + 1);
@@ -358,7 +366,7 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int jb = j0 + t;
-    if (jb < njobs && colok) {
+    if (e0[t] && colok) {
       const uint32_t o = jobs[jb].out;
       uint32_t* p = dst.p[o >> REF_SHIFT] + (size_t)(o & REF_INDEX_MASK) * w + col;
       if (isplit == 1) *p = accv[t];
@@ -374,6 +382,7 @@ __global__ void ks_init_kernel(const KsJob* __restrict__ jobs, int njobs, const 
   const int jb = blockIdx.x;
   if (jb >= njobs) return;
   const KsJob K = jobs[jb];
+  if (K.ex0 == REF_NONE) return;  // padding job
   const int w = n_lwe + 1;
   uint32_t* o = dst.p[K.out >> REF_SHIFT] + (size_t)(K.out & REF_INDEX_MASK) * w;
   for (int c = threadIdx.x; c < w; c += blockDim.x) {
@@ -409,12 +418,12 @@ __global__ void lwe_scale_kernel(const uint32_t* __restrict__ in, uint32_t* __re
   if (k < words) out[k] = (uint32_t)sign * in[k];
 }
 
-__global__ void gather_kernel(const uint32_t* __restrict__ refs, int cnt, SrcBases src,
+__global__ void gather_kernel(const uint32_t* __restrict__ refs, int cnt, SrcBases src, uint32_t index_offset,
                               uint32_t* __restrict__ out, int n_lwe) {
   const int j = blockIdx.x;
   if (j >= cnt) return;
   const uint32_t r = refs[j];
-  const uint32_t* s = src.p[r >> REF_SHIFT] + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
+  const uint32_t* s = src.p[r >> REF_SHIFT] + (size_t)((r & REF_INDEX_MASK) + index_offset) * (n_lwe + 1);
   for (int c = threadIdx.x; c <= n_lwe; c += blockDim.x) out[(size_t)j * (n_lwe + 1) + c] = s[c];
 }
 
@@ -518,10 +527,10 @@ hipError_t launch_lwe_scale(const uint32_t* d_in, uint32_t* d_out, size_t words,
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const uint32_t* d_refs, int cnt, const SrcBases& src, uint32_t* d_out, int n_lwe,
-                         hipStream_t s) {
+hipError_t launch_gather(const uint32_t* d_refs, int cnt, const SrcBases& src, uint32_t index_offset,
+                         uint32_t* d_out, int n_lwe, hipStream_t s) {
   if (cnt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_kernel, dim3(cnt), dim3(256), 0, s, d_refs, cnt, src, d_out, n_lwe);
+  hipLaunchKernelGGL(gather_kernel, dim3(cnt), dim3(256), 0, s, d_refs, cnt, src, index_offset, d_out, n_lwe);
   return hipGetLastError();
 }
 

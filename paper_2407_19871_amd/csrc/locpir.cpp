@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/locpir.h"
+#include "internal.h"
 #include "jobs.h"
 #include "kernels.h"
 
@@ -33,8 +34,9 @@ using lp::KsJob;
 // ---------------------------------------------------------------- errors
 namespace {
 thread_local std::string g_err;
+}  // namespace
 
-lp_status fail(lp_status code, const char* fmt, ...) {
+lp_status lp::fail(lp_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -44,11 +46,8 @@ lp_status fail(lp_status code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess) return fail(LP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+namespace {
+using lp::fail;
 
 bool params_ok(const lp_params* P, std::string* why) {
   if (!P) { *why = "null params"; return false; }
@@ -126,36 +125,6 @@ void parallel_rows(size_t rows, const std::function<void(size_t)>& fn) {
   for (auto& x : th) x.join();
 }
 }  // namespace
-
-// ---------------------------------------------------------------- handles
-struct lp_secret_key {
-  lp_params P;
-  std::vector<uint8_t> s;  // LWE key, n bits
-  std::vector<uint8_t> S;  // ring key, N bits
-};
-
-struct lp_cloud_key {
-  lp_params P;
-  std::vector<uint32_t> bsk;  // [n][2l][2][N]
-  std::vector<uint32_t> ksk;  // [N][t][base-1][n+1]
-};
-
-namespace {
-struct Plan;
-}
-
-struct lp_device_key {
-  lp_params P;
-  int device = 0;
-  uint64_t* bsk_ntt = nullptr;             // [n][2l][2][N] NTT domain
-  uint32_t* ksk = nullptr;                 // [N][t][base-1][n+1]
-  const uint64_t** bsk_tab = nullptr;      // device array {bsk_ntt}
-  const uint32_t** ksk_tab = nullptr;      // device array {ksk}
-  lp::Twiddles tw{};
-  size_t bytes = 0;
-  std::mutex mu;
-  std::map<std::tuple<uint32_t, uint32_t, uint32_t, int>, std::shared_ptr<Plan>> plans;
-};
 
 extern "C" size_t lp_bsk_words(const lp_params* P) {
   return P ? (size_t)P->n * 2 * P->l * 2 * P->N : 0;
@@ -395,21 +364,23 @@ struct DeviceTables {
 std::mutex g_tw_mu;
 std::map<int, DeviceTables> g_tw;
 
+}  // namespace
+
 // Twiddle tables of the current device, uploaded once and kept for the
 // process lifetime.
-lp_status device_twiddles(lp::Twiddles* out) {
+lp_status lp::device_twiddles(lp::Twiddles* out) {
   int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
+  LP_HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_tw_mu);
   auto it = g_tw.find(dev);
   if (it == g_tw.end()) {
     std::vector<uint64_t> f, i;
     if (!make_twiddles(f, i)) return fail(LP_EDEVICE, "twiddle construction failed");
     DeviceTables t;
-    HIP_TRY(hipMalloc(&t.fwd, 1024 * 8));
-    HIP_TRY(hipMalloc(&t.inv, 1024 * 8));
-    HIP_TRY(hipMemcpy(t.fwd, f.data(), 1024 * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(t.inv, i.data(), 1024 * 8, hipMemcpyHostToDevice));
+    LP_HIP_TRY(hipMalloc(&t.fwd, 1024 * 8));
+    LP_HIP_TRY(hipMalloc(&t.inv, 1024 * 8));
+    LP_HIP_TRY(hipMemcpy(t.fwd, f.data(), 1024 * 8, hipMemcpyHostToDevice));
+    LP_HIP_TRY(hipMemcpy(t.inv, i.data(), 1024 * 8, hipMemcpyHostToDevice));
     it = g_tw.emplace(dev, t).first;
   }
   out->fwd = it->second.fwd;
@@ -417,47 +388,30 @@ lp_status device_twiddles(lp::Twiddles* out) {
   return LP_OK;
 }
 
-inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-}  // namespace
+using lp::as_stream;
+using lp::device_twiddles;
+using lp::pick_br_wpb;
+using lp::pick_ks_split;
+using lp::pick_ks_tile;
+using lp::ProfScope;
+using lp::ScopedDevice;
+using lp::kProfBR;
+using lp::kProfKS;
 
 // ---------------------------------------------------------------- profiling
-namespace {
-enum ProfKind { kProfBR = 0, kProfKS = 1, kProfKinds = 2 };
-const char* kProfNames[kProfKinds] = {"blind_rotate", "keyswitch"};
-struct ProfRecord {
-  int kind;
-  uint64_t jobs;
-  hipEvent_t start, stop;
-};
+namespace lp {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof;
-
-// Brackets one launch with events when profiling is on.
-struct ProfScope {
-  bool on = false;
-  ProfRecord rec{};
-  hipStream_t s;
-  ProfScope(int kind, uint64_t jobs, hipStream_t st) : s(st) {
-    {
-      std::lock_guard<std::mutex> lk(g_prof_mu);
-      on = g_prof_on;
-    }
-    if (!on || jobs == 0) { on = false; return; }
-    rec.kind = kind;
-    rec.jobs = jobs;
-    if (hipEventCreate(&rec.start) != hipSuccess) { on = false; return; }
-    if (hipEventCreate(&rec.stop) != hipSuccess) { (void)hipEventDestroy(rec.start); on = false; return; }
-    (void)hipEventRecord(rec.start, s);
-  }
-  ~ProfScope() {
-    if (!on) return;
-    (void)hipEventRecord(rec.stop, s);
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof.push_back(rec);
-  }
-};
-}  // namespace
+}  // namespace lp
+using lp::g_prof;
+using lp::g_prof_mu;
+using lp::g_prof_on;
+using lp::ProfRecord;
+using lp::kProfKinds;
+namespace {
+const char* kProfNames[lp::kProfKinds] = {"blind_rotate", "keyswitch"};
+}
 
 extern "C" lp_status lp_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -503,7 +457,7 @@ extern "C" lp_status lp_device_key_create(const lp_cloud_key* ck, void* stream, 
   hipStream_t s = as_stream(stream);
   auto k = std::make_unique<lp_device_key>();
   k->P = ck->P;
-  HIP_TRY(hipGetDevice(&k->device));
+  LP_HIP_TRY(hipGetDevice(&k->device));
   lp_status st = device_twiddles(&k->tw);
   if (st != LP_OK) return st;
   const size_t bw = ck->bsk.size(), kw = ck->ksk.size();
@@ -566,42 +520,6 @@ bool gate_combo(lp_gate g, GateCombo* c) {
   return false;
 }
 
-// Launch shapes.  Defaults come from measurements on MI355X; the
-// environment variables LOCPIR_BR_WAVES, LOCPIR_BR_WIDE_MAX, LOCPIR_KS_TILE
-// and LOCPIR_KS_SPLIT override them (for the autotuner).
-int env_int(const char* name, int dflt) {
-  const char* v = std::getenv(name);
-  return (v && *v) ? std::atoi(v) : dflt;
-}
-int pick_ks_tile(size_t njobs) {
-  const int t = env_int("LOCPIR_KS_TILE", 0);
-  if (t == 1 || t == 4 || t == 8 || t == 16) return t;
-  return njobs >= 4096 ? 16 : njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1;
-}
-int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
-  const int forced = env_int("LOCPIR_KS_SPLIT", 0);
-  if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
-  const size_t blocks = ((n_lwe + 64) / 64) * ((njobs + tile - 1) / tile);
-  int sp = 1;
-  while (sp < 16 && blocks * sp < 2048) sp *= 2;
-  return sp;
-}
-int pick_br_wpb(size_t njobs) {
-  const int forced = env_int("LOCPIR_BR_WAVES", 0);
-  if (forced == 1 || forced == 3) return forced;
-  return (int)njobs <= env_int("LOCPIR_BR_WIDE_MAX", 512) ? 3 : 1;
-}
-
-struct ScopedDevice {
-  int prev = -1;
-  explicit ScopedDevice(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-    else prev = -1;
-  }
-  ~ScopedDevice() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 }  // namespace
 
 extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
@@ -619,13 +537,13 @@ extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, c
   hipStream_t s = as_stream(stream);
   const uint32_t n = dk->P.n, N = dk->P.N;
   if (gc.nbr == 0) {
-    HIP_TRY(lp::launch_lwe_scale(d_in0, d_out, cnt * (n + 1), gc.c0, s));
+    LP_HIP_TRY(lp::launch_lwe_scale(d_in0, d_out, cnt * (n + 1), gc.c0, s));
     return LP_OK;
   }
   const size_t nbr = cnt * gc.nbr;
   const size_t ex_bytes = nbr * (N + 1) * 4, br_bytes = nbr * sizeof(BrJob), ks_bytes = cnt * sizeof(KsJob);
   char* scratch = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&scratch, ex_bytes + br_bytes + ks_bytes + 512, s));
+  LP_HIP_TRY(hipMallocAsync((void**)&scratch, ex_bytes + br_bytes + ks_bytes + 512, s));
   uint32_t* ex = reinterpret_cast<uint32_t*>(scratch);
   BrJob* br = reinterpret_cast<BrJob*>(scratch + ((ex_bytes + 255) & ~size_t(255)));
   KsJob* ks = reinterpret_cast<KsJob*>(reinterpret_cast<char*>(br) + ((br_bytes + 255) & ~size_t(255)));
@@ -663,7 +581,7 @@ extern "C" lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t*
   std::vector<KsJob> jobs(cnt);
   for (size_t k = 0; k < cnt; ++k) jobs[k] = KsJob{(uint32_t)k, lp::REF_NONE, 0u, lp::make_ref(0, (uint32_t)k), 0u, {0, 0, 0}};
   KsJob* dj = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&dj, cnt * sizeof(KsJob), s));
+  LP_HIP_TRY(hipMallocAsync((void**)&dj, cnt * sizeof(KsJob), s));
   hipError_t e = hipMemcpyAsync(dj, jobs.data(), cnt * sizeof(KsJob), hipMemcpyHostToDevice, s);
   lp::DstBases dst{};
   dst.p[0] = d_out;
@@ -680,291 +598,6 @@ extern "C" lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t*
   return LP_OK;
 }
 
-// ---------------------------------------------------------------- bbox circuit
-namespace {
-// A ciphertext of the circuit: an input or gate-output slot, possibly
-// negated (HomNOT is free: it negates the sample), or the noiseless trivial
-// sample (0, v).
-struct CRef {
-  int32_t slot = -1;  // -1: trivial
-  bool neg = false;
-  uint32_t tval = 0;
-  int level = 0;
-};
-
-struct Gate {
-  int kind;  // LP_GATE_AND, LP_GATE_XNOR, LP_GATE_XOR or LP_GATE_MUX
-  CRef in[3];
-  int level;
-  int32_t out;
-};
-
-CRef cnot(CRef r) {
-  if (r.slot < 0) r.tval = 0u - r.tval;
-  else r.neg = !r.neg;
-  return r;
-}
-
-struct Circuit {
-  int32_t n_slots = 0;
-  std::vector<Gate> gates;
-  std::vector<CRef> outputs;
-
-  CRef input() {
-    CRef r;
-    r.slot = n_slots++;
-    return r;
-  }
-  CRef gate(int kind, CRef a, CRef b, CRef c = CRef()) {
-    Gate g;
-    g.kind = kind;
-    g.in[0] = a;
-    g.in[1] = b;
-    g.in[2] = c;
-    g.level = 1 + std::max({a.level, b.level, kind == LP_GATE_MUX ? c.level : 0});
-    g.out = n_slots++;
-    gates.push_back(g);
-    CRef r;
-    r.slot = g.out;
-    r.level = g.level;
-    return r;
-  }
-  // Algorithm 2 (HomCompS): Enc(1) iff a < b.  t0 starts as the trivial
-  // Enc(0) = (0, -1/8); signed inputs flip both MSBs first; then per bit from
-  // the LSB: t1 = XNOR(a_i, b_i), t0 = MUX(t1, t0, b_i).
-  CRef comp_s(std::vector<CRef> a, std::vector<CRef> b, bool is_signed) {
-    const size_t l = a.size();
-    if (is_signed) {
-      a[l - 1] = cnot(a[l - 1]);
-      b[l - 1] = cnot(b[l - 1]);
-    }
-    CRef t0;
-    t0.tval = 0xE0000000u;
-    for (size_t i = 0; i < l; ++i) {
-      CRef t1 = gate(LP_GATE_XNOR, a[i], b[i]);
-      t0 = gate(LP_GATE_MUX, t1, t0, b[i]);
-    }
-    return t0;
-  }
-};
-
-// Algorithms 3-5 for one query shape.
-Circuit build_bbox(uint32_t l, uint32_t N, uint32_t m, bool is_signed) {
-  Circuit C;
-  std::vector<CRef> X(l), Y(l);
-  for (auto& r : X) r = C.input();
-  for (auto& r : Y) r = C.input();
-  std::vector<std::vector<CRef>> B(4 * N, std::vector<CRef>(l));
-  for (auto& v : B)
-    for (auto& r : v) r = C.input();
-  std::vector<CRef> S((size_t)N * m);
-  for (auto& r : S) r = C.input();
-  std::vector<std::vector<CRef>> T(m);
-  for (uint32_t bi = 0; bi < N; ++bi) {
-    // x_l = HomCompLE(x1, x) = NOT HomCompS(x, x1);  x_r = HomCompS(x, x2)
-    CRef xl = cnot(C.comp_s(X, B[4 * bi + 0], is_signed));
-    CRef xr = C.comp_s(X, B[4 * bi + 1], is_signed);
-    CRef yl = cnot(C.comp_s(Y, B[4 * bi + 2], is_signed));
-    CRef yr = C.comp_s(Y, B[4 * bi + 3], is_signed);
-    CRef v1 = C.gate(LP_GATE_AND, xl, xr);
-    CRef v2 = C.gate(LP_GATE_AND, yl, yr);
-    CRef f = C.gate(LP_GATE_AND, v1, v2);
-    for (uint32_t j = 0; j < m; ++j) T[j].push_back(C.gate(LP_GATE_AND, f, S[(size_t)bi * m + j]));  // Alg. 4
-  }
-  // Algorithm 5 as a balanced XOR tree: pairs left to right, odd one carried
-  for (uint32_t j = 0; j < m; ++j) {
-    std::vector<CRef> cur = T[j];
-    while (cur.size() > 1) {
-      std::vector<CRef> nxt;
-      for (size_t k = 0; k + 1 < cur.size(); k += 2) nxt.push_back(C.gate(LP_GATE_XOR, cur[k], cur[k + 1]));
-      if (cur.size() & 1) nxt.push_back(cur.back());
-      cur.swap(nxt);
-    }
-    C.outputs.push_back(cur[0]);
-  }
-  return C;
-}
-
-struct Plan {
-  uint32_t l, N, m;
-  int is_signed;
-  uint32_t n_inputs = 0, n_slots = 0;
-  uint64_t n_br = 0, n_ks = 0;
-  std::vector<int> br_off, br_cnt, ks_off, ks_cnt;  // per level, into the job arrays
-  int max_br = 0;
-  BrJob* d_br = nullptr;
-  KsJob* d_ks = nullptr;
-  uint32_t* d_out_refs = nullptr;
-  int levels() const { return (int)br_cnt.size(); }
-  ~Plan() {
-    if (d_br) (void)hipFree(d_br);
-    if (d_ks) (void)hipFree(d_ks);
-    if (d_out_refs) (void)hipFree(d_out_refs);
-  }
-};
-
-// Host part of a plan: jobs grouped by level.
-void schedule(const Circuit& C, uint32_t n_inputs, Plan& P, std::vector<BrJob>& br, std::vector<KsJob>& ks,
-              std::vector<uint32_t>& out_refs) {
-  int depth = 0;
-  for (auto& g : C.gates) depth = std::max(depth, g.level);
-  std::vector<std::vector<const Gate*>> by_level(depth + 1);
-  for (auto& g : C.gates) by_level[g.level].push_back(&g);
-  P.n_inputs = n_inputs;
-  P.n_slots = (uint32_t)C.n_slots;
-  // operand (coef * ref) folded into a blind-rotation input
-  auto put = [](BrJob& j, int which, const CRef& r, int32_t coef) {
-    if (r.slot < 0) {
-      j.cst += (uint32_t)coef * r.tval;
-      return;
-    }
-    const uint32_t ref = lp::make_ref(0, (uint32_t)r.slot);
-    const int32_t c = r.neg ? -coef : coef;
-    if (which == 0) { j.in0 = ref; j.c0 = c; }
-    else { j.in1 = ref; j.c1 = c; }
-  };
-  for (int L = 1; L <= depth; ++L) {
-    P.br_off.push_back((int)br.size());
-    P.ks_off.push_back((int)ks.size());
-    int slot = 0;
-    for (const Gate* g : by_level[L]) {
-      BrJob j{lp::REF_NONE, lp::REF_NONE, 0, 0, 0u, 0u, 0u, 0u};
-      KsJob k{lp::REF_NONE, lp::REF_NONE, 0u, lp::make_ref(0, (uint32_t)g->out), 0u, {0, 0, 0}};
-      if (g->kind == LP_GATE_MUX) {
-        BrJob j1 = j, j2 = j;
-        j1.cst = j2.cst = 0xE0000000u;  // -1/8
-        put(j1, 0, g->in[0], 1);         // sel AND t
-        put(j1, 1, g->in[1], 1);
-        put(j2, 0, g->in[0], -1);        // NOT sel AND f
-        put(j2, 1, g->in[2], 1);
-        j1.out = (uint32_t)slot++;
-        j2.out = (uint32_t)slot++;
-        br.push_back(j1);
-        br.push_back(j2);
-        k.ex0 = j1.out;
-        k.ex1 = j2.out;
-        k.cst = 0x20000000u;             // + 1/8
-        P.n_br += 2;
-      } else {
-        GateCombo gc;
-        gate_combo((lp_gate)g->kind, &gc);
-        j.cst = gc.cst;
-        put(j, 0, g->in[0], gc.c0);
-        put(j, 1, g->in[1], gc.c1);
-        j.out = (uint32_t)slot++;
-        br.push_back(j);
-        k.ex0 = j.out;
-        P.n_br += 1;
-      }
-      ks.push_back(k);
-      P.n_ks += 1;
-    }
-    P.br_cnt.push_back((int)br.size() - P.br_off.back());
-    P.ks_cnt.push_back((int)ks.size() - P.ks_off.back());
-    P.max_br = std::max(P.max_br, slot);
-  }
-  for (auto& o : C.outputs) out_refs.push_back(lp::make_ref(0, (uint32_t)o.slot));
-}
-
-lp_status get_plan(lp_device_key* dk, uint32_t l, uint32_t N, uint32_t m, int is_signed, std::shared_ptr<Plan>* out) {
-  std::lock_guard<std::mutex> lk(dk->mu);
-  auto key = std::make_tuple(l, N, m, is_signed);
-  auto it = dk->plans.find(key);
-  if (it != dk->plans.end()) {
-    *out = it->second;
-    return LP_OK;
-  }
-  Circuit C = build_bbox(l, N, m, is_signed != 0);
-  auto P = std::make_shared<Plan>();
-  P->l = l;
-  P->N = N;
-  P->m = m;
-  P->is_signed = is_signed;
-  std::vector<BrJob> br;
-  std::vector<KsJob> ks;
-  std::vector<uint32_t> refs;
-  schedule(C, 2 * l + 4 * l * N + N * m, *P, br, ks, refs);
-  if (P->n_slots > lp::REF_INDEX_MASK) return fail(LP_EINVAL, "query too large");
-  HIP_TRY(hipMalloc(&P->d_br, std::max<size_t>(1, br.size()) * sizeof(BrJob)));
-  HIP_TRY(hipMalloc(&P->d_ks, std::max<size_t>(1, ks.size()) * sizeof(KsJob)));
-  HIP_TRY(hipMalloc(&P->d_out_refs, std::max<size_t>(1, refs.size()) * 4));
-  HIP_TRY(hipMemcpy(P->d_br, br.data(), br.size() * sizeof(BrJob), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(P->d_ks, ks.data(), ks.size() * sizeof(KsJob), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(P->d_out_refs, refs.data(), refs.size() * 4, hipMemcpyHostToDevice));
-  dk->plans[key] = P;
-  *out = P;
-  return LP_OK;
-}
-}  // namespace
-
-extern "C" lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,
-                                    uint32_t* n_levels) {
-  if (l == 0 || l > 64 || n_boxes == 0 || m == 0) return fail(LP_EINVAL, "lp_bbox_counts: empty shape");
-  Circuit C = build_bbox(l, n_boxes, m, true);
-  Plan P;
-  std::vector<BrJob> br;
-  std::vector<KsJob> ks;
-  std::vector<uint32_t> refs;
-  schedule(C, 0, P, br, ks, refs);
-  if (n_br) *n_br = P.n_br;
-  if (n_ks) *n_ks = P.n_ks;
-  if (n_levels) *n_levels = (uint32_t)P.levels();
-  return LP_OK;
-}
-
-extern "C" lp_status lp_eval_bbox_query(const lp_device_key* dkc, const lp_bbox_query* q, uint32_t* d_out,
-                                        void* stream) {
-  if (!dkc || !q || !d_out) return fail(LP_EINVAL, "lp_eval_bbox_query: null argument");
-  if (q->l == 0 || q->l > 64 || q->n_boxes == 0 || q->m == 0)
-    return fail(LP_EINVAL, "lp_eval_bbox_query: empty or oversized query shape");
-  if (!q->d_x || !q->d_y || !q->d_bounds || !q->d_payload) return fail(LP_EINVAL, "lp_eval_bbox_query: null input");
-  lp_device_key* dk = const_cast<lp_device_key*>(dkc);
-  ScopedDevice sd(dk->device);
-  std::shared_ptr<Plan> P;
-  lp_status st = get_plan(dk, q->l, q->n_boxes, q->m, q->is_signed ? 1 : 0, &P);
-  if (st != LP_OK) return st;
-  hipStream_t s = as_stream(stream);
-  const uint32_t n = dk->P.n, w = n + 1, Nr = dk->P.N;
-  const size_t pool_bytes = (size_t)P->n_slots * w * 4, ex_bytes = (size_t)P->max_br * (Nr + 1) * 4;
-  uint32_t* pool = nullptr;
-  uint32_t* ex = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&pool, pool_bytes, s));
-  hipError_t e = hipMallocAsync((void**)&ex, std::max<size_t>(ex_bytes, 4), s);
-  const size_t l = q->l, Nb = q->n_boxes, m = q->m;
-  size_t off = 0;
-  auto put = [&](const uint32_t* src, size_t cts) {
-    if (e == hipSuccess) e = hipMemcpyAsync(pool + off * w, src, cts * w * 4, hipMemcpyDeviceToDevice, s);
-    off += cts;
-  };
-  put(q->d_x, l);
-  put(q->d_y, l);
-  put(q->d_bounds, 4 * l * Nb);
-  put(q->d_payload, Nb * m);
-  lp::SrcBases src{};
-  src.p[0] = pool;
-  lp::DstBases dst{};
-  dst.p[0] = pool;
-  for (int L = 0; L < P->levels() && e == hipSuccess; ++L) {
-    {
-      ProfScope ps(kProfBR, (uint64_t)P->br_cnt[L], s);
-      e = lp::launch_blind_rotate(P->d_br + P->br_off[L], P->br_cnt[L], src, ex, dk->bsk_tab, (int)n, (int)n, 0,
-                                  dk->tw, pick_br_wpb(P->br_cnt[L]), s);
-    }
-    if (e == hipSuccess) {
-      ProfScope ps(kProfKS, (uint64_t)P->ks_cnt[L], s);
-      const int tile = pick_ks_tile(P->ks_cnt[L]);
-      e = lp::launch_keyswitch(P->d_ks + P->ks_off[L], P->ks_cnt[L], ex, dst, dk->ksk_tab, (int)n, (int)Nr,
-                               (int)dk->P.ks_t, (int)dk->P.ks_base_bit, tile, pick_ks_split(P->ks_cnt[L], tile, n), s);
-    }
-  }
-  if (e == hipSuccess) e = lp::launch_gather(P->d_out_refs, (int)m, src, d_out, (int)n, s);
-  hipError_t e2 = hipFreeAsync(pool, s);
-  hipError_t e3 = ex ? hipFreeAsync(ex, s) : hipSuccess;
-  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_eval_bbox_query: %s", hipGetErrorString(e));
-  if (e2 != hipSuccess || e3 != hipSuccess) return fail(LP_EDEVICE, "lp_eval_bbox_query: free failed");
-  return LP_OK;
-}
-
 // ---------------------------------------------------------------- diagnostics
 extern "C" lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint32_t* d_poly, size_t cnt,
                                              uint32_t* d_out, void* stream) {
@@ -976,7 +609,7 @@ extern "C" lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint
   lp_status st = device_twiddles(&tw);
   if (st != LP_OK) return st;
   uint64_t* tmp = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&tmp, cnt * 1024 * 8, s));
+  LP_HIP_TRY(hipMallocAsync((void**)&tmp, cnt * 1024 * 8, s));
   hipError_t e = lp::launch_bsk_to_ntt(d_poly, tmp, (int)cnt, tw, s);
   if (e == hipSuccess) e = lp::launch_debug_polymul(d_digits, tmp, d_out, (int)cnt, tw, s);
   hipError_t e2 = hipFreeAsync(tmp, s);
@@ -996,7 +629,7 @@ extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32
   for (size_t k = 0; k < cnt; ++k)
     jobs[k] = BrJob{lp::make_ref(0, (uint32_t)k), lp::REF_NONE, 1, 0, 0u, (uint32_t)k, 0u, 0u};
   BrJob* dj = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&dj, cnt * sizeof(BrJob), s));
+  LP_HIP_TRY(hipMallocAsync((void**)&dj, cnt * sizeof(BrJob), s));
   hipError_t e = hipMemcpyAsync(dj, jobs.data(), cnt * sizeof(BrJob), hipMemcpyHostToDevice, s);
   lp::SrcBases src{};
   src.p[0] = d_in;
@@ -1016,7 +649,7 @@ extern "C" void lp_cloud_key_free(lp_cloud_key* ck) { delete ck; }
 extern "C" void lp_device_key_free(lp_device_key* dk) {
   if (!dk) return;
   ScopedDevice sd(dk->device);
-  dk->plans.clear();
+  lp::sched_forget_key(dk);
   if (dk->bsk_ntt) (void)hipFree(dk->bsk_ntt);
   if (dk->ksk) (void)hipFree(dk->ksk);
   if (dk->bsk_tab) (void)hipFree(dk->bsk_tab);
