@@ -118,6 +118,73 @@ def microbench(lp, torch, sk, dk, sizes=(1, 64, 1024, 16384)):
     return {"batched_nand_bootstraps_per_s": res, "one_per_launch_bootstraps_per_s": round(one, 1)}
 
 
+def serve_bench(requests_per_rate: int, seed: int = 5):
+    """Serving: requests with their own keys (a pool of client keys, each
+    uploaded and converted on the GPU per request), 16- or 32-bit signed
+    coordinates, 1..256 boxes log-uniform, 32-bit payloads.  A burst measures
+    the saturated rate, then Poisson arrivals at 0.25/0.5/0.75/0.95 of it."""
+    import math
+    import torch
+    import paper_2407_19871_amd as lp
+    from oracle import plain
+    from paper_2407_19871_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(seed)
+    clients = [lp.keygen(None, 5000 + c) for c in range(8)]
+
+    def make_request(i):
+        c = i % len(clients)
+        l = 16 if rng.random() < 0.5 else 32
+        nb = int(min(256, max(1, math.floor(math.exp(rng.uniform(0, math.log(257)))))))
+        q = W.random_query(10000 + i, l, nb, 32, region=W.KOREA if i % 2 else W.ZERO_STRADDLE,
+                           force_inside=bool(rng.random() < 0.8))
+        xb, yb, bb, pb = q.plain_bits()
+        sk, ck = clients[c]
+        ct = sk.encrypt_bits(np.concatenate([xb, yb, bb, pb]), seed=20000 + i)
+        L, N = q.l, q.n_boxes
+        parts = (ct[:L], ct[L:2 * L], ct[2 * L:2 * L + 4 * L * N], ct[2 * L + 4 * L * N:])
+        return q, c, parts
+
+    def run(reqs, arrivals):
+        srv = lp.Server(200 << 30)
+        t0 = time.perf_counter()
+        tickets = []
+        for (q, c, parts), at in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            tickets.append(srv.submit(clients[c][1], q.l, q.n_boxes, q.m, True, *parts))
+        lats, ok = [], True
+        for (q, c, parts), t in zip(reqs, tickets):
+            st, out, lat = srv.poll(t)
+            d, _ = clients[c][0].decrypt_bits(out)
+            ok &= st == 0 and W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, q.l, q.m, True)
+            lats.append(lat)
+        wall = time.perf_counter() - t0
+        stats = srv.stats()
+        srv.close()
+        n_br = sum(lp.bbox_counts(q.l, q.n_boxes, q.m)[0] for q, _, _ in reqs)
+        return {"queries_per_s": round(len(reqs) / wall, 3), "bootstraps_per_s": round(n_br / wall, 1),
+                "p50_ms": round(float(np.percentile(lats, 50)) * 1e3, 1),
+                "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1),
+                "requests": len(reqs), "ticks": stats["ticks"], "correct": bool(ok)}
+
+    burst = [make_request(i) for i in range(requests_per_rate)]
+    sat = run(burst, [0.0] * len(burst))
+    res = {"metric": "serving: p50/p99 latency and queries/s under Poisson arrivals on 1 MI355X",
+           "saturated": sat, "rates": []}
+    for k, f in enumerate((0.25, 0.5, 0.75, 0.95)):
+        reqs = [make_request(1000 * (k + 1) + i) for i in range(requests_per_rate)]
+        lam = f * sat["queries_per_s"]
+        arr = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+        r = run(reqs, list(arr))
+        r["offered_fraction"] = f
+        r["offered_queries_per_s"] = round(lam, 3)
+        res["rates"].append(r)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,11 +194,17 @@ def main():
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run device copies of this many bytes (traffic calibration)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="serving benchmark with this many requests per arrival rate (separate JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the gate-bootstrap path here runs on a single MI355X "
               f"and has no multi-GPU mode (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve_bench(args.serve)
+        return
 
     import torch
 

@@ -45,6 +45,8 @@ typedef int32_t lp_status;
 #define LP_EDEVICE (-3)      /* a HIP call failed                         */
 #define LP_EUNSUPPORTED (-4) /* parameters the GPU kernels do not handle  */
 #define LP_EBUDGET (-5)      /* server admission beyond the memory budget */
+#define LP_EAGAIN (-6)       /* server request not finished yet           */
+#define LP_ECANCELED (-7)    /* server request cancelled                  */
 
 /* TFHE parameters.  n, lwe_sigma: LWE dimension and noise of gate
  * ciphertexts (KeyGen outputs n and sigma, Sec. 2.3).  N, k: ring degree and
@@ -167,6 +169,57 @@ lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_que
 /* Bootstraps, key switches and depth levels of that circuit. */
 lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,
                          uint32_t* n_levels);
+
+/* ---- query server (continuous batching) ------------------------------------
+ * Serves bounding-box queries from many clients, each request bringing its
+ * own cloud key (PK).  A scheduler thread admits queued requests in arrival
+ * order while the device bytes they need (keys, ciphertext pool, extract and
+ * job buffers; see lp_server_request_bytes) fit hbm_budget and fewer than
+ * max_inflight are admitted.  Each scheduler tick runs the next depth level
+ * of every admitted request in one fused blind-rotation launch and one fused
+ * key-switch launch; requests that arrive meanwhile join at the next tick.
+ * A finished request's result is kept on the host until polled; its device
+ * memory is released at once.  A failing request (allocation, upload) ends
+ * alone; the others continue.  Latency is measured from submit to the end of
+ * the result copy.  The server runs on the HIP device current at creation. */
+typedef struct lp_server lp_server;
+typedef struct {
+  size_t hbm_budget;     /* device bytes the admitted requests may hold together     */
+  uint32_t max_inflight; /* admitted requests at once; 0 = bounded by the budget only */
+  int32_t simulate;      /* 1: schedule without a GPU (results are zero); for tests   */
+  uint64_t fail_ticket;  /* fault injection: this ticket's set-up fails (0 = none)    */
+} lp_server_config;
+/* A query whose ciphertexts are in host memory (same layout as lp_bbox_query). */
+typedef struct {
+  uint32_t l, n_boxes, m;
+  int32_t is_signed;
+  const uint32_t* x;
+  const uint32_t* y;
+  const uint32_t* bounds;
+  const uint32_t* payload;
+} lp_bbox_query_host;
+typedef struct {
+  uint64_t submitted, admitted, completed, failed, cancelled, ticks, fused_bootstraps;
+  uint32_t pending, active;
+  size_t bytes_in_use, peak_bytes;
+} lp_server_stats;
+lp_status lp_server_create(const lp_server_config* cfg, lp_server** out);
+/* Device bytes a request of this key and shape holds while admitted. */
+lp_status lp_server_request_bytes(const lp_cloud_key* ck, const lp_bbox_query_host* q, size_t* bytes);
+/* Copies the query's ciphertexts and queues it; ck must stay alive until the
+ * request ends.  LP_EBUDGET if it can never fit the budget, LP_EINVAL for a
+ * malformed shape.  *ticket identifies the request. */
+lp_status lp_server_submit(lp_server* s, const lp_cloud_key* ck, const lp_bbox_query_host* q, uint64_t* ticket);
+/* LP_EAGAIN while the request runs (wait = 0), or blocks until it ends
+ * (wait != 0).  On LP_OK copies the m result ciphertexts to out (host,
+ * may be NULL) and the latency in seconds; other statuses report how the
+ * request ended.  A ticket can be polled to completion once. */
+lp_status lp_server_poll(lp_server* s, uint64_t ticket, int wait, uint32_t* out, double* latency_s);
+/* Ends a queued or running request at the next tick with LP_ECANCELED. */
+lp_status lp_server_cancel(lp_server* s, uint64_t ticket);
+lp_status lp_server_stats_get(lp_server* s, lp_server_stats* out);
+/* Finishes every queued and running request, then frees the server. */
+void lp_server_free(lp_server* s);
 
 /* ---- diagnostics (device) ------------------------------------------------ */
 

@@ -41,6 +41,23 @@ class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64), ("jobs", C.c_uint64), ("total_ms", C.c_double)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_uint32), ("simulate", C.c_int32),
+                ("fail_ticket", C.c_uint64)]
+
+
+class HostQuery(C.Structure):
+    _fields_ = [("l", C.c_uint32), ("n_boxes", C.c_uint32), ("m", C.c_uint32), ("is_signed", C.c_int32),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("bounds", C.c_void_p), ("payload", C.c_void_p)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("failed", C.c_uint64), ("cancelled", C.c_uint64), ("ticks", C.c_uint64),
+                ("fused_bootstraps", C.c_uint64), ("pending", C.c_uint32), ("active", C.c_uint32),
+                ("bytes_in_use", C.c_size_t), ("peak_bytes", C.c_size_t)]
+
+
 class BBoxQuery(C.Structure):
     _fields_ = [("l", C.c_uint32), ("n_boxes", C.c_uint32), ("m", C.c_uint32), ("is_signed", C.c_int32),
                 ("d_x", C.c_void_p), ("d_y", C.c_void_p), ("d_bounds", C.c_void_p), ("d_payload", C.c_void_p)]
@@ -86,6 +103,13 @@ def lib() -> C.CDLL:
         "lp_debug_blind_rotate": (i32, [vp, vp, sz, u32, vp, vp]),
         "lp_profile_enable": (i32, [i32]),
         "lp_profile_collect": (i32, [C.POINTER(KernelStat), C.POINTER(C.c_int)]),
+        "lp_server_create": (i32, [C.POINTER(ServerConfig), C.POINTER(vp)]),
+        "lp_server_request_bytes": (i32, [vp, C.POINTER(HostQuery), C.POINTER(sz)]),
+        "lp_server_submit": (i32, [vp, vp, C.POINTER(HostQuery), C.POINTER(u64)]),
+        "lp_server_poll": (i32, [vp, u64, i32, vp, C.POINTER(C.c_double)]),
+        "lp_server_cancel": (i32, [vp, u64]),
+        "lp_server_stats_get": (i32, [vp, C.POINTER(ServerStats)]),
+        "lp_server_free": (None, [vp]),
         "lp_secret_key_free": (None, [vp]),
         "lp_cloud_key_free": (None, [vp]),
         "lp_device_key_free": (None, [vp]),
@@ -341,3 +365,69 @@ def profile_collect() -> dict:
     _check(lib().lp_profile_collect(arr, C.byref(cnt)))
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "jobs": int(arr[i].jobs),
                                    "total_ms": float(arr[i].total_ms)} for i in range(cnt.value)}
+
+
+# ------------------------------------------------------------------ server
+LP_EAGAIN = -6
+LP_ECANCELED = -7
+
+
+class Server:
+    """Continuous-batching query server (lp_server_*).  Queries are host
+    arrays (x, y, bounds, payload) of uint32 ciphertexts."""
+
+    def __init__(self, hbm_budget: int, max_inflight: int = 0, simulate: bool = False, fail_ticket: int = 0):
+        self._keep = {}
+        cfg = ServerConfig(hbm_budget, max_inflight, 1 if simulate else 0, fail_ticket)
+        h = C.c_void_p()
+        _check(lib().lp_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _LIB is not None:
+            _LIB.lp_server_free(h)
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _host_query(l, n_boxes, m, is_signed, x, y, bounds, payload):
+        arrs = [np.ascontiguousarray(np.asarray(a, np.uint32)) for a in (x, y, bounds, payload)]
+        return HostQuery(l, n_boxes, m, int(bool(is_signed)), *[_np_ptr(a) for a in arrs]), arrs
+
+    def request_bytes(self, ck: CloudKey, l, n_boxes, m, is_signed, x, y, bounds, payload) -> int:
+        q, _ = self._host_query(l, n_boxes, m, is_signed, x, y, bounds, payload)
+        b = C.c_size_t()
+        _check(lib().lp_server_request_bytes(ck._h, C.byref(q), C.byref(b)))
+        return int(b.value)
+
+    def submit(self, ck: CloudKey, l, n_boxes, m, is_signed, x, y, bounds, payload) -> int:
+        q, arrs = self._host_query(l, n_boxes, m, is_signed, x, y, bounds, payload)
+        t = C.c_uint64()
+        _check(lib().lp_server_submit(self._h, ck._h, C.byref(q), C.byref(t)))
+        self._keep[int(t.value)] = (ck, m, ck.params.n + 1)   # keep the key alive until done
+        return int(t.value)
+
+    def poll(self, ticket: int, wait: bool = True):
+        """(status, result array or None, latency seconds)"""
+        ck, m, w = self._keep[ticket]
+        out = np.zeros((m, w), np.uint32)
+        lat = C.c_double()
+        st = lib().lp_server_poll(self._h, ticket, 1 if wait else 0, _np_ptr(out), C.byref(lat))
+        if st == LP_EAGAIN:
+            return st, None, None
+        self._keep.pop(ticket, None)
+        return st, (out if st == 0 else None), float(lat.value)
+
+    def cancel(self, ticket: int):
+        _check(lib().lp_server_cancel(self._h, ticket))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().lp_server_stats_get(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}

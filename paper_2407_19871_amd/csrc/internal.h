@@ -6,10 +6,12 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <memory>
 #include <mutex>
 #include <vector>
 
 #include "../../include/locpir.h"
+#include "jobs.h"
 #include "kernels.h"
 
 struct lp_secret_key {
@@ -53,6 +55,30 @@ lp_status device_twiddles(Twiddles* out);
 
 // Drops every cached query program that references dk.
 void sched_forget_key(const lp_device_key* dk);
+
+// Jobs of one bounding-box query shape (Algorithms 2-5), by depth level.
+// Ciphertext operands are pool slots (make_ref(0, slot)); blind-rotation
+// outputs and key-switch inputs index the level's extract buffer from 0.
+// Input slots come first: x (l), y (l), bounds (N x 4 x l), payload (N x m).
+struct Plan {
+  uint32_t l = 0, N = 0, m = 0;
+  int is_signed = 0;
+  uint32_t n_inputs = 0, n_slots = 0;
+  uint64_t n_br = 0, n_ks = 0;
+  std::vector<std::vector<BrJob>> br;
+  std::vector<std::vector<KsJob>> ks;
+  std::vector<uint32_t> out_slots;
+  int levels() const { return (int)br.size(); }
+  size_t max_level_br() const {
+    size_t mx = 0;
+    for (auto& v : br) mx = v.size() > mx ? v.size() : mx;
+    return mx;
+  }
+};
+// Cached plan of a shape (thread-safe).
+std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed);
+// Key-switch tile for a fused launch with per-key job counts.
+int fused_ks_tile(const std::vector<size_t>& per_key, size_t total);
 
 // ---- launch shapes ---------------------------------------------------------
 // Defaults come from measurements on MI355X; LOCPIR_BR_WAVES,

@@ -14,6 +14,9 @@ constexpr uint32_t REF_NONE = 0xFFFFFFFFu;
 constexpr int REF_SHIFT = 28;
 constexpr uint32_t REF_INDEX_MASK = (1u << REF_SHIFT) - 1;
 constexpr int MAX_BASES = 8;
+// Base id selecting the pool of the job's key (table `pool_tab[key]`): the
+// query server gives every request its own key and its own pool.
+constexpr uint32_t KEY_POOL_BASE = 15;
 
 __host__ __device__ inline uint32_t make_ref(uint32_t base, uint32_t index) { return (base << REF_SHIFT) | index; }
 

@@ -22,16 +22,18 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
 // Blind rotation + sample extraction (or raw accumulator output) of njobs
 // jobs.  ex: extract buffer, N+1 words per slot (2N per slot when raw_acc).
 // waves_per_job: 1 (one wave per bootstrap) or 3 (one wave per gadget level).
+// d_pool_tab (may be null) resolves operands with base KEY_POOL_BASE to the
+// pool of the job's key.
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
-                               const uint64_t* const* d_bsk_tab, int n_lwe, int steps, int raw_acc,
-                               Twiddles tw, int waves_per_job, hipStream_t s);
+                               const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe,
+                               int steps, int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s);
 
 // Key switching of njobs jobs (tiles of `tile` consecutive jobs share one
 // key; jobs with ex0 == REF_NONE are padding and skipped); the ring index is
 // split into `isplit` ranges (N divisible by 64 isplit).
 hipError_t launch_keyswitch(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
-                            const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t,
-                            int ks_base_bit, int tile, int isplit, hipStream_t s);
+                            const uint32_t* const* d_ksk_tab, uint32_t* const* d_pool_tab, int n_lwe, int N,
+                            int ks_t, int ks_base_bit, int tile, int isplit, hipStream_t s);
 
 // Descriptors of cnt equal gates on arrays in0/in1/in2 (bases 0, 1, 2).
 // nbr = 1: one blind rotation per gate with (cst, c0*in0 + c1*in1);

@@ -149,8 +149,8 @@ __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restri
 template <int W>
 __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
-    const uint64_t* const* __restrict__ bsk_tab, int n_lwe, int steps, int raw_acc,
-    const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
+    const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
+    int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
   __shared__ uint32_t s_acc[2][RING_N];
   __shared__ __align__(16) uint32_t s_tr[W][2][LDS_HALF];
   __shared__ uint16_t s_abar[MAX_LWE + 4];
@@ -166,10 +166,14 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 
   // modulus switch of the combined input (0, cst) + c0 in0 + c1 in1
   {
-    const uint32_t* in0 = J.in0 == REF_NONE ? nullptr
-                                            : src.p[J.in0 >> REF_SHIFT] + (size_t)(J.in0 & REF_INDEX_MASK) * (n_lwe + 1);
-    const uint32_t* in1 = J.in1 == REF_NONE ? nullptr
-                                            : src.p[J.in1 >> REF_SHIFT] + (size_t)(J.in1 & REF_INDEX_MASK) * (n_lwe + 1);
+    auto operand = [&](uint32_t r) -> const uint32_t* {
+      if (r == REF_NONE) return nullptr;
+      const uint32_t base = r >> REF_SHIFT;
+      const uint32_t* b = base == KEY_POOL_BASE ? pool_tab[J.key] : src.p[base];
+      return b + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
+    };
+    const uint32_t* in0 = operand(J.in0);
+    const uint32_t* in1 = operand(J.in1);
     for (int c = threadIdx.x; c <= n_lwe; c += 64 * W) {
       uint32_t v = (c == n_lwe) ? J.cst : 0u;
       if (in0) v += (uint32_t)J.c0 * in0[c];
@@ -302,7 +306,8 @@ template <int T, int BB>
 __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__ jobs, int njobs,
                                                        const uint32_t* __restrict__ ex, DstBases dst,
                                                        const uint32_t* const* __restrict__ ksk_tab,
-                                                       int n_lwe, int N, int ks_t) {
+                                                       uint32_t* const* __restrict__ pool_tab, int n_lwe, int N,
+                                                       int ks_t) {
   constexpr int NROWS = (1 << BB) - 1;
   const int lane = threadIdx.x;
   const int col = blockIdx.x * 64 + lane;
@@ -368,7 +373,8 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
     const int jb = j0 + t;
     if (e0[t] && colok) {
       const uint32_t o = jobs[jb].out;
-      uint32_t* p = dst.p[o >> REF_SHIFT] + (size_t)(o & REF_INDEX_MASK) * w + col;
+      uint32_t* b = (o >> REF_SHIFT) == KEY_POOL_BASE ? pool_tab[jobs[jb].key] : dst.p[o >> REF_SHIFT];
+      uint32_t* p = b + (size_t)(o & REF_INDEX_MASK) * w + col;
       if (isplit == 1) *p = accv[t];
       else atomicAdd(p, accv[t]);  // accv already holds minus the partial sum
     }
@@ -378,13 +384,14 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
 // Output of a split key switch before accumulation: (0, ..., 0, b'), with
 // b' = cst + b(ex0) (+ b(ex1)).
 __global__ void ks_init_kernel(const KsJob* __restrict__ jobs, int njobs, const uint32_t* __restrict__ ex,
-                               DstBases dst, int n_lwe, int N) {
+                               DstBases dst, uint32_t* const* __restrict__ pool_tab, int n_lwe, int N) {
   const int jb = blockIdx.x;
   if (jb >= njobs) return;
   const KsJob K = jobs[jb];
   if (K.ex0 == REF_NONE) return;  // padding job
   const int w = n_lwe + 1;
-  uint32_t* o = dst.p[K.out >> REF_SHIFT] + (size_t)(K.out & REF_INDEX_MASK) * w;
+  uint32_t* b = (K.out >> REF_SHIFT) == KEY_POOL_BASE ? pool_tab[K.key] : dst.p[K.out >> REF_SHIFT];
+  uint32_t* o = b + (size_t)(K.out & REF_INDEX_MASK) * w;
   for (int c = threadIdx.x; c < w; c += blockDim.x) {
     uint32_t v = 0u;
     if (c == n_lwe) {
@@ -461,17 +468,17 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
 }
 
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
-                               const uint64_t* const* d_bsk_tab, int n_lwe, int steps, int raw_acc, Twiddles tw,
-                               int waves_per_job, hipStream_t s) {
+                               const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
+                               int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   switch (waves_per_job) {
     case 1:
       hipLaunchKernelGGL(blind_rotate_kernel<1>, dim3(njobs), dim3(64), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
-                         n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
     case 3:
       hipLaunchKernelGGL(blind_rotate_kernel<3>, dim3(njobs), dim3(192), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
-                         n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
     default:
       return hipErrorInvalidValue;
@@ -481,34 +488,34 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
 
 template <int T>
 static hipError_t launch_ks_t(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
-                              const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t, int bb, int isplit,
-                              hipStream_t s) {
+                              const uint32_t* const* d_ksk_tab, uint32_t* const* pt, int n_lwe, int N, int ks_t,
+                              int bb, int isplit, hipStream_t s) {
   dim3 grid((n_lwe + 1 + 63) / 64, (njobs + T - 1) / T, isplit);
   if (isplit > 1) {
-    hipLaunchKernelGGL(ks_init_kernel, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, d_ex, dst, n_lwe, N);
+    hipLaunchKernelGGL(ks_init_kernel, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, d_ex, dst, pt, n_lwe, N);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   switch (bb) {
-    case 1: hipLaunchKernelGGL((keyswitch_kernel<T, 1>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
-    case 2: hipLaunchKernelGGL((keyswitch_kernel<T, 2>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
-    case 3: hipLaunchKernelGGL((keyswitch_kernel<T, 3>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
-    case 4: hipLaunchKernelGGL((keyswitch_kernel<T, 4>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t); break;
+    case 1: hipLaunchKernelGGL((keyswitch_kernel<T, 1>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
+    case 2: hipLaunchKernelGGL((keyswitch_kernel<T, 2>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
+    case 3: hipLaunchKernelGGL((keyswitch_kernel<T, 3>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
+    case 4: hipLaunchKernelGGL((keyswitch_kernel<T, 4>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_keyswitch(const KsJob* d_jobs, int njobs, const uint32_t* d_ex, const DstBases& dst,
-                            const uint32_t* const* d_ksk_tab, int n_lwe, int N, int ks_t, int ks_base_bit,
-                            int tile, int isplit, hipStream_t s) {
+                            const uint32_t* const* d_ksk_tab, uint32_t* const* d_pool_tab, int n_lwe, int N,
+                            int ks_t, int ks_base_bit, int tile, int isplit, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   if (isplit < 1 || N % (64 * isplit) != 0) return hipErrorInvalidValue;
   switch (tile) {
-    case 1: return launch_ks_t<1>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
-    case 4: return launch_ks_t<4>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
-    case 8: return launch_ks_t<8>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
-    case 16: return launch_ks_t<16>(d_jobs, njobs, d_ex, dst, d_ksk_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
+    case 1: return launch_ks_t<1>(d_jobs, njobs, d_ex, dst, d_ksk_tab, d_pool_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
+    case 4: return launch_ks_t<4>(d_jobs, njobs, d_ex, dst, d_ksk_tab, d_pool_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
+    case 8: return launch_ks_t<8>(d_jobs, njobs, d_ex, dst, d_ksk_tab, d_pool_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
+    case 16: return launch_ks_t<16>(d_jobs, njobs, d_ex, dst, d_ksk_tab, d_pool_tab, n_lwe, N, ks_t, ks_base_bit, isplit, s);
     default: return hipErrorInvalidValue;
   }
 }

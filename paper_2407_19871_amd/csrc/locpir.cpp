@@ -556,12 +556,12 @@ extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, c
   dst.p[0] = d_out;
   if (e == hipSuccess) {
     ProfScope ps(kProfBR, nbr, s);
-    e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, (int)n, (int)n, 0, dk->tw, pick_br_wpb(nbr), s);
+    e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, pick_br_wpb(nbr), s);
   }
   if (e == hipSuccess) {
     ProfScope ps(kProfKS, cnt, s);
     const int tile = pick_ks_tile(cnt);
-    e = lp::launch_keyswitch(ks, (int)cnt, ex, dst, dk->ksk_tab, (int)n, (int)N, (int)dk->P.ks_t,
+    e = lp::launch_keyswitch(ks, (int)cnt, ex, dst, dk->ksk_tab, nullptr, (int)n, (int)N, (int)dk->P.ks_t,
                              (int)dk->P.ks_base_bit, tile, pick_ks_split(cnt, tile, n), s);
   }
   hipError_t e2 = hipFreeAsync(scratch, s);
@@ -587,7 +587,7 @@ extern "C" lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t*
   dst.p[0] = d_out;
   if (e == hipSuccess) {
     const int tile = pick_ks_tile(cnt);
-    e = lp::launch_keyswitch(dj, (int)cnt, d_in, dst, dk->ksk_tab, (int)dk->P.n, (int)dk->P.N, (int)dk->P.ks_t,
+    e = lp::launch_keyswitch(dj, (int)cnt, d_in, dst, dk->ksk_tab, nullptr, (int)dk->P.n, (int)dk->P.N, (int)dk->P.ks_t,
                              (int)dk->P.ks_base_bit, tile, pick_ks_split(cnt, tile, dk->P.n), s);
   }
   // the host staging vector must outlive the copy
@@ -635,7 +635,7 @@ extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32
   src.p[0] = d_in;
   const int st = (int)std::min<uint32_t>(steps, dk->P.n);
   if (e == hipSuccess)
-    e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, (int)dk->P.n, st, 1, dk->tw,
+    e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, nullptr, (int)dk->P.n, st, 1, dk->tw,
                                 pick_br_wpb(cnt), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipError_t e2 = hipFreeAsync(dj, s);

@@ -136,20 +136,6 @@ void combo(int kind, uint32_t* cst, int32_t* c0, int32_t* c1) {
 }
 
 // ---------------------------------------------------------------- plans
-// Jobs of one query shape, by level.  Ciphertext operands are pool slots
-// (make_ref(0, slot)); blind-rotation outputs and key-switch inputs index
-// the level's extract buffer from 0.
-struct Plan {
-  uint32_t l = 0, N = 0, m = 0;
-  int is_signed = 0;
-  uint32_t n_inputs = 0, n_slots = 0;
-  uint64_t n_br = 0, n_ks = 0;
-  std::vector<std::vector<BrJob>> br;
-  std::vector<std::vector<KsJob>> ks;
-  std::vector<uint32_t> out_slots;
-  int levels() const { return (int)br.size(); }
-};
-
 std::shared_ptr<const Plan> make_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed) {
   Circuit C = build_bbox(l, N, m, is_signed != 0);
   auto P = std::make_shared<Plan>();
@@ -218,6 +204,7 @@ std::shared_ptr<const Plan> make_plan(uint32_t l, uint32_t N, uint32_t m, int is
 
 std::mutex g_plan_mu;
 std::map<std::tuple<uint32_t, uint32_t, uint32_t, int>, std::shared_ptr<const Plan>> g_plans;
+}  // namespace
 
 std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -228,6 +215,8 @@ std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_
   g_plans[key] = P;
   return P;
 }
+
+namespace {
 
 // ---------------------------------------------------------------- programs
 // Queries (each under its own key) fused level by level, with device job
@@ -267,6 +256,8 @@ struct Program {
   }
 };
 
+}  // namespace
+
 // Tile of a fused key-switch launch: the default for the level's size,
 // halved while per-key padding would waste more than a quarter of it.
 int fused_ks_tile(const std::vector<size_t>& per_key, size_t total) {
@@ -279,6 +270,8 @@ int fused_ks_tile(const std::vector<size_t>& per_key, size_t total) {
   }
   return t;
 }
+
+namespace {
 
 lp_status build_program(const std::vector<const lp_device_key*>& keys,
                         const std::vector<std::shared_ptr<const Plan>>& plans, std::shared_ptr<Program>* out) {
@@ -374,14 +367,14 @@ lp_status build_program(const std::vector<const lp_device_key*>& keys,
 hipError_t launch_level_br(const Program& G, int L, hipStream_t s) {
   SrcBases src{};
   src.p[0] = G.pool;
-  return launch_blind_rotate(G.d_br + G.br_off[L], G.br_cnt[L], src, G.ex, G.d_bsk_tab, (int)G.n_lwe,
+  return launch_blind_rotate(G.d_br + G.br_off[L], G.br_cnt[L], src, G.ex, G.d_bsk_tab, nullptr, (int)G.n_lwe,
                              (int)G.n_lwe, 0, G.tw, G.br_waves[L], s);
 }
 
 hipError_t launch_level_ks(const Program& G, int L, hipStream_t s) {
   DstBases dst{};
   dst.p[0] = G.pool;
-  return launch_keyswitch(G.d_ks + G.ks_off[L], G.ks_cnt[L], G.ex, dst, G.d_ksk_tab, (int)G.n_lwe, (int)G.Nr,
+  return launch_keyswitch(G.d_ks + G.ks_off[L], G.ks_cnt[L], G.ex, dst, G.d_ksk_tab, nullptr, (int)G.n_lwe, (int)G.Nr,
                           (int)G.ks_t, (int)G.ks_bb, G.ks_tile[L], G.ks_split[L], s);
 }
 

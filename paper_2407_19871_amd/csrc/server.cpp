@@ -1,0 +1,441 @@
+// Query server: continuous batching of bounding-box queries from many
+// clients, each request carrying its own keys.
+//
+// A scheduler thread owns one HIP stream.  Requests wait in a FIFO queue
+// until the device bytes they need (keys, ciphertext pool, extract and job
+// buffers) fit the configured budget; an admitted request gets its own device
+// key and pool.  Every tick fuses the next depth level of every admitted
+// request into one blind-rotation launch and one key-switch launch (jobs
+// select their request's key and pool through per-tick tables), then
+// advances each request by one level.  Requests that arrive while others are
+// on the GPU join at the next tick, so their work shares launches with the
+// requests already in flight.  A finished request's result is copied to the
+// host and its device memory released.
+//
+// simulate = 1 runs the same admission and scheduling without touching a
+// GPU (results are zero), which lets the host logic be tested on a CPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "jobs.h"
+#include "kernels.h"
+
+namespace {
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t ticket = 0;
+  const lp_cloud_key* ck = nullptr;
+  uint32_t l = 0, N = 0, m = 0;
+  int is_signed = 0;
+  std::vector<uint32_t> inputs;  // n_inputs * (n+1) words
+  std::shared_ptr<const lp::Plan> plan;
+  size_t bytes = 0;
+  lp_device_key* dk = nullptr;
+  uint32_t* pool = nullptr;
+  int level = 0;
+  std::vector<uint32_t> out;
+  lp_status status = LP_EAGAIN;
+  bool cancel = false;
+  Clock::time_point t_submit;
+  double latency = 0.0;
+};
+
+template <typename T>
+hipError_t grow(T** p, size_t* cap, size_t need) {
+  if (need <= *cap) return hipSuccess;
+  const size_t n = std::max(need, *cap * 2);
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return e;
+  }
+  *p = nullptr;
+  *cap = 0;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e == hipSuccess) *cap = n;
+  return e;
+}
+}  // namespace
+
+struct lp_server {
+  lp_server_config cfg{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> pending;
+  std::vector<std::shared_ptr<Request>> active;
+  std::map<uint64_t, std::shared_ptr<Request>> all;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  lp_server_stats st{};
+  std::thread worker;
+  hipStream_t stream = nullptr;
+  // device buffers reused across ticks
+  lp::BrJob* d_br = nullptr;
+  size_t cap_br = 0;
+  lp::KsJob* d_ks = nullptr;
+  size_t cap_ks = 0;
+  uint32_t* ex = nullptr;
+  size_t cap_ex = 0;
+  const uint64_t** d_bsk_tab = nullptr;
+  size_t cap_bt = 0;
+  const uint32_t** d_ksk_tab = nullptr;
+  size_t cap_kt = 0;
+  uint32_t** d_pool_tab = nullptr;
+  size_t cap_pt = 0;
+};
+
+namespace {
+
+size_t request_bytes(const lp_params& P, const lp::Plan& plan) {
+  const size_t w = P.n + 1;
+  const size_t key = lp_bsk_words(&P) * 8 + lp_ksk_words(&P) * 4;
+  const size_t pool = (size_t)plan.n_slots * w * 4;
+  const size_t lvl = plan.max_level_br();
+  const size_t ex = lvl * (P.N + 1) * 4;
+  const size_t jobs = lvl * (sizeof(lp::BrJob) + sizeof(lp::KsJob)) * 2;
+  return key + pool + ex + jobs;
+}
+
+lp_status check_host_query(const lp_bbox_query_host* q) {
+  if (!q) return lp::fail(LP_EINVAL, "null query");
+  if (q->l == 0 || q->l > 64 || q->n_boxes == 0 || q->n_boxes > 4096 || q->m == 0 || q->m > 4096)
+    return lp::fail(LP_EINVAL, "query shape out of range (l=%u, boxes=%u, m=%u)", q->l, q->n_boxes, q->m);
+  if (!q->x || !q->y || !q->bounds || !q->payload) return lp::fail(LP_EINVAL, "null query input");
+  return LP_OK;
+}
+
+void release(lp_server* S, Request& r) {
+  if (!S->cfg.simulate) {
+    if (r.pool) (void)hipFree(r.pool);
+    if (r.dk) lp_device_key_free(r.dk);
+  }
+  r.pool = nullptr;
+  r.dk = nullptr;
+}
+
+// Caller holds S->mu.
+void finish_locked(lp_server* S, Request& r, lp_status status) {
+  r.status = status;
+  r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
+  S->st.bytes_in_use -= r.bytes;
+  if (status == LP_OK) S->st.completed++;
+  else if (status == LP_ECANCELED) S->st.cancelled++;
+  else S->st.failed++;
+  r.inputs.clear();
+  r.inputs.shrink_to_fit();
+  S->cv_done.notify_all();
+}
+
+lp_status setup_request(lp_server* S, Request& r) {
+  if (r.ticket == S->cfg.fail_ticket) return lp::fail(LP_ENOMEM, "request %llu: injected allocation failure",
+                                                       (unsigned long long)r.ticket);
+  if (S->cfg.simulate) return LP_OK;
+  lp_status st = lp_device_key_create(r.ck, S->stream, &r.dk);
+  if (st != LP_OK) return st;
+  const size_t w = r.ck->P.n + 1;
+  hipError_t e = hipMalloc(&r.pool, (size_t)r.plan->n_slots * w * 4);
+  if (e != hipSuccess) return lp::fail(LP_ENOMEM, "request pool: %s", hipGetErrorString(e));
+  e = hipMemcpyAsync(r.pool, r.inputs.data(), r.inputs.size() * 4, hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return lp::fail(LP_EDEVICE, "request upload: %s", hipGetErrorString(e));
+  return LP_OK;
+}
+
+// One fused level over the admitted requests.
+lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, uint64_t* n_br_out) {
+  using lp::BrJob;
+  using lp::KsJob;
+  std::vector<BrJob> br;
+  std::vector<KsJob> ks;
+  std::vector<size_t> per_key;
+  size_t ks_total = 0;
+  std::vector<uint32_t> ex_base(act.size());
+  uint32_t ex_cnt = 0;
+  for (size_t k = 0; k < act.size(); ++k) {
+    const lp::Plan& P = *act[k]->plan;
+    const int L = act[k]->level;
+    ex_base[k] = ex_cnt;
+    for (BrJob j : P.br[L]) {
+      if (j.in0 != lp::REF_NONE) j.in0 = lp::make_ref(lp::KEY_POOL_BASE, j.in0 & lp::REF_INDEX_MASK);
+      if (j.in1 != lp::REF_NONE) j.in1 = lp::make_ref(lp::KEY_POOL_BASE, j.in1 & lp::REF_INDEX_MASK);
+      j.out += ex_base[k];
+      j.key = (uint32_t)k;
+      br.push_back(j);
+    }
+    ex_cnt += (uint32_t)P.br[L].size();
+    per_key.push_back(P.ks[L].size());
+    ks_total += P.ks[L].size();
+  }
+  const int tile = lp::fused_ks_tile(per_key, ks_total);
+  for (size_t k = 0; k < act.size(); ++k) {
+    const lp::Plan& P = *act[k]->plan;
+    size_t cnt = 0;
+    for (KsJob j : P.ks[act[k]->level]) {
+      j.ex0 += ex_base[k];
+      if (j.ex1 != lp::REF_NONE) j.ex1 += ex_base[k];
+      j.out = lp::make_ref(lp::KEY_POOL_BASE, j.out & lp::REF_INDEX_MASK);
+      j.key = (uint32_t)k;
+      ks.push_back(j);
+      ++cnt;
+    }
+    for (; cnt % tile; ++cnt) ks.push_back(KsJob{lp::REF_NONE, lp::REF_NONE, 0u, 0u, (uint32_t)k, {0, 0, 0}});
+  }
+  *n_br_out = br.size();
+  if (S->cfg.simulate) {
+    std::this_thread::sleep_for(std::chrono::microseconds(200));
+    return LP_OK;
+  }
+  const lp_params& Pp = act[0]->ck->P;
+  std::vector<const uint64_t*> bt(act.size());
+  std::vector<const uint32_t*> kt(act.size());
+  std::vector<uint32_t*> pt(act.size());
+  for (size_t k = 0; k < act.size(); ++k) {
+    bt[k] = act[k]->dk->bsk_ntt;
+    kt[k] = act[k]->dk->ksk;
+    pt[k] = act[k]->pool;
+  }
+  hipError_t e = grow(&S->d_br, &S->cap_br, br.size());
+  if (e == hipSuccess) e = grow(&S->d_ks, &S->cap_ks, ks.size());
+  if (e == hipSuccess) e = grow(&S->ex, &S->cap_ex, (size_t)ex_cnt * (Pp.N + 1));
+  if (e == hipSuccess) e = grow(&S->d_bsk_tab, &S->cap_bt, act.size());
+  if (e == hipSuccess) e = grow(&S->d_ksk_tab, &S->cap_kt, act.size());
+  if (e == hipSuccess) e = grow(&S->d_pool_tab, &S->cap_pt, act.size());
+  if (e == hipSuccess) e = hipMemcpyAsync(S->d_br, br.data(), br.size() * sizeof(BrJob), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->d_ks, ks.data(), ks.size() * sizeof(KsJob), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->d_bsk_tab, bt.data(), bt.size() * 8, hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->d_ksk_tab, kt.data(), kt.size() * 8, hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->d_pool_tab, pt.data(), pt.size() * 8, hipMemcpyHostToDevice, S->stream);
+  lp::SrcBases src{};
+  lp::DstBases dst{};
+  const lp::Twiddles tw = act[0]->dk->tw;
+  if (e == hipSuccess) {
+    lp::ProfScope ps(lp::kProfBR, br.size(), S->stream);
+    e = lp::launch_blind_rotate(S->d_br, (int)br.size(), src, S->ex, S->d_bsk_tab, S->d_pool_tab, (int)Pp.n, (int)Pp.n,
+                                0, tw, lp::pick_br_wpb(br.size()), S->stream);
+  }
+  if (e == hipSuccess) {
+    lp::ProfScope ps(lp::kProfKS, ks.size(), S->stream);
+    e = lp::launch_keyswitch(S->d_ks, (int)ks.size(), S->ex, dst, S->d_ksk_tab, S->d_pool_tab, (int)Pp.n, (int)Pp.N,
+                             (int)Pp.ks_t, (int)Pp.ks_base_bit, tile, lp::pick_ks_split(ks.size(), tile, Pp.n),
+                             S->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return lp::fail(LP_EDEVICE, "server tick: %s", hipGetErrorString(e));
+  return LP_OK;
+}
+
+lp_status collect_output(lp_server* S, Request& r) {
+  const size_t w = r.ck->P.n + 1;
+  r.out.assign((size_t)r.m * w, 0u);
+  if (S->cfg.simulate) return LP_OK;
+  for (uint32_t j = 0; j < r.m; ++j) {
+    hipError_t e = hipMemcpyAsync(r.out.data() + (size_t)j * w, r.pool + (size_t)r.plan->out_slots[j] * w, w * 4,
+                                  hipMemcpyDeviceToHost, S->stream);
+    if (e != hipSuccess) return lp::fail(LP_EDEVICE, "result copy: %s", hipGetErrorString(e));
+  }
+  hipError_t e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return lp::fail(LP_EDEVICE, "result copy: %s", hipGetErrorString(e));
+  return LP_OK;
+}
+
+void worker_main(lp_server* S) {
+  if (!S->cfg.simulate) (void)hipSetDevice(S->device);
+  for (;;) {
+    std::vector<std::shared_ptr<Request>> admit, act;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || !S->active.empty(); });
+      if (S->stop && S->pending.empty() && S->active.empty()) break;
+      // FIFO admission by budget and slot count
+      while (!S->pending.empty()) {
+        auto& r = S->pending.front();
+        if (r->cancel) {
+          S->st.bytes_in_use += r->bytes;  // finish_locked releases it
+          finish_locked(S, *r, LP_ECANCELED);
+          S->pending.pop_front();
+          continue;
+        }
+        if (S->cfg.max_inflight && S->active.size() + admit.size() >= S->cfg.max_inflight) break;
+        if (S->st.bytes_in_use + r->bytes > S->cfg.hbm_budget) break;
+        S->st.bytes_in_use += r->bytes;
+        S->st.peak_bytes = std::max(S->st.peak_bytes, S->st.bytes_in_use);
+        admit.push_back(r);
+        S->pending.pop_front();
+      }
+    }
+    for (auto& r : admit) {
+      lp_status st = setup_request(S, *r);
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (st != LP_OK) {
+        release(S, *r);
+        finish_locked(S, *r, st);
+      } else {
+        S->active.push_back(r);
+        S->st.admitted++;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto it = S->active.begin(); it != S->active.end();) {
+        if ((*it)->cancel) {
+          release(S, **it);
+          finish_locked(S, **it, LP_ECANCELED);
+          it = S->active.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      act = S->active;
+      S->st.active = (uint32_t)act.size();
+      S->st.pending = (uint32_t)S->pending.size();
+    }
+    if (act.empty()) continue;
+    uint64_t nbr = 0;
+    lp_status st = tick(S, act, &nbr);
+    std::vector<std::shared_ptr<Request>> done;
+    for (auto& r : act) {
+      if (st == LP_OK && ++r->level < r->plan->levels()) continue;
+      done.push_back(r);
+    }
+    std::vector<lp_status> done_st;
+    for (auto& r : done) done_st.push_back(st == LP_OK ? collect_output(S, *r) : st);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st.ticks++;
+    S->st.fused_bootstraps += nbr;
+    for (size_t i = 0; i < done.size(); ++i) {
+      release(S, *done[i]);
+      finish_locked(S, *done[i], done_st[i]);
+      S->active.erase(std::find(S->active.begin(), S->active.end(), done[i]));
+    }
+  }
+}
+}  // namespace
+
+extern "C" lp_status lp_server_create(const lp_server_config* cfg, lp_server** out) {
+  if (!cfg || !out) return lp::fail(LP_EINVAL, "lp_server_create: null argument");
+  if (cfg->hbm_budget == 0) return lp::fail(LP_EINVAL, "lp_server_create: zero budget");
+  auto S = std::make_unique<lp_server>();
+  S->cfg = *cfg;
+  if (!cfg->simulate) {
+    LP_HIP_TRY(hipGetDevice(&S->device));
+    LP_HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+  }
+  lp_server* raw = S.release();
+  raw->worker = std::thread(worker_main, raw);
+  *out = raw;
+  return LP_OK;
+}
+
+extern "C" lp_status lp_server_request_bytes(const lp_cloud_key* ck, const lp_bbox_query_host* q, size_t* bytes) {
+  if (!ck || !bytes) return lp::fail(LP_EINVAL, "lp_server_request_bytes: null argument");
+  lp_status st = check_host_query(q);
+  if (st != LP_OK) return st;
+  *bytes = request_bytes(ck->P, *lp::get_plan(q->l, q->n_boxes, q->m, q->is_signed ? 1 : 0));
+  return LP_OK;
+}
+
+extern "C" lp_status lp_server_submit(lp_server* S, const lp_cloud_key* ck, const lp_bbox_query_host* q,
+                                      uint64_t* ticket) {
+  if (!S || !ck || !ticket) return lp::fail(LP_EINVAL, "lp_server_submit: null argument");
+  lp_status st = check_host_query(q);
+  if (st != LP_OK) return st;
+  if (!S->cfg.simulate && (ck->P.N != 1024 || ck->P.l != 3 || ck->P.bg_bit != 7 || ck->P.n > 1024))
+    return lp::fail(LP_EUNSUPPORTED, "lp_server_submit: parameters the GPU kernels do not handle");
+  auto r = std::make_shared<Request>();
+  r->ck = ck;
+  r->l = q->l;
+  r->N = q->n_boxes;
+  r->m = q->m;
+  r->is_signed = q->is_signed ? 1 : 0;
+  r->plan = lp::get_plan(r->l, r->N, r->m, r->is_signed);
+  r->bytes = request_bytes(ck->P, *r->plan);
+  if (r->bytes > S->cfg.hbm_budget)
+    return lp::fail(LP_EBUDGET, "lp_server_submit: request needs %zu bytes, budget is %zu", r->bytes,
+                    S->cfg.hbm_budget);
+  const size_t w = ck->P.n + 1, l = q->l, N = q->n_boxes, m = q->m;
+  r->inputs.resize((size_t)r->plan->n_inputs * w);
+  uint32_t* p = r->inputs.data();
+  std::memcpy(p, q->x, l * w * 4);
+  std::memcpy(p + l * w, q->y, l * w * 4);
+  std::memcpy(p + 2 * l * w, q->bounds, 4 * l * N * w * 4);
+  std::memcpy(p + (2 * l + 4 * l * N) * w, q->payload, N * m * w * 4);
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return lp::fail(LP_EINVAL, "lp_server_submit: server is shutting down");
+    r->ticket = S->next_ticket++;
+    S->all[r->ticket] = r;
+    S->pending.push_back(r);
+    S->st.submitted++;
+    S->st.pending = (uint32_t)S->pending.size();
+  }
+  S->cv_work.notify_one();
+  *ticket = r->ticket;
+  return LP_OK;
+}
+
+extern "C" lp_status lp_server_poll(lp_server* S, uint64_t ticket, int wait, uint32_t* out, double* latency_s) {
+  if (!S) return lp::fail(LP_EINVAL, "lp_server_poll: null server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->all.find(ticket);
+  if (it == S->all.end()) return lp::fail(LP_EINVAL, "lp_server_poll: unknown ticket %llu", (unsigned long long)ticket);
+  std::shared_ptr<Request> r = it->second;
+  if (r->status == LP_EAGAIN) {
+    if (!wait) return LP_EAGAIN;
+    S->cv_done.wait(lk, [&] { return r->status != LP_EAGAIN; });
+  }
+  if (latency_s) *latency_s = r->latency;
+  const lp_status st = r->status;
+  if (st == LP_OK && out) std::memcpy(out, r->out.data(), r->out.size() * 4);
+  S->all.erase(ticket);
+  if (st != LP_OK) return lp::fail(st, "request %llu ended with status %d", (unsigned long long)ticket, (int)st);
+  return LP_OK;
+}
+
+extern "C" lp_status lp_server_cancel(lp_server* S, uint64_t ticket) {
+  if (!S) return lp::fail(LP_EINVAL, "lp_server_cancel: null server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(ticket);
+  if (it == S->all.end()) return lp::fail(LP_EINVAL, "lp_server_cancel: unknown ticket");
+  it->second->cancel = true;
+  S->cv_work.notify_one();
+  return LP_OK;
+}
+
+extern "C" lp_status lp_server_stats_get(lp_server* S, lp_server_stats* out) {
+  if (!S || !out) return lp::fail(LP_EINVAL, "lp_server_stats_get: null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->st;
+  out->pending = (uint32_t)S->pending.size();
+  out->active = (uint32_t)S->active.size();
+  return LP_OK;
+}
+
+extern "C" void lp_server_free(lp_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  if (!S->cfg.simulate) {
+    for (void* p : {(void*)S->d_br, (void*)S->d_ks, (void*)S->ex, (void*)S->d_bsk_tab, (void*)S->d_ksk_tab,
+                    (void*)S->d_pool_tab})
+      if (p) (void)hipFree(p);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+  }
+  delete S;
+}

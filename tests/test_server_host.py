@@ -1,0 +1,102 @@
+"""Query-server host logic on the CPU (simulate mode: same admission and
+scheduling, no GPU): budget-bound admission never drops or corrupts
+requests, over-budget and malformed requests are refused, one failing
+request does not disturb the others, cancellation ends a request."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2407_19871_amd as lp
+
+
+@pytest.fixture(scope="module")
+def ck():
+    p = lp.params_default()
+    # key contents do not matter in simulate mode; sizes do
+    return lp.CloudKey.from_arrays(p, np.zeros(lp.bsk_words(p), np.uint32), np.zeros(lp.ksk_words(p), np.uint32))
+
+
+def query(l, nb, m):
+    w = 631
+    return (l, nb, m, True, np.zeros((l, w), np.uint32), np.zeros((l, w), np.uint32),
+            np.zeros((4 * l * nb, w), np.uint32), np.zeros((nb * m, w), np.uint32))
+
+
+def test_budget_queues_requests_and_completes_all(ck):
+    probe = lp.Server(1 << 40, simulate=True)
+    one = probe.request_bytes(ck, *query(16, 2, 4))
+    probe.close()
+    srv = lp.Server(int(one * 2.5), simulate=True)
+    tickets = [srv.submit(ck, *query(16, 2, 4)) for _ in range(7)]
+    for t in tickets:
+        st, out, lat = srv.poll(t, wait=True)
+        assert st == 0 and out.shape == (4, 631) and lat >= 0
+    s = srv.stats()
+    assert s["completed"] == 7 and s["failed"] == 0 and s["admitted"] == 7
+    assert s["peak_bytes"] <= int(one * 2.5)       # never more than two admitted together
+    assert s["peak_bytes"] >= one
+    assert s["bytes_in_use"] == 0
+    srv.close()
+
+
+def test_max_inflight_limits_admission(ck):
+    srv = lp.Server(1 << 40, max_inflight=1, simulate=True)
+    one = srv.request_bytes(ck, *query(8, 1, 2))
+    tickets = [srv.submit(ck, *query(8, 1, 2)) for _ in range(4)]
+    for t in tickets:
+        assert srv.poll(t)[0] == 0
+    assert srv.stats()["peak_bytes"] == one
+    srv.close()
+
+
+def test_over_budget_and_malformed_requests_are_refused(ck):
+    srv = lp.Server(1 << 20, simulate=True)
+    with pytest.raises(lp.LocpirError) as e:
+        srv.submit(ck, *query(16, 2, 4))
+    assert e.value.code == -5
+    srv.close()
+    srv = lp.Server(1 << 40, simulate=True)
+    for bad in (query(0, 1, 1), query(16, 0, 1), query(16, 1, 0), query(65, 1, 1)):
+        with pytest.raises(lp.LocpirError) as e:
+            srv.submit(ck, *bad)
+        assert e.value.code == -1
+    srv.close()
+
+
+def test_failing_request_does_not_disturb_others(ck):
+    srv = lp.Server(1 << 40, simulate=True, fail_ticket=3)
+    tickets = [srv.submit(ck, *query(8, 1, 2)) for _ in range(5)]
+    res = {t: srv.poll(t)[0] for t in tickets}
+    assert res[3] == -2                      # LP_ENOMEM from the injected failure
+    assert all(res[t] == 0 for t in tickets if t != 3)
+    s = srv.stats()
+    assert s["failed"] == 1 and s["completed"] == 4 and s["bytes_in_use"] == 0
+    srv.close()
+
+
+def test_cancel_queued_request(ck):
+    probe = lp.Server(1 << 40, simulate=True)
+    one = probe.request_bytes(ck, *query(32, 8, 8))
+    probe.close()
+    srv = lp.Server(one, simulate=True)      # one request at a time
+    t1 = srv.submit(ck, *query(32, 8, 8))
+    t2 = srv.submit(ck, *query(32, 8, 8))
+    srv.cancel(t2)
+    assert srv.poll(t1)[0] == 0
+    assert srv.poll(t2)[0] == lp.LP_ECANCELED
+    s = srv.stats()
+    assert s["cancelled"] == 1 and s["bytes_in_use"] == 0
+    srv.close()
+
+
+def test_continuous_batching_fuses_levels(ck):
+    # two requests submitted together share ticks: fewer ticks than the sum
+    # of their depths
+    srv = lp.Server(1 << 40, simulate=True)
+    _, _, depth = lp.bbox_counts(16, 4, 8)
+    ts = [srv.submit(ck, *query(16, 4, 8)) for _ in range(2)]
+    for t in ts:
+        assert srv.poll(t)[0] == 0
+    assert srv.stats()["ticks"] < 2 * depth
+    srv.close()
