@@ -39,6 +39,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 ALG_LANE_CYCLES_PER_BR = 630 * ((6 + 2) * 5120 * 40 + 12 * 1024 * 35)
 KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd/csrc/ntt32.h",
                   "paper_2407_19871_amd/csrc/gl64.h"]
+TUNE_BUCKETS = (1, 16, 32, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16384)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_bbox16x16_traffic.txt")
 
 
@@ -132,6 +133,8 @@ def serve_bench(requests_per_rate: int, seed: int = 5):
     torch.cuda.set_device(0)
     rng = np.random.default_rng(seed)
     clients = [lp.keygen(None, 5000 + c) for c in range(8)]
+    # launch shapes are per device, not per key: tune once with one client key
+    lp.autotune(lp.DeviceKey(clients[0][1]), buckets=TUNE_BUCKETS, br_steps=64)
 
     def make_request(i):
         c = i % len(clients)
@@ -196,6 +199,8 @@ def main():
                     help="also run device copies of this many bytes (traffic calibration)")
     ap.add_argument("--serve", type=int, default=0,
                     help="serving benchmark with this many requests per arrival rate (separate JSON line)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes instead of timing them on this device first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the gate-bootstrap path here runs on a single MI355X "
@@ -225,6 +230,13 @@ def main():
     d_p = lp.to_device(cts[2 * l + 4 * l * N:])
     dk = lp.DeviceKey(ck)
     n_br, n_ks, levels = lp.bbox_counts(l, N, m)
+    tune = None
+    if not args.no_autotune:
+        # launch shapes per batch size, timed on this device before anything
+        # is measured (covers the query's level widths and the batch sizes)
+        t0 = time.perf_counter()
+        rows = lp.autotune(dk, buckets=TUNE_BUCKETS, br_steps=64)
+        tune = {"seconds": round(time.perf_counter() - t0, 2), "br_steps_timed": 64, "rows": rows}
     out = torch.empty((m, 631), dtype=torch.int32, device="cuda")
 
     def step():
@@ -290,6 +302,7 @@ def main():
         "kernels": {"blind_rotate_ms": round(br["total_ms"], 3), "keyswitch_ms": round(ks["total_ms"], 3),
                     "launches": br["launches"] + ks["launches"]},
         "roofline": roofline,
+        "autotune": tune,
     }
     if not args.no_micro:
         res["microbench"] = microbench(lp, torch, sk, dk)

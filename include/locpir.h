@@ -251,6 +251,48 @@ typedef struct {
 lp_status lp_profile_enable(int on);
 lp_status lp_profile_collect(lp_kernel_stat* stats, int* count);
 
+/* ---- launch-shape autotuning --------------------------------------------- */
+
+/* One row of a device's launch-shape table.  A launch of `count` jobs uses
+ * the first row (rows sorted by `jobs`, ascending) with count <= jobs, or
+ * the last row when count exceeds every bound.
+ *   br_waves: waves cooperating on one blind rotation, 1 (throughput) or 3
+ *             (one gadget level per wave, latency);
+ *   ks_tile:  key switches per wave tile, 1, 4, 8 or 16;
+ *   ks_split: ranges the ring index of a key switch is split into (partial
+ *             sums added atomically), 1, 2, 4, 8 or 16;
+ *   br_us, ks_us: measured microseconds per job of the chosen shapes at
+ *             `jobs` (0 when the row was installed with lp_tune_set).
+ * The environment variables LOCPIR_BR_WAVES, LOCPIR_KS_TILE and
+ * LOCPIR_KS_SPLIT, when set to a valid value, override the table. */
+typedef struct {
+  uint32_t jobs;
+  int32_t br_waves, ks_tile, ks_split;
+  float br_us, ks_us;
+} lp_tune_entry;
+#define LP_TUNE_MAX_ROWS 32
+
+/* Times every blind-rotation and key-switch launch shape at each batch size
+ * in bucket_jobs (nbuckets <= LP_TUNE_MAX_ROWS, each 1..65536, distinct) on
+ * the calling thread's current device, with dk's key, random inputs and the
+ * blind rotation cut to br_steps (1..n) key bits (the per-step cost does not
+ * depend on the bit); installs the fastest shapes as the device's table and
+ * writes the rows, sorted by jobs, to out (nbuckets entries, may be NULL).
+ * Synchronous on `stream`.  Cached query programs are dropped so that later
+ * queries launch with the new shapes. */
+lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket_jobs, int nbuckets, uint32_t br_steps,
+                      void* stream, lp_tune_entry* out);
+/* Installs rows (validated: jobs 1..2^22 and distinct, shapes from the sets
+ * above; n <= LP_TUNE_MAX_ROWS; sorted by the library)
+ * as the current device's table; n = 0 clears it (built-in defaults). */
+lp_status lp_tune_set(const lp_tune_entry* rows, int n);
+/* Copies the current device's table: at most *n rows; *n receives the count. */
+lp_status lp_tune_get(lp_tune_entry* rows, int* n);
+/* The shapes a launch of `jobs` jobs gets now on the current device
+ * (environment, then table, then built-in defaults); n_lwe sizes the
+ * default key-switch split.  br_us and ks_us are returned as 0. */
+lp_status lp_tune_pick(uint32_t jobs, uint32_t n_lwe, lp_tune_entry* out);
+
 void lp_secret_key_free(lp_secret_key* sk);
 void lp_cloud_key_free(lp_cloud_key* ck);
 void lp_device_key_free(lp_device_key* dk);

@@ -41,6 +41,20 @@ class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64), ("jobs", C.c_uint64), ("total_ms", C.c_double)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("jobs", C.c_uint32), ("br_waves", C.c_int32), ("ks_tile", C.c_int32), ("ks_split", C.c_int32),
+                ("br_us", C.c_float), ("ks_us", C.c_float)]
+
+    def as_dict(self) -> dict:
+        return {"jobs": int(self.jobs), "br_waves": int(self.br_waves), "ks_tile": int(self.ks_tile),
+                "ks_split": int(self.ks_split), "br_us": round(float(self.br_us), 3),
+                "ks_us": round(float(self.ks_us), 3)}
+
+
+TUNE_MAX_ROWS = 32
+DEFAULT_TUNE_BUCKETS = (1, 16, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16384)
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_uint32), ("simulate", C.c_int32),
                 ("fail_ticket", C.c_uint64)]
@@ -103,6 +117,10 @@ def lib() -> C.CDLL:
         "lp_debug_blind_rotate": (i32, [vp, vp, sz, u32, vp, vp]),
         "lp_profile_enable": (i32, [i32]),
         "lp_profile_collect": (i32, [C.POINTER(KernelStat), C.POINTER(C.c_int)]),
+        "lp_autotune": (i32, [vp, C.POINTER(u32), C.c_int, u32, vp, C.POINTER(TuneEntry)]),
+        "lp_tune_set": (i32, [C.POINTER(TuneEntry), C.c_int]),
+        "lp_tune_get": (i32, [C.POINTER(TuneEntry), C.POINTER(C.c_int)]),
+        "lp_tune_pick": (i32, [u32, u32, C.POINTER(TuneEntry)]),
         "lp_server_create": (i32, [C.POINTER(ServerConfig), C.POINTER(vp)]),
         "lp_server_request_bytes": (i32, [vp, C.POINTER(HostQuery), C.POINTER(sz)]),
         "lp_server_submit": (i32, [vp, vp, C.POINTER(HostQuery), C.POINTER(u64)]),
@@ -365,6 +383,77 @@ def profile_collect() -> dict:
     _check(lib().lp_profile_collect(arr, C.byref(cnt)))
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "jobs": int(arr[i].jobs),
                                    "total_ms": float(arr[i].total_ms)} for i in range(cnt.value)}
+
+
+# ------------------------------------------------------------------ autotuning
+def autotune(dk: DeviceKey, buckets=DEFAULT_TUNE_BUCKETS, br_steps: int = 64, stream=None) -> list:
+    """Times the launch shapes at each batch size and installs the fastest
+    per size for the current device (lp_autotune); returns the rows."""
+    b = (C.c_uint32 * len(buckets))(*buckets)
+    out = (TuneEntry * len(buckets))()
+    _check(lib().lp_autotune(dk._h, b, len(buckets), br_steps, _stream_ptr(stream), out))
+    return [r.as_dict() for r in out]
+
+
+def tune_table() -> list:
+    """The current device's installed rows (empty: built-in defaults)."""
+    arr = (TuneEntry * TUNE_MAX_ROWS)()
+    n = C.c_int(TUNE_MAX_ROWS)
+    _check(lib().lp_tune_get(arr, C.byref(n)))
+    return [arr[i].as_dict() for i in range(n.value)]
+
+
+def set_tune_table(rows) -> None:
+    """Installs rows (dicts with jobs, br_waves, ks_tile, ks_split); [] clears."""
+    arr = (TuneEntry * max(1, len(rows)))()
+    for i, r in enumerate(rows):
+        arr[i] = TuneEntry(int(r["jobs"]), int(r["br_waves"]), int(r["ks_tile"]), int(r["ks_split"]),
+                           float(r.get("br_us", 0.0)), float(r.get("ks_us", 0.0)))
+    _check(lib().lp_tune_set(arr, len(rows)))
+
+
+def tune_pick(jobs: int, n_lwe: int = 630) -> dict:
+    """Shapes a launch of `jobs` jobs gets now (environment, table, defaults)."""
+    r = TuneEntry()
+    _check(lib().lp_tune_pick(jobs, n_lwe, C.byref(r)))
+    d = r.as_dict()
+    del d["br_us"], d["ks_us"]
+    return d
+
+
+def _kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "ntt32.h", "gl64.h", "jobs.h"):
+        with open(os.path.join(os.path.dirname(__file__), "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def save_tune(path: str, rows=None, device_name: str = "") -> None:
+    """Writes rows (default: the installed table) as a JSON cache tagged with
+    the library version, a hash of the kernel sources and the device name."""
+    import json
+    doc = {"version": lib().lp_version().decode(), "kernels": _kernel_sources_hash(), "device": device_name,
+           "rows": tune_table() if rows is None else list(rows)}
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+
+
+def load_tune(path: str, device_name: str = "") -> bool:
+    """Installs a JSON cache written by save_tune if it matches this library,
+    these kernel sources and the device name; returns whether it did."""
+    import json
+    try:
+        with open(path) as f:
+            doc = json.load(f)
+    except (OSError, ValueError):
+        return False
+    if (doc.get("version") != lib().lp_version().decode() or doc.get("kernels") != _kernel_sources_hash()
+            or doc.get("device") != device_name):
+        return False
+    set_tune_table(doc["rows"])
+    return True
 
 
 # ------------------------------------------------------------------ server

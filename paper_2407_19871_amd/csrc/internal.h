@@ -81,32 +81,24 @@ std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_
 int fused_ks_tile(const std::vector<size_t>& per_key, size_t total);
 
 // ---- launch shapes ---------------------------------------------------------
-// Defaults come from measurements on MI355X; LOCPIR_BR_WAVES,
-// LOCPIR_BR_WIDE_MAX, LOCPIR_KS_TILE and LOCPIR_KS_SPLIT override them (the
-// autotuner sets them while it sweeps).
+// Each launch asks for its shapes by job count: a valid LOCPIR_BR_WAVES,
+// LOCPIR_KS_TILE or LOCPIR_KS_SPLIT in the environment wins, then the
+// current device's autotuned table (tune.cpp), then built-in defaults
+// measured on MI355X.
 inline int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return (v && *v) ? std::atoi(v) : dflt;
 }
-inline int pick_ks_tile(size_t njobs) {
-  const int t = env_int("LOCPIR_KS_TILE", 0);
-  if (t == 1 || t == 4 || t == 8 || t == 16) return t;
-  return njobs >= 4096 ? 16 : njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1;
-}
-inline int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
-  const int forced = env_int("LOCPIR_KS_SPLIT", 0);
-  if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
-  const size_t blocks = ((n_lwe + 64) / 64) * ((njobs + tile - 1) / tile);
-  int sp = 1;
-  while (sp < 16 && blocks * sp < 2048) sp *= 2;
-  return sp;
-}
+int pick_ks_tile(size_t njobs);
+int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe);
 // Waves per bootstrap: 3 (latency mode) for narrow launches, else 1.
-inline int pick_br_wpb(size_t njobs) {
-  const int forced = env_int("LOCPIR_BR_WAVES", 0);
-  if (forced == 1 || forced == 3) return forced;
-  return (int)njobs <= env_int("LOCPIR_BR_WIDE_MAX", 512) ? 3 : 1;
-}
+int pick_br_wpb(size_t njobs);
+// Built-in defaults (no environment, no table).
+int default_ks_tile(size_t njobs);
+int default_ks_split(size_t njobs, int tile, uint32_t n_lwe);
+int default_br_wpb(size_t njobs);
+// Drops every cached query program (after the shape table changed).
+void sched_forget_all();
 
 struct ScopedDevice {
   int prev = -1;

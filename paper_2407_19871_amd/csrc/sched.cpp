@@ -493,6 +493,12 @@ lp_status check_query(const lp_bbox_query& q) {
 
 }  // namespace
 
+void sched_forget_all() {
+  std::lock_guard<std::mutex> lk(g_prog_mu);
+  g_progs.clear();
+  g_prog_order.clear();
+}
+
 void sched_forget_key(const lp_device_key* dk) {
   std::lock_guard<std::mutex> lk(g_prog_mu);
   for (auto it = g_progs.begin(); it != g_progs.end();) {
