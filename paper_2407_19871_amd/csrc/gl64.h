@@ -93,17 +93,51 @@ GL_INLINE uint64_t gl_mul(uint64_t a, uint64_t b) {
   return gl_reduce128(lo, hi);
 }
 
-// x * 2^S mod p for a compile-time S.  2^96 = -1 folds S into [0, 96).  For
-// 0 < s < 32 the product is w0 + 2^32 w1 + 2^64 w2 with w2 < 2^31, i.e.
-// (w1:w0) + EPS w2 (mod p); for 32 <= s < 64 the three high words are
-// reduced by gl_reduce128; s in [64, 96) is two smaller shifts.
+// ---- reduced operands -----------------------------------------------------
+// A value in [0, p] is "reduced" (p stands for 0).  Adding or subtracting a
+// reduced operand needs only one correction, which is why the transforms
+// keep every twiddle product reduced.
+
+// a + b, any a, reduced b: a carry leaves s = a + b - 2^64 < p, so adding
+// EPS cannot carry again.
+GL_INLINE uint64_t gl_add_r(uint64_t a, uint64_t b) {
+  uint64_t s;
+  const bool c = __builtin_add_overflow(a, b, &s);
+  return s + (c ? GL_EPS : 0ull);
+}
+
+// a - b, any a, reduced b, as a + ~b + k (~b = 2^64 - 1 - b).  If a >= b,
+// k = 1 gives a - b.  If a < b the result is a - b + p, which lies in
+// [0, p) because b <= p; modulo 2^64 that is a + ~b + 1 - EPS, so
+// k = 2 - 2^32.
+GL_INLINE uint64_t gl_sub_r(uint64_t a, uint64_t b) {
+  const uint64_t k = a < b ? 0xFFFFFFFF00000002ull : 1ull;
+  return (a + ~b) + k;
+}
+
+// -y for reduced y: p - y = ~y + 2 - 2^32 (mod 2^64), again reduced.
+GL_INLINE uint64_t gl_neg_r(uint64_t y) { return ~y + 0xFFFFFFFF00000002ull; }
+
+// x * 2^S mod p for a compile-time S; the result is lazy for S mod 192 in
+// (0, 64) and reduced otherwise (see gl_mul_pow2_r).  2^96 = -1 folds S
+// into [0, 96) with a negation.
+//   0 < s < 32:   x 2^s = w0 + 2^32 w1 + 2^64 w2 with w2 < 2^31, i.e.
+//                 (w1:w0) + EPS w2;
+//   32 <= s < 64: the three high words are reduced by gl_reduce128;
+//   64 <= s < 96: with k = 96 - s, x = xh 2^k + xl (xl < 2^k):
+//                 x 2^s = xh 2^96 + xl 2^(s-64) 2^64 = -xh + w EPS, where
+//                 w = xl 2^(s-64) < 2^32; w EPS < p and xh < 2^63, so one
+//                 reduced subtraction gives a value in [0, p).
+template <int S>
+GL_INLINE uint64_t gl_mul_pow2_r(uint64_t x);
+
 template <int S>
 GL_INLINE uint64_t gl_mul_pow2(uint64_t x) {
   constexpr int s = ((S % 192) + 192) % 192;
   if constexpr (s == 0) {
     return x;
   } else if constexpr (s >= 96) {
-    return gl_neg(gl_mul_pow2<s - 96>(x));
+    return gl_neg_r(gl_mul_pow2_r<s - 96>(x));
   } else if constexpr (s < 32) {
     const uint64_t low = x << s;
     const uint32_t w2 = (uint32_t)(x >> (64 - s));
@@ -114,7 +148,20 @@ GL_INLINE uint64_t gl_mul_pow2(uint64_t x) {
   } else if constexpr (s < 64) {
     return gl_reduce128(x << s, x >> (64 - s));
   } else {
-    return gl_mul_pow2<32>(gl_mul_pow2<s - 32>(x));
+    const uint64_t xh = x >> (96 - s);
+    const uint32_t w = (uint32_t)x << (s - 64);
+    return gl_sub_r(((uint64_t)w << 32) - w, xh);
+  }
+}
+
+// x * 2^S reduced to [0, p].
+template <int S>
+GL_INLINE uint64_t gl_mul_pow2_r(uint64_t x) {
+  constexpr int s = ((S % 192) + 192) % 192;
+  if constexpr (s < 64) {
+    return gl_canon(gl_mul_pow2<s>(x));
+  } else {
+    return gl_mul_pow2<s>(x);  // reduced by construction
   }
 }
 

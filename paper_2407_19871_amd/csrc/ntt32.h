@@ -12,10 +12,19 @@
 // rho and omega are powers of two, so both passes use shift twiddles
 // (gl_mul_pow2); only the twist needs general multiplications.
 //
-// Pass 1 runs merged Cooley-Tukey butterflies (natural order in, slot i
-// holds ka = brv5(i) out); pass 2 runs Gentleman-Sande butterflies (natural
-// in, slot i' holds kb = brv5(i') out).  The inverse passes undo them in the
-// opposite order; their factor 32 each is folded into the inverse twist.
+// Every butterfly is Cooley-Tukey, t = w b then (a + t, a - t), with the
+// twiddle product t reduced to [0, p] so that the sum and difference need
+// one correction each (gl_add_r, gl_sub_r).
+//   pass 1 forward: merged negacyclic butterflies, natural order in, slot i
+//     holds ka = brv5(i) out;
+//   pass 2 forward: merged cyclic butterflies (root omega, twiddle 1 on the
+//     first block of each stage), natural in, slot i holds kb = brv5(i) out;
+//   pass 2 inverse: cyclic decimation in time with omega^-1, bit-reversed
+//     in, natural out (factor 32 left over);
+//   pass 1 inverse: the same cyclic inverse with rho^-2 = omega^-1, since
+//     B(ka) = sum_j2 (a_j2 rho^j2) (rho^2)^(ka j2), followed by the
+//     post-twist a_j2 *= rho^-j2 (factor 32 left over).
+// The two factors 32 are folded into the inverse twist.
 #pragma once
 #include <type_traits>
 
@@ -44,9 +53,9 @@ __device__ __forceinline__ void fwd1_stage(uint64_t (&a)[32]) {
     constexpr int z = 3 * brv5(k);
     static_for<0, LEN>([&](auto jj) {
       constexpr int j = start + decltype(jj)::value;
-      uint64_t t = gl_mul_pow2<z>(a[j + LEN]);
-      a[j + LEN] = gl_sub(a[j], t);
-      a[j] = gl_add(a[j], t);
+      const uint64_t t = gl_mul_pow2_r<z>(a[j + LEN]);
+      a[j + LEN] = gl_sub_r(a[j], t);
+      a[j] = gl_add_r(a[j], t);
     });
   });
 }
@@ -74,17 +83,21 @@ __device__ __forceinline__ void fwd1(uint64_t (&a)[32]) {
   fwd1_rest(a);
 }
 
-// ---- pass 2, forward: cyclic GS DIF, root omega = 2^6 ---------------------
+// ---- pass 2, forward: merged cyclic CT, root omega = 2^6 ------------------
+// Block b of the stage with 16/LEN blocks splits X^(2 LEN) - r^2 with
+// r = omega^(LEN brv(b)), brv over log2(16/LEN) bits.
 template <int LEN>
 __device__ __forceinline__ void fwd2_stage(uint64_t (&a)[32]) {
+  constexpr int nbits = LEN == 16 ? 0 : LEN == 8 ? 1 : LEN == 4 ? 2 : LEN == 2 ? 3 : 4;
   static_for<0, 32 / (2 * LEN)>([&](auto blk) {
-    constexpr int start = decltype(blk)::value * 2 * LEN;
+    constexpr int b = decltype(blk)::value;
+    constexpr int start = b * 2 * LEN;
+    constexpr int z = 6 * LEN * (brv5(b) >> (5 - nbits));
     static_for<0, LEN>([&](auto jj) {
-      constexpr int j = decltype(jj)::value;
-      constexpr int e = 6 * (16 / LEN) * j; /* omega_{2 LEN}^j */
-      uint64_t u = a[start + j], v = a[start + j + LEN];
-      a[start + j] = gl_add(u, v);
-      a[start + j + LEN] = gl_mul_pow2<e>(gl_sub(u, v));
+      constexpr int j = start + decltype(jj)::value;
+      const uint64_t t = gl_mul_pow2_r<z>(a[j + LEN]);  // z = 0: reduction only
+      a[j + LEN] = gl_sub_r(a[j], t);
+      a[j] = gl_add_r(a[j], t);
     });
   });
 }
@@ -97,52 +110,38 @@ __device__ __forceinline__ void fwd2(uint64_t (&a)[32]) {
   fwd2_stage<1>(a);
 }
 
-// ---- pass 2, inverse: cyclic CT DIT with omega^-1 (factor 32 left over) ---
+// ---- cyclic inverse: CT DIT with omega^-1 (factor 32 left over) ----------
 template <int LEN>
-__device__ __forceinline__ void inv2_stage(uint64_t (&a)[32]) {
+__device__ __forceinline__ void inv_cyclic_stage(uint64_t (&a)[32]) {
   static_for<0, 32 / (2 * LEN)>([&](auto blk) {
     constexpr int start = decltype(blk)::value * 2 * LEN;
     static_for<0, LEN>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
       constexpr int e = (192 - 6 * (16 / LEN) * j) % 192;
-      uint64_t u = a[start + j];
-      uint64_t v = gl_mul_pow2<e>(a[start + j + LEN]);
-      a[start + j] = gl_add(u, v);
-      a[start + j + LEN] = gl_sub(u, v);
+      const uint64_t t = gl_mul_pow2_r<e>(a[start + j + LEN]);
+      a[start + j + LEN] = gl_sub_r(a[start + j], t);
+      a[start + j] = gl_add_r(a[start + j], t);
     });
   });
 }
 
-__device__ __forceinline__ void inv2(uint64_t (&a)[32]) {
-  inv2_stage<1>(a);
-  inv2_stage<2>(a);
-  inv2_stage<4>(a);
-  inv2_stage<8>(a);
-  inv2_stage<16>(a);
+__device__ __forceinline__ void inv_cyclic(uint64_t (&a)[32]) {
+  inv_cyclic_stage<1>(a);
+  inv_cyclic_stage<2>(a);
+  inv_cyclic_stage<4>(a);
+  inv_cyclic_stage<8>(a);
+  inv_cyclic_stage<16>(a);
 }
 
-// ---- pass 1, inverse: GS butterflies with rho^-brv5(k) (factor 32 left) ---
-template <int LEN>
-__device__ __forceinline__ void inv1_stage(uint64_t (&a)[32]) {
-  static_for<0, 32 / (2 * LEN)>([&](auto blk) {
-    constexpr int start = decltype(blk)::value * 2 * LEN;
-    constexpr int k = 32 / (2 * LEN) + start / (2 * LEN);
-    constexpr int z = (192 - 3 * brv5(k)) % 192;
-    static_for<0, LEN>([&](auto jj) {
-      constexpr int j = start + decltype(jj)::value;
-      uint64_t t = a[j];
-      a[j] = gl_add(t, a[j + LEN]);
-      a[j + LEN] = gl_mul_pow2<z>(gl_sub(t, a[j + LEN]));
-    });
-  });
-}
+__device__ __forceinline__ void inv2(uint64_t (&a)[32]) { inv_cyclic(a); }
 
+// ---- pass 1, inverse: cyclic inverse, then a_j2 *= rho^-j2 ----------------
 __device__ __forceinline__ void inv1(uint64_t (&a)[32]) {
-  inv1_stage<1>(a);
-  inv1_stage<2>(a);
-  inv1_stage<4>(a);
-  inv1_stage<8>(a);
-  inv1_stage<16>(a);
+  inv_cyclic(a);
+  static_for<1, 32>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    a[j] = gl_mul_pow2<192 - 3 * j>(a[j]);
+  });
 }
 
 }  // namespace lp
