@@ -188,6 +188,96 @@ def serve_bench(requests_per_rate: int, seed: int = 5):
     print(json.dumps(res), flush=True)
 
 
+def clients_bench(n_clients: int, steps: int, warmup: int, seed: int = 4):
+    """Many clients at once, each with its own keys: the first half use 32-bit
+    floor(deg * 1e6) signed coordinates, the second half 16-bit 9.7 ones; box
+    counts uniform in 1..64; 32-bit payloads; the Korea-like region, the
+    zero-straddling one for odd clients.  All queries run as one fused program:
+    level L of every query is one blind-rotation and one key-switch launch,
+    each replayed from its hipGraph.  Every result is checked against the
+    plaintext predicate."""
+    import torch
+    import paper_2407_19871_amd as lp
+    from oracle import plain
+    from paper_2407_19871_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(seed)
+    t0 = time.perf_counter()
+    lp.autotune(lp.DeviceKey(lp.keygen(None, 1000 * seed + 999)[1]), buckets=TUNE_BUCKETS, br_steps=64)
+    keys, sks, qs, items = [], [], [], []
+    n_br = n_ks = 0
+    for c in range(n_clients):
+        l = 32 if c < n_clients // 2 else 16
+        nb = int(rng.integers(1, 65))
+        q = W.random_query(40000 + c, l, nb, 32, region=W.ZERO_STRADDLE if c % 2 else W.KOREA)
+        sk, ck = lp.keygen(None, 1000 * seed + c)
+        keys.append(lp.DeviceKey(ck))
+        del ck
+        xb, yb, bb, pb = q.plain_bits()
+        ct = sk.encrypt_bits(np.concatenate([xb, yb, bb, pb]), seed=50000 + c)
+        L, N = q.l, q.n_boxes
+        items.append((L, N, q.m, True, *[lp.to_device(a) for a in
+                                         (ct[:L], ct[L:2 * L], ct[2 * L:2 * L + 4 * L * N], ct[2 * L + 4 * L * N:])]))
+        sks.append(sk)
+        qs.append(q)
+        br, ks, _ = lp.bbox_counts(L, N, q.m)
+        n_br += br
+        n_ks += ks
+        if (c + 1) % 32 == 0:
+            print(f"clients: {c + 1} keys and queries on the device", file=sys.stderr, flush=True)
+    setup = time.perf_counter() - t0
+    outs = None
+    for _ in range(warmup):
+        outs = lp.eval_bbox_batch(keys, items, outs)
+    torch.cuda.synchronize()
+    print("clients: warm-up done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        outs = lp.eval_bbox_batch(keys, items, outs)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ok = True
+    for sk, q, o in zip(sks, qs, outs):
+        d, _ = sk.decrypt_bits(lp.to_host(o))
+        ok &= W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, q.l, q.m, True)
+    res = {"metric": "fused queries of many clients with their own keys on 1 MI355X",
+           "clients": n_clients, "bootstraps": n_br, "keyswitches": n_ks,
+           "levels": max(lp.bbox_counts(q.l, q.n_boxes, q.m)[2] for q in qs),
+           "device_key_gb": round(sum(k.bytes for k in keys) / 1e9, 2),
+           "seconds_per_batch": round(wall, 3), "bootstraps_per_s": round(n_br / wall, 1),
+           "queries_per_s": round(n_clients / wall, 3), "steps": steps, "warmup": warmup,
+           "setup_s": round(setup, 1), "correct_vs_predicate": bool(ok)}
+    print(json.dumps(res), flush=True)
+
+
+def small_query(lp, torch, reps: int = 5):
+    """The 8-bit unsigned coordinates vs one box query with an 8-bit payload
+    (107 bootstraps in 12 levels), with its own key."""
+    from oracle import plain
+    from paper_2407_19871_amd import workloads as W
+    q = W.random_query_u8(1, force_inside=True)
+    sk, ck = lp.keygen(None, 1)
+    dk = lp.DeviceKey(ck)
+    xb, yb, bb, pb = q.plain_bits()
+    ct = sk.encrypt_bits(np.concatenate([xb, yb, bb, pb]), seed=1)
+    l, N, m = q.l, q.n_boxes, q.m
+    parts = [lp.to_device(a) for a in (ct[:l], ct[l:2 * l], ct[2 * l:2 * l + 4 * l * N], ct[2 * l + 4 * l * N:])]
+    out = lp.eval_bbox_query(dk, l, N, m, False, *parts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lp.eval_bbox_query(dk, l, N, m, False, *parts, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    d, _ = sk.decrypt_bits(lp.to_host(out))
+    n_br, _, levels = lp.bbox_counts(l, N, m)
+    return {"workload": "8-bit unsigned point vs 1 encrypted box, 8-bit payload", "bootstraps": n_br,
+            "levels": levels, "ms_per_query": round(dt * 1e3, 2), "bootstraps_per_s": round(n_br / dt, 1),
+            "correct_vs_predicate": bool(W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m,
+                                                                         False))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +289,8 @@ def main():
                     help="also run device copies of this many bytes (traffic calibration)")
     ap.add_argument("--serve", type=int, default=0,
                     help="serving benchmark with this many requests per arrival rate (separate JSON line)")
+    ap.add_argument("--clients", type=int, default=0,
+                    help="fused queries of this many clients with their own keys (separate JSON line)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing them on this device first")
     args = ap.parse_args()
@@ -209,6 +301,9 @@ def main():
 
     if args.serve:
         serve_bench(args.serve)
+        return
+    if args.clients:
+        clients_bench(args.clients, args.steps, args.warmup)
         return
 
     import torch
@@ -306,6 +401,7 @@ def main():
     }
     if not args.no_micro:
         res["microbench"] = microbench(lp, torch, sk, dk)
+        res["small_query"] = small_query(lp, torch)
     if args.copy_probe:
         src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)

@@ -55,6 +55,14 @@ __device__ __forceinline__ uint64_t from_other_half(uint64_t v, int lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// The bootstrapping key as a global-address-space pointer: the key table
+// yields a generic pointer, and loads through it would otherwise be FLAT
+// loads that also count against the LDS wait counter.
+typedef __attribute__((address_space(1))) const uint64_t gmem_u64;
+__device__ __forceinline__ const gmem_u64* as_global(const uint64_t* p) {
+  return (const gmem_u64*)(const void*)p;
+}
+
 // 32 x 32 transpose through a half-wave LDS block of 32 x 33 words, in two
 // 32-bit passes (low words, then high words): on entry lane l holds row l
 // (a[i] = (l, i)); on exit lane l holds column l (a[m] = (m, l)).  Rows are
@@ -75,10 +83,17 @@ __device__ __forceinline__ void transpose32(uint64_t (&a)[32], uint32_t* buf, in
   wave_fence();
 }
 
-// Twist between the passes: slot i of lane l times psi^((2 brv5(i)+1) l).
-__device__ __forceinline__ void twist_fwd(uint64_t (&f)[32], const uint64_t* __restrict__ tw, int l) {
+// Twist between the passes: slot i of lane l times tw[i * 32 + l].  All 32
+// table loads are issued before the first product (global address space,
+// so they wait on the vector-memory counter alone) and the latency is paid
+// once per twist.
+__device__ __forceinline__ void twist(uint64_t (&f)[32], const uint64_t* __restrict__ tw, int l) {
+  const gmem_u64* t = as_global(tw) + l;
+  uint64_t w[32];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) f[i] = gl_mul(f[i], tw[i * 32 + l]);
+  for (int i = 0; i < 32; ++i) w[i] = t[i * 32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) f[i] = gl_mul(f[i], w[i]);
 }
 
 // Forward negacyclic NTT of one polynomial per half-wave.  In: lane l,
@@ -87,7 +102,7 @@ __device__ __forceinline__ void twist_fwd(uint64_t (&f)[32], const uint64_t* __r
 __device__ __forceinline__ void ntt_fwd(uint64_t (&f)[32], uint32_t* buf, const uint64_t* __restrict__ tw_f,
                                         int l) {
   fwd1(f);
-  twist_fwd(f, tw_f, l);
+  twist(f, tw_f, l);
   transpose32(f, buf, l);
   fwd2(f);
 }
@@ -97,7 +112,7 @@ __device__ __forceinline__ void ntt_fwd_digits(const int32_t (&d)[32], uint64_t 
                                                const uint64_t* __restrict__ tw_f, int l) {
   fwd1_first_stage_digits(d, f);
   fwd1_rest(f);
-  twist_fwd(f, tw_f, l);
+  twist(f, tw_f, l);
   transpose32(f, buf, l);
   fwd2(f);
 }
@@ -106,8 +121,7 @@ __device__ __forceinline__ void ntt_fwd_digits(const int32_t (&d)[32], uint64_t 
 __device__ __forceinline__ void ntt_inv(uint64_t (&f)[32], uint32_t* buf, const uint64_t* __restrict__ tw_i,
                                         int l) {
   inv2(f);
-#pragma unroll
-  for (int m = 0; m < 32; ++m) f[m] = gl_mul(f[m], tw_i[m * 32 + l]);
+  twist(f, tw_i, l);
   transpose32(f, buf, l);
   inv1(f);
 }
@@ -192,14 +206,30 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
   }
   __syncthreads();
 
-  const uint64_t* __restrict__ bsk = bsk_tab[J.key];
+  const gmem_u64* bsk = as_global(bsk_tab[J.key]);
   const int nsteps = steps < n_lwe ? steps : n_lwe;
 
   for (int i = 0; i < nsteps; ++i) {
     const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
     if (a == 0) continue;  // X^0 ACC - ACC = 0 decomposes to zero digits
 
-    const uint64_t* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+    // BSK_i in the NTT domain: rows (p, j) = 3p + j, each with components q
+    // = 0, 1; this half-wave reads row (h, jj) for q = h ("own") and q = 1-h.
+    const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+    // W > 1: the wave's gadget level is fixed, so both rows are loaded now
+    // and arrive while the digits are transformed.
+    uint64_t kpre[W > 1 ? 64 : 1];
+    if constexpr (W > 1) {
+      const gmem_u64* ko = step_key + (size_t)((h * 3 + wave) * 2 + h) * RING_N + l * 2;
+      const gmem_u64* kt = step_key + (size_t)((h * 3 + wave) * 2 + (1 - h)) * RING_N + l * 2;
+#pragma unroll
+      for (int sp = 0; sp < 16; ++sp) {
+        kpre[4 * sp + 0] = ko[sp * 64];
+        kpre[4 * sp + 1] = ko[sp * 64 + 1];
+        kpre[4 * sp + 2] = kt[sp * 64];
+        kpre[4 * sp + 3] = kt[sp * 64 + 1];
+      }
+    }
     uint64_t outv[32];
 #pragma nounroll
     for (int jj = (W == 1 ? 0 : wave); jj < (W == 1 ? 3 : wave + 1); ++jj) {
@@ -218,15 +248,26 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
       uint64_t f[32];
       ntt_fwd_digits(dg, f, buf, opaque(tw_f), l);
 
+      // W == 1: the rows of this level, loaded where they are used
       const int row = h * 3 + jj;
-      const uint64_t* k_own = step_key + (size_t)(row * 2 + h) * RING_N;
-      const uint64_t* k_oth = step_key + (size_t)(row * 2 + (1 - h)) * RING_N;
+      const gmem_u64* k_own = step_key + (size_t)(row * 2 + h) * RING_N + l * 2;
+      const gmem_u64* k_oth = step_key + (size_t)(row * 2 + (1 - h)) * RING_N + l * 2;
 #pragma unroll
       for (int sp = 0; sp < 16; ++sp) {
-        const ulonglong2 ko = *reinterpret_cast<const ulonglong2*>(k_own + sp * 64 + l * 2);
-        const ulonglong2 kt = *reinterpret_cast<const ulonglong2*>(k_oth + sp * 64 + l * 2);
-        const uint64_t x0 = gl_mul(f[2 * sp], ko.x), x1 = gl_mul(f[2 * sp + 1], ko.y);
-        const uint64_t y0 = gl_mul(f[2 * sp], kt.x), y1 = gl_mul(f[2 * sp + 1], kt.y);
+        uint64_t k0, k1, k2, k3;
+        if constexpr (W > 1) {
+          k0 = kpre[4 * sp];
+          k1 = kpre[4 * sp + 1];
+          k2 = kpre[4 * sp + 2];
+          k3 = kpre[4 * sp + 3];
+        } else {
+          k0 = k_own[sp * 64];
+          k1 = k_own[sp * 64 + 1];
+          k2 = k_oth[sp * 64];
+          k3 = k_oth[sp * 64 + 1];
+        }
+        const uint64_t x0 = gl_mul(f[2 * sp], k0), x1 = gl_mul(f[2 * sp + 1], k1);
+        const uint64_t y0 = gl_mul(f[2 * sp], k2), y1 = gl_mul(f[2 * sp + 1], k3);
         const uint64_t t0 = gl_add(x0, from_other_half(y0, lane));
         const uint64_t t1 = gl_add(x1, from_other_half(y1, lane));
         if (W == 1 && jj > 0) {
