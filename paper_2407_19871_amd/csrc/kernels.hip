@@ -8,9 +8,10 @@
 //   that component in registers.  Each step i:
 //     1. D_h = X^{a_i} ACC_h - ACC_h via this half's LDS block;
 //     2. for each gadget level j: digits of D_h -> forward NTT (first stage
-//        fused with the digit extraction) -> multiply by BSK_i[(h, j)][q]
-//        for q = h and q = 1-h; the q = 1-h products cross to the other
-//        half (lane ^ 32) so half h accumulates output component q = h;
+//        fused with the digit extraction); the transform crosses to the
+//        other half (lane ^ 32), and half h accumulates output component h
+//        = NTT(d_(h,j)) BSK_i[(h,j)][h] + NTT(d_(1-h,j)) BSK_i[(1-h,j)][h]
+//        with one modular reduction per coefficient;
 //     3. inverse NTT of the accumulated component, centred lift mod 2^32,
 //        ACC_h += result.
 //   The bootstrapping key is streamed from global memory in the NTT
@@ -153,11 +154,10 @@ __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restri
 // Blind rotation.  W waves cooperate on one bootstrap:
 //   W = 1: the wave runs the three gadget levels in turn (throughput mode:
 //          independent bootstraps fill the GPU);
-//   W = 3: wave w runs gadget level w; waves 1 and 2 hand their partial
-//          products to wave 0 through their own transpose blocks, 16 slots
-//          at a time; wave 0 runs the inverse NTT and updates the
-//          accumulator (latency mode for narrow circuit levels; 35 KB of LDS,
-//          so four bootstraps fit one CU).
+//   W = 3: wave w runs gadget level w and the inverse NTT of that level's
+//          partial product, and adds its lifted partial into the LDS
+//          accumulator with LDS atomics (latency mode for narrow circuit
+//          levels; 35 KB of LDS, so four bootstraps fit one CU).
 // The accumulator lives in LDS ([component][coefficient] u32); each level
 // re-reads it to form X^a ACC - ACC.
 template <int W>
@@ -214,14 +214,16 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     if (a == 0) continue;  // X^0 ACC - ACC = 0 decomposes to zero digits
 
     // BSK_i in the NTT domain: rows (p, j) = 3p + j, each with components q
-    // = 0, 1; this half-wave reads row (h, jj) for q = h ("own") and q = 1-h.
+    // = 0, 1.  Output component h of level j is
+    //   NTT(d_(h,j)) BSK[(h,j)][h] + NTT(d_(1-h,j)) BSK[(1-h,j)][h],
+    // so this half-wave reads component h of rows (h, j) and (1-h, j).
     const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
     // W > 1: the wave's gadget level is fixed, so both rows are loaded now
     // and arrive while the digits are transformed.
     uint64_t kpre[W > 1 ? 64 : 1];
     if constexpr (W > 1) {
       const gmem_u64* ko = step_key + (size_t)((h * 3 + wave) * 2 + h) * RING_N + l * 2;
-      const gmem_u64* kt = step_key + (size_t)((h * 3 + wave) * 2 + (1 - h)) * RING_N + l * 2;
+      const gmem_u64* kt = step_key + (size_t)(((1 - h) * 3 + wave) * 2 + h) * RING_N + l * 2;
 #pragma unroll
       for (int sp = 0; sp < 16; ++sp) {
         kpre[4 * sp + 0] = ko[sp * 64];
@@ -245,13 +247,14 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
         const uint32_t D = ((e & 1024u) ? (0u - v) : v) - acc[j];
         dg[m] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
       }
+      // W > 1: every wave has read the accumulator before any adds to it
+      if constexpr (W > 1) __syncthreads();
       uint64_t f[32];
       ntt_fwd_digits(dg, f, buf, opaque(tw_f), l);
 
       // W == 1: the rows of this level, loaded where they are used
-      const int row = h * 3 + jj;
-      const gmem_u64* k_own = step_key + (size_t)(row * 2 + h) * RING_N + l * 2;
-      const gmem_u64* k_oth = step_key + (size_t)(row * 2 + (1 - h)) * RING_N + l * 2;
+      const gmem_u64* k_own = step_key + (size_t)((h * 3 + jj) * 2 + h) * RING_N + l * 2;
+      const gmem_u64* k_oth = step_key + (size_t)(((1 - h) * 3 + jj) * 2 + h) * RING_N + l * 2;
 #pragma unroll
       for (int sp = 0; sp < 16; ++sp) {
         uint64_t k0, k1, k2, k3;
@@ -266,10 +269,10 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
           k2 = k_oth[sp * 64];
           k3 = k_oth[sp * 64 + 1];
         }
-        const uint64_t x0 = gl_mul(f[2 * sp], k0), x1 = gl_mul(f[2 * sp + 1], k1);
-        const uint64_t y0 = gl_mul(f[2 * sp], k2), y1 = gl_mul(f[2 * sp + 1], k3);
-        const uint64_t t0 = gl_add(x0, from_other_half(y0, lane));
-        const uint64_t t1 = gl_add(x1, from_other_half(y1, lane));
+        // the other half holds the same level's transform of component 1-h
+        const uint64_t g0 = from_other_half(f[2 * sp], lane), g1 = from_other_half(f[2 * sp + 1], lane);
+        const uint64_t t0 = gl_mul_sum(f[2 * sp], k0, g0, k2);
+        const uint64_t t1 = gl_mul_sum(f[2 * sp + 1], k1, g1, k3);
         if (W == 1 && jj > 0) {
           outv[2 * sp] = gl_add(outv[2 * sp], t0);
           outv[2 * sp + 1] = gl_add(outv[2 * sp + 1], t1);
@@ -281,31 +284,13 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     }
 
     if constexpr (W > 1) {
-      // hand-off of 16 slots at a time through the helpers' transpose blocks
-      // (2 x 1056 words >= 16 slots x 64 lanes x 2 words)
+      // Each wave inverts its own level's partial product.  A partial is an
+      // exact integer polynomial (|coefficient| < 2^49 < p/2), so its centred
+      // lift mod 2^32 is exact, and adding the lifted partials of the W
+      // levels in LDS gives the lift of their sum.
+      ntt_inv(outv, buf, opaque(tw_i), l);
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        if (wave > 0) {
-          uint64_t* part = reinterpret_cast<uint64_t*>(s_tr[wave][0]);
-#pragma unroll
-          for (int s = 0; s < 16; ++s) part[s * 64 + lane] = outv[half * 16 + s];
-        }
-        __syncthreads();
-        if (wave == 0) {
-#pragma unroll
-          for (int w = 1; w < W; ++w) {
-            const uint64_t* part = reinterpret_cast<const uint64_t*>(s_tr[w][0]);
-#pragma unroll
-            for (int s = 0; s < 16; ++s) outv[half * 16 + s] = gl_add(outv[half * 16 + s], part[s * 64 + lane]);
-          }
-        }
-        __syncthreads();
-      }
-      if (wave == 0) {
-        ntt_inv(outv, buf, opaque(tw_i), l);
-#pragma unroll
-        for (int m = 0; m < 32; ++m) acc[l + 32 * m] += gl_lift_u32(outv[m]);
-      }
+      for (int m = 0; m < 32; ++m) atomicAdd(&acc[l + 32 * m], gl_lift_u32(outv[m]));
       __syncthreads();
     } else {
       ntt_inv(outv, buf, opaque(tw_i), l);
