@@ -169,6 +169,12 @@ lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_que
 /* Bootstraps, key switches and depth levels of that circuit. */
 lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,
                          uint32_t* n_levels);
+/* Blind rotations per depth level of that circuit as the library schedules
+ * it (signed shape; every gate as late as its consumers allow, so that the
+ * comparator XNORs share the MUX levels).  widths: host array of *n_levels
+ * entries on input; *n_levels receives the depth (entries beyond the
+ * array are not written). */
+lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t m, uint32_t* widths, uint32_t* n_levels);
 
 /* ---- query server (continuous batching) ------------------------------------
  * Serves bounding-box queries from many clients, each request bringing its

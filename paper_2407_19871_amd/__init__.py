@@ -113,6 +113,7 @@ def lib() -> C.CDLL:
         "lp_eval_bbox_query": (i32, [vp, C.POINTER(BBoxQuery), vp, vp]),
         "lp_eval_bbox_batch": (i32, [C.POINTER(vp), C.POINTER(BBoxQuery), sz, C.POINTER(vp), vp]),
         "lp_bbox_counts": (i32, [u32, u32, u32, C.POINTER(u64), C.POINTER(u64), C.POINTER(u32)]),
+        "lp_bbox_level_widths": (i32, [u32, u32, u32, C.POINTER(u32), C.POINTER(u32)]),
         "lp_debug_negacyclic_mul": (i32, [vp, vp, sz, vp, vp]),
         "lp_debug_blind_rotate": (i32, [vp, vp, sz, u32, vp, vp]),
         "lp_profile_enable": (i32, [i32]),
@@ -248,6 +249,15 @@ def bbox_counts(l: int, n_boxes: int, m: int):
     br, ks, lv = C.c_uint64(), C.c_uint64(), C.c_uint32()
     _check(lib().lp_bbox_counts(l, n_boxes, m, C.byref(br), C.byref(ks), C.byref(lv)))
     return int(br.value), int(ks.value), int(lv.value)
+
+
+def bbox_level_widths(l: int, n_boxes: int, m: int) -> list:
+    """Blind rotations per depth level as the library schedules the circuit."""
+    n = C.c_uint32(0)
+    _check(lib().lp_bbox_level_widths(l, n_boxes, m, None, C.byref(n)))
+    arr = (C.c_uint32 * max(1, n.value))()
+    _check(lib().lp_bbox_level_widths(l, n_boxes, m, arr, C.byref(n)))
+    return [int(arr[k]) for k in range(n.value)]
 
 
 # ------------------------------------------------------------------ device side

@@ -147,6 +147,26 @@ std::shared_ptr<const Plan> make_plan(uint32_t l, uint32_t N, uint32_t m, int is
   P->n_slots = (uint32_t)C.n_slots;
   int depth = 0;
   for (auto& g : C.gates) depth = std::max(depth, g.level);
+  // As late as possible: a gate runs at depth + 1 - (longest path from it to
+  // an output, in gates).  The depth is unchanged and every producer stays
+  // at a lower level than its consumers, but gates off the critical path
+  // move next to their consumers: XNOR of comparator bit i joins the level
+  // of the MUX of bit i-1 instead of piling up at level 1, so no level is
+  // wider than it needs to be.  Gates are stored in topological order.
+  {
+    std::vector<int> producer((size_t)C.n_slots, -1);
+    for (size_t k = 0; k < C.gates.size(); ++k) producer[(size_t)C.gates[k].out] = (int)k;
+    std::vector<int> height(C.gates.size(), 1);
+    for (size_t k = C.gates.size(); k-- > 0;) {
+      const Gate& g = C.gates[k];
+      for (int r = 0; r < (g.kind == LP_GATE_MUX ? 3 : 2); ++r) {
+        if (g.in[r].slot < 0) continue;
+        const int pk = producer[(size_t)g.in[r].slot];
+        if (pk >= 0) height[(size_t)pk] = std::max(height[(size_t)pk], height[k] + 1);
+      }
+    }
+    for (size_t k = 0; k < C.gates.size(); ++k) C.gates[k].level = depth + 1 - height[k];
+  }
   P->br.resize(depth);
   P->ks.resize(depth);
   auto put = [](BrJob& j, int which, const CRef& r, int32_t coef) {
@@ -527,6 +547,17 @@ extern "C" lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, ui
                                     uint32_t* n_levels) {
   if (l == 0 || l > 64 || n_boxes == 0 || m == 0) return lp::fail(LP_EINVAL, "lp_bbox_counts: empty shape");
   lp::plan_counts(l, n_boxes, m, n_br, n_ks, n_levels);
+  return LP_OK;
+}
+
+extern "C" lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t m, uint32_t* widths,
+                                          uint32_t* n_levels) {
+  if (l == 0 || l > 64 || n_boxes == 0 || m == 0) return lp::fail(LP_EINVAL, "lp_bbox_level_widths: empty shape");
+  if (!n_levels || (*n_levels > 0 && !widths)) return lp::fail(LP_EINVAL, "lp_bbox_level_widths: null argument");
+  auto P = lp::get_plan(l, n_boxes, m, 1);
+  const uint32_t depth = (uint32_t)P->levels();
+  for (uint32_t k = 0; k < depth && k < *n_levels; ++k) widths[k] = (uint32_t)P->br[k].size();
+  *n_levels = depth;
   return LP_OK;
 }
 

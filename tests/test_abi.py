@@ -76,6 +76,40 @@ def test_plan_counts_match_oracle_walk(l, N, m):
     assert lp.bbox_counts(l, N, m) == (br, ks, depth)
 
 
+@pytest.mark.parametrize("l,N,m", [(8, 1, 8), (16, 16, 32), (13, 8, 9), (32, 4, 3)])
+def test_level_widths_schedule(l, N, m):
+    """Gates are scheduled as late as their consumers allow: the depth and
+    gate counts are those of the circuit, and comparator bit i's XNOR shares
+    the level of the MUX of bit i-1 (the MUX of a two-bootstrap gate).  With
+    a power-of-two box count every box sits at the same depth."""
+    w = lp.bbox_level_widths(l, N, m)
+    br, _, depth = lp.bbox_counts(l, N, m)
+    assert len(w) == depth and sum(w) == br and min(w) > 0
+    per_bit = 4 * N  # comparators
+    assert w[0] == per_bit  # XNOR of bit 0 only
+    assert w[1:l] == [3 * per_bit] * (l - 1)  # MUX of bit i-1 (2 bootstraps) + XNOR of bit i
+    assert w[l] == 2 * per_bit  # MUX of the MSB
+    assert w[l + 1:l + 4] == [2 * N, N, N * m]  # validation ANDs, bitwiseAND
+    tree, cur = [], N
+    while cur > 1:
+        tree.append((cur // 2) * m)
+        cur = (cur + 1) // 2
+    assert w[l + 4:] == tree
+
+
+@pytest.mark.parametrize("l,N,m", [(13, 9, 9), (32, 5, 3), (16, 3, 32)])
+def test_level_widths_ragged_box_count(l, N, m):
+    """An odd box count carries a box's products past XOR rounds, and that
+    box's comparators move later with them: the first level holds fewer
+    XNORs, the total and the depth are unchanged, and no level is wider
+    than all boxes' MUX and XNOR work together."""
+    w = lp.bbox_level_widths(l, N, m)
+    br, _, depth = lp.bbox_counts(l, N, m)
+    assert len(w) == depth and sum(w) == br and min(w) > 0
+    assert w[0] < 4 * N
+    assert max(w) <= max(3 * 4 * N, N * m)
+
+
 def test_error_paths_do_not_throw():
     p = lp.params_default()
     bad = lp.Params(p.n, 1000, 1, 7, 3, 2, 8, p.lwe_sigma, p.bk_sigma)  # N not a power of two
