@@ -82,9 +82,24 @@ def cpu_baseline(seed: int):
     _, th2 = ctx.gate_batch("MUX", ct[o:o + nm], ct[o + nm:o + 2 * nm], ct[o + 2 * nm:o + 3 * nm])
     dt = time.perf_counter() - t0
     n_br = nx + 2 * nm
+    # one thread: the oracle's single-gate entry, 8 XNOR + 4 MUX gates
+    t0 = time.perf_counter()
+    for k in range(8):
+        ctx.gate("XNOR", ct[k], ct[nx + k])
+    for k in range(4):
+        ctx.gate("MUX", ct[o + k], ct[o + nm + k], ct[o + 2 * nm + k])
+    dt1 = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(n_br / dt, 2), "unit": "bootstraps/s", "cores": int(max(th1, th2)), "kind": "oracle",
             "sample": f"{nx} XNOR + {nm} MUX gates = {n_br} bootstraps with key switching, "
-                      f"same parameters, {dt:.1f} s", "host_cpus": os.cpu_count()}
+                      f"same parameters, {dt:.1f} s", "host_cpus": os.cpu_count(), "cpu_model": model,
+            "single_core": {"value": round(16 / dt1, 2), "unit": "bootstraps/s",
+                            "sample": f"8 XNOR + 4 MUX gates = 16 bootstraps on one thread, {dt1:.1f} s"}}
 
 
 def microbench(lp, torch, sk, dk, sizes=(1, 64, 1024, 16384)):
@@ -175,6 +190,7 @@ def serve_bench(requests_per_rate: int, seed: int = 5):
 
     burst = [make_request(i) for i in range(requests_per_rate)]
     sat = run(burst, [0.0] * len(burst))
+    print(f"serve: burst done, {sat['queries_per_s']} queries/s", file=sys.stderr, flush=True)
     res = {"metric": "serving: p50/p99 latency and queries/s under Poisson arrivals on 1 MI355X",
            "saturated": sat, "rates": []}
     for k, f in enumerate((0.25, 0.5, 0.75, 0.95)):
@@ -182,6 +198,7 @@ def serve_bench(requests_per_rate: int, seed: int = 5):
         lam = f * sat["queries_per_s"]
         arr = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
         r = run(reqs, list(arr))
+        print(f"serve: rate {f} done, p50 {r['p50_ms']} ms", file=sys.stderr, flush=True)
         r["offered_fraction"] = f
         r["offered_queries_per_s"] = round(lam, 3)
         res["rates"].append(r)
