@@ -122,6 +122,7 @@ def microbench(lp, torch, sk, dk, sizes=(1, 64, 1024, 16384)):
         d, _ = sk.decrypt_bits(lp.to_host(out))
         assert (d == 1 - (bits[:B] & bits[B:])).all()
         res[str(B)] = round(B / dt, 1)
+        print(f"bench: NAND batch {B}: {res[str(B)]} bootstraps/s", file=sys.stderr, flush=True)
     # one bootstrap per launch: 16 single-gate launches back to back
     ct = sk.encrypt_bits(rng.integers(0, 2, 32).astype(np.uint8), seed=99)
     cs = [(lp.to_device(ct[k:k + 1]), lp.to_device(ct[16 + k:17 + k])) for k in range(16)]
@@ -349,6 +350,7 @@ def main():
         t0 = time.perf_counter()
         rows = lp.autotune(dk, buckets=TUNE_BUCKETS, br_steps=64)
         tune = {"seconds": round(time.perf_counter() - t0, 2), "br_steps_timed": 64, "rows": rows}
+        print(f"bench: autotune done in {tune['seconds']} s", file=sys.stderr, flush=True)
     out = torch.empty((m, 631), dtype=torch.int32, device="cuda")
 
     def step():
@@ -374,6 +376,7 @@ def main():
     wall = time.perf_counter() - t0
     stats = lp.profile_collect()
     lp.profile_enable(False)
+    print(f"bench: {args.steps} queries timed, {wall * 1e3 / args.steps:.1f} ms each", file=sys.stderr, flush=True)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
 
     br = stats.get("blind_rotate", {"launches": 0, "jobs": 0, "total_ms": 0.0})
