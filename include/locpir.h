@@ -284,6 +284,9 @@ typedef struct {
  * blind rotation cut to br_steps (1..n) key bits (the per-step cost does not
  * depend on the bit); installs the fastest shapes as the device's table and
  * writes the rows, sorted by jobs, to out (nbuckets entries, may be NULL).
+ * A key-switch shape is scored together with the blind rotation launched
+ * after it: in a circuit every key switch is followed by one, and the shape
+ * can change that rotation's time through the cache state it leaves.
  * Synchronous on `stream`.  Cached query programs are dropped so that later
  * queries launch with the new shapes. */
 lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket_jobs, int nbuckets, uint32_t br_steps,

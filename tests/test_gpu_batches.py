@@ -40,3 +40,21 @@ def test_mux_batch_ragged(okeys, octx, dkey):
     exp, _ = octx.gate_batch("MUX", cs, ct, cf)
     assert (got == exp).all()
     assert (bits_of(okeys, got)[0] == np.where(s == 1, t, f)).all()
+
+
+def test_nand_batch_full_size_sampled(okeys, octx, dkey):
+    """The batched microbenchmark's largest launch (16384 NAND gates, one
+    shared key): every output decrypts to the truth table, and 32 sampled
+    outputs equal the oracle's gates bit for bit."""
+    B = 16384
+    a = W.random_bits(5001, B)
+    b = W.random_bits(5002, B)
+    c1 = O.encrypt_bits(okeys, a, seed=5003)
+    c2 = O.encrypt_bits(okeys, b, seed=5004)
+    got = as_u32(lp.bootstrap_batch(dkey, "NAND", lp.to_device(c1), lp.to_device(c2)))
+    d, ph = bits_of(okeys, got)
+    assert (d == 1 - (a & b)).all()
+    assert np.abs(np.abs(ph.astype(np.int64)) - 2**29).max() < 2**28
+    idx = np.random.default_rng(5005).choice(B, 32, replace=False)
+    exp, _ = octx.gate_batch("NAND", c1[idx], c2[idx])
+    assert (got[idx] == exp).all()
