@@ -41,6 +41,7 @@ KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd
                   "paper_2407_19871_amd/csrc/gl64.h"]
 TUNE_BUCKETS = (1, 16, 32, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16384)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_bbox16x16_traffic.txt")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_valu_issue.txt")
 
 
 def kernel_hash() -> str:
@@ -63,6 +64,18 @@ def load_traffic():
     if d.get("kernel_hash") != kernel_hash():
         return None
     return d
+
+
+def load_valu():
+    """VALU issue fractions of the blind-rotation kernel from the committed
+    rocprofv3 SQ_INSTS_VALU summary, if it was taken on this kernel."""
+    if not os.path.exists(VALU_SUMMARY):
+        return None
+    m = re.search(r"^valu_json:\s*(\{.*\})\s*$", open(VALU_SUMMARY).read(), re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    return d if d.get("kernel_hash") == kernel_hash() else None
 
 
 def cpu_baseline(seed: int):
@@ -383,6 +396,7 @@ def main():
     ks = stats.get("keyswitch", {"launches": 0, "jobs": 0, "total_ms": 0.0})
     achieved = ALG_LANE_CYCLES_PER_BR * br["jobs"] / (br["total_ms"] / 1e3) / 1e12 if br["total_ms"] else 0.0
     traffic = load_traffic()
+    valu = load_valu()
     roofline = {
         "bound": "alu", "kernel": "blind_rotate_kernel",
         "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
@@ -391,6 +405,8 @@ def main():
         "avg_launch_ms": round(br["total_ms"] / max(1, br["launches"]), 3),
         "bootstraps_per_launch": round(br["jobs"] / max(1, br["launches"]), 1),
         "op_unit": "32-bit VALU lane-cycles, 1.30e9 per bootstrap (algorithmic count)",
+        # measured: rocprofv3 SQ_INSTS_VALU x 4 cycles / (kernel time x 2.4 GHz x 1024 SIMDs)
+        "valu_issue_frac_rocprof": valu["query_valu_issue_frac"] if valu else None,
     }
 
     res = {
@@ -421,6 +437,8 @@ def main():
     }
     if not args.no_micro:
         res["microbench"] = microbench(lp, torch, sk, dk)
+        big = (valu or {}).get("launches", {}).get("1x16384")
+        res["microbench"]["valu_issue_frac_rocprof_16384"] = big["valu_issue_frac"] if big else None
         res["small_query"] = small_query(lp, torch)
     if args.copy_probe:
         src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda")
