@@ -37,23 +37,12 @@ GL_INLINE uint64_t gl_add(uint64_t a, uint64_t b) {
   return s + (c2 ? GL_EPS : 0ull);
 }
 
-// a - b.  A borrow means the true difference is d - 2^64 = d - EPS (mod p).
-// Subtracting EPS can borrow again only when d < EPS; the wrapped value is
-// then at least 2^64 - EPS and a second EPS cannot borrow.
-GL_INLINE uint64_t gl_sub(uint64_t a, uint64_t b) {
-  uint64_t d;
-  const bool b1 = __builtin_sub_overflow(a, b, &d);
-  const bool b2 = __builtin_sub_overflow(d, b1 ? GL_EPS : 0ull, &d);
-  return d - (b2 ? GL_EPS : 0ull);
-}
-
-// -a (mod p) as p - a, for a canonicalised first (a = 0 maps to 0)
+// Reduces any 64-bit value to [0, p): x >= p iff x + EPS carries.
 GL_INLINE uint64_t gl_canon(uint64_t a) {
   uint64_t t;
-  const bool c = __builtin_add_overflow(a, GL_EPS, &t);  // carries iff a >= p
+  const bool c = __builtin_add_overflow(a, GL_EPS, &t);
   return c ? t : a;
 }
-GL_INLINE uint64_t gl_neg(uint64_t a) { return gl_sub(0ull, a); }
 
 // x = lo + 2^64 hi (any 128-bit value) mod p:
 //   x = lo + 2^64 hl + 2^96 hh = lo - hh + EPS * hl   (mod p).

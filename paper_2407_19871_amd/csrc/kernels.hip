@@ -7,9 +7,9 @@
 //   1 = body B); lane l = lane % 32 holds coefficients l + 32 m, m < 32, of
 //   that component in registers.  Each step i:
 //     1. D_h = X^{a_i} ACC_h - ACC_h via this half's LDS block;
-//     2. for each gadget level j: digits of D_h -> forward NTT (first stage
-//        fused with the digit extraction); the transform crosses to the
-//        other half (lane ^ 32), and half h accumulates output component h
+//     2. for each gadget level j: digits of D_h -> forward NTT (first two
+//        stages fused with the digit extraction); the transform crosses to
+//        the other half (lane ^ 32), and half h accumulates output component h
 //        = NTT(d_(h,j)) BSK_i[(h,j)][h] + NTT(d_(1-h,j)) BSK_i[(1-h,j)][h]
 //        with one modular reduction per coefficient;
 //     3. inverse NTT of the accumulated component, centred lift mod 2^32,
@@ -108,10 +108,10 @@ __device__ __forceinline__ void ntt_fwd(uint64_t (&f)[32], uint32_t* buf, const 
   fwd2(f);
 }
 
-// The same for small signed digits, first butterfly stage fused.
+// The same for small signed digits, first two butterfly stages fused.
 __device__ __forceinline__ void ntt_fwd_digits(const int32_t (&d)[32], uint64_t (&f)[32], uint32_t* buf,
                                                const uint64_t* __restrict__ tw_f, int l) {
-  fwd1_first_stage_digits(d, f);
+  fwd1_first_stages_digits(d, f);
   fwd1_rest(f);
   twist(f, tw_f, l);
   transpose32(f, buf, l);

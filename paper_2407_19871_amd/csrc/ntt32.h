@@ -60,19 +60,29 @@ __device__ __forceinline__ void fwd1_stage(uint64_t (&a)[32]) {
   });
 }
 
-// First stage on small signed integers (gadget digits, |d| <= 64): the
-// twiddle is rho^16 = 2^48 and a +- 2^48 b is exact in 64-bit integers.
-__device__ __forceinline__ void fwd1_first_stage_digits(const int32_t (&d)[32], uint64_t (&a)[32]) {
-  static_for<0, 16>([&](auto jj) {
+// The first two stages on small signed integers (gadget digits, |d| <= 64),
+// exact in int64.  Stage 1 pairs j, j+16 with twiddle rho^16 = 2^48.  Stage
+// 2 pairs j, j+8 with 2^24 in the first half and j+16, j+24 with 2^72 in the
+// second; with 2^64 = 2^32 - 1 and 2^96 = -1 (mod p),
+//   2^24 (d1 + 2^48 d3) = 2^24 d1 + (2^40 - 2^8) d3,
+//   2^72 (d1 - 2^48 d3) = (2^40 - 2^8) d1 + 2^24 d3   (mod p),
+// so every stage-2 output is a signed integer below 2^55 in magnitude and
+// becomes a residue once.
+__device__ __forceinline__ void fwd1_first_stages_digits(const int32_t (&d)[32], uint64_t (&a)[32]) {
+  static_for<0, 8>([&](auto jj) {
     constexpr int j = decltype(jj)::value;
-    int64_t lo = d[j], hi = (int64_t)d[j + 16] * (int64_t)(1ll << 48);
-    a[j] = gl_from_i64(lo + hi);
-    a[j + 16] = gl_from_i64(lo - hi);
+    const int64_t d0 = d[j], d1 = d[j + 8], d2 = d[j + 16], d3 = d[j + 24];
+    const int64_t s0 = d0 + d2 * (1ll << 48), s1 = d0 - d2 * (1ll << 48);
+    const int64_t p = d1 * (1ll << 24) + d3 * ((1ll << 40) - (1ll << 8));
+    const int64_t q = d1 * ((1ll << 40) - (1ll << 8)) + d3 * (1ll << 24);
+    a[j] = gl_from_i64(s0 + p);
+    a[j + 8] = gl_from_i64(s0 - p);
+    a[j + 16] = gl_from_i64(s1 + q);
+    a[j + 24] = gl_from_i64(s1 - q);
   });
 }
 
 __device__ __forceinline__ void fwd1_rest(uint64_t (&a)[32]) {
-  fwd1_stage<8>(a);
   fwd1_stage<4>(a);
   fwd1_stage<2>(a);
   fwd1_stage<1>(a);
@@ -80,6 +90,7 @@ __device__ __forceinline__ void fwd1_rest(uint64_t (&a)[32]) {
 
 __device__ __forceinline__ void fwd1(uint64_t (&a)[32]) {
   fwd1_stage<16>(a);
+  fwd1_stage<8>(a);
   fwd1_rest(a);
 }
 
