@@ -282,6 +282,57 @@ def clients_bench(n_clients: int, steps: int, warmup: int, seed: int = 4):
     print(json.dumps(res), flush=True)
 
 
+def sweep_bench(reps: int = 3, seed: int = 6):
+    """The paper's experiment shapes on the GPU, 8- to 32-bit synthetic
+    queries over the Korea-like region (a continent-sized one at 8 bits), one
+    query at a time: Fig. 4a (N = 10
+    boxes, m = 9, l = 8/16/24/32), Table 2 (N = m = 9, l = 13 and 16) and a
+    sweep over N at l = 16, m = 9.  The paper's CPU times (6-core Ryzen 5
+    3500X, TFHE 1.1) are listed beside the Fig. 4a and Table 2 shapes as
+    context, not as a target."""
+    import torch
+    import paper_2407_19871_amd as lp
+    from oracle import plain
+    from paper_2407_19871_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    sk, ck = lp.keygen(None, seed)
+    dk = lp.DeviceKey(ck)
+    lp.autotune(dk, buckets=TUNE_BUCKETS, br_steps=64)
+    fig4a = {8: 3.256, 16: 6.139, 24: 8.764, 32: 11.670}  # seconds, Fig. 4a
+    table2 = {13: 4.88, 16: 5.67}                          # seconds, Table 2 (lambda 128)
+    shapes = [("fig4a", l, 10, 9, fig4a[l]) for l in (8, 16, 24, 32)]
+    shapes += [("table2", l, 9, 9, table2[l]) for l in (13, 16)]
+    shapes += [("boxes", 16, N, 9, None) for N in (1, 4, 16, 28)]
+    rows = []
+    for k, (kind, l, N, m, paper_s) in enumerate(shapes):
+        # 8-bit codes step 2 degrees: a Korea-sized tiling of 10 boxes would
+        # quantize to empty boxes, so that shape tiles a continent-sized region
+        region = W.KOREA if l >= 13 else (-60.0, 60.0, -120.0, 120.0)
+        q = W.random_query(60000 + k, l, N, m, region=region, force_inside=True)
+        xb, yb, bb, pb = q.plain_bits()
+        ct = sk.encrypt_bits(np.concatenate([xb, yb, bb, pb]), seed=61000 + k)
+        parts = [lp.to_device(a) for a in (ct[:l], ct[l:2 * l], ct[2 * l:2 * l + 4 * l * N], ct[2 * l + 4 * l * N:])]
+        out = lp.eval_bbox_query(dk, l, N, m, True, *parts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lp.eval_bbox_query(dk, l, N, m, True, *parts, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        d, _ = sk.decrypt_bits(lp.to_host(out))
+        n_br, _, levels = lp.bbox_counts(l, N, m)
+        row = {"kind": kind, "l": l, "boxes": N, "m": m, "bootstraps": n_br, "levels": levels,
+               "ms_per_query": round(dt * 1e3, 1), "bootstraps_per_s": round(n_br / dt, 1),
+               "correct_vs_predicate": bool(W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m,
+                                                                            True))}
+        if paper_s is not None:
+            row["paper_cpu_s"] = paper_s
+        rows.append(row)
+        print(f"sweep: {kind} l={l} N={N}: {row['ms_per_query']} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "paper experiment shapes: bbox query latency on 1 MI355X", "rows": rows}), flush=True)
+
+
 def small_query(lp, torch, reps: int = 5):
     """The 8-bit unsigned coordinates vs one box query with an 8-bit payload
     (107 bootstraps in 12 levels), with its own key."""
@@ -320,6 +371,8 @@ def main():
                     help="also run device copies of this many bytes (traffic calibration)")
     ap.add_argument("--serve", type=int, default=0,
                     help="serving benchmark with this many requests per arrival rate (separate JSON line)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="the paper's Fig. 4a / Table 2 query shapes and a box-count sweep (separate JSON line)")
     ap.add_argument("--clients", type=int, default=0,
                     help="fused queries of this many clients with their own keys (separate JSON line)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -335,6 +388,9 @@ def main():
         return
     if args.clients:
         clients_bench(args.clients, args.steps, args.warmup)
+        return
+    if args.sweep:
+        sweep_bench()
         return
 
     import torch

@@ -34,8 +34,8 @@ def quantize(deg: float, l: int) -> int:
         v = math.floor(deg * 128.0)
     elif l == 32:
         v = math.floor(deg * 1e6)
-    else:
-        v = math.floor(deg * (1 << (l - 9)))
+    else:  # 9 integer bits (signed degrees), l - 9 fraction bits; fewer than 9 bits scale down
+        v = math.floor(deg * 2.0 ** (l - 9))
     lo, hi = -(1 << (l - 1)), (1 << (l - 1)) - 1
     if not lo <= v <= hi:
         raise ValueError(f"{deg} does not fit {l}-bit fixed point")
