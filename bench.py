@@ -286,8 +286,9 @@ def sweep_bench(reps: int = 3, seed: int = 6):
     """The paper's experiment shapes on the GPU, 8- to 32-bit synthetic
     queries over the Korea-like region (a continent-sized one at 8 bits), one
     query at a time: Fig. 4a (N = 10
-    boxes, m = 9, l = 8/16/24/32), Table 2 (N = m = 9, l = 13 and 16) and a
-    sweep over N at l = 16, m = 9.  The paper's CPU times (6-core Ryzen 5
+    boxes, m = 9, l = 8/16/24/32), Table 2 (N = m = 9, l = 13 and 16, under
+    both the lambda 128 and the lambda 80 parameter sets) and a sweep over N
+    at l = 16, m = 9.  The paper's CPU times (6-core Ryzen 5
     3500X, TFHE 1.1) are listed beside the Fig. 4a and Table 2 shapes as
     context, not as a target."""
     import torch
@@ -296,16 +297,19 @@ def sweep_bench(reps: int = 3, seed: int = 6):
     from paper_2407_19871_amd import workloads as W
 
     torch.cuda.set_device(0)
-    sk, ck = lp.keygen(None, seed)
-    dk = lp.DeviceKey(ck)
-    lp.autotune(dk, buckets=TUNE_BUCKETS, br_steps=64)
+    keys = {}
+    for name, params in (("lambda128", None), ("lambda80", lp.params_lambda80())):
+        sk, ck = lp.keygen(params, seed)
+        keys[name] = (sk, lp.DeviceKey(ck))
+    lp.autotune(keys["lambda128"][1], buckets=TUNE_BUCKETS, br_steps=64)
     fig4a = {8: 3.256, 16: 6.139, 24: 8.764, 32: 11.670}  # seconds, Fig. 4a
-    table2 = {13: 4.88, 16: 5.67}                          # seconds, Table 2 (lambda 128)
-    shapes = [("fig4a", l, 10, 9, fig4a[l]) for l in (8, 16, 24, 32)]
-    shapes += [("table2", l, 9, 9, table2[l]) for l in (13, 16)]
-    shapes += [("boxes", 16, N, 9, None) for N in (1, 4, 16, 28)]
+    table2 = {"lambda128": {13: 4.88, 16: 5.67}, "lambda80": {13: 4.36, 16: 5.12}}  # seconds, Table 2
+    shapes = [("fig4a", "lambda128", l, 10, 9, fig4a[l]) for l in (8, 16, 24, 32)]
+    shapes += [("table2", ps, l, 9, 9, table2[ps][l]) for ps in ("lambda128", "lambda80") for l in (13, 16)]
+    shapes += [("boxes", "lambda128", 16, N, 9, None) for N in (1, 4, 16, 28)]
     rows = []
-    for k, (kind, l, N, m, paper_s) in enumerate(shapes):
+    for k, (kind, ps, l, N, m, paper_s) in enumerate(shapes):
+        sk, dk = keys[ps]
         # 8-bit codes step 2 degrees: a Korea-sized tiling of 10 boxes would
         # quantize to empty boxes, so that shape tiles a continent-sized region
         region = W.KOREA if l >= 13 else (-60.0, 60.0, -120.0, 120.0)
@@ -322,14 +326,14 @@ def sweep_bench(reps: int = 3, seed: int = 6):
         dt = (time.perf_counter() - t0) / reps
         d, _ = sk.decrypt_bits(lp.to_host(out))
         n_br, _, levels = lp.bbox_counts(l, N, m)
-        row = {"kind": kind, "l": l, "boxes": N, "m": m, "bootstraps": n_br, "levels": levels,
+        row = {"kind": kind, "params": ps, "l": l, "boxes": N, "m": m, "bootstraps": n_br, "levels": levels,
                "ms_per_query": round(dt * 1e3, 1), "bootstraps_per_s": round(n_br / dt, 1),
                "correct_vs_predicate": bool(W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m,
                                                                             True))}
         if paper_s is not None:
             row["paper_cpu_s"] = paper_s
         rows.append(row)
-        print(f"sweep: {kind} l={l} N={N}: {row['ms_per_query']} ms", file=sys.stderr, flush=True)
+        print(f"sweep: {kind} {ps} l={l} N={N}: {row['ms_per_query']} ms", file=sys.stderr, flush=True)
     print(json.dumps({"metric": "paper experiment shapes: bbox query latency on 1 MI355X", "rows": rows}), flush=True)
 
 

@@ -63,6 +63,9 @@ class Params:
 
 
 DEFAULT = Params()
+# The paper's lambda 80 set as read here (Table 2 gives only n = 540 and
+# sigma = 2^-20.2; ring, gadget and key-switching parameters as in DEFAULT).
+LAMBDA80 = Params(n=540, lwe_sigma=2.0 ** -20.2)
 
 
 def lib():

@@ -157,6 +157,15 @@ def params_default() -> Params:
     return p
 
 
+def params_lambda80() -> Params:
+    """The paper's lambda 80 set (Table 2: n = 540, sigma = 2^-20.2); the
+    ring, gadget and key-switching parameters are those of the default set."""
+    p = params_default()
+    p.n = 540
+    p.lwe_sigma = 2.0 ** -20.2
+    return p
+
+
 def bsk_words(p: Params) -> int:
     return int(lib().lp_bsk_words(C.byref(p)))
 

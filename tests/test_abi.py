@@ -50,6 +50,19 @@ def test_keygen_matches_oracle_bit_for_bit(pkeys, okeys):
     assert (ksk == okeys.ksk).all()
 
 
+def test_keygen_lambda80_matches_oracle_bit_for_bit():
+    """The lambda 80 set (n = 540): keys and encryptions equal the oracle's."""
+    sk, ck = lp.keygen(lp.params_lambda80(), 4)
+    ok = O.keygen(4, O.LAMBDA80)
+    s, S = sk.export()
+    bsk, ksk = ck.export()
+    assert len(s) == 540 and (s == ok.s_lwe).all() and (S == ok.s_ring).all()
+    assert (bsk == ok.bsk).all() and (ksk == ok.ksk).all()
+    bits = np.random.default_rng(5).integers(0, 2, 64).astype(np.uint8)
+    ct = sk.encrypt_bits(bits, seed=6)
+    assert ct.shape == (64, 541) and (ct == O.encrypt_bits(ok, bits, seed=6)).all()
+
+
 def test_encrypt_matches_oracle_and_decrypts(pkeys, okeys):
     sk, _ = pkeys
     bits = np.random.default_rng(3).integers(0, 2, 300).astype(np.uint8)

@@ -5,6 +5,8 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import plain
+from paper_2407_19871_amd import workloads as W
 
 P = O.DEFAULT
 Q32 = 2**32
@@ -197,3 +199,35 @@ def test_bootstrap_noise_matches_model(okeys, octx):
     err = ph.astype(np.int64) - np.where(bits == 1, 2**29, -(2**29))
     ratio = err.std() / model
     assert 0.5 < ratio < 2.0, ratio
+
+
+@pytest.fixture(scope="module")
+def okeys80():
+    k = O.keygen(8, O.LAMBDA80)
+    return k, O.Ctx(k)
+
+
+def test_lambda80_gates_and_query(okeys80):
+    """The lambda 80 set (n = 540): every two-input gate on all input pairs
+    and a MUX on all triples decrypt to their truth tables within the phase
+    bound, and a small query decrypts to the plaintext predicate."""
+    keys, ctx = okeys80
+    pairs = [(a, b) for a in (0, 1) for b in (0, 1)]
+    c1 = O.encrypt_bits(keys, [a for a, _ in pairs], seed=81)
+    c2 = O.encrypt_bits(keys, [b for _, b in pairs], seed=82)
+    for gate, f in TRUTH.items():
+        out, _ = ctx.gate_batch(gate, c1, c2)
+        d, ph = O.decrypt_bits(keys, out)
+        assert list(d) == [f(a, b) for a, b in pairs], gate
+        assert np.abs(np.abs(ph.astype(np.int64)) - 2**29).max() < 2**28
+    trip = [(s, t, f) for s in (0, 1) for t in (0, 1) for f in (0, 1)]
+    cs, ct, cf = (O.encrypt_bits(keys, [v[i] for v in trip], seed=83 + i) for i in range(3))
+    out, _ = ctx.gate_batch("MUX", cs, ct, cf)
+    assert list(O.decrypt_bits(keys, out)[0]) == [t if s else f for s, t, f in trip]
+    q = W.random_query(84, 13, 2, 3, force_inside=True)
+    xb, yb, bb, pb = q.plain_bits()
+    cts = O.encrypt_bits(keys, np.concatenate([xb, yb, bb, pb]), seed=85)
+    l, N = q.l, q.n_boxes
+    res = ctx.bbox_query(l, N, q.m, True, cts[:l], cts[l:2 * l], cts[2 * l:2 * l + 4 * l * N], cts[2 * l + 4 * l * N:])
+    d, _ = O.decrypt_bits(keys, res)
+    assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, q.m, True)
