@@ -106,6 +106,12 @@ size_t lp_ksk_words(const lp_params* P);
  * (seed, first_index + k).  ct: cnt*(n+1) uint32, host. */
 lp_status lp_encrypt_bits(const lp_secret_key* sk, const uint8_t* bits, size_t cnt, uint64_t seed,
                           uint64_t first_index, uint32_t* ct);
+/* The client's fresh samples of Sec. 3, sent once with PK: LWE encryptions
+ * of the torus value 0, ct[k] = (a, <a,s> + e) drawn from (seed,
+ * first_index + k) on streams of their own.  The cloud turns them into
+ * encrypted services with lp_preprocess.  ct: cnt*(n+1) uint32, host. */
+lp_status lp_encrypt_zeros(const lp_secret_key* sk, size_t cnt, uint64_t seed, uint64_t first_index, uint32_t* ct);
+
 /* Decrypt(ct, K) of Sec. 2.3: bit = sign of the phase b - <a,s>.  phase may
  * be NULL; otherwise it receives the signed phase (int32 Torus32). */
 lp_status lp_decrypt_bits(const lp_secret_key* sk, const uint32_t* ct, size_t cnt, uint8_t* bits,
@@ -165,6 +171,27 @@ lp_status lp_eval_bbox_query(const lp_device_key* dk, const lp_bbox_query* q, ui
  * environment variable LOCPIR_GRAPHS=0 to launch the kernels directly. */
 lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
                              uint32_t* const* d_outs, void* stream);
+
+/* Preprocess (Algorithm 1), cloud side: the cloud encrypts its plaintext
+ * service bits S_i[j] without the secret key by adding the trivial sample
+ * (0, f(bit)) to one of the client's fresh samples of zero each:
+ * d_out[k] = d_zero[k] + (0, f(d_bits[k])), f(nonzero) = +1/8 and
+ * f(0) = -1/8, the encoding of Encrypt.  d_zero, d_out: cnt*(n+1) uint32;
+ * d_bits: cnt bytes; all on the key's device.  d_out may equal d_zero.  An
+ * all-zero d_zero gives noiseless trivial samples, which is how the cloud
+ * enters its own plaintext box bounds.  cnt = 0 is a no-op. */
+lp_status lp_preprocess(const lp_device_key* dk, const uint32_t* d_zero, const uint8_t* d_bits, size_t cnt,
+                        uint32_t* d_out, void* stream);
+
+/* Bytes the protocol of Sec. 3 moves for one query shape, ciphertexts as
+ * cnt*(n+1) little-endian uint32 words with no header (the sizes Sec. 5
+ * reports): one LWE sample; PK (bootstrapping and key-switching keys in
+ * Torus32 form); the n_boxes*m fresh samples for the services; one encrypted
+ * coordinate (l samples); the query (x and y); the result (m samples). */
+typedef struct {
+  size_t lwe_sample, public_key, service_samples, coordinate, query, result;
+} lp_wire_bytes;
+lp_status lp_bbox_wire_bytes(const lp_params* P, uint32_t l, uint32_t n_boxes, uint32_t m, lp_wire_bytes* out);
 
 /* Bootstraps, key switches and depth levels of that circuit. */
 lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,

@@ -91,6 +91,7 @@ def lib():
     L.orc_gauss_torus.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_double]
     L.orc_keygen.argtypes = [P, C.c_uint64, u8p, u8p, u32p, u32p]
     L.orc_encrypt_bits.argtypes = [P, u8p, u8p, C.c_size_t, C.c_uint64, C.c_uint64, u32p]
+    L.orc_encrypt_zeros.argtypes = [P, u8p, C.c_size_t, C.c_uint64, C.c_uint64, u32p]
     L.orc_decrypt_bits.argtypes = [P, u8p, u32p, C.c_size_t, u8p, i32p]
     L.orc_phase.restype = C.c_uint32
     L.orc_phase.argtypes = [C.c_uint32, u8p, u32p]
@@ -212,6 +213,31 @@ def encrypt_bits(keys: Keys, bits, seed: int, first_index: int = 0) -> np.ndarra
     ct = np.zeros((len(bits), P.n + 1), np.uint32)
     lib().orc_encrypt_bits(C.byref(P.c()), keys.s_lwe, bits, len(bits), seed, first_index, ct)
     return ct
+
+
+def encrypt_zeros(keys: Keys, cnt: int, seed: int, first_index: int = 0) -> np.ndarray:
+    """The client's fresh samples of Sec. 3: encryptions of the torus value 0."""
+    P = keys.params
+    ct = np.zeros((cnt, P.n + 1), np.uint32)
+    lib().orc_encrypt_zeros(C.byref(P.c()), keys.s_lwe, cnt, seed, first_index, ct)
+    return ct
+
+
+def preprocess(zero_ct, bits) -> np.ndarray:
+    """Algorithm 1 (Preprocess): the cloud encrypts its plaintext service bits
+    by adding the trivial sample (0, f(bit)) to one fresh client sample of
+    zero each, f(1) = +1/8 and f(0) = -1/8 on the torus (the encoding of
+    Encrypt in Sec. 2.3).  zero_ct: [cnt][n+1]; bits: cnt values in {0, 1}.
+    An all-zero zero_ct gives the noiseless trivial samples of the bits."""
+    zero_ct = np.asarray(zero_ct, np.uint32)
+    bits = np.asarray(bits, np.uint8).reshape(-1)
+    if zero_ct.ndim != 2 or len(zero_ct) != len(bits):
+        raise ValueError("preprocess: one zero sample per bit")
+    if bits.size and bits.max() > 1:
+        raise ValueError("preprocess: bits must be 0/1")
+    out = zero_ct.copy()
+    out[:, -1] += np.where(bits == 1, np.uint32(1 << 29), np.uint32((1 << 32) - (1 << 29)))
+    return out
 
 
 def decrypt_bits(keys: Keys, ct):

@@ -50,7 +50,7 @@ int32_t orc_gauss_torus(uint64_t seed, uint64_t stream, uint64_t idx, double sig
 
 /* stream numbers */
 enum { ST_SK_LWE = 0, ST_SK_RING = 1, ST_BSK_A = 2, ST_BSK_E = 3, ST_KSK_A = 4,
-       ST_KSK_E = 5, ST_ENC_A = 6, ST_ENC_E = 7 };
+       ST_KSK_E = 5, ST_ENC_A = 6, ST_ENC_E = 7, ST_ZERO_A = 8, ST_ZERO_E = 9 };
 
 static uint32_t rand_u32(uint64_t seed, uint64_t stream, uint64_t idx) {
   return (uint32_t)(orc_rand_u64(seed, stream, idx) >> 32);
@@ -339,6 +339,15 @@ void orc_encrypt_bits(const orc_params* P, const uint8_t* s_lwe, const uint8_t* 
     lwe_encrypt(P->n, s_lwe, mu, seed, ST_ENC_A, ST_ENC_E, first_index + k, P->lwe_sigma,
                 ct + k * (P->n + 1));
   }
+}
+
+/* The client's fresh samples of Sec. 3: LWE encryptions of the torus value
+ * 0, which the cloud later turns into payload ciphertexts (Algorithm 1). */
+void orc_encrypt_zeros(const orc_params* P, const uint8_t* s_lwe, size_t cnt, uint64_t seed,
+                       uint64_t first_index, uint32_t* ct) {
+  for (size_t k = 0; k < cnt; k++)
+    lwe_encrypt(P->n, s_lwe, 0u, seed, ST_ZERO_A, ST_ZERO_E, first_index + k, P->lwe_sigma,
+                ct + k * (P->n + 1));
 }
 
 /* Decrypt: the phase rounded to the nearer of -1/8, +1/8, i.e. its sign */

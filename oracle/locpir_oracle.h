@@ -73,6 +73,8 @@ void orc_keygen(const orc_params* P, uint64_t seed, uint8_t* s_lwe, uint8_t* s_r
 /* ---- Encrypt / Decrypt (Sec. 2.3) ---- */
 void orc_encrypt_bits(const orc_params* P, const uint8_t* s_lwe, const uint8_t* bits,
                       size_t cnt, uint64_t seed, uint64_t first_index, uint32_t* ct);
+void orc_encrypt_zeros(const orc_params* P, const uint8_t* s_lwe, size_t cnt, uint64_t seed,
+                       uint64_t first_index, uint32_t* ct);
 void orc_decrypt_bits(const orc_params* P, const uint8_t* s_lwe, const uint32_t* ct,
                       size_t cnt, uint8_t* bits, int32_t* phase);
 uint32_t orc_phase(uint32_t dim, const uint8_t* key, const uint32_t* ct);

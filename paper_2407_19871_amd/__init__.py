@@ -105,6 +105,9 @@ def lib() -> C.CDLL:
         "lp_bsk_words": (sz, [PP]),
         "lp_ksk_words": (sz, [PP]),
         "lp_encrypt_bits": (i32, [vp, vp, sz, u64, u64, vp]),
+        "lp_encrypt_zeros": (i32, [vp, sz, u64, u64, vp]),
+        "lp_preprocess": (i32, [vp, vp, vp, sz, vp, vp]),
+        "lp_bbox_wire_bytes": (i32, [vp, u32, u32, u32, vp]),
         "lp_decrypt_bits": (i32, [vp, vp, sz, vp, vp]),
         "lp_device_key_create": (i32, [vp, vp, C.POINTER(vp)]),
         "lp_device_key_bytes": (i32, [vp, C.POINTER(sz)]),
@@ -206,6 +209,12 @@ class SecretKey:
         bits = np.ascontiguousarray(np.asarray(bits, np.uint8).reshape(-1))
         ct = np.zeros((len(bits), self.params.n + 1), np.uint32)
         _check(lib().lp_encrypt_bits(self._h, _np_ptr(bits), len(bits), seed, first_index, _np_ptr(ct)))
+        return ct
+
+    def encrypt_zeros(self, cnt: int, seed: int, first_index: int = 0) -> np.ndarray:
+        """The client's fresh samples of zero for Preprocess (Sec. 3)."""
+        ct = np.zeros((cnt, self.params.n + 1), np.uint32)
+        _check(lib().lp_encrypt_zeros(self._h, cnt, seed, first_index, _np_ptr(ct)))
         return ct
 
     def decrypt_bits(self, ct):
@@ -341,6 +350,30 @@ def keyswitch_batch(dk: DeviceKey, big, out=None, stream=None):
         out = torch.empty((cnt, dk.params.n + 1), dtype=torch.int32, device=big.device)
     _check(lib().lp_keyswitch_batch(dk._h, _dev_ptr(big), cnt, _dev_ptr(out), _stream_ptr(stream)))
     return out
+
+
+def preprocess(dk: DeviceKey, zero, bits, out=None, stream=None):
+    """Algorithm 1 on the device: zero [cnt][n+1] int32 samples of zero, bits
+    a uint8 device tensor of cnt bytes."""
+    torch = _torch()
+    cnt = zero.shape[0]
+    if bits.dtype != torch.uint8 or bits.numel() != cnt:
+        raise LocpirError(-1, "preprocess: bits must be a uint8 tensor with one byte per sample")
+    if out is None:
+        out = torch.empty_like(zero)
+    _check(lib().lp_preprocess(dk._h, _dev_ptr(zero), _dev_ptr(bits), cnt, _dev_ptr(out), _stream_ptr(stream)))
+    return out
+
+
+class WireBytes(C.Structure):
+    _fields_ = [("lwe_sample", C.c_size_t), ("public_key", C.c_size_t), ("service_samples", C.c_size_t),
+                ("coordinate", C.c_size_t), ("query", C.c_size_t), ("result", C.c_size_t)]
+
+
+def bbox_wire_bytes(params: Params, l: int, n_boxes: int, m: int) -> dict:
+    w = WireBytes()
+    _check(lib().lp_bbox_wire_bytes(C.byref(params), l, n_boxes, m, C.byref(w)))
+    return {k: int(getattr(w, k)) for k, _ in WireBytes._fields_}
 
 
 def eval_bbox_query(dk: DeviceKey, l, n_boxes, m, is_signed, x, y, bounds, payload, out=None, stream=None):

@@ -27,6 +27,7 @@
 #include "internal.h"
 #include "jobs.h"
 #include "kernels.h"
+#include "protocol.h"
 
 using lp::BrJob;
 using lp::KsJob;
@@ -109,7 +110,7 @@ struct Stream {
 };
 
 enum : uint64_t { kStLweKey = 0, kStRingKey = 1, kStBskMask = 2, kStBskNoise = 3, kStKskMask = 4,
-                  kStKskNoise = 5, kStEncMask = 6, kStEncNoise = 7 };
+                  kStKskNoise = 5, kStEncMask = 6, kStEncNoise = 7, kStZeroMask = 8, kStZeroNoise = 9 };
 
 void parallel_rows(size_t rows, const std::function<void(size_t)>& fn) {
   unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -286,6 +287,32 @@ extern "C" lp_status lp_encrypt_bits(const lp_secret_key* sk, const uint8_t* bit
     const uint32_t mu = bits[k] ? 0x20000000u : 0xE0000000u;  // f(m) = m/4 - 1/8
     lwe_sample(n, sk->s.data(), mu, mask, noise, first_index + k, sk->P.lwe_sigma, ct + k * (n + 1));
   }
+  return LP_OK;
+}
+
+extern "C" lp_status lp_encrypt_zeros(const lp_secret_key* sk, size_t cnt, uint64_t seed, uint64_t first_index,
+                                      uint32_t* ct) {
+  if (!sk || (cnt && !ct)) return fail(LP_EINVAL, "lp_encrypt_zeros: null argument");
+  const uint32_t n = sk->P.n;
+  const Stream mask(seed, kStZeroMask), noise(seed, kStZeroNoise);
+  for (size_t k = 0; k < cnt; ++k)
+    lwe_sample(n, sk->s.data(), 0u, mask, noise, first_index + k, sk->P.lwe_sigma, ct + k * (n + 1));
+  return LP_OK;
+}
+
+extern "C" lp_status lp_bbox_wire_bytes(const lp_params* P, uint32_t l, uint32_t n_boxes, uint32_t m,
+                                        lp_wire_bytes* out) {
+  std::string why;
+  if (!params_ok(P, &why)) return fail(LP_EINVAL, "lp_bbox_wire_bytes: %s", why.c_str());
+  if (!out) return fail(LP_EINVAL, "lp_bbox_wire_bytes: null output");
+  if (l == 0 || l > 64 || n_boxes == 0 || m == 0) return fail(LP_EINVAL, "lp_bbox_wire_bytes: empty shape");
+  const size_t s = ((size_t)P->n + 1) * 4;
+  out->lwe_sample = s;
+  out->public_key = (lp_bsk_words(P) + lp_ksk_words(P)) * 4;
+  out->service_samples = (size_t)n_boxes * m * s;
+  out->coordinate = (size_t)l * s;
+  out->query = 2 * (size_t)l * s;
+  out->result = (size_t)m * s;
   return LP_OK;
 }
 
@@ -567,6 +594,16 @@ extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, c
   hipError_t e2 = hipFreeAsync(scratch, s);
   if (e != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e2));
+  return LP_OK;
+}
+
+extern "C" lp_status lp_preprocess(const lp_device_key* dk, const uint32_t* d_zero, const uint8_t* d_bits, size_t cnt,
+                                   uint32_t* d_out, void* stream) {
+  if (!dk) return fail(LP_EINVAL, "lp_preprocess: null key");
+  if (cnt == 0) return LP_OK;
+  if (!d_zero || !d_bits || !d_out) return fail(LP_EINVAL, "lp_preprocess: null buffer");
+  ScopedDevice sd(dk->device);
+  LP_HIP_TRY(lp::launch_preprocess(d_zero, d_bits, d_out, cnt, (int)dk->P.n, as_stream(stream)));
   return LP_OK;
 }
 

@@ -134,3 +134,38 @@ def test_error_paths_do_not_throw():
     assert lp.lib().lp_bbox_counts(0, 1, 1, None, None, None) == -1
     with pytest.raises(lp.LocpirError):
         lp.SecretKey.from_arrays(p, np.full(p.n, 2, np.uint8), np.zeros(p.N, np.uint8))
+
+
+def test_encrypt_zeros_matches_oracle_both_parameter_sets(pkeys, okeys):
+    sk, _ = pkeys
+    z = sk.encrypt_zeros(70, seed=12, first_index=3)
+    assert z.shape == (70, 631) and (z == O.encrypt_zeros(okeys, 70, seed=12, first_index=3)).all()
+    _, ph = sk.decrypt_bits(z)
+    assert np.abs(ph).max() < 2**28
+    assert sk.encrypt_zeros(0, seed=1).shape == (0, 631)
+    ok80 = O.keygen(21, O.LAMBDA80)
+    sk80 = lp.SecretKey.from_arrays(lp.params_lambda80(), ok80.s_lwe, ok80.s_ring)
+    assert (sk80.encrypt_zeros(9, seed=4) == O.encrypt_zeros(ok80, 9, seed=4)).all()
+
+
+def test_wire_bytes_match_paper_sizes():
+    # the printed sizes of Sec. 5 (memory size) and Sec. 1 (contribution), in
+    # KiB truncated to the printed digits
+    import json, math, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sizes.json")))
+    trunc = lambda v, d: math.floor(v / 1024 * 10**d) / 10**d
+    p80, p128 = lp.params_lambda80(), lp.params_default()
+    w80_13, w80_16 = lp.bbox_wire_bytes(p80, 13, 9, 9), lp.bbox_wire_bytes(p80, 16, 9, 9)
+    w128_13, w128_16 = lp.bbox_wire_bytes(p128, 13, 9, 9), lp.bbox_wire_bytes(p128, 16, 9, 9)
+    assert trunc(w80_16["lwe_sample"], 2) == g["tlwe_sample_kib_lambda80"]
+    assert trunc(w80_13["coordinate"], 1) == g["gps_coordinate_kib"]["lambda80_l13"]
+    assert trunc(w80_16["coordinate"], 1) == g["gps_coordinate_kib"]["lambda80_l16"]
+    assert trunc(w128_13["coordinate"], 0) == g["gps_coordinate_kib"]["lambda128_l13"]
+    assert trunc(w128_16["coordinate"], 1) == g["gps_coordinate_kib"]["lambda128_l16"]
+    assert trunc(w80_16["service_samples"], 0) == g["service_samples_kib"]["lambda80_81"]
+    assert trunc(w128_16["service_samples"], 0) == g["service_samples_kib"]["lambda128_81"]
+    assert abs(w128_16["result"] / 1000 - g["result_kbytes_m9"]) / g["result_kbytes_m9"] < 0.01
+    assert w128_16["query"] == 2 * w128_16["coordinate"]
+    assert w128_16["public_key"] == (lp.bsk_words(p128) + lp.ksk_words(p128)) * 4
+    with pytest.raises(lp.LocpirError):
+        lp.bbox_wire_bytes(p128, 0, 9, 9)

@@ -45,3 +45,12 @@ def test_lambda80_query(keys80):
     assert (got == exp).all()
     d, _ = O.decrypt_bits(ok, got)
     assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, True)
+
+
+def test_lambda80_preprocess(keys80):
+    import torch
+    ok, _, dk = keys80
+    z = O.encrypt_zeros(ok, 333, seed=97)
+    bits = W.random_bits(98, 333)
+    got = as_u32(lp.preprocess(dk, lp.to_device(z), torch.from_numpy(bits).to("cuda")))
+    assert got.shape == (333, 541) and (got == O.preprocess(z, bits)).all()

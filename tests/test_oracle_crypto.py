@@ -231,3 +231,52 @@ def test_lambda80_gates_and_query(okeys80):
     res = ctx.bbox_query(l, N, q.m, True, cts[:l], cts[l:2 * l], cts[2 * l:2 * l + 4 * l * N], cts[2 * l + 4 * l * N:])
     d, _ = O.decrypt_bits(keys, res)
     assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, q.m, True)
+
+
+def test_zero_samples_and_preprocess(okeys):
+    """Sec. 3 and Algorithm 1: the client's fresh samples carry phase e alone
+    (Gaussian at the LWE width, inside the decryption bound), and Preprocess
+    shifts each phase by exactly f(bit) = +-1/8 without touching the mask,
+    so the services decrypt to the cloud's bits; an all-zero sample gives the
+    noiseless trivial encryption."""
+    z = O.encrypt_zeros(okeys, 4000, seed=31)
+    _, ph0 = O.decrypt_bits(okeys, z)
+    ph0 = ph0.astype(np.int64)
+    sig = P.lwe_sigma * Q32
+    assert np.abs(ph0).max() < 2**28
+    assert abs(ph0.mean()) < 4 * sig / np.sqrt(len(ph0))
+    assert 0.95 < ph0.std() / sig < 1.05
+    # streams of their own: not the masks of Encrypt under the same seed
+    assert not (z[:8, :P.n] == O.encrypt_bits(okeys, np.zeros(8, np.uint8), seed=31)[:, :P.n]).any(axis=1).all()
+    bits = np.random.default_rng(32).integers(0, 2, 4000).astype(np.uint8)
+    c = O.preprocess(z, bits)
+    d, ph = O.decrypt_bits(okeys, c)
+    assert (d == bits).all() and (c[:, :P.n] == z[:, :P.n]).all()
+    shift = (ph.astype(np.int64) - ph0) % Q32
+    assert (shift == np.where(bits == 1, 2**29, Q32 - 2**29)).all()
+    t = O.preprocess(np.zeros((16, P.n + 1), np.uint32), bits[:16])
+    dt, pht = O.decrypt_bits(okeys, t)
+    assert (dt == bits[:16]).all() and (pht.astype(np.int64) == np.where(bits[:16] == 1, 2**29, -2**29)).all()
+    with pytest.raises(ValueError):
+        O.preprocess(z[:2], np.array([0, 2], np.uint8))
+    with pytest.raises(ValueError):
+        O.preprocess(z[:3], np.array([0, 1], np.uint8))
+
+
+@pytest.mark.parametrize("seed,inside", [(41, True), (42, False)])
+def test_protocol_query_through_oracle(okeys, octx, seed, inside):
+    """The protocol of Sec. 3 end to end on the oracle: the client sends
+    N*m fresh samples of zero and its encrypted coordinates; the cloud
+    encrypts its services with Preprocess and enters its plaintext bounds
+    as trivial samples; the result decrypts to the plaintext predicate."""
+    q = W.random_query_u8(seed, force_inside=inside)
+    l, N, m = q.l, q.n_boxes, q.m
+    xb, yb, bb, pb = q.plain_bits()
+    gps = O.encrypt_bits(okeys, np.concatenate([xb, yb]), seed=seed)
+    zero = O.encrypt_zeros(okeys, N * m, seed=seed + 100)
+    payload = O.preprocess(zero, pb)
+    bounds = O.preprocess(np.zeros((4 * l * N, P.n + 1), np.uint32), bb)
+    res = octx.bbox_query(l, N, m, False, gps[:l], gps[l:], bounds, payload)
+    d, ph = O.decrypt_bits(okeys, res)
+    assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, False)
+    assert np.abs(np.abs(ph.astype(np.int64)) - 2**29).max() < 2**28
