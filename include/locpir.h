@@ -9,7 +9,7 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Torus32: a torus value t is the uint32 round(t * 2^32) mod 2^32; sums wrap.
- * LWE ciphertext ("TLWE sample" in the paper, Sec. 2.3): n+1 little-endian
+ * LWE ciphertext ("TLWE sample" in the paper, Sec. 2.2): n+1 little-endian
  *   uint32 words, mask a[0..n) then body b.  Arrays of ciphertexts are
  *   [count][n+1], densely packed.  Bit encoding f(m) = m/4 - 1/8, i.e. the
  *   plaintext of bit 1 is +2^29 and of bit 0 is -2^29.
@@ -49,7 +49,7 @@ typedef int32_t lp_status;
 #define LP_ECANCELED (-7)    /* server request cancelled                  */
 
 /* TFHE parameters.  n, lwe_sigma: LWE dimension and noise of gate
- * ciphertexts (KeyGen outputs n and sigma, Sec. 2.3).  N, k: ring degree and
+ * ciphertexts (KeyGen outputs n and sigma, Sec. 2.2).  N, k: ring degree and
  * TRLWE dimension of the accumulator; bg_bit, l: gadget base 2^bg_bit and
  * levels; bk_sigma: noise of the bootstrapping key; ks_base_bit, ks_t:
  * key-switching base 2^ks_base_bit and digit count.  The GPU kernels support
@@ -63,7 +63,7 @@ typedef struct lp_secret_key lp_secret_key; /* client: LWE key s, ring key S    
 typedef struct lp_cloud_key lp_cloud_key;   /* PK = {bootstrapping key, KS key}  */
 typedef struct lp_device_key lp_device_key; /* PK resident on one GPU            */
 
-/* Gates (Sec. 2.3 EvalGate; the paper's HomAND, HomXNOR, HomMUX, HomXOR,
+/* Gates (Sec. 2.2 EvalGate; the paper's HomAND, HomXNOR, HomMUX, HomXOR,
  * HomNOT, plus the other two-input gates of the same construction).
  * MUX(in0 = select, in1 = if one, in2 = if zero).  NOT and COPY do not
  * bootstrap. */
@@ -82,7 +82,7 @@ lp_status lp_params_default(lp_params* out);
 
 /* ---- client side (host) -------------------------------------------------- */
 
-/* KeyGen(lambda) of Sec. 2.3 with the parameters given: a binary LWE key s,
+/* KeyGen(lambda) of Sec. 2.2 with the parameters given: a binary LWE key s,
  * a binary ring key S, PK = {BSK, KSK}.  Deterministic in seed (SplitMix64
  * counter-based draws).  BSK_i is a TGSW encryption of s_i: 2l TRLWE rows,
  * row (p, j) = TRLWE_S(0) + s_i/Bg^(j+1) on component p.  KSK[i][j][v-1]
@@ -101,7 +101,7 @@ lp_status lp_cloud_key_params(const lp_cloud_key* ck, lp_params* out);
 size_t lp_bsk_words(const lp_params* P);
 size_t lp_ksk_words(const lp_params* P);
 
-/* Encrypt(m, K, n, sigma) of Sec. 2.3, bit by bit (Sec. 4.1): ct[k] =
+/* Encrypt(m, K, n, sigma) of Sec. 2.2, bit by bit (Sec. 4.1): ct[k] =
  * (a, <a,s> + f(bits[k]) + e), a uniform, e ~ N(0, lwe_sigma), drawn from
  * (seed, first_index + k).  ct: cnt*(n+1) uint32, host. */
 lp_status lp_encrypt_bits(const lp_secret_key* sk, const uint8_t* bits, size_t cnt, uint64_t seed,
@@ -112,7 +112,7 @@ lp_status lp_encrypt_bits(const lp_secret_key* sk, const uint8_t* bits, size_t c
  * encrypted services with lp_preprocess.  ct: cnt*(n+1) uint32, host. */
 lp_status lp_encrypt_zeros(const lp_secret_key* sk, size_t cnt, uint64_t seed, uint64_t first_index, uint32_t* ct);
 
-/* Decrypt(ct, K) of Sec. 2.3: bit = sign of the phase b - <a,s>.  phase may
+/* Decrypt(ct, K) of Sec. 2.2: bit = sign of the phase b - <a,s>.  phase may
  * be NULL; otherwise it receives the signed phase (int32 Torus32). */
 lp_status lp_decrypt_bits(const lp_secret_key* sk, const uint32_t* ct, size_t cnt, uint8_t* bits,
                           int32_t* phase);
@@ -184,7 +184,7 @@ lp_status lp_preprocess(const lp_device_key* dk, const uint32_t* d_zero, const u
                         uint32_t* d_out, void* stream);
 
 /* Bytes the protocol of Sec. 3 moves for one query shape, ciphertexts as
- * cnt*(n+1) little-endian uint32 words with no header (the sizes Sec. 5
+ * cnt*(n+1) little-endian uint32 words with no header (the sizes Sec. 6.1
  * reports): one LWE sample; PK (bootstrapping and key-switching keys in
  * Torus32 form); the n_boxes*m fresh samples for the services; one encrypted
  * coordinate (l samples); the query (x and y); the result (m samples). */

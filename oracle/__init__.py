@@ -63,7 +63,7 @@ class Params:
 
 
 DEFAULT = Params()
-# The paper's lambda 80 set as read here (Table 2 gives only n = 540 and
+# The paper's lambda 80 set as read here (Sec. 5 gives only n = 540 and
 # sigma = 2^-20.2; ring, gadget and key-switching parameters as in DEFAULT).
 LAMBDA80 = Params(n=540, lwe_sigma=2.0 ** -20.2)
 
@@ -227,7 +227,7 @@ def preprocess(zero_ct, bits) -> np.ndarray:
     """Algorithm 1 (Preprocess): the cloud encrypts its plaintext service bits
     by adding the trivial sample (0, f(bit)) to one fresh client sample of
     zero each, f(1) = +1/8 and f(0) = -1/8 on the torus (the encoding of
-    Encrypt in Sec. 2.3).  zero_ct: [cnt][n+1]; bits: cnt values in {0, 1}.
+    Encrypt in Sec. 2.2).  zero_ct: [cnt][n+1]; bits: cnt values in {0, 1}.
     An all-zero zero_ct gives the noiseless trivial samples of the bits."""
     zero_ct = np.asarray(zero_ct, np.uint32)
     bits = np.asarray(bits, np.uint8).reshape(-1)

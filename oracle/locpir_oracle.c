@@ -272,7 +272,7 @@ static void poly_mul_binary(uint32_t N, const uint32_t* A, const uint8_t* S, uin
 }
 
 /* ======================================================================
- * KeyGen, Encrypt, Decrypt (Sec. 2.3).
+ * KeyGen, Encrypt, Decrypt (Sec. 2.2).
  * ==================================================================== */
 size_t orc_bsk_words(const orc_params* P) { return (size_t)P->n * (2 * P->l) * 2 * P->N; }
 size_t orc_ksk_words(const orc_params* P) {
@@ -533,7 +533,7 @@ static void lwe_lincomb(uint32_t dim, uint32_t* out, uint32_t cst, const uint32_
 
 /* Gates: a linear pre-combination whose phase sign is the gate's truth value,
  * then a gate bootstrap.  HomAND = Bootstrap((0,-1/8) + c1 + c2) as printed
- * in Sec. 2.3; the others are the same construction with other constants. */
+ * in Sec. 2.2; the others are the same construction with other constants. */
 void orc_gate(const orc_ctx* C, int gate, const uint32_t* c1, const uint32_t* c2,
               const uint32_t* c3, uint32_t* out) {
   const uint32_t n = C->P.n, N = C->P.N;

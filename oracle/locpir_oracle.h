@@ -8,9 +8,9 @@
  *
  * What it computes (paper: "Fast Private Location-based Information
  * Retrieval over the Torus", LocPIR):
- *   - TFHE KeyGen / Encrypt / Decrypt of single bits (Sec. 2.3), with the
+ *   - TFHE KeyGen / Encrypt / Decrypt of single bits (Sec. 2.2), with the
  *     encoding f(m) = m/4 - 1/8 and the phase b - a.K;
- *   - gate bootstrapping (Sec. 2.3, EvalGate and the HomAND identity; the
+ *   - gate bootstrapping (Sec. 2.2, EvalGate and the HomAND identity; the
  *     other basic gates follow the cited TFHE construction): modulus
  *     switch, blind rotation by CMux external products, sample extraction
  *     and LWE key switching;
@@ -64,13 +64,13 @@ void orc_negacyclic_mul_schoolbook(uint32_t N, const int64_t* a, const int64_t* 
 uint64_t orc_rand_u64(uint64_t seed, uint64_t stream, uint64_t idx);
 int32_t orc_gauss_torus(uint64_t seed, uint64_t stream, uint64_t idx, double sigma);
 
-/* ---- keys (KeyGen, Sec. 2.3) ---- */
+/* ---- keys (KeyGen, Sec. 2.2) ---- */
 size_t orc_bsk_words(const orc_params* P); /* n * 2l * 2 * N                */
 size_t orc_ksk_words(const orc_params* P); /* N * t * (base-1) * (n+1)      */
 void orc_keygen(const orc_params* P, uint64_t seed, uint8_t* s_lwe, uint8_t* s_ring,
                 uint32_t* bsk, uint32_t* ksk);
 
-/* ---- Encrypt / Decrypt (Sec. 2.3) ---- */
+/* ---- Encrypt / Decrypt (Sec. 2.2) ---- */
 void orc_encrypt_bits(const orc_params* P, const uint8_t* s_lwe, const uint8_t* bits,
                       size_t cnt, uint64_t seed, uint64_t first_index, uint32_t* ct);
 void orc_encrypt_zeros(const orc_params* P, const uint8_t* s_lwe, size_t cnt, uint64_t seed,

@@ -161,7 +161,7 @@ def params_default() -> Params:
 
 
 def params_lambda80() -> Params:
-    """The paper's lambda 80 set (Table 2: n = 540, sigma = 2^-20.2); the
+    """The paper's lambda 80 set (Sec. 5: n = 540, sigma = 2^-20.2); the
     ring, gadget and key-switching parameters are those of the default set."""
     p = params_default()
     p.n = 540

@@ -149,7 +149,7 @@ def test_encrypt_zeros_matches_oracle_both_parameter_sets(pkeys, okeys):
 
 
 def test_wire_bytes_match_paper_sizes():
-    # the printed sizes of Sec. 5 (memory size) and Sec. 1 (contribution), in
+    # the printed sizes of Sec. 6.1 (memory size) and Sec. 1.1 (contribution), in
     # KiB truncated to the printed digits
     import json, math, os
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sizes.json")))

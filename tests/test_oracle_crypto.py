@@ -32,7 +32,7 @@ def test_encrypt_decrypt_roundtrip(okeys):
     d, ph = O.decrypt_bits(okeys, ct)
     assert (d == bits).all()
     err = ph.astype(np.int64) - np.where(bits == 1, 2**29, -(2**29))
-    assert np.abs(err).max() < 2**28               # |e| < 1/16 (Sec. 2.3)
+    assert np.abs(err).max() < 2**28               # |e| < 1/16 (Sec. 2.2)
     sig = P.lwe_sigma * Q32
     assert 0.85 < err.std() / sig < 1.15
 
