@@ -210,7 +210,10 @@ lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t m, uint32_
  * job buffers; see lp_server_request_bytes) fit hbm_budget and fewer than
  * max_inflight are admitted.  Each scheduler tick runs the next depth level
  * of every admitted request in one fused blind-rotation launch and one fused
- * key-switch launch; requests that arrive meanwhile join at the next tick.
+ * key-switch launch per parameter shape (requests fuse with those of equal
+ * n, ks_base_bit and ks_t; keys of the lambda 128 and lambda 80 sets are
+ * served side by side in separate launches); requests that arrive meanwhile
+ * join at the next tick.  stats.ticks counts fused launch pairs.
  * A finished request's result is kept on the host until polled; its device
  * memory is released at once.  A failing request (allocation, upload) ends
  * alone; the others continue.  Latency is measured from submit to the end of

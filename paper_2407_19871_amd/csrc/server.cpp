@@ -153,7 +153,13 @@ lp_status setup_request(lp_server* S, Request& r) {
   return LP_OK;
 }
 
-// One fused level over the admitted requests.
+// Requests fuse only with requests of the same LWE dimension and key-switching
+// shape: a fused launch reads every request's pool with one sample stride.
+bool same_shape(const lp_params& a, const lp_params& b) {
+  return a.n == b.n && a.ks_t == b.ks_t && a.ks_base_bit == b.ks_base_bit;
+}
+
+// One fused level over admitted requests of one shape.
 lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, uint64_t* n_br_out) {
   using lp::BrJob;
   using lp::KsJob;
@@ -231,7 +237,9 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, u
                              (int)Pp.ks_t, (int)Pp.ks_base_bit, tile, lp::pick_ks_split(ks.size(), tile, Pp.n),
                              S->stream);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+  // the host job arrays must outlive every copy queued above, also on failure
+  const hipError_t es = hipStreamSynchronize(S->stream);
+  if (e == hipSuccess) e = es;
   if (e != hipSuccess) return lp::fail(LP_EDEVICE, "server tick: %s", hipGetErrorString(e));
   return LP_OK;
 }
@@ -302,17 +310,29 @@ void worker_main(lp_server* S) {
       S->st.pending = (uint32_t)S->pending.size();
     }
     if (act.empty()) continue;
-    uint64_t nbr = 0;
-    lp_status st = tick(S, act, &nbr);
-    std::vector<std::shared_ptr<Request>> done;
+    std::vector<std::vector<std::shared_ptr<Request>>> groups;
     for (auto& r : act) {
-      if (st == LP_OK && ++r->level < r->plan->levels()) continue;
-      done.push_back(r);
+      auto g = std::find_if(groups.begin(), groups.end(), [&](const std::vector<std::shared_ptr<Request>>& v) {
+        return same_shape(v[0]->ck->P, r->ck->P);
+      });
+      if (g == groups.end()) groups.push_back({r});
+      else g->push_back(r);
     }
+    uint64_t nbr = 0;
+    std::vector<std::shared_ptr<Request>> done;
     std::vector<lp_status> done_st;
-    for (auto& r : done) done_st.push_back(st == LP_OK ? collect_output(S, *r) : st);
+    for (auto& g : groups) {
+      uint64_t n = 0;
+      const lp_status st = tick(S, g, &n);
+      nbr += n;
+      for (auto& r : g) {
+        if (st == LP_OK && ++r->level < r->plan->levels()) continue;
+        done.push_back(r);
+        done_st.push_back(st == LP_OK ? collect_output(S, *r) : st);
+      }
+    }
     std::lock_guard<std::mutex> lk(S->mu);
-    S->st.ticks++;
+    S->st.ticks += groups.size();
     S->st.fused_bootstraps += nbr;
     for (size_t i = 0; i < done.size(); ++i) {
       release(S, *done[i]);

@@ -54,3 +54,31 @@ def test_server_results_equal_alone_and_predicate():
         assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, q.l, q.m, q.is_signed), k
     ctx = O.Ctx(okeys[0])
     assert (results[0][1] == ctx.bbox_query(qs[0].l, 1, qs[0].m, False, *parts[0])).all()
+
+
+def test_server_mixed_parameter_sets():
+    """lambda 128 and lambda 80 clients in flight together: each result
+    equals the same query alone under its own key and decrypts to the
+    predicate."""
+    cuda_or_skip()
+    ok = [O.keygen(71), O.keygen(72, O.LAMBDA80)]
+    cks = [lp.CloudKey.from_arrays(lp.params_default(), ok[0].bsk, ok[0].ksk),
+           lp.CloudKey.from_arrays(lp.params_lambda80(), ok[1].bsk, ok[1].ksk)]
+    qs = [W.random_query(73, 13, 2, 3, force_inside=True), W.random_query(74, 13, 2, 3, force_inside=True),
+          W.random_query_u8(75, force_inside=True)]
+    owner = [0, 1, 1]
+    parts = [enc(ok[owner[k]], q, 950 + k) for k, q in enumerate(qs)]
+    srv = lp.Server(64 << 30)
+    tickets = [srv.submit(cks[owner[k]], q.l, q.n_boxes, q.m, q.is_signed, *parts[k]) for k, q in enumerate(qs)]
+    results = [srv.poll(t) for t in tickets]
+    srv.close()
+    assert all(r[0] == 0 for r in results)
+    dks = [lp.DeviceKey(ck) for ck in cks]
+    for k, q in enumerate(qs):
+        got = results[k][1]
+        assert got.shape == (q.m, cks[owner[k]].params.n + 1)
+        alone = lp.to_host(lp.eval_bbox_query(dks[owner[k]], q.l, q.n_boxes, q.m, q.is_signed,
+                                              *[lp.to_device(v) for v in parts[k]]))
+        assert (got == alone).all(), k
+        d, _ = bits_of(ok[owner[k]], got)
+        assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, q.l, q.m, q.is_signed), k

@@ -100,3 +100,22 @@ def test_continuous_batching_fuses_levels(ck):
         assert srv.poll(t)[0] == 0
     assert srv.stats()["ticks"] < 2 * depth
     srv.close()
+
+
+def test_mixed_parameter_sets_run_in_separate_launches(ck):
+    # a lambda 80 request (541-word samples) never shares a fused launch with
+    # a lambda 128 one (631 words): each tick counts one launch pair per shape
+    p80 = lp.params_lambda80()
+    ck80 = lp.CloudKey.from_arrays(p80, np.zeros(lp.bsk_words(p80), np.uint32), np.zeros(lp.ksk_words(p80), np.uint32))
+    l, nb, m = 8, 2, 3
+    q80 = (l, nb, m, True, np.zeros((l, 541), np.uint32), np.zeros((l, 541), np.uint32),
+           np.zeros((4 * l * nb, 541), np.uint32), np.zeros((nb * m, 541), np.uint32))
+    srv = lp.Server(1 << 40, simulate=True)
+    t = [srv.submit(ck, *query(l, nb, m)), srv.submit(ck80, *q80)]
+    r = [srv.poll(x) for x in t]
+    assert r[0][0] == 0 and r[0][1].shape == (m, 631)
+    assert r[1][0] == 0 and r[1][1].shape == (m, 541)
+    depth = lp.bbox_counts(l, nb, m)[2]
+    s = srv.stats()
+    assert s["ticks"] == 2 * depth and s["completed"] == 2 and s["bytes_in_use"] == 0
+    srv.close()
