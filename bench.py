@@ -286,9 +286,10 @@ def sweep_bench(reps: int = 3, seed: int = 6):
     """The paper's experiment shapes on the GPU, 8- to 32-bit synthetic
     queries over the Korea-like region (a continent-sized one at 8 bits), one
     query at a time: Fig. 4a (N = 10
-    boxes, m = 9, l = 8/16/24/32), Table 2 (N = m = 9, l = 13 and 16, under
-    both the lambda 128 and the lambda 80 parameter sets) and a sweep over N
-    at l = 16, m = 9.  The paper's CPU times (6-core Ryzen 5
+    boxes, m = 9, l = 8/16/24/32), Table 2 (the nine city boxes and services
+    printed in Table 1, N = m = 9, at l = 13 and 16, under both the lambda 128
+    and the lambda 80 parameter sets, for a point in Seoul) and a sweep over
+    N at l = 16, m = 9.  The paper's CPU times (6-core Ryzen 5
     3500X, TFHE 1.1) are listed beside the Fig. 4a and Table 2 shapes as
     context, not as a target."""
     import torch
@@ -307,13 +308,18 @@ def sweep_bench(reps: int = 3, seed: int = 6):
     shapes = [("fig4a", "lambda128", l, 10, 9, fig4a[l]) for l in (8, 16, 24, 32)]
     shapes += [("table2", ps, l, 9, 9, table2[ps][l]) for ps in ("lambda128", "lambda80") for l in (13, 16)]
     shapes += [("boxes", "lambda128", 16, N, 9, None) for N in (1, 4, 16, 28)]
+    with open(os.path.join(ROOT, "tests", "golden", "table1_covid_boxes.json")) as f:
+        table1 = json.load(f)["rows"]
     rows = []
     for k, (kind, ps, l, N, m, paper_s) in enumerate(shapes):
         sk, dk = keys[ps]
-        # 8-bit codes step 2 degrees: a Korea-sized tiling of 10 boxes would
-        # quantize to empty boxes, so that shape tiles a continent-sized region
-        region = W.KOREA if l >= 13 else (-60.0, 60.0, -120.0, 120.0)
-        q = W.random_query(60000 + k, l, N, m, region=region, force_inside=True)
+        if kind == "table2":
+            q = W.table1_query((37.55, 127.0), table1, l=l, m=m)
+        else:
+            # 8-bit codes step 2 degrees: a Korea-sized tiling of 10 boxes would
+            # quantize to empty boxes, so that shape tiles a continent-sized region
+            region = W.KOREA if l >= 13 else (-60.0, 60.0, -120.0, 120.0)
+            q = W.random_query(60000 + k, l, N, m, region=region, force_inside=True)
         xb, yb, bb, pb = q.plain_bits()
         ct = sk.encrypt_bits(np.concatenate([xb, yb, bb, pb]), seed=61000 + k)
         parts = [lp.to_device(a) for a in (ct[:l], ct[l:2 * l], ct[2 * l:2 * l + 4 * l * N], ct[2 * l + 4 * l * N:])]
@@ -327,6 +333,7 @@ def sweep_bench(reps: int = 3, seed: int = 6):
         d, _ = sk.decrypt_bits(lp.to_host(out))
         n_br, _, levels = lp.bbox_counts(l, N, m)
         row = {"kind": kind, "params": ps, "l": l, "boxes": N, "m": m, "bootstraps": n_br, "levels": levels,
+               "inputs": "Table 1 boxes and services" if kind == "table2" else "synthetic tiling",
                "ms_per_query": round(dt * 1e3, 1), "bootstraps_per_s": round(n_br / dt, 1),
                "correct_vs_predicate": bool(W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m,
                                                                             True))}
