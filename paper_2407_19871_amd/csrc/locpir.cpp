@@ -1,6 +1,6 @@
 // Host side of liblocpir: the C ABI declared in include/locpir.h.
 //
-//   * client operations (KeyGen, Encrypt, Decrypt of Sec. 2.3) on the host;
+//   * client operations (KeyGen, Encrypt, Decrypt of Sec. 2.2) on the host;
 //   * device keys: upload and NTT-domain conversion of the bootstrapping key;
 //   * gate batches and key-switch batches on the GPU;
 //   * the bounding-box circuit of Algorithms 2-5 compiled to a level plan
@@ -530,7 +530,7 @@ struct GateCombo {
 };
 
 // Linear pre-combination whose phase sign is the gate's value; HomAND =
-// Bootstrap((0, -1/8) + c1 + c2) (Sec. 2.3), the rest alike.
+// Bootstrap((0, -1/8) + c1 + c2) (Sec. 2.2), the rest alike.
 bool gate_combo(lp_gate g, GateCombo* c) {
   const uint32_t E = 0x20000000u, Qr = 0x40000000u;  // 1/8, 1/4
   switch (g) {

@@ -3,7 +3,7 @@
 // Preprocess (Algorithm 1): the cloud encrypts its plaintext service bits
 // without the secret key by adding the trivial sample (0, f(bit)) to one of
 // the client's fresh samples of zero each; f(1) = +1/8 and f(0) = -1/8 on
-// the torus, the encoding of Encrypt (Sec. 2.3).  It is a streaming copy
+// the torus, the encoding of Encrypt (Sec. 2.2).  It is a streaming copy
 // that changes one word per sample, bound by HBM.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
