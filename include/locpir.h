@@ -133,6 +133,16 @@ lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32
                              const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
                              uint32_t* d_out, void* stream);
 
+/* The same gates without the key switch: d_out_big[k] (N+1 words, LWE of
+ * dimension N under the ring key S) is the sample that gate's key switch
+ * takes: the sample extracted from the blind rotation of the gate's input
+ * combination, or for MUX (0, 1/8) + u1 + u2 of its two rotations.
+ * lp_keyswitch_batch of d_out_big equals lp_bootstrap_batch bit for bit.
+ * NOT and COPY do not bootstrap: LP_EINVAL.  cnt = 0 is a no-op. */
+lp_status lp_bootstrap_batch_noks(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                                  const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
+                                  uint32_t* d_out_big, void* stream);
+
 /* Key switching alone: d_in holds cnt extracted samples of N+1 words under
  * the ring key; d_out receives cnt samples of n+1 words under s. */
 lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,

@@ -108,6 +108,8 @@ def lib():
     L.orc_keyswitch.argtypes = [vp, u32p, u32p]
     L.orc_bootstrap_raw.argtypes = [vp, u32p, vp, vp]
     L.orc_gate.argtypes = [vp, C.c_int, vp, vp, vp, u32p]
+    L.orc_gate_big_batch.restype = C.c_int
+    L.orc_gate_big_batch.argtypes = [vp, C.c_int, C.c_size_t, vp, vp, vp, u32p]
     L.orc_gate_batch.restype = C.c_int
     L.orc_gate_batch.argtypes = [vp, C.c_int, C.c_size_t, vp, vp, vp, u32p]
     L.orc_bbox_query.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
@@ -305,6 +307,17 @@ class Ctx:
         out = np.zeros((cnt, w), np.uint32)
         th = lib().orc_gate_batch(self._c, GATES[gate], cnt, *[_ptr(a) for a in arrs], out)
         return out, th
+
+    def gate_big_batch(self, gate: str, c1, c2=None, c3=None):
+        """cnt bootstrapped gates up to their key switch: [cnt][N+1], the
+        samples under the ring key that the key switch takes."""
+        w = self.P.n + 1
+        arrs = [None if c is None else np.ascontiguousarray(c, np.uint32).reshape(-1, w) for c in (c1, c2, c3)]
+        cnt = arrs[0].shape[0]
+        big = np.zeros((cnt, self.P.N + 1), np.uint32)
+        if not lib().orc_gate_big_batch(self._c, GATES[gate], cnt, *[_ptr(a) for a in arrs], big):
+            raise ValueError(f"{gate} does not bootstrap")
+        return big
 
     def bbox_query(self, l, n_boxes, m, is_signed, x, y, bounds, payload):
         w = self.P.n + 1

@@ -534,37 +534,48 @@ static void lwe_lincomb(uint32_t dim, uint32_t* out, uint32_t cst, const uint32_
 /* Gates: a linear pre-combination whose phase sign is the gate's truth value,
  * then a gate bootstrap.  HomAND = Bootstrap((0,-1/8) + c1 + c2) as printed
  * in Sec. 2.2; the others are the same construction with other constants. */
-void orc_gate(const orc_ctx* C, int gate, const uint32_t* c1, const uint32_t* c2,
-              const uint32_t* c3, uint32_t* out) {
+int orc_gate_big(const orc_ctx* C, int gate, const uint32_t* c1, const uint32_t* c2,
+                 const uint32_t* c3, uint32_t* big) {
   const uint32_t n = C->P.n, N = C->P.N;
   uint32_t* tmp = (uint32_t*)malloc(sizeof(uint32_t) * (n + 1));
+  int ok = 1;
   switch (gate) {
-    case ORC_NOT: lwe_lincomb(n, out, 0, c1, -1, NULL, 0); break;
-    case ORC_COPY: lwe_lincomb(n, out, 0, c1, 1, NULL, 0); break;
-    case ORC_NAND: lwe_lincomb(n, tmp, EIGHTH, c1, -1, c2, -1); orc_bootstrap_raw(C, tmp, NULL, out); break;
-    case ORC_AND: lwe_lincomb(n, tmp, 0u - EIGHTH, c1, 1, c2, 1); orc_bootstrap_raw(C, tmp, NULL, out); break;
-    case ORC_OR: lwe_lincomb(n, tmp, EIGHTH, c1, 1, c2, 1); orc_bootstrap_raw(C, tmp, NULL, out); break;
-    case ORC_NOR: lwe_lincomb(n, tmp, 0u - EIGHTH, c1, -1, c2, -1); orc_bootstrap_raw(C, tmp, NULL, out); break;
-    case ORC_XOR: lwe_lincomb(n, tmp, QUARTER, c1, 2, c2, 2); orc_bootstrap_raw(C, tmp, NULL, out); break;
-    case ORC_XNOR: lwe_lincomb(n, tmp, 0u - QUARTER, c1, -2, c2, -2); orc_bootstrap_raw(C, tmp, NULL, out); break;
+    case ORC_NAND: lwe_lincomb(n, tmp, EIGHTH, c1, -1, c2, -1); break;
+    case ORC_AND: lwe_lincomb(n, tmp, 0u - EIGHTH, c1, 1, c2, 1); break;
+    case ORC_OR: lwe_lincomb(n, tmp, EIGHTH, c1, 1, c2, 1); break;
+    case ORC_NOR: lwe_lincomb(n, tmp, 0u - EIGHTH, c1, -1, c2, -1); break;
+    case ORC_XOR: lwe_lincomb(n, tmp, QUARTER, c1, 2, c2, 2); break;
+    case ORC_XNOR: lwe_lincomb(n, tmp, 0u - QUARTER, c1, -2, c2, -2); break;
     case ORC_MUX: {
       /* u1 = sel AND t, u2 = (NOT sel) AND f, each bootstrapped without key
-       * switching; out = KeySwitch((0, 1/8) + u1 + u2) */
+       * switching; big = (0, 1/8) + u1 + u2 */
       uint32_t* u1 = (uint32_t*)malloc(sizeof(uint32_t) * (N + 1));
       uint32_t* u2 = (uint32_t*)malloc(sizeof(uint32_t) * (N + 1));
-      uint32_t* big = (uint32_t*)malloc(sizeof(uint32_t) * (N + 1));
       lwe_lincomb(n, tmp, 0u - EIGHTH, c1, 1, c2, 1);
       orc_bootstrap_raw(C, tmp, u1, NULL);
       lwe_lincomb(n, tmp, 0u - EIGHTH, c1, -1, c3, 1);
       orc_bootstrap_raw(C, tmp, u2, NULL);
       lwe_lincomb(N, big, EIGHTH, u1, 1, u2, 1);
-      orc_keyswitch(C, big, out);
-      free(u1); free(u2); free(big);
-      break;
+      free(u1); free(u2);
+      free(tmp);
+      return 1;
     }
-    default: memset(out, 0, sizeof(uint32_t) * (n + 1));
+    default: ok = 0;
   }
+  if (ok) orc_bootstrap_raw(C, tmp, big, NULL);
   free(tmp);
+  return ok;
+}
+
+void orc_gate(const orc_ctx* C, int gate, const uint32_t* c1, const uint32_t* c2,
+              const uint32_t* c3, uint32_t* out) {
+  const uint32_t n = C->P.n, N = C->P.N;
+  if (gate == ORC_NOT) { lwe_lincomb(n, out, 0, c1, -1, NULL, 0); return; }
+  if (gate == ORC_COPY) { lwe_lincomb(n, out, 0, c1, 1, NULL, 0); return; }
+  uint32_t* big = (uint32_t*)malloc(sizeof(uint32_t) * (N + 1));
+  if (orc_gate_big(C, gate, c1, c2, c3, big)) orc_keyswitch(C, big, out);
+  else memset(out, 0, sizeof(uint32_t) * (n + 1));
+  free(big);
 }
 
 int orc_gate_batch(const orc_ctx* C, int gate, size_t cnt, const uint32_t* c1,
@@ -582,6 +593,16 @@ int orc_gate_batch(const orc_ctx* C, int gate, size_t cnt, const uint32_t* c1,
       orc_gate(C, gate, c1 + k * w, c2 ? c2 + k * w : NULL, c3 ? c3 + k * w : NULL, out + k * w);
   }
   return threads;
+}
+
+int orc_gate_big_batch(const orc_ctx* C, int gate, size_t cnt, const uint32_t* c1,
+                       const uint32_t* c2, const uint32_t* c3, uint32_t* big) {
+  const size_t w = C->P.n + 1, wb = C->P.N + 1;
+  int ok = 1;
+  #pragma omp parallel for schedule(dynamic, 1) reduction(&& : ok)
+  for (long long k = 0; k < (long long)cnt; k++)
+    ok = ok && orc_gate_big(C, gate, c1 + k * w, c2 ? c2 + k * w : NULL, c3 ? c3 + k * w : NULL, big + k * wb);
+  return ok;
 }
 
 /* ======================================================================

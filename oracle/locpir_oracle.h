@@ -101,6 +101,15 @@ void orc_keyswitch(const orc_ctx* C, const uint32_t* lwe_big, uint32_t* out);
  * extraction into out_big (N+1 words, may be NULL), then key switching into
  * out (n+1 words, may be NULL) */
 void orc_bootstrap_raw(const orc_ctx* C, const uint32_t* ct, uint32_t* out_big, uint32_t* out);
+/* one bootstrapped gate up to its key switch: big (N+1 words) is the sample
+ * the key switch takes; returns 0 (big untouched) for NOT, COPY and unknown
+ * gates, which do not bootstrap */
+int orc_gate_big(const orc_ctx* C, int gate, const uint32_t* c1, const uint32_t* c2,
+                 const uint32_t* c3, uint32_t* big);
+/* cnt of them over the host's threads; big: cnt x (N+1); 0 if the gate
+ * does not bootstrap */
+int orc_gate_big_batch(const orc_ctx* C, int gate, size_t cnt, const uint32_t* c1,
+                       const uint32_t* c2, const uint32_t* c3, uint32_t* big);
 /* one gate; MUX(c1 = select, c2 = if one, c3 = if zero) */
 void orc_gate(const orc_ctx* C, int gate, const uint32_t* c1, const uint32_t* c2,
               const uint32_t* c3, uint32_t* out);

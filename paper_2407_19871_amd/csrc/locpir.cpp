@@ -27,7 +27,7 @@
 #include "internal.h"
 #include "jobs.h"
 #include "kernels.h"
-#include "protocol.h"
+#include "lwe_ops.h"
 
 using lp::BrJob;
 using lp::KsJob;
@@ -549,17 +549,23 @@ bool gate_combo(lp_gate g, GateCombo* c) {
 
 }  // namespace
 
-extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
-                                        const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt, uint32_t* d_out,
-                                        void* stream) {
-  if (!dk) return fail(LP_EINVAL, "lp_bootstrap_batch: null key");
+namespace {
+// Gate bootstrapping of a batch: blind rotations (sample extraction
+// included) and, with_ks, the key switch into d_out (cnt * (n+1) words);
+// without it d_out receives the samples the key switch would take
+// (cnt * (N+1) words).
+lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                          const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt, uint32_t* d_out, bool with_ks,
+                          void* stream) {
+  if (!dk) return fail(LP_EINVAL, "%s: null key", who);
   GateCombo gc;
-  if (!gate_combo(gate, &gc)) return fail(LP_EINVAL, "lp_bootstrap_batch: unknown gate %d", (int)gate);
+  if (!gate_combo(gate, &gc)) return fail(LP_EINVAL, "%s: unknown gate %d", who, (int)gate);
+  if (!with_ks && gc.nbr == 0) return fail(LP_EINVAL, "%s: NOT and COPY do not bootstrap", who);
   if (cnt == 0) return LP_OK;
-  if (!d_in0 || !d_out) return fail(LP_EINVAL, "lp_bootstrap_batch: null buffer");
-  if (gc.nbr >= 1 && gate != LP_GATE_MUX && !d_in1) return fail(LP_EINVAL, "lp_bootstrap_batch: gate needs d_in1");
-  if (gate == LP_GATE_MUX && (!d_in1 || !d_in2)) return fail(LP_EINVAL, "lp_bootstrap_batch: MUX needs three inputs");
-  if (cnt > (size_t)(lp::REF_INDEX_MASK / 2)) return fail(LP_EINVAL, "lp_bootstrap_batch: batch too large");
+  if (!d_in0 || !d_out) return fail(LP_EINVAL, "%s: null buffer", who);
+  if (gc.nbr >= 1 && gate != LP_GATE_MUX && !d_in1) return fail(LP_EINVAL, "%s: gate needs d_in1", who);
+  if (gate == LP_GATE_MUX && (!d_in1 || !d_in2)) return fail(LP_EINVAL, "%s: MUX needs three inputs", who);
+  if (cnt > (size_t)(lp::REF_INDEX_MASK / 2)) return fail(LP_EINVAL, "%s: batch too large", who);
   ScopedDevice sd(dk->device);
   hipStream_t s = as_stream(stream);
   const uint32_t n = dk->P.n, N = dk->P.N;
@@ -568,10 +574,13 @@ extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, c
     return LP_OK;
   }
   const size_t nbr = cnt * gc.nbr;
-  const size_t ex_bytes = nbr * (N + 1) * 4, br_bytes = nbr * sizeof(BrJob), ks_bytes = cnt * sizeof(KsJob);
+  // single-rotation gates without a key switch extract straight into d_out
+  const bool direct = !with_ks && gc.nbr == 1;
+  const size_t ex_bytes = direct ? 0 : nbr * (N + 1) * 4, br_bytes = nbr * sizeof(BrJob),
+               ks_bytes = cnt * sizeof(KsJob);
   char* scratch = nullptr;
   LP_HIP_TRY(hipMallocAsync((void**)&scratch, ex_bytes + br_bytes + ks_bytes + 512, s));
-  uint32_t* ex = reinterpret_cast<uint32_t*>(scratch);
+  uint32_t* ex = direct ? d_out : reinterpret_cast<uint32_t*>(scratch);
   BrJob* br = reinterpret_cast<BrJob*>(scratch + ((ex_bytes + 255) & ~size_t(255)));
   KsJob* ks = reinterpret_cast<KsJob*>(reinterpret_cast<char*>(br) + ((br_bytes + 255) & ~size_t(255)));
   hipError_t e = lp::launch_make_batch_jobs(gc.nbr, gc.cst, gc.c0, gc.c1, d_in1 != nullptr, cnt, br, ks, s);
@@ -585,16 +594,32 @@ extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, c
     ProfScope ps(kProfBR, nbr, s);
     e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, pick_br_wpb(nbr), s);
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess && with_ks) {
     ProfScope ps(kProfKS, cnt, s);
     const int tile = pick_ks_tile(cnt);
     e = lp::launch_keyswitch(ks, (int)cnt, ex, dst, dk->ksk_tab, nullptr, (int)n, (int)N, (int)dk->P.ks_t,
                              (int)dk->P.ks_base_bit, tile, pick_ks_split(cnt, tile, n), s);
+  } else if (e == hipSuccess && !direct) {
+    // MUX: (0, 1/8) + u1 + u2, the sample its key switch would take
+    e = lp::launch_lwe_pair_sum(ex, d_out, cnt, (int)N + 1, 0x20000000u, s);
   }
   hipError_t e2 = hipFreeAsync(scratch, s);
-  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e));
-  if (e2 != hipSuccess) return fail(LP_EDEVICE, "lp_bootstrap_batch: %s", hipGetErrorString(e2));
+  if (e != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e2));
   return LP_OK;
+}
+}  // namespace
+
+extern "C" lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                                        const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt, uint32_t* d_out,
+                                        void* stream) {
+  return bootstrap_batch("lp_bootstrap_batch", dk, gate, d_in0, d_in1, d_in2, cnt, d_out, true, stream);
+}
+
+extern "C" lp_status lp_bootstrap_batch_noks(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                                             const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
+                                             uint32_t* d_out_big, void* stream) {
+  return bootstrap_batch("lp_bootstrap_batch_noks", dk, gate, d_in0, d_in1, d_in2, cnt, d_out_big, false, stream);
 }
 
 extern "C" lp_status lp_preprocess(const lp_device_key* dk, const uint32_t* d_zero, const uint8_t* d_bits, size_t cnt,

@@ -1,4 +1,4 @@
-// Launchers of the protocol kernels (protocol.hip).
+// Launchers of the streaming LWE kernels (lwe_ops.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -11,5 +11,10 @@ namespace lp {
 // alias zero.
 hipError_t launch_preprocess(const uint32_t* d_zero, const uint8_t* d_bits, uint32_t* d_out, size_t cnt,
                              int n_lwe, hipStream_t s);
+
+// out[k] = (0, cst) + ex[2k] + ex[2k+1] over cnt output samples of w words
+// (the MUX sum of two extracted samples); out must not alias ex.
+hipError_t launch_lwe_pair_sum(const uint32_t* d_ex, uint32_t* d_out, size_t cnt, int w, uint32_t cst,
+                               hipStream_t s);
 
 }  // namespace lp

@@ -58,3 +58,23 @@ def test_nand_batch_full_size_sampled(okeys, octx, dkey):
     idx = np.random.default_rng(5005).choice(B, 32, replace=False)
     exp, _ = octx.gate_batch("NAND", c1[idx], c2[idx])
     assert (got[idx] == exp).all()
+
+
+@pytest.mark.parametrize("gate,B", [("NAND", 97), ("XNOR", 64), ("MUX", 45)])
+def test_gates_before_key_switching(okeys, octx, dkey, gate, B):
+    ins = [O.encrypt_bits(okeys, W.random_bits(160 + B + i, B), seed=170 + i) for i in range(3 if gate == "MUX" else 2)]
+    d_ins = [lp.to_device(c) for c in ins]
+    big = lp.bootstrap_batch_noks(dkey, gate, *d_ins)
+    assert big.shape == (B, 1025)
+    assert (as_u32(big) == octx.gate_big_batch(gate, *ins)).all()
+    # key switching the samples gives the whole gate
+    full = as_u32(lp.bootstrap_batch(dkey, gate, *d_ins))
+    assert (as_u32(lp.keyswitch_batch(dkey, big)) == full).all()
+
+
+def test_gates_before_key_switching_edges(dkey):
+    import torch
+    e = torch.empty((0, 631), dtype=torch.int32, device="cuda")
+    assert lp.bootstrap_batch_noks(dkey, "NAND", e, e).shape == (0, 1025)
+    with pytest.raises(lp.LocpirError):
+        lp.bootstrap_batch_noks(dkey, "NOT", lp.to_device(np.zeros((3, 631), np.uint32)))

@@ -280,3 +280,28 @@ def test_protocol_query_through_oracle(okeys, octx, seed, inside):
     d, ph = O.decrypt_bits(okeys, res)
     assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, False)
     assert np.abs(np.abs(ph.astype(np.int64)) - 2**29).max() < 2**28
+
+
+def test_gates_before_key_switching(okeys, octx):
+    """The sample a gate hands to its key switch is an LWE encryption, under
+    the ring key S, of the gate's value (+-1/8 with the bootstrap's noise);
+    key switching it reproduces the whole gate bit for bit.  NOT and COPY do
+    not bootstrap and are refused."""
+    pairs = [(a, b) for a in (0, 1) for b in (0, 1)]
+    c1 = O.encrypt_bits(okeys, [a for a, _ in pairs], seed=141)
+    c2 = O.encrypt_bits(okeys, [b for _, b in pairs], seed=142)
+    trip = [(s, t, f) for s in (0, 1) for t in (0, 1) for f in (0, 1)]
+    cs, ct, cf = (O.encrypt_bits(okeys, [v[i] for v in trip], seed=143 + i) for i in range(3))
+    cases = [(g, (c1, c2), [f(a, b) for a, b in pairs]) for g, f in TRUTH.items()]
+    cases.append(("MUX", (cs, ct, cf), [t if s else f for s, t, f in trip]))
+    for gate, ins, want in cases:
+        big = octx.gate_big_batch(gate, *ins)
+        assert big.shape == (len(want), P.N + 1)
+        ph = np.array([sgn32(O.phase(b, okeys.s_ring)) for b in big])
+        assert list((ph > 0).astype(int)) == want, gate
+        assert np.abs(np.abs(ph) - 2**29).max() < 2**28, gate
+        full, _ = octx.gate_batch(gate, *ins)
+        assert all((octx.keyswitch(b) == o).all() for b, o in zip(big, full)), gate
+    for gate in ("NOT", "COPY"):
+        with pytest.raises(ValueError):
+            octx.gate_big_batch(gate, c1)
