@@ -98,6 +98,16 @@ lp_status lp_secret_key_export(const lp_secret_key* sk, uint8_t* s, uint8_t* S);
 lp_status lp_cloud_key_import(const lp_params* P, const uint32_t* bsk, const uint32_t* ksk, lp_cloud_key** ck);
 lp_status lp_cloud_key_export(const lp_cloud_key* ck, uint32_t* bsk, uint32_t* ksk);
 lp_status lp_cloud_key_params(const lp_cloud_key* ck, lp_params* out);
+/* PK as one byte blob for the client's upload (Sec. 3): a 64-byte header
+ * ("LPCK", format version 1, the parameters as u32 n, N, k, bg_bit, l,
+ * ks_base_bit, ks_t and f64 lwe_sigma, bk_sigma, little-endian, zero padded)
+ * followed by the bsk and ksk words in the layouts above.  serialize: with
+ * buf == NULL, *len receives the size; otherwise *len must hold at least
+ * that many bytes and receives the size written.  deserialize: a new key
+ * owned by the caller; LP_EINVAL for a foreign, truncated or inconsistent
+ * blob. */
+lp_status lp_cloud_key_serialize(const lp_cloud_key* ck, void* buf, size_t* len);
+lp_status lp_cloud_key_deserialize(const void* buf, size_t len, lp_cloud_key** ck);
 size_t lp_bsk_words(const lp_params* P);
 size_t lp_ksk_words(const lp_params* P);
 
@@ -196,7 +206,8 @@ lp_status lp_preprocess(const lp_device_key* dk, const uint32_t* d_zero, const u
 /* Bytes the protocol of Sec. 3 moves for one query shape, ciphertexts as
  * cnt*(n+1) little-endian uint32 words with no header (the sizes Sec. 6.1
  * reports): one LWE sample; PK (bootstrapping and key-switching keys in
- * Torus32 form); the n_boxes*m fresh samples for the services; one encrypted
+ * Torus32 form; lp_cloud_key_serialize adds its 64-byte header); the
+ * n_boxes*m fresh samples for the services; one encrypted
  * coordinate (l samples); the query (x and y); the result (m samples). */
 typedef struct {
   size_t lwe_sample, public_key, service_samples, coordinate, query, result;

@@ -102,6 +102,8 @@ def lib() -> C.CDLL:
         "lp_cloud_key_import": (i32, [PP, vp, vp, C.POINTER(vp)]),
         "lp_cloud_key_export": (i32, [vp, vp, vp]),
         "lp_cloud_key_params": (i32, [vp, PP]),
+        "lp_cloud_key_serialize": (i32, [vp, vp, C.POINTER(sz)]),
+        "lp_cloud_key_deserialize": (i32, [vp, sz, C.POINTER(vp)]),
         "lp_bsk_words": (sz, [PP]),
         "lp_ksk_words": (sz, [PP]),
         "lp_encrypt_bits": (i32, [vp, vp, sz, u64, u64, vp]),
@@ -255,6 +257,22 @@ class CloudKey:
         ksk = np.zeros(ksk_words(self.params), np.uint32)
         _check(lib().lp_cloud_key_export(self._h, _np_ptr(bsk), _np_ptr(ksk)))
         return bsk, ksk
+
+    def serialize(self) -> bytes:
+        """PK as the client uploads it (lp_cloud_key_serialize)."""
+        n = C.c_size_t()
+        _check(lib().lp_cloud_key_serialize(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().lp_cloud_key_serialize(self._h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    @classmethod
+    def deserialize(cls, blob: bytes) -> "CloudKey":
+        h = C.c_void_p()
+        _check(lib().lp_cloud_key_deserialize(blob, len(blob), C.byref(h)))
+        p = Params()
+        _check(lib().lp_cloud_key_params(h, C.byref(p)))
+        return cls(h, p)
 
 
 def keygen(params: Params | None, seed: int):

@@ -270,6 +270,69 @@ extern "C" lp_status lp_cloud_key_export(const lp_cloud_key* ck, uint32_t* bsk, 
   return LP_OK;
 }
 
+// ---------------------------------------------------------------- PK wire format
+// 64-byte header, then the key words (the host is little-endian):
+//   0  "LPCK"   4  format version (1)   8  n, N, k, bg_bit, l, ks_base_bit,
+//   ks_t (u32 each)   36  lwe_sigma, bk_sigma (f64)   52  zero padding
+//   64  bsk words   then  ksk words   (all u32)
+namespace {
+constexpr size_t kPkHeader = 64;
+constexpr uint32_t kPkVersion = 1;
+}  // namespace
+
+extern "C" lp_status lp_cloud_key_serialize(const lp_cloud_key* ck, void* buf, size_t* len) {
+  if (!ck || !len) return fail(LP_EINVAL, "lp_cloud_key_serialize: null argument");
+  const size_t need = kPkHeader + (ck->bsk.size() + ck->ksk.size()) * 4;
+  if (!buf) {
+    *len = need;
+    return LP_OK;
+  }
+  if (*len < need) return fail(LP_EINVAL, "lp_cloud_key_serialize: buffer of %zu bytes, need %zu", *len, need);
+  unsigned char* b = static_cast<unsigned char*>(buf);
+  std::memset(b, 0, kPkHeader);
+  std::memcpy(b, "LPCK", 4);
+  std::memcpy(b + 4, &kPkVersion, 4);
+  const uint32_t f[7] = {ck->P.n, ck->P.N, ck->P.k, ck->P.bg_bit, ck->P.l, ck->P.ks_base_bit, ck->P.ks_t};
+  std::memcpy(b + 8, f, sizeof f);
+  std::memcpy(b + 36, &ck->P.lwe_sigma, 8);
+  std::memcpy(b + 44, &ck->P.bk_sigma, 8);
+  std::memcpy(b + kPkHeader, ck->bsk.data(), ck->bsk.size() * 4);
+  std::memcpy(b + kPkHeader + ck->bsk.size() * 4, ck->ksk.data(), ck->ksk.size() * 4);
+  *len = need;
+  return LP_OK;
+}
+
+extern "C" lp_status lp_cloud_key_deserialize(const void* buf, size_t len, lp_cloud_key** ck) {
+  if (!buf || !ck) return fail(LP_EINVAL, "lp_cloud_key_deserialize: null argument");
+  const unsigned char* b = static_cast<const unsigned char*>(buf);
+  uint32_t version = 0;
+  if (len < kPkHeader || std::memcmp(b, "LPCK", 4) != 0)
+    return fail(LP_EINVAL, "lp_cloud_key_deserialize: not a serialized cloud key");
+  std::memcpy(&version, b + 4, 4);
+  if (version != kPkVersion) return fail(LP_EINVAL, "lp_cloud_key_deserialize: format version %u", version);
+  uint32_t f[7];
+  std::memcpy(f, b + 8, sizeof f);
+  lp_params P{f[0], f[1], f[2], f[3], f[4], f[5], f[6], 0.0, 0.0};
+  std::memcpy(&P.lwe_sigma, b + 36, 8);
+  std::memcpy(&P.bk_sigma, b + 44, 8);
+  std::string why;
+  if (!params_ok(&P, &why)) return fail(LP_EINVAL, "lp_cloud_key_deserialize: %s", why.c_str());
+  const size_t nb = lp_bsk_words(&P), nk = lp_ksk_words(&P);
+  if (len != kPkHeader + (nb + nk) * 4)
+    return fail(LP_EINVAL, "lp_cloud_key_deserialize: %zu bytes, the parameters need %zu", len,
+                kPkHeader + (nb + nk) * 4);
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(b + kPkHeader);
+  if (reinterpret_cast<uintptr_t>(w) % alignof(uint32_t) == 0) return lp_cloud_key_import(&P, w, w + nb, ck);
+  // unaligned blob: copy the words out first
+  try {
+    std::vector<uint32_t> words(nb + nk);
+    std::memcpy(words.data(), b + kPkHeader, (nb + nk) * 4);
+    return lp_cloud_key_import(&P, words.data(), words.data() + nb, ck);
+  } catch (const std::bad_alloc&) {
+    return fail(LP_ENOMEM, "lp_cloud_key_deserialize: out of host memory");
+  }
+}
+
 extern "C" lp_status lp_cloud_key_params(const lp_cloud_key* ck, lp_params* out) {
   if (!ck || !out) return fail(LP_EINVAL, "lp_cloud_key_params: null argument");
   *out = ck->P;

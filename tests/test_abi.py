@@ -169,3 +169,30 @@ def test_wire_bytes_match_paper_sizes():
     assert w128_16["public_key"] == (lp.bsk_words(p128) + lp.ksk_words(p128)) * 4
     with pytest.raises(lp.LocpirError):
         lp.bbox_wire_bytes(p128, 0, 9, 9)
+
+
+def test_cloud_key_blob_roundtrip_and_refusals(okeys):
+    import struct
+    for p, ok in ((lp.params_default(), okeys), (lp.params_lambda80(), O.keygen(23, O.LAMBDA80))):
+        ck = lp.CloudKey.from_arrays(p, ok.bsk, ok.ksk)
+        blob = ck.serialize()
+        assert len(blob) == 64 + lp.bbox_wire_bytes(p, 16, 1, 1)["public_key"]
+        assert blob[:4] == b"LPCK" and struct.unpack_from("<8I", blob, 4)[1:] == (p.n, p.N, 1, 7, 3, 2, 8)
+        back = lp.CloudKey.deserialize(blob)
+        assert back.params.n == p.n and back.params.lwe_sigma == p.lwe_sigma
+        bsk, ksk = back.export()
+        assert (bsk == ok.bsk).all() and (ksk == ok.ksk).all()
+        # an unaligned copy of the blob reads the same
+        shifted = bytearray(len(blob) + 1)
+        shifted[1:] = blob
+        mv = memoryview(shifted)[1:]
+        h = ctypes.c_void_p()
+        buf = (ctypes.c_char * len(blob)).from_buffer(shifted, 1)
+        assert lp.lib().lp_cloud_key_deserialize(buf, len(blob), ctypes.byref(h)) == 0
+        lp.CloudKey(h, p)   # frees it
+        del mv, buf
+    for bad in (b"XXXX" + blob[4:], blob[:-4], blob[:40], blob[:4] + struct.pack("<I", 2) + blob[8:],
+                blob[:8] + struct.pack("<I", 0) + blob[12:]):
+        with pytest.raises(lp.LocpirError) as e:
+            lp.CloudKey.deserialize(bad)
+        assert e.value.code == -1
