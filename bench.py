@@ -288,7 +288,8 @@ def sweep_bench(reps: int = 3, seed: int = 6):
     query at a time: Fig. 4a (N = 10
     boxes, m = 9, l = 8/16/24/32), Table 2 (the nine city boxes and services
     printed in Table 1, N = m = 9, at l = 13 and 16, under both the lambda 128
-    and the lambda 80 parameter sets, for a point in Seoul) and a sweep over
+    and the lambda 80 parameter sets, for a point in Seoul), Fig. 4b (l = 16,
+    N = 10, m = 1 to 64; the paper prints no values for it) and a sweep over
     N at l = 16, m = 9.  The paper's CPU times (6-core Ryzen 5
     3500X, TFHE 1.1) are listed beside the Fig. 4a and Table 2 shapes as
     context, not as a target."""
@@ -307,6 +308,7 @@ def sweep_bench(reps: int = 3, seed: int = 6):
     table2 = {"lambda128": {13: 4.88, 16: 5.67}, "lambda80": {13: 4.36, 16: 5.12}}  # seconds, Table 2
     shapes = [("fig4a", "lambda128", l, 10, 9, fig4a[l]) for l in (8, 16, 24, 32)]
     shapes += [("table2", ps, l, 9, 9, table2[ps][l]) for ps in ("lambda128", "lambda80") for l in (13, 16)]
+    shapes += [("fig4b", "lambda128", 16, 10, m, None) for m in (1, 16, 32, 64)]
     shapes += [("boxes", "lambda128", 16, N, 9, None) for N in (1, 4, 16, 28)]
     with open(os.path.join(ROOT, "tests", "golden", "table1_covid_boxes.json")) as f:
         table1 = json.load(f)["rows"]
