@@ -121,6 +121,36 @@ def cpu_baseline(seed: int):
                             "sample": f"8 XNOR + 4 MUX gates = 16 bootstraps on one thread, {dt1:.1f} s"}}
 
 
+def summarize_launches(launches, depth: int, l: int):
+    """Per-kind totals, the time-weighted fraction of the chip's 1024 SIMDs
+    that hold a blind-rotation wave, and the split of a query's time into
+    the paper's Table 2 phases by depth level.  A query launches one blind
+    rotation and one key switch per level, in level order; levels [0, l]
+    are the comparators (the XNOR level and l MUX levels), the next three
+    the validation ANDs (bounds, box, service), the rest the XOR tree.
+    With an odd box count one box's chain runs a few levels late, so the
+    split by level is then approximate."""
+    tot = {k: {"launches": 0, "jobs": 0, "total_ms": 0.0} for k in ("blind_rotate", "keyswitch")}
+    busy = 0.0
+    per_level = np.zeros(depth)
+    n_rot, level = 0, 0
+    for r in launches:
+        t = tot[r["name"]]
+        t["launches"] += 1
+        t["jobs"] += r["jobs"]
+        t["total_ms"] += r["ms"]
+        if r["name"] == "blind_rotate":
+            busy += r["ms"] * min(r["jobs"] * r["shape"], 1024) / 1024
+            level = n_rot % depth
+            n_rot += 1
+        per_level[level] += r["ms"]   # a key switch belongs to the rotation before it
+    per_level /= max(1, n_rot // depth)
+    br_ms = tot["blind_rotate"]["total_ms"]
+    phases = {"comparison": per_level[:l + 1].sum(), "validation": per_level[l + 1:l + 4].sum(),
+              "hom_add_xor": per_level[l + 4:].sum()}
+    return tot, (busy / br_ms if br_ms else None), {k: round(float(v), 2) for k, v in phases.items()}
+
+
 def microbench(lp, torch, sk, dk, sizes=(1, 64, 1024, 16384)):
     """Batched NAND bootstraps (one launch pair per batch) and the plain
     one-bootstrap-per-launch path."""
@@ -340,14 +370,20 @@ def sweep_bench(reps: int = 3, seed: int = 6):
         parts = [lp.to_device(a) for a in (ct[:l], ct[l:2 * l], ct[2 * l:2 * l + 4 * l * N], ct[2 * l + 4 * l * N:])]
         out = lp.eval_bbox_query(dk, l, N, m, True, *parts)
         torch.cuda.synchronize()
+        lp.profile_enable(True)
+        lp.profile_collect_launches()
         t0 = time.perf_counter()
         for _ in range(reps):
             lp.eval_bbox_query(dk, l, N, m, True, *parts, out=out)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
+        launches = lp.profile_collect_launches()
+        lp.profile_enable(False)
         d, _ = sk.decrypt_bits(lp.to_host(out))
         n_br, _, levels = lp.bbox_counts(l, N, m)
+        _, busy, phases = summarize_launches(launches, levels, l)
         row = {"kind": kind, "params": ps, "l": l, "boxes": N, "m": m, "bootstraps": n_br, "levels": levels,
+               "phases_ms": phases, "busy_simd_frac": round(busy, 3) if busy is not None else None,
                "inputs": "Table 1 boxes and services" if kind == "table2" else "synthetic tiling",
                "ms_per_query": round(dt * 1e3, 1), "bootstraps_per_s": round(n_br / dt, 1),
                "correct_vs_predicate": bool(W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m,
@@ -459,7 +495,7 @@ def main():
     correct = W.from_bits(d) == expect
 
     lp.profile_enable(True)
-    lp.profile_collect()
+    lp.profile_collect_launches()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -469,8 +505,9 @@ def main():
         ev[k][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stats = lp.profile_collect()
+    launches = lp.profile_collect_launches()
     lp.profile_enable(False)
+    stats, busy_simd, phases = summarize_launches(launches, levels, l)
     print(f"bench: {args.steps} queries timed, {wall * 1e3 / args.steps:.1f} ms each", file=sys.stderr, flush=True)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
 
@@ -496,6 +533,11 @@ def main():
         "alg_bytes_per_launch": int(BSK_NTT_BYTES + BR_JOB_BYTES * br["jobs"] / max(1, br["launches"])),
         # measured: rocprofv3 SQ_INSTS_VALU x 4 cycles / (kernel time x 2.4 GHz x 1024 SIMDs)
         "valu_issue_frac_rocprof": valu["query_valu_issue_frac"] if valu else None,
+        # time-weighted share of the 1024 SIMDs holding a rotation wave (narrow
+        # levels leave most of the chip idle), and the issue rate of those
+        "busy_simd_frac": round(busy_simd, 4) if busy_simd is not None else None,
+        "valu_issue_frac_busy_simds": round(valu["query_valu_issue_frac"] / busy_simd, 4)
+        if valu and busy_simd else None,
     }
 
     res = {
@@ -522,6 +564,8 @@ def main():
         "kernels": {"blind_rotate_ms": round(br["total_ms"], 3), "keyswitch_ms": round(ks["total_ms"], 3),
                     "launches": br["launches"] + ks["launches"]},
         "roofline": roofline,
+        # the paper's Table 2 phases of one query, by depth level (ms)
+        "phases_ms": phases,
         "autotune": tune,
     }
     if not args.no_micro:

@@ -307,6 +307,19 @@ typedef struct {
 } lp_kernel_stat;
 lp_status lp_profile_enable(int on);
 lp_status lp_profile_collect(lp_kernel_stat* stats, int* count);
+/* The same record one launch at a time, oldest first: name as above; jobs;
+ * shape: waves per bootstrap (blind rotation) or key switches per tile (key
+ * switching); ms: event-measured duration.  Writes min(*count, recorded)
+ * entries, sets *count to the number written and clears the whole record.
+ * A query launches one blind rotation and one key switch per depth level,
+ * in level order. */
+typedef struct {
+  const char* name;
+  uint64_t jobs;
+  int32_t shape;
+  double ms;
+} lp_launch_record;
+lp_status lp_profile_collect_launches(lp_launch_record* recs, int* count);
 
 /* ---- launch-shape autotuning --------------------------------------------- */
 

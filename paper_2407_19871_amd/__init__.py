@@ -41,6 +41,10 @@ class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64), ("jobs", C.c_uint64), ("total_ms", C.c_double)]
 
 
+class LaunchRecord(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("jobs", C.c_uint64), ("shape", C.c_int32), ("ms", C.c_double)]
+
+
 class TuneEntry(C.Structure):
     _fields_ = [("jobs", C.c_uint32), ("br_waves", C.c_int32), ("ks_tile", C.c_int32), ("ks_split", C.c_int32),
                 ("br_us", C.c_float), ("ks_us", C.c_float)]
@@ -124,6 +128,7 @@ def lib() -> C.CDLL:
         "lp_debug_blind_rotate": (i32, [vp, vp, sz, u32, vp, vp]),
         "lp_profile_enable": (i32, [i32]),
         "lp_profile_collect": (i32, [C.POINTER(KernelStat), C.POINTER(C.c_int)]),
+        "lp_profile_collect_launches": (i32, [C.POINTER(LaunchRecord), C.POINTER(C.c_int)]),
         "lp_autotune": (i32, [vp, C.POINTER(u32), C.c_int, u32, vp, C.POINTER(TuneEntry)]),
         "lp_tune_set": (i32, [C.POINTER(TuneEntry), C.c_int]),
         "lp_tune_get": (i32, [C.POINTER(TuneEntry), C.POINTER(C.c_int)]),
@@ -465,6 +470,15 @@ def profile_collect() -> dict:
     _check(lib().lp_profile_collect(arr, C.byref(cnt)))
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "jobs": int(arr[i].jobs),
                                    "total_ms": float(arr[i].total_ms)} for i in range(cnt.value)}
+
+
+def profile_collect_launches(capacity: int = 1 << 16) -> list:
+    """[{"name", "jobs", "shape", "ms"}] per recorded launch, oldest first."""
+    arr = (LaunchRecord * capacity)()
+    cnt = C.c_int(capacity)
+    _check(lib().lp_profile_collect_launches(arr, C.byref(cnt)))
+    return [{"name": arr[i].name.decode(), "jobs": int(arr[i].jobs), "shape": int(arr[i].shape),
+             "ms": float(arr[i].ms)} for i in range(cnt.value)]
 
 
 # ------------------------------------------------------------------ autotuning

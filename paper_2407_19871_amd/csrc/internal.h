@@ -116,6 +116,7 @@ enum ProfKind { kProfBR = 0, kProfKS = 1, kProfKinds = 2 };
 struct ProfRecord {
   int kind;
   uint64_t jobs;
+  int shape;  // waves per bootstrap (blind rotation) or jobs per tile (key switching)
   hipEvent_t start, stop;
 };
 extern std::mutex g_prof_mu;
@@ -127,7 +128,7 @@ struct ProfScope {
   bool on = false;
   ProfRecord rec{};
   hipStream_t s;
-  ProfScope(int kind, uint64_t jobs, hipStream_t st) : s(st) {
+  ProfScope(int kind, uint64_t jobs, int shape, hipStream_t st) : s(st) {
     {
       std::lock_guard<std::mutex> lk(g_prof_mu);
       on = g_prof_on;
@@ -138,6 +139,7 @@ struct ProfScope {
     }
     rec.kind = kind;
     rec.jobs = jobs;
+    rec.shape = shape;
     if (hipEventCreate(&rec.start) != hipSuccess) {
       on = false;
       return;

@@ -509,31 +509,56 @@ extern "C" lp_status lp_profile_enable(int on) {
   return LP_OK;
 }
 
+namespace {
+// Takes the recorded launches and their event-measured durations (ms),
+// oldest first, and clears the record.
+lp_status drain_profile(const char* who, std::vector<ProfRecord>* recs, std::vector<float>* ms) {
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs->swap(g_prof);
+  }
+  lp_status st = LP_OK;
+  ms->assign(recs->size(), 0.f);
+  for (size_t i = 0; i < recs->size(); ++i) {
+    ProfRecord& r = (*recs)[i];
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&(*ms)[i], r.start, r.stop);
+    if (e != hipSuccess) st = fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e));
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  return st;
+}
+}  // namespace
+
 extern "C" lp_status lp_profile_collect(lp_kernel_stat* stats, int* count) {
   if (!count) return fail(LP_EINVAL, "lp_profile_collect: null count");
   std::vector<ProfRecord> recs;
-  {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    recs.swap(g_prof);
-  }
+  std::vector<float> ms;
+  const lp_status st = drain_profile("lp_profile_collect", &recs, &ms);
   lp_kernel_stat agg[kProfKinds];
   for (int k = 0; k < kProfKinds; ++k) agg[k] = lp_kernel_stat{kProfNames[k], 0, 0, 0.0};
-  lp_status st = LP_OK;
-  for (auto& r : recs) {
-    float ms = 0.f;
-    hipError_t e = hipEventSynchronize(r.stop);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
-    if (e != hipSuccess) st = fail(LP_EDEVICE, "lp_profile_collect: %s", hipGetErrorString(e));
-    agg[r.kind].launches += 1;
-    agg[r.kind].jobs += r.jobs;
-    agg[r.kind].total_ms += ms;
-    (void)hipEventDestroy(r.start);
-    (void)hipEventDestroy(r.stop);
+  for (size_t i = 0; i < recs.size(); ++i) {
+    agg[recs[i].kind].launches += 1;
+    agg[recs[i].kind].jobs += recs[i].jobs;
+    agg[recs[i].kind].total_ms += ms[i];
   }
   const int n = std::min(*count, (int)kProfKinds);
   if (stats)
     for (int k = 0; k < n; ++k) stats[k] = agg[k];
   *count = stats ? n : 0;
+  return st;
+}
+
+extern "C" lp_status lp_profile_collect_launches(lp_launch_record* recs, int* count) {
+  if (!count || (*count > 0 && !recs)) return fail(LP_EINVAL, "lp_profile_collect_launches: null argument");
+  std::vector<ProfRecord> all;
+  std::vector<float> ms;
+  const lp_status st = drain_profile("lp_profile_collect_launches", &all, &ms);
+  const int n = (int)std::min<size_t>(std::max(*count, 0), all.size());
+  for (int i = 0; i < n; ++i)
+    recs[i] = lp_launch_record{kProfNames[all[i].kind], all[i].jobs, all[i].shape, (double)ms[i]};
+  *count = n;
   return st;
 }
 
@@ -654,12 +679,13 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   lp::DstBases dst{};
   dst.p[0] = d_out;
   if (e == hipSuccess) {
-    ProfScope ps(kProfBR, nbr, s);
-    e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, pick_br_wpb(nbr), s);
+    const int waves = pick_br_wpb(nbr);
+    ProfScope ps(kProfBR, nbr, waves, s);
+    e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, waves, s);
   }
   if (e == hipSuccess && with_ks) {
-    ProfScope ps(kProfKS, cnt, s);
     const int tile = pick_ks_tile(cnt);
+    ProfScope ps(kProfKS, cnt, tile, s);
     e = lp::launch_keyswitch(ks, (int)cnt, ex, dst, dk->ksk_tab, nullptr, (int)n, (int)N, (int)dk->P.ks_t,
                              (int)dk->P.ks_base_bit, tile, pick_ks_split(cnt, tile, n), s);
   } else if (e == hipSuccess && !direct) {

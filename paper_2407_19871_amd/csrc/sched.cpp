@@ -449,11 +449,11 @@ lp_status run_program(Program& G, const lp_bbox_query* qs, uint32_t* const* d_ou
   }
   for (int L = 0; L < G.levels(); ++L) {
     {
-      ProfScope ps(kProfBR, (uint64_t)G.br_cnt[L], s);
+      ProfScope ps(kProfBR, (uint64_t)G.br_cnt[L], G.br_waves[L], s);
       LP_HIP_TRY(use_graphs ? hipGraphLaunch(G.g_br[L], s) : launch_level_br(G, L, s));
     }
     {
-      ProfScope ps(kProfKS, (uint64_t)G.ks_cnt[L], s);
+      ProfScope ps(kProfKS, (uint64_t)G.ks_cnt[L], G.ks_tile[L], s);
       LP_HIP_TRY(use_graphs ? hipGraphLaunch(G.g_ks[L], s) : launch_level_ks(G, L, s));
     }
   }

@@ -227,12 +227,13 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, u
   lp::DstBases dst{};
   const lp::Twiddles tw = act[0]->dk->tw;
   if (e == hipSuccess) {
-    lp::ProfScope ps(lp::kProfBR, br.size(), S->stream);
+    const int waves = lp::pick_br_wpb(br.size());
+    lp::ProfScope ps(lp::kProfBR, br.size(), waves, S->stream);
     e = lp::launch_blind_rotate(S->d_br, (int)br.size(), src, S->ex, S->d_bsk_tab, S->d_pool_tab, (int)Pp.n, (int)Pp.n,
-                                0, tw, lp::pick_br_wpb(br.size()), S->stream);
+                                0, tw, waves, S->stream);
   }
   if (e == hipSuccess) {
-    lp::ProfScope ps(lp::kProfKS, ks.size(), S->stream);
+    lp::ProfScope ps(lp::kProfKS, ks.size(), tile, S->stream);
     e = lp::launch_keyswitch(S->d_ks, (int)ks.size(), S->ex, dst, S->d_ksk_tab, S->d_pool_tab, (int)Pp.n, (int)Pp.N,
                              (int)Pp.ks_t, (int)Pp.ks_base_bit, tile, lp::pick_ks_split(ks.size(), tile, Pp.n),
                              S->stream);

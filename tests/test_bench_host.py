@@ -1,0 +1,37 @@
+"""Host logic of the benchmark (no GPU): how per-launch profile records of
+a query become per-kind totals, the busy-SIMD share and the Table 2 phase
+split by depth level."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def records(widths, steps, waves=3, skip_ks_at=None):
+    out = []
+    for _ in range(steps):
+        for lev, w in enumerate(widths):
+            out.append({"name": "blind_rotate", "jobs": w, "shape": waves, "ms": 10.0 + lev})
+            if lev != skip_ks_at:
+                out.append({"name": "keyswitch", "jobs": w, "shape": 4, "ms": 1.0})
+    return out
+
+
+def test_phase_split_by_level_and_busy_share():
+    # l = 2: levels 0..2 comparators, 3..5 validation, 6.. XOR tree
+    widths = [64, 192, 128, 32, 16, 512, 256, 128]
+    tot, busy, ph = bench.summarize_launches(records(widths, 3), len(widths), 2)
+    assert tot["blind_rotate"]["launches"] == 24 and tot["keyswitch"]["launches"] == 24
+    assert tot["blind_rotate"]["jobs"] == 3 * sum(widths)
+    assert ph == {"comparison": 11 + 12 + 13, "validation": 14 + 15 + 16, "hom_add_xor": 17 + 18}
+    want = sum((10 + i) * min(w * 3, 1024) / 1024 for i, w in enumerate(widths)) / sum(10 + i for i in range(8))
+    assert busy == pytest.approx(want)
+
+
+def test_missing_key_switch_record_keeps_levels_aligned():
+    widths = [8, 8, 8, 8, 8]
+    _, _, ph = bench.summarize_launches(records(widths, 2, skip_ks_at=1), len(widths), 1)
+    assert ph == {"comparison": 11 + 11, "validation": 13 + 14 + 15, "hom_add_xor": 0.0}

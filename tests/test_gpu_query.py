@@ -58,3 +58,22 @@ def test_16bit_16box_query_full_size(okeys, octx, dkey):
     assert (got == exp).all()
     d, _ = bits_of(okeys, got)
     assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, 16, 32, True)
+
+
+def test_query_launch_records_follow_the_levels(okeys, dkey):
+    # one blind rotation and one key switch per depth level, in level order,
+    # each rotation as wide as the scheduler's level
+    q = W.random_query(7, 16, 4, 3, force_inside=True)
+    x, y, bounds, pay = encrypt_query(okeys, q, 70)
+    args = [lp.to_device(v) for v in (x, y, bounds, pay)]
+    lp.eval_bbox_query(dkey, q.l, q.n_boxes, q.m, True, *args)
+    cuda_or_skip().cuda.synchronize()
+    lp.profile_enable(True)
+    lp.profile_collect_launches()
+    lp.eval_bbox_query(dkey, q.l, q.n_boxes, q.m, True, *args)
+    recs = lp.profile_collect_launches()
+    lp.profile_enable(False)
+    widths = lp.bbox_level_widths(q.l, q.n_boxes, q.m)
+    assert [r["name"] for r in recs] == ["blind_rotate", "keyswitch"] * len(widths)
+    assert [r["jobs"] for r in recs[0::2]] == widths
+    assert all(r["shape"] == lp.tune_pick(r["jobs"])["br_waves"] and r["ms"] > 0 for r in recs[0::2])
