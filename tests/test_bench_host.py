@@ -35,3 +35,11 @@ def test_missing_key_switch_record_keeps_levels_aligned():
     widths = [8, 8, 8, 8, 8]
     _, _, ph = bench.summarize_launches(records(widths, 2, skip_ks_at=1), len(widths), 1)
     assert ph == {"comparison": 11 + 11, "validation": 13 + 14 + 15, "hom_add_xor": 0.0}
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""

@@ -1,0 +1,38 @@
+"""The benchmark's output contract on the GPU: a short run of bench.py prints
+one JSON line with the fields the report is read from, a correct query, a
+roofline of the dominant kernel and the oracle timed beside it."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from gpu_common import cuda_or_skip
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_json_line():
+    cuda_or_skip()
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1", "--warmup", "1",
+                        "--no-micro", "--no-autotune"], capture_output=True, text=True, timeout=280, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 1 and d["warmup"] == 1 and d["value"] > 0
+    assert d["unit"] == "bootstraps/s" and d["higher_is_better"] is True and d["vs_baseline"] is None
+    assert d["correct_vs_predicate"] is True and "workload" in d["config"]
+    roof = d["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in roof, k
+    assert roof["bound"] == "alu" and 0 < roof["frac"] < 1.5 and roof["peak"] > 0
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
+    assert set(d["phases_ms"]) == {"comparison", "validation", "hom_add_xor"}
