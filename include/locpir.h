@@ -24,9 +24,11 @@
  * Errors: every call returns lp_status (0 on success, negative on error) and
  *   never throws; lp_last_error() gives a thread-local message for the last
  *   failing call of the calling thread.
- * Thread safety: handles are immutable after creation except for the query
- *   plan cache inside an lp_device_key, which is internally locked.  Calls
- *   that share an lp_device_key on different streams may run concurrently.
+ * Thread safety: handles are immutable after creation.  The library's own
+ *   caches (compiled query programs, launch-shape tables, twiddle tables)
+ *   are internally locked.  Calls that share an lp_device_key on different
+ *   streams may run concurrently; calls that share a stream and a compiled
+ *   program are serialised.
  */
 #ifndef LOCPIR_H
 #define LOCPIR_H
@@ -79,6 +81,10 @@ const char* lp_version(void);
 /* Default parameters: n = 630, lwe_sigma = 2^-15, N = 1024, k = 1,
  * bg_bit = 7, l = 3, bk_sigma = 2^-25, ks_base_bit = 2, ks_t = 8. */
 lp_status lp_params_default(lp_params* out);
+/* The paper's lambda 80 set (Sec. 5): n = 540, lwe_sigma = 2^-20.2; the
+ * paper gives nothing else for it, so the ring, gadget and key-switching
+ * parameters are the default ones. */
+lp_status lp_params_lambda80(lp_params* out);
 
 /* ---- client side (host) -------------------------------------------------- */
 

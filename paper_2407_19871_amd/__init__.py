@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
         "lp_last_error": (C.c_char_p, []),
         "lp_version": (C.c_char_p, []),
         "lp_params_default": (i32, [PP]),
+        "lp_params_lambda80": (i32, [PP]),
         "lp_keygen": (i32, [PP, u64, C.POINTER(vp), C.POINTER(vp)]),
         "lp_secret_key_import": (i32, [PP, vp, vp, C.POINTER(vp)]),
         "lp_secret_key_export": (i32, [vp, vp, vp]),
@@ -171,9 +172,8 @@ def params_default() -> Params:
 def params_lambda80() -> Params:
     """The paper's lambda 80 set (Sec. 5: n = 540, sigma = 2^-20.2); the
     ring, gadget and key-switching parameters are those of the default set."""
-    p = params_default()
-    p.n = 540
-    p.lwe_sigma = 2.0 ** -20.2
+    p = Params()
+    _check(lib().lp_params_lambda80(C.byref(p)))
     return p
 
 

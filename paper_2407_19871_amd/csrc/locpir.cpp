@@ -143,6 +143,12 @@ extern "C" lp_status lp_params_default(lp_params* out) {
   return LP_OK;
 }
 
+extern "C" lp_status lp_params_lambda80(lp_params* out) {
+  if (!out) return fail(LP_EINVAL, "null output");
+  *out = lp_params{540, 1024, 1, 7, 3, 2, 8, std::exp2(-20.2), std::ldexp(1.0, -25)};
+  return LP_OK;
+}
+
 // ---------------------------------------------------------------- KeyGen
 // B = A * S in Z_{2^32}[X]/(X^N + 1) for a binary S: B[j] = sum over set
 // bits t of S of (X^t A)[j].  With the sign-extended table
