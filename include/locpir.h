@@ -175,7 +175,9 @@ lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t* d_in, size
  *   d_bounds:    n_boxes x {x1, x2, y1, y2} x l ciphertexts
  *   d_payload:   n_boxes x m ciphertexts
  * d_out receives m ciphertexts.  The circuit is cut into depth levels; each
- * level is one batched bootstrap launch plus one key-switch launch. */
+ * level is one batched bootstrap launch plus one key-switch launch.
+ * LP_EINVAL for l outside 1..64, n_boxes outside 1..65536, m outside
+ * 1..4096 or a null input. */
 typedef struct {
   uint32_t l, n_boxes, m;
   int32_t is_signed;
