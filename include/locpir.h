@@ -144,7 +144,9 @@ lp_status lp_device_key_bytes(const lp_device_key* dk, size_t* bytes);
  * d_in1[k], d_in2[k]).  d_in1 is ignored for NOT/COPY; d_in2 is used by MUX
  * only.  All arrays are cnt*(n+1) uint32 on the key's device.  Every
  * bootstrapped gate runs the blind rotation, sample extraction and key
- * switching (MUX: two blind rotations, one key switch).  cnt = 0 is a no-op. */
+ * switching (MUX: two blind rotations, one key switch).  d_out may be one of
+ * the inputs (it is written by the key switch, after every input was read).
+ * cnt = 0 is a no-op. */
 lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
                              const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
                              uint32_t* d_out, void* stream);
@@ -154,7 +156,9 @@ lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32
  * takes: the sample extracted from the blind rotation of the gate's input
  * combination, or for MUX (0, 1/8) + u1 + u2 of its two rotations.
  * lp_keyswitch_batch of d_out_big equals lp_bootstrap_batch bit for bit.
- * NOT and COPY do not bootstrap: LP_EINVAL.  cnt = 0 is a no-op. */
+ * d_out_big (cnt*(N+1) uint32) must not overlap the inputs: the rotations
+ * write it while others still read theirs.  NOT and COPY do not bootstrap:
+ * LP_EINVAL.  cnt = 0 is a no-op. */
 lp_status lp_bootstrap_batch_noks(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
                                   const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
                                   uint32_t* d_out_big, void* stream);

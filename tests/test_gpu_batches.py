@@ -78,3 +78,13 @@ def test_gates_before_key_switching_edges(dkey):
     assert lp.bootstrap_batch_noks(dkey, "NAND", e, e).shape == (0, 1025)
     with pytest.raises(lp.LocpirError):
         lp.bootstrap_batch_noks(dkey, "NOT", lp.to_device(np.zeros((3, 631), np.uint32)))
+
+
+def test_gate_output_may_overwrite_an_input(okeys, dkey):
+    ins = [O.encrypt_bits(okeys, W.random_bits(230 + i, 50), seed=240 + i) for i in range(3)]
+    d = [lp.to_device(c) for c in ins]
+    nand = as_u32(lp.bootstrap_batch(dkey, "NAND", d[0], d[1]))
+    mux = as_u32(lp.bootstrap_batch(dkey, "MUX", d[0], d[1], d[2]))
+    lp.bootstrap_batch(dkey, "MUX", d[0], d[1], d[2], out=d[2])
+    lp.bootstrap_batch(dkey, "NAND", d[0], d[1], out=d[0])
+    assert (as_u32(d[2]) == mux).all() and (as_u32(d[0]) == nand).all()
