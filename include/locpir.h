@@ -164,7 +164,8 @@ lp_status lp_bootstrap_batch_noks(const lp_device_key* dk, lp_gate gate, const u
                                   uint32_t* d_out_big, void* stream);
 
 /* Key switching alone: d_in holds cnt extracted samples of N+1 words under
- * the ring key; d_out receives cnt samples of n+1 words under s. */
+ * the ring key; d_out receives cnt samples of n+1 words under s.  d_out must
+ * not overlap d_in. */
 lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,
                              uint32_t* d_out, void* stream);
 
