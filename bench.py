@@ -44,7 +44,9 @@ BR_JOB_BYTES = (2 * 631 + 1025) * 4
 # butterfly is 40 and a pointwise multiply-accumulate 35 lane-cycles.
 ALG_LANE_CYCLES_PER_BR = 630 * ((6 + 2) * 5120 * 40 + 12 * 1024 * 35)
 KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd/csrc/ntt32.h",
-                  "paper_2407_19871_amd/csrc/gl64.h"]
+                  "paper_2407_19871_amd/csrc/ntt64.h", "paper_2407_19871_amd/csrc/gl64.h"]
+# blind-rotation kernel of each launch shape (waves per bootstrap)
+SHAPE_KERNEL = {1: "blind_rotate_kernel<1>", 3: "blind_rotate_kernel<3>", 6: "blind_rotate_split_kernel"}
 TUNE_BUCKETS = (1, 16, 32, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16384)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_bbox16x16_traffic.txt")
 VALU_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_valu_issue.txt")
@@ -57,9 +59,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """Per-launch HBM bytes of the blind-rotation kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on this kernel."""
+def load_traffic(kernel: str):
+    """Per-launch HBM bytes of one blind-rotation kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on these
+    kernel sources."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     txt = open(TRAFFIC_SUMMARY).read()
@@ -69,7 +72,7 @@ def load_traffic():
     d = json.loads(m.group(1))
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return d
+    return d.get("kernels", {}).get(kernel)
 
 
 def load_valu():
@@ -146,6 +149,15 @@ def summarize_launches(launches, depth: int, l: int):
         per_level[level] += r["ms"]   # a key switch belongs to the rotation before it
     per_level /= max(1, n_rot // depth)
     br_ms = tot["blind_rotate"]["total_ms"]
+    # rotation launches by shape (waves per bootstrap), i.e. by kernel
+    by_shape = {}
+    for r in launches:
+        if r["name"] == "blind_rotate":
+            t = by_shape.setdefault(r["shape"], {"launches": 0, "jobs": 0, "total_ms": 0.0})
+            t["launches"] += 1
+            t["jobs"] += r["jobs"]
+            t["total_ms"] += r["ms"]
+    tot["blind_rotate_by_shape"] = by_shape
     phases = {"comparison": per_level[:l + 1].sum(), "validation": per_level[l + 1:l + 4].sum(),
               "hom_add_xor": per_level[l + 4:].sum()}
     return tot, (busy / br_ms if br_ms else None), {k: round(float(v), 2) for k, v in phases.items()}
@@ -513,24 +525,40 @@ def main():
 
     br = stats.get("blind_rotate", {"launches": 0, "jobs": 0, "total_ms": 0.0})
     ks = stats.get("keyswitch", {"launches": 0, "jobs": 0, "total_ms": 0.0})
-    achieved = ALG_LANE_CYCLES_PER_BR * br["jobs"] / (br["total_ms"] / 1e3) / 1e12 if br["total_ms"] else 0.0
-    traffic = load_traffic()
+    by_shape = stats.get("blind_rotate_by_shape", {})
+
+    def tops(jobs, ms):
+        return ALG_LANE_CYCLES_PER_BR * jobs / (ms / 1e3) / 1e12 if ms else 0.0
+
+    # the dominant kernel: the rotation shape with the most time in the query
+    dom = max(by_shape, key=lambda w: by_shape[w]["total_ms"]) if by_shape else 3
+    dk_ = by_shape.get(dom, {"launches": 0, "jobs": 0, "total_ms": 0.0})
+    dom_avg_ms = dk_["total_ms"] / max(1, dk_["launches"])
+    achieved = tops(dk_["jobs"], dk_["total_ms"])
+    traffic = load_traffic(SHAPE_KERNEL[dom])
     valu = load_valu()
     roofline = {
-        "bound": "alu", "kernel": "blind_rotate_kernel",
+        "bound": "alu", "kernel": SHAPE_KERNEL[dom],
         "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
         "frac": round(achieved / VALU_PEAK_TOPS, 4),
         "traffic": traffic["bytes_per_launch"] if traffic else None,
-        "avg_launch_ms": round(br["total_ms"] / max(1, br["launches"]), 3),
-        "bootstraps_per_launch": round(br["jobs"] / max(1, br["launches"]), 1),
+        "avg_launch_ms": round(dom_avg_ms, 3),
+        "bootstraps_per_launch": round(dk_["jobs"] / max(1, dk_["launches"]), 1),
         "op_unit": "32-bit VALU lane-cycles, 1.30e9 per bootstrap (algorithmic count)",
+        # every rotation launch of the query, by kernel, and all of them together
+        "by_kernel": {SHAPE_KERNEL[w]: {"launches": v["launches"], "jobs": v["jobs"],
+                                        "total_ms": round(v["total_ms"], 3),
+                                        "avg_launch_ms": round(v["total_ms"] / max(1, v["launches"]), 3),
+                                        "frac": round(tops(v["jobs"], v["total_ms"]) / VALU_PEAK_TOPS, 4)}
+                      for w, v in sorted(by_shape.items())},
+        "all_rotations_frac": round(tops(br["jobs"], br["total_ms"]) / VALU_PEAK_TOPS, 4),
         # HBM side of the same kernel: rocprofv3 bytes per launch over the live
         # launch time, and the algorithmic bytes (key once, job ciphertexts)
-        "hbm_gbs_rocprof": round(traffic["bytes_per_launch"] / (br["total_ms"] / max(1, br["launches"]) / 1e3) / 1e9, 2)
-        if traffic and br["total_ms"] else None,
-        "hbm_frac_rocprof": round(traffic["bytes_per_launch"] / (br["total_ms"] / max(1, br["launches"]) / 1e3) / 1e9
-                                  / HBM_PEAK_GBS, 5) if traffic and br["total_ms"] else None,
-        "alg_bytes_per_launch": int(BSK_NTT_BYTES + BR_JOB_BYTES * br["jobs"] / max(1, br["launches"])),
+        "hbm_gbs_rocprof": round(traffic["bytes_per_launch"] / (dom_avg_ms / 1e3) / 1e9, 2)
+        if traffic and dom_avg_ms else None,
+        "hbm_frac_rocprof": round(traffic["bytes_per_launch"] / (dom_avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 5)
+        if traffic and dom_avg_ms else None,
+        "alg_bytes_per_launch": int(BSK_NTT_BYTES + BR_JOB_BYTES * dk_["jobs"] / max(1, dk_["launches"])),
         # measured: rocprofv3 SQ_INSTS_VALU x 4 cycles / (kernel time x 2.4 GHz x 1024 SIMDs)
         "valu_issue_frac_rocprof": valu["query_valu_issue_frac"] if valu else None,
         # time-weighted share of the 1024 SIMDs holding a rotation wave (narrow

@@ -231,10 +231,17 @@ lp_status lp_bbox_wire_bytes(const lp_params* P, uint32_t l, uint32_t n_boxes, u
 lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_br, uint64_t* n_ks,
                          uint32_t* n_levels);
 /* Blind rotations per depth level of that circuit as the library schedules
- * it (signed shape; every gate as late as its consumers allow, so that the
- * comparator XNORs share the MUX levels).  widths: host array of *n_levels
- * entries on input; *n_levels receives the depth (entries beyond the
- * array are not written). */
+ * a lone query of the shape on the calling thread's current device (signed
+ * shape).  Only the comparators' XNORs have slack; they go either early
+ * (all at the first level, then l levels of MUXes alone) when that lets the
+ * MUX levels run as split rotations (br_waves 6, see lp_tune_entry) and a
+ * level holding MUXes and XNORs together could not, or late (each next to
+ * the MUX that uses it, as late as its consumers allow) otherwise; queries
+ * fused by lp_eval_bbox_batch and the server use the late placement.  The
+ * environment variable LOCPIR_XNOR_EARLY = 0 or 1 overrides the choice.
+ * The depth is the same either way.  widths: host array of *n_levels
+ * entries on input; *n_levels receives the depth (entries beyond the array
+ * are not written). */
 lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t m, uint32_t* widths, uint32_t* n_levels);
 
 /* ---- query server (continuous batching) ------------------------------------
@@ -333,14 +340,27 @@ typedef struct {
   double ms;
 } lp_launch_record;
 lp_status lp_profile_collect_launches(lp_launch_record* recs, int* count);
+/* Split blind rotations (br_waves 6) pair two workgroups that wait for each
+ * other's transforms every step; each wait is bounded (about a second of
+ * polling), so a partner that never arrives cannot hang the device.  Such a
+ * wait ends the job's exchange, its output is then undefined, and the
+ * current device's count of these events, since the library was loaded,
+ * goes up by one per wave.  Writes that count to *count (synchronous: waits
+ * for the device).  Pairing draws tickets on arrival, so the count stays 0
+ * unless other work holds every CU for the whole bound. */
+lp_status lp_split_stall_count(uint32_t* count);
 
 /* ---- launch-shape autotuning --------------------------------------------- */
 
 /* One row of a device's launch-shape table.  A launch of `count` jobs uses
  * the first row (rows sorted by `jobs`, ascending) with count <= jobs, or
  * the last row when count exceeds every bound.
- *   br_waves: waves cooperating on one blind rotation, 1 (throughput) or 3
- *             (one gadget level per wave, latency);
+ *   br_waves: waves cooperating on one blind rotation, 1 (throughput), 3
+ *             (one gadget level per wave, latency) or 6 (the rotation split
+ *             over two workgroups, normally two CUs, each owning one
+ *             accumulator component and trading forward transforms with
+ *             the other every step; lower latency again, for launches of at
+ *             most 128 rotations -- a wider launch that looks up 6 runs 3);
  *   ks_tile:  key switches per wave tile, 1, 4, 8 or 16;
  *   ks_split: ranges the ring index of a key switch is split into (partial
  *             sums added atomically), 1, 2, 4, 8 or 16;

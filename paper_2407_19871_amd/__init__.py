@@ -130,6 +130,7 @@ def lib() -> C.CDLL:
         "lp_profile_enable": (i32, [i32]),
         "lp_profile_collect": (i32, [C.POINTER(KernelStat), C.POINTER(C.c_int)]),
         "lp_profile_collect_launches": (i32, [C.POINTER(LaunchRecord), C.POINTER(C.c_int)]),
+        "lp_split_stall_count": (i32, [C.POINTER(u32)]),
         "lp_autotune": (i32, [vp, C.POINTER(u32), C.c_int, u32, vp, C.POINTER(TuneEntry)]),
         "lp_tune_set": (i32, [C.POINTER(TuneEntry), C.c_int]),
         "lp_tune_get": (i32, [C.POINTER(TuneEntry), C.POINTER(C.c_int)]),
@@ -459,6 +460,14 @@ def debug_blind_rotate(dk: DeviceKey, ct, steps: int, out=None, stream=None):
 
 
 # ------------------------------------------------------------------ profiling
+def split_stall_count() -> int:
+    """Waits of split blind rotations on the current device that ended
+    without their partner workgroup (0 in normal operation)."""
+    c = C.c_uint32(0)
+    _check(lib().lp_split_stall_count(C.byref(c)))
+    return int(c.value)
+
+
 def profile_enable(on: bool = True):
     _check(lib().lp_profile_enable(1 if on else 0))
 

@@ -75,8 +75,11 @@ struct Plan {
     return mx;
   }
 };
-// Cached plan of a shape (thread-safe).
-std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed);
+// Cached plan of a shape (thread-safe); xnor_early places the comparators'
+// XNORs all at the first level instead of next to the MUX that uses them.
+std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed, bool xnor_early);
+// The placement a lone query of this shape gets on the current device.
+bool choose_xnor_early(uint32_t l, uint32_t N);
 // Key-switch tile for a fused launch with per-key job counts.
 int fused_ks_tile(const std::vector<size_t>& per_key, size_t total);
 
@@ -91,7 +94,8 @@ inline int env_int(const char* name, int dflt) {
 }
 int pick_ks_tile(size_t njobs);
 int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe);
-// Waves per bootstrap: 3 (latency mode) for narrow launches, else 1.
+// Waves per bootstrap: 6 (split over two workgroups) up to kSplitMaxJobs,
+// 3 (one gadget level per wave) for other narrow launches, else 1.
 int pick_br_wpb(size_t njobs);
 // Built-in defaults (no environment, no table).
 int default_ks_tile(size_t njobs);

@@ -19,14 +19,39 @@ struct Twiddles {
 hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, Twiddles tw,
                              hipStream_t s);
 
+// Exchange area of split blind rotations (waves_per_job = 6: one bootstrap
+// on two workgroups that trade their forward transforms every step).  The
+// owner allocates it for at most max_jobs jobs per launch; the sync words
+// are zero before the first launch and every launch leaves them zero.  One
+// launch at a time may use an area.
+constexpr int kSplitMaxJobs = 128;
+struct SplitArea {
+  uint64_t* xbuf = nullptr;  // [job][role 2][step parity 2][level 3][1024] u64
+  uint32_t* sync = nullptr;  // tickets, finish count, then 8 flag words per job
+  int max_jobs = 0;
+};
+size_t split_xbuf_bytes(int max_jobs);
+size_t split_sync_bytes(int max_jobs);
+// Synchronous allocation (hipMalloc, zeroed); split_area_free releases it.
+hipError_t split_area_alloc(SplitArea* a, int max_jobs);
+void split_area_free(SplitArea* a);
+// Stream-ordered allocation (hipMallocAsync, cleared by a kernel) and release.
+hipError_t split_area_alloc_async(SplitArea* a, int max_jobs, hipStream_t s);
+hipError_t split_area_free_async(SplitArea* a, hipStream_t s);
+// Waits of split launches that ran out of polls on this device since the
+// process started (0 unless a partner workgroup never arrived).
+hipError_t split_stall_count(uint32_t* out);
+
 // Blind rotation + sample extraction (or raw accumulator output) of njobs
 // jobs.  ex: extract buffer, N+1 words per slot (2N per slot when raw_acc).
-// waves_per_job: 1 (one wave per bootstrap) or 3 (one wave per gadget level).
+// waves_per_job: 1 (one wave per bootstrap), 3 (one wave per gadget level)
+// or 6 (split over two workgroups; needs `split` with room for njobs).
 // d_pool_tab (may be null) resolves operands with base KEY_POOL_BASE to the
 // pool of the job's key.
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe,
-                               int steps, int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s);
+                               int steps, int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
+                               const SplitArea* split = nullptr);
 
 // Key switching of njobs jobs (tiles of `tile` consecutive jobs share one
 // key; jobs with ex0 == REF_NONE are padding and skipped); the ring index is

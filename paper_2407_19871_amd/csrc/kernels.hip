@@ -24,6 +24,7 @@
 #include "jobs.h"
 #include "kernels.h"
 #include "ntt32.h"
+#include "ntt64.h"
 
 namespace lp {
 
@@ -125,6 +126,61 @@ __device__ __forceinline__ void ntt_inv(uint64_t (&f)[32], uint32_t* buf, const 
   twist(f, tw_i, l);
   transpose32(f, buf, l);
   inv1(f);
+}
+
+// ---- whole-wave transforms (layout of ntt64.h) ------------------------------
+// 32 x 32 transpose of one polynomial held by a whole wave: on entry lane
+// (h, l) slot s holds element (l, 2s + h) of the matrix; on exit element
+// (2s + h, l).  Two 32-bit passes through a 32 x 33 word block.
+__device__ __forceinline__ void transpose64(uint64_t (&a)[16], uint32_t* buf, int h, int l) {
+  uint32_t lo[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)a[s];
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) lo[s] = buf[(2 * s + h) * ROW + l];
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)(a[s] >> 32);
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) a[s] = ((uint64_t)buf[(2 * s + h) * ROW + l] << 32) | lo[s];
+  wave_fence();
+}
+
+// Slot s of lane (h, l) times tw[(2s + h) * 32 + l] (the 32-lane tables,
+// position 2s + h standing for the 32-lane slot); for each slot the wave
+// reads 64 consecutive entries.
+__device__ __forceinline__ void twist64(uint64_t (&f)[16], const uint64_t* __restrict__ tw, int lane) {
+  const gmem_u64* t = as_global(tw) + lane;
+  uint64_t w[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) w[s] = t[s * 64];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], w[s]);
+}
+
+// Forward transform of gadget digits: in, slot s of lane (h, l) holds
+// coefficient l + 32 (2s + h); out, the value at offset 64 s + 2 l + h of
+// the NTT-domain key layout.
+__device__ __forceinline__ void ntt64_fwd_digits(const int32_t (&d)[16], uint64_t (&f)[16], uint32_t* buf,
+                                                 const uint64_t* __restrict__ tw_f, int lane) {
+  const int h = lane >> 5, l = lane & 31;
+  fwd64_p1_digits(d, f);
+  fwd64_p1_rest(f, lane);
+  twist64(f, tw_f, lane);
+  transpose64(f, buf, h, l);
+  fwd64_p2(f, lane);
+}
+
+// Inverse of ntt64_fwd_digits including the 1/1024 scaling.
+__device__ __forceinline__ void ntt64_inv(uint64_t (&f)[16], uint32_t* buf, const uint64_t* __restrict__ tw_i,
+                                          int lane) {
+  const int h = lane >> 5, l = lane & 31;
+  inv64_p2(f, lane);
+  twist64(f, tw_i, lane);
+  transpose64(f, buf, h, l);
+  inv64_p1(f, lane);
 }
 
 // Offset of (slot s, lane l) inside one NTT-domain polynomial.
@@ -322,6 +378,207 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Split blind rotation: one bootstrap on two workgroups of three waves,
+// normally on two CUs of one XCD, for levels too narrow to fill the GPU.
+// Workgroup role c owns accumulator component c (0 = mask A, 1 = body B);
+// its wave j runs gadget level j with whole-wave transforms (ntt64.h).
+// Output component c of level j needs the level-j transforms of both
+// components,
+//   P_(c,j) = NTT(d_(c,j)) BSK[(c,j)][c] + NTT(d_(1-c,j)) BSK[(1-c,j)][c],
+// so every step each wave publishes its forward transform and reads its
+// partner wave's through L2:
+//   1. D_c = X^a ACC_c - ACC_c, digits of level j -> forward NTT F_(c,j);
+//   2. store F_(c,j) in this role's exchange slot, then raise the wave's
+//      flag to the step count; wait for the partner's flag; load F_(1-c,j);
+//   3. P_(c,j) -> inverse NTT -> centred lift -> ACC_c += (LDS atomics).
+// Exchange data and flags use agent-scope relaxed atomics (coherent across
+// the CUs and XCDs of the device, no cache maintenance); a full vector
+// memory wait orders the data before the flag, and the data loads depend on
+// the observed flag.  Slots alternate by the parity of the executed-step
+// count: a role rewrites a slot only after the partner has raised its flag
+// for the following step, which it does after its loads of that slot.
+//
+// Pairing: each workgroup draws a ticket on arrival; tickets t and t ^ 8 of
+// a block of 16 form a pair (job 8 (t >> 4) + (t & 7), role (t >> 3) & 1),
+// so a workgroup only ever waits for one of the next 15 arrivals (no
+// co-residency assumption), and with round-robin dispatch over the eight
+// XCDs both halves of a pair usually share an L2.  Every wait is bounded:
+// a partner missing for SPLIT_SPIN_LIMIT polls ends the wait, counts in
+// g_split_stalls, and the job's output is then undefined; the kernel still
+// exits.  The last workgroup to finish clears the tickets and flags.
+constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
+constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
+
+__device__ uint32_t g_split_stalls;
+
+__device__ __forceinline__ void vm_wait_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
+    const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
+    const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
+    int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
+    uint32_t* __restrict__ sync) {
+  __shared__ uint32_t s_acc[RING_N];
+  __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
+  __shared__ uint16_t s_abar[MAX_LWE + 4];
+  __shared__ uint32_t s_ticket, s_last;
+
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(sync, 1u);
+  __syncthreads();
+  const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_ticket);
+  const int job = (int)((t >> 4) * 8 + (t & 7));
+  const int c = (int)((t >> 3) & 1);
+
+  if (job < njobs) {
+    const BrJob J = jobs[job];
+    uint32_t* buf = s_tr[wave];
+    {
+      auto operand = [&](uint32_t r) -> const uint32_t* {
+        if (r == REF_NONE) return nullptr;
+        const uint32_t base = r >> REF_SHIFT;
+        const uint32_t* b = base == KEY_POOL_BASE ? pool_tab[J.key] : src.p[base];
+        return b + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
+      };
+      const uint32_t* in0 = operand(J.in0);
+      const uint32_t* in1 = operand(J.in1);
+      for (int k = threadIdx.x; k <= n_lwe; k += 192) {
+        uint32_t v = (k == n_lwe) ? J.cst : 0u;
+        if (in0) v += (uint32_t)J.c0 * in0[k];
+        if (in1) v += (uint32_t)J.c1 * in1[k];
+        s_abar[k] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
+      }
+    }
+    __syncthreads();
+    // ACC_0 = 0, ACC_1 = X^{-b} v (coefficient j: +1/8 if (j + b) mod 2N < N)
+    const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
+    for (int j = threadIdx.x; j < RING_N; j += 192)
+      s_acc[j] = c == 0 ? 0u : ((((uint32_t)j + bbar) & 2047u) < 1024u ? 0x20000000u : 0xE0000000u);
+    __syncthreads();
+
+    const gmem_u64* bsk = as_global(bsk_tab[J.key]);
+    const int nsteps = steps < n_lwe ? steps : n_lwe;
+    uint64_t* my_x = xbuf + ((size_t)(job * 2 + c) * 6 + wave) * RING_N;
+    const uint64_t* peer_x = xbuf + ((size_t)(job * 2 + (1 - c)) * 6 + wave) * RING_N;
+    uint32_t* my_flag = sync + SPLIT_FLAGS + job * 8 + c * 4 + wave;
+    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * 8 + (1 - c) * 4 + wave;
+    const int sh = 25 - 7 * wave;
+    uint32_t done = 0;  // executed steps, the same count in both roles
+    bool stalled = false;
+
+    for (int i = 0; i < nsteps; ++i) {
+      const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
+      if (a == 0) continue;  // X^0 ACC - ACC = 0: no digits, no exchange
+
+      // key rows (c, j) and (1-c, j), component c, at this lane's offsets
+      const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+      const gmem_u64* ko = step_key + (size_t)((c * 3 + wave) * 2 + c) * RING_N + 2 * l + h;
+      const gmem_u64* kt = step_key + (size_t)(((1 - c) * 3 + wave) * 2 + c) * RING_N + 2 * l + h;
+      uint64_t kown[16], koth[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        kown[s] = ko[s * 64];
+        koth[s] = kt[s * 64];
+      }
+
+      int32_t dg[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const uint32_t j = (uint32_t)(l + 32 * (2 * s + h));
+        const uint32_t e = (j - a) & 2047u;
+        const uint32_t v = s_acc[e & 1023u];
+        const uint32_t D = ((e & 1024u) ? (0u - v) : v) - s_acc[j];
+        dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+      }
+      __syncthreads();  // every wave has read ACC_c before any adds to it
+      uint64_t f[16];
+      ntt64_fwd_digits(dg, f, buf, opaque(tw_f), lane);
+
+      const size_t par = (size_t)(done & 1u) * 3 * RING_N;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
+      vm_wait_all();
+      if (lane == 0) store_agent(my_flag, done + 1);
+      if (!stalled) {
+        int it = 0;
+        while (load_agent(peer_flag) < done + 1) {
+          if (++it == SPLIT_SPIN_LIMIT) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (it == SPLIT_SPIN_LIMIT) {
+          stalled = true;
+          if (lane == 0) atomicAdd(&g_split_stalls, 1u);
+        }
+      }
+      vm_wait_all();
+      uint64_t g[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) f[s] = gl_mul_sum(f[s], kown[s], g[s], koth[s]);
+
+      // the level's partial is an exact integer polynomial (|coefficient| <
+      // 2^49), so lifting each partial and adding mod 2^32 is exact
+      ntt64_inv(f, buf, opaque(tw_i), lane);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) atomicAdd(&s_acc[l + 32 * (2 * s + h)], gl_lift_u32(f[s]));
+      ++done;
+      __syncthreads();
+    }
+
+    if (raw_acc) {
+      uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
+      for (int j = threadIdx.x; j < RING_N; j += 192) o[j] = s_acc[j];
+    } else {
+      // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
+      uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
+      if (c == 0) {
+        for (int j = threadIdx.x; j < RING_N; j += 192) {
+          if (j == 0) o[0] = s_acc[0];
+          else o[RING_N - j] = 0u - s_acc[j];
+        }
+      } else if (threadIdx.x == 0) {
+        o[RING_N] = s_acc[0];
+      }
+    }
+  }
+
+  // the last workgroup to finish clears the tickets and flags for the next
+  // launch on this area (every other one has finished using them)
+  vm_wait_all();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(sync + 1, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (s_last) {
+    const int nflags = (int)(gridDim.x / 2) * 8;
+    for (int k = threadIdx.x; k < nflags; k += 192) store_agent(sync + SPLIT_FLAGS + k, 0u);
+    if (threadIdx.x == 0) {
+      store_agent(sync, 0u);
+      store_agent(sync + 1, 0u);
+    }
+  }
+}
+
+__global__ void split_area_clear_kernel(uint32_t* sync, int words) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < words) sync[k] = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // Key switching: a tile of T jobs x 64 output columns per wave.  For every
 // (i, j) the wave reads the base-1 KSK rows of that digit position once and
 // each job of the tile subtracts the row its digit selects.  With
@@ -495,7 +752,8 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
 
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
-                               int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s) {
+                               int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
+                               const SplitArea* split) {
   if (njobs <= 0) return hipSuccess;
   switch (waves_per_job) {
     case 1:
@@ -506,10 +764,77 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       hipLaunchKernelGGL(blind_rotate_kernel<3>, dim3(njobs), dim3(192), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
+    case 6: {
+      if (!split || !split->xbuf || !split->sync || njobs > split->max_jobs) return hipErrorInvalidValue;
+      const int grid = 16 * ((njobs + 7) / 8);
+      hipLaunchKernelGGL(blind_rotate_split_kernel, dim3(grid), dim3(192), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
+                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync);
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+static int split_jobs_padded(int max_jobs) { return (max_jobs + 7) / 8 * 8; }
+size_t split_xbuf_bytes(int max_jobs) { return (size_t)split_jobs_padded(max_jobs) * 12 * RING_N * 8; }
+size_t split_sync_bytes(int max_jobs) { return (size_t)(SPLIT_FLAGS + split_jobs_padded(max_jobs) * 8) * 4; }
+
+hipError_t split_area_alloc(SplitArea* a, int max_jobs) {
+  if (!a || max_jobs < 1 || max_jobs > kSplitMaxJobs) return hipErrorInvalidValue;
+  *a = SplitArea{};
+  hipError_t e = hipMalloc((void**)&a->xbuf, split_xbuf_bytes(max_jobs));
+  if (e == hipSuccess) e = hipMalloc((void**)&a->sync, split_sync_bytes(max_jobs));
+  if (e == hipSuccess) e = hipMemset(a->sync, 0, split_sync_bytes(max_jobs));
+  if (e != hipSuccess) {
+    split_area_free(a);
+    return e;
+  }
+  a->max_jobs = max_jobs;
+  return hipSuccess;
+}
+
+void split_area_free(SplitArea* a) {
+  if (!a) return;
+  if (a->xbuf) (void)hipFree(a->xbuf);
+  if (a->sync) (void)hipFree(a->sync);
+  *a = SplitArea{};
+}
+
+hipError_t split_area_alloc_async(SplitArea* a, int max_jobs, hipStream_t s) {
+  if (!a || max_jobs < 1 || max_jobs > kSplitMaxJobs) return hipErrorInvalidValue;
+  *a = SplitArea{};
+  hipError_t e = hipMallocAsync((void**)&a->xbuf, split_xbuf_bytes(max_jobs), s);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&a->sync, split_sync_bytes(max_jobs), s);
+  if (e == hipSuccess) {
+    const int words = (int)(split_sync_bytes(max_jobs) / 4);
+    hipLaunchKernelGGL(split_area_clear_kernel, dim3((words + 255) / 256), dim3(256), 0, s, a->sync, words);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    (void)split_area_free_async(a, s);
+    return e;
+  }
+  a->max_jobs = max_jobs;
+  return hipSuccess;
+}
+
+hipError_t split_area_free_async(SplitArea* a, hipStream_t s) {
+  if (!a) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (a->xbuf) e = hipFreeAsync(a->xbuf, s);
+  if (a->sync) {
+    const hipError_t e2 = hipFreeAsync(a->sync, s);
+    if (e == hipSuccess) e = e2;
+  }
+  *a = SplitArea{};
+  return e;
+}
+
+hipError_t split_stall_count(uint32_t* out) {
+  if (!out) return hipErrorInvalidValue;
+  return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_split_stalls), sizeof(uint32_t), 0, hipMemcpyDeviceToHost);
 }
 
 template <int T>

@@ -509,6 +509,13 @@ namespace {
 const char* kProfNames[lp::kProfKinds] = {"blind_rotate", "keyswitch"};
 }
 
+extern "C" lp_status lp_split_stall_count(uint32_t* count) {
+  if (!count) return fail(LP_EINVAL, "lp_split_stall_count: null argument");
+  LP_HIP_TRY(hipDeviceSynchronize());
+  LP_HIP_TRY(lp::split_stall_count(count));
+  return LP_OK;
+}
+
 extern "C" lp_status lp_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
@@ -684,10 +691,13 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   src.p[2] = d_in2;
   lp::DstBases dst{};
   dst.p[0] = d_out;
+  const int waves = pick_br_wpb(nbr);
+  lp::SplitArea split;  // stream-ordered, freed below
+  if (e == hipSuccess && waves == 6) e = lp::split_area_alloc_async(&split, (int)nbr, s);
   if (e == hipSuccess) {
-    const int waves = pick_br_wpb(nbr);
     ProfScope ps(kProfBR, nbr, waves, s);
-    e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, waves, s);
+    e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, waves, s,
+                                &split);
   }
   if (e == hipSuccess && with_ks) {
     const int tile = pick_ks_tile(cnt);
@@ -699,6 +709,8 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
     e = lp::launch_lwe_pair_sum(ex, d_out, cnt, (int)N + 1, 0x20000000u, s);
   }
   hipError_t e2 = hipFreeAsync(scratch, s);
+  const hipError_t e3 = lp::split_area_free_async(&split, s);
+  if (e2 == hipSuccess) e2 = e3;
   if (e != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e2));
   return LP_OK;
@@ -791,11 +803,16 @@ extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32
   lp::SrcBases src{};
   src.p[0] = d_in;
   const int st = (int)std::min<uint32_t>(steps, dk->P.n);
+  const int waves = pick_br_wpb(cnt);
+  lp::SplitArea split;
+  if (e == hipSuccess && waves == 6) e = lp::split_area_alloc_async(&split, (int)cnt, s);
   if (e == hipSuccess)
-    e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, nullptr, (int)dk->P.n, st, 1, dk->tw,
-                                pick_br_wpb(cnt), s);
+    e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, nullptr, (int)dk->P.n, st, 1, dk->tw, waves, s,
+                                &split);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipError_t e2 = hipFreeAsync(dj, s);
+  const hipError_t e3 = lp::split_area_free_async(&split, s);
+  if (e2 == hipSuccess) e2 = e3;
   if (e != hipSuccess || e2 != hipSuccess) return fail(LP_EDEVICE, "lp_debug_blind_rotate: %s", hipGetErrorString(e != hipSuccess ? e : e2));
   return LP_OK;
 }

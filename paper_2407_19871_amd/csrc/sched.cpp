@@ -136,7 +136,7 @@ void combo(int kind, uint32_t* cst, int32_t* c0, int32_t* c1) {
 }
 
 // ---------------------------------------------------------------- plans
-std::shared_ptr<const Plan> make_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed) {
+std::shared_ptr<const Plan> make_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed, bool xnor_early) {
   Circuit C = build_bbox(l, N, m, is_signed != 0);
   auto P = std::make_shared<Plan>();
   P->l = l;
@@ -147,13 +147,18 @@ std::shared_ptr<const Plan> make_plan(uint32_t l, uint32_t N, uint32_t m, int is
   P->n_slots = (uint32_t)C.n_slots;
   int depth = 0;
   for (auto& g : C.gates) depth = std::max(depth, g.level);
-  // As late as possible: a gate runs at depth + 1 - (longest path from it to
-  // an output, in gates).  The depth is unchanged and every producer stays
-  // at a lower level than its consumers, but gates off the critical path
-  // move next to their consumers: XNOR of comparator bit i joins the level
-  // of the MUX of bit i-1 instead of piling up at level 1, so no level is
-  // wider than it needs to be.  Gates are stored in topological order.
-  {
+  // Two placements of the gates off the critical path (the comparators'
+  // XNORs; every other gate has no slack), with the same depth:
+  //   early (as soon as possible, the level from the inputs): every XNOR at
+  //     level 1, then l levels of MUXes alone (2 bootstraps per comparator);
+  //   late (as late as possible: depth + 1 - the longest path from the gate
+  //     to an output, in gates): the XNOR of comparator bit i joins the
+  //     level of the MUX of bit i-1, so no level is wider than 3 bootstraps
+  //     per comparator.
+  // Early suits a device on which the narrower MUX levels run faster per
+  // launch than the mixed ones (split rotations); late keeps every level
+  // narrow.  Gates are stored in topological order.
+  if (!xnor_early) {
     std::vector<int> producer((size_t)C.n_slots, -1);
     for (size_t k = 0; k < C.gates.size(); ++k) producer[(size_t)C.gates[k].out] = (int)k;
     std::vector<int> height(C.gates.size(), 1);
@@ -223,17 +228,30 @@ std::shared_ptr<const Plan> make_plan(uint32_t l, uint32_t N, uint32_t m, int is
 }
 
 std::mutex g_plan_mu;
-std::map<std::tuple<uint32_t, uint32_t, uint32_t, int>, std::shared_ptr<const Plan>> g_plans;
+std::map<std::tuple<uint32_t, uint32_t, uint32_t, int, bool>, std::shared_ptr<const Plan>> g_plans;
 }  // namespace
 
-std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed) {
+std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed, bool xnor_early) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
-  auto key = std::make_tuple(l, N, m, is_signed);
+  auto key = std::make_tuple(l, N, m, is_signed, xnor_early);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) return it->second;
-  auto P = make_plan(l, N, m, is_signed);
+  auto P = make_plan(l, N, m, is_signed, xnor_early);
   g_plans[key] = P;
   return P;
+}
+
+// A single query's XNORs go early when that is what lets its MUX levels
+// (2 bootstraps per comparator, 4N comparators) run as split rotations,
+// which the mixed levels (3 per comparator) cannot; otherwise late.  On
+// MI355X a split launch takes about 0.73 of a one-level-per-wave one, and
+// the early level 1 (l XNORs per comparator) costs less than the l - 1
+// levels gain.  LOCPIR_XNOR_EARLY = 0 or 1 overrides.
+bool choose_xnor_early(uint32_t l, uint32_t N) {
+  const int forced = env_int("LOCPIR_XNOR_EARLY", -1);
+  if (forced == 0 || forced == 1) return forced == 1;
+  const size_t comparators = 4 * (size_t)N;
+  return l >= 2 && pick_br_wpb(2 * comparators) == 6 && pick_br_wpb(3 * comparators) != 6;
 }
 
 namespace {
@@ -260,6 +278,7 @@ struct Program {
   uint32_t* pool = nullptr;
   uint32_t* ex = nullptr;
   Twiddles tw{};
+  SplitArea split;  // exchange area of the levels that run split rotations
   hipStream_t capture = nullptr;
   std::vector<hipGraphExec_t> g_br, g_ks;
   bool graphs_ready = false;
@@ -273,6 +292,7 @@ struct Program {
     for (void* p : {(void*)d_br, (void*)d_ks, (void*)d_bsk_tab, (void*)d_ksk_tab, (void*)d_out_refs, (void*)pool,
                     (void*)ex})
       if (p) (void)hipFree(p);
+    split_area_free(&split);
   }
 };
 
@@ -380,6 +400,10 @@ lp_status build_program(const std::vector<const lp_device_key*>& keys,
   LP_HIP_TRY(hipMemcpy(G->d_bsk_tab, bsk_tab.data(), nq * sizeof(void*), hipMemcpyHostToDevice));
   LP_HIP_TRY(hipMemcpy(G->d_ksk_tab, ksk_tab.data(), nq * sizeof(void*), hipMemcpyHostToDevice));
   LP_HIP_TRY(hipMemcpy(G->d_out_refs, out_refs.data(), out_refs.size() * 4, hipMemcpyHostToDevice));
+  int split_jobs = 0;
+  for (int L = 0; L < depth; ++L)
+    if (G->br_waves[L] == 6) split_jobs = std::max(split_jobs, G->br_cnt[L]);
+  if (split_jobs > 0) LP_HIP_TRY(split_area_alloc(&G->split, split_jobs));
   *out = G;
   return LP_OK;
 }
@@ -388,7 +412,7 @@ hipError_t launch_level_br(const Program& G, int L, hipStream_t s) {
   SrcBases src{};
   src.p[0] = G.pool;
   return launch_blind_rotate(G.d_br + G.br_off[L], G.br_cnt[L], src, G.ex, G.d_bsk_tab, nullptr, (int)G.n_lwe,
-                             (int)G.n_lwe, 0, G.tw, G.br_waves[L], s);
+                             (int)G.n_lwe, 0, G.tw, G.br_waves[L], s, &G.split);
 }
 
 hipError_t launch_level_ks(const Program& G, int L, hipStream_t s) {
@@ -488,9 +512,11 @@ lp_status get_program(const std::vector<const lp_device_key*>& keys, const lp_bb
     *out = it->second;
     return LP_OK;
   }
+  // placement: chosen for a lone query; fused queries keep every level narrow
+  const bool early = keys.size() == 1 && choose_xnor_early(qs[0].l, qs[0].n_boxes);
   std::vector<std::shared_ptr<const Plan>> plans;
   for (size_t k = 0; k < keys.size(); ++k)
-    plans.push_back(get_plan(qs[k].l, qs[k].n_boxes, qs[k].m, qs[k].is_signed ? 1 : 0));
+    plans.push_back(get_plan(qs[k].l, qs[k].n_boxes, qs[k].m, qs[k].is_signed ? 1 : 0, early));
   std::shared_ptr<Program> G;
   lp_status st = build_program(keys, plans, &G);
   if (st != LP_OK) return st;
@@ -535,7 +561,7 @@ void sched_forget_key(const lp_device_key* dk) {
 
 // Host-side plan statistics for the server and the counts entry point.
 void plan_counts(uint32_t l, uint32_t N, uint32_t m, uint64_t* n_br, uint64_t* n_ks, uint32_t* levels) {
-  auto P = get_plan(l, N, m, 1);
+  auto P = get_plan(l, N, m, 1, false);
   if (n_br) *n_br = P->n_br;
   if (n_ks) *n_ks = P->n_ks;
   if (levels) *levels = (uint32_t)P->levels();
@@ -554,7 +580,7 @@ extern "C" lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t
                                           uint32_t* n_levels) {
   if (l == 0 || l > 64 || n_boxes == 0 || m == 0) return lp::fail(LP_EINVAL, "lp_bbox_level_widths: empty shape");
   if (!n_levels || (*n_levels > 0 && !widths)) return lp::fail(LP_EINVAL, "lp_bbox_level_widths: null argument");
-  auto P = lp::get_plan(l, n_boxes, m, 1);
+  auto P = lp::get_plan(l, n_boxes, m, 1, lp::choose_xnor_early(l, n_boxes));
   const uint32_t depth = (uint32_t)P->levels();
   for (uint32_t k = 0; k < depth && k < *n_levels; ++k) widths[k] = (uint32_t)P->br[k].size();
   *n_levels = depth;

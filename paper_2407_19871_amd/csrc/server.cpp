@@ -94,6 +94,7 @@ struct lp_server {
   size_t cap_kt = 0;
   uint32_t** d_pool_tab = nullptr;
   size_t cap_pt = 0;
+  lp::SplitArea split;  // exchange area of split rotations, made at first use
 };
 
 namespace {
@@ -226,11 +227,19 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, u
   lp::SrcBases src{};
   lp::DstBases dst{};
   const lp::Twiddles tw = act[0]->dk->tw;
+  const int waves = lp::pick_br_wpb(br.size());
+  if (e == hipSuccess && waves == 6 && S->split.max_jobs < (int)br.size()) {
+    // ticks run one at a time, so the previous area is idle once the stream is
+    e = hipStreamSynchronize(S->stream);
+    if (e == hipSuccess) {
+      lp::split_area_free(&S->split);
+      e = lp::split_area_alloc(&S->split, lp::kSplitMaxJobs);
+    }
+  }
   if (e == hipSuccess) {
-    const int waves = lp::pick_br_wpb(br.size());
     lp::ProfScope ps(lp::kProfBR, br.size(), waves, S->stream);
     e = lp::launch_blind_rotate(S->d_br, (int)br.size(), src, S->ex, S->d_bsk_tab, S->d_pool_tab, (int)Pp.n, (int)Pp.n,
-                                0, tw, waves, S->stream);
+                                0, tw, waves, S->stream, &S->split);
   }
   if (e == hipSuccess) {
     lp::ProfScope ps(lp::kProfKS, ks.size(), tile, S->stream);
@@ -363,7 +372,7 @@ extern "C" lp_status lp_server_request_bytes(const lp_cloud_key* ck, const lp_bb
   if (!ck || !bytes) return lp::fail(LP_EINVAL, "lp_server_request_bytes: null argument");
   lp_status st = check_host_query(q);
   if (st != LP_OK) return st;
-  *bytes = request_bytes(ck->P, *lp::get_plan(q->l, q->n_boxes, q->m, q->is_signed ? 1 : 0));
+  *bytes = request_bytes(ck->P, *lp::get_plan(q->l, q->n_boxes, q->m, q->is_signed ? 1 : 0, false));
   return LP_OK;
 }
 
@@ -380,7 +389,7 @@ extern "C" lp_status lp_server_submit(lp_server* S, const lp_cloud_key* ck, cons
   r->N = q->n_boxes;
   r->m = q->m;
   r->is_signed = q->is_signed ? 1 : 0;
-  r->plan = lp::get_plan(r->l, r->N, r->m, r->is_signed);
+  r->plan = lp::get_plan(r->l, r->N, r->m, r->is_signed, false);
   r->bytes = request_bytes(ck->P, *r->plan);
   if (r->bytes > S->cfg.hbm_budget)
     return lp::fail(LP_EBUDGET, "lp_server_submit: request needs %zu bytes, budget is %zu", r->bytes,
@@ -456,6 +465,7 @@ extern "C" void lp_server_free(lp_server* S) {
     for (void* p : {(void*)S->d_br, (void*)S->d_ks, (void*)S->ex, (void*)S->d_bsk_tab, (void*)S->d_ksk_tab,
                     (void*)S->d_pool_tab})
       if (p) (void)hipFree(p);
+    lp::split_area_free(&S->split);
     if (S->stream) (void)hipStreamDestroy(S->stream);
   }
   delete S;

@@ -2,8 +2,10 @@
 //
 // Two shapes decide how a level of gates runs: the number of waves that
 // cooperate on one blind rotation (1: independent bootstraps fill the GPU;
-// 3: one gadget level per wave, for levels too narrow to fill it) and the
-// key-switch tile and ring-index split.  The best choice depends on the
+// 3: one gadget level per wave, for levels too narrow to fill it; 6: the
+// bootstrap split over two workgroups, one accumulator component each, for
+// levels of at most kSplitMaxJobs jobs) and the key-switch tile and
+// ring-index split.  The best choice depends on the
 // job count, so the autotuner times every shape at a set of batch sizes on
 // the device itself and installs the fastest per size as that device's
 // table; every launch then looks its job count up in the table.
@@ -23,7 +25,7 @@ std::map<int, std::vector<lp_tune_entry>> g_tune;  // device -> rows sorted by j
 
 constexpr uint32_t kMaxTuneJobs = 1u << 22;      // row bound
 constexpr uint32_t kMaxTuneBucket = 1u << 16;    // batch size the autotuner times
-const int kWaves[] = {1, 3};
+const int kWaves[] = {1, 3, 6};
 const int kTiles[] = {1, 4, 8, 16};
 const int kSplits[] = {1, 2, 4, 8, 16};
 
@@ -34,7 +36,7 @@ bool one_of(int v, const int* set, int n) {
 }
 
 bool row_ok(const lp_tune_entry& r) {
-  return r.jobs >= 1 && r.jobs <= kMaxTuneJobs && one_of(r.br_waves, kWaves, 2) && one_of(r.ks_tile, kTiles, 4) &&
+  return r.jobs >= 1 && r.jobs <= kMaxTuneJobs && one_of(r.br_waves, kWaves, 3) && one_of(r.ks_tile, kTiles, 4) &&
          one_of(r.ks_split, kSplits, 5);
 }
 
@@ -82,7 +84,7 @@ int default_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   return sp;
 }
 
-int default_br_wpb(size_t njobs) { return njobs <= 512 ? 3 : 1; }
+int default_br_wpb(size_t njobs) { return njobs <= (size_t)kSplitMaxJobs ? 6 : njobs <= 512 ? 3 : 1; }
 
 int pick_ks_tile(size_t njobs) {
   const int t = env_int("LOCPIR_KS_TILE", 0);
@@ -102,11 +104,14 @@ int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   return default_ks_split(njobs, tile, n_lwe);
 }
 
+// A split shape (6) applies up to kSplitMaxJobs jobs; a wider launch that
+// looks it up (the table's last row, or a forced shape) takes 3 instead.
 int pick_br_wpb(size_t njobs) {
+  auto fit = [&](int w) { return w == 6 && njobs > (size_t)kSplitMaxJobs ? 3 : w; };
   const int forced = env_int("LOCPIR_BR_WAVES", 0);
-  if (one_of(forced, kWaves, 2)) return forced;
+  if (one_of(forced, kWaves, 3)) return fit(forced);
   lp_tune_entry r;
-  if (tuned_row(njobs, &r)) return r.br_waves;
+  if (tuned_row(njobs, &r)) return fit(r.br_waves);
   return default_br_wpb(njobs);
 }
 
@@ -165,9 +170,11 @@ struct TuneBuffers {
   lp::BrJob* br = nullptr;
   lp::KsJob* ks = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
+  lp::SplitArea split;
   ~TuneBuffers() {
     for (void* p : {(void*)in, (void*)ex, (void*)out, (void*)br, (void*)ks})
       if (p) (void)hipFree(p);
+    lp::split_area_free(&split);
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
   }
@@ -199,6 +206,8 @@ extern "C" lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket
   LP_HIP_TRY(hipMalloc(&B.ks, maxB * sizeof(lp::KsJob)));
   LP_HIP_TRY(hipEventCreate(&B.t0));
   LP_HIP_TRY(hipEventCreate(&B.t1));
+  if (sizes.front() <= (uint32_t)lp::kSplitMaxJobs)
+    LP_HIP_TRY(lp::split_area_alloc(&B.split, (int)std::min<size_t>(maxB, lp::kSplitMaxJobs)));
   {
     std::vector<uint32_t> h(2 * maxB * w);
     uint64_t st = 0x5EED0F7A11ull;
@@ -233,11 +242,12 @@ extern "C" lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket
     r.jobs = jobs;
     float best = -1.f;
     for (int W : lp::kWaves) {
+      if (W == 6 && jobs > (uint32_t)lp::kSplitMaxJobs) continue;
       float ms = 0.f;
       lp_status st = time(
           [&] {
             return lp::launch_blind_rotate(B.br, (int)jobs, src, B.ex, dk->bsk_tab, nullptr, (int)n, (int)br_steps, 0,
-                                           dk->tw, W, s);
+                                           dk->tw, W, s, &B.split);
           },
           2, &ms);
       if (st != LP_OK) return st;
@@ -264,7 +274,7 @@ extern "C" lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket
                                                   (int)dk->P.ks_t, (int)dk->P.ks_base_bit, T, S, s);
               if (e != hipSuccess) return e;
               return lp::launch_blind_rotate(B.br, (int)jobs, src, B.ex, dk->bsk_tab, nullptr, (int)n, (int)br_steps,
-                                             0, dk->tw, r.br_waves, s);
+                                             0, dk->tw, r.br_waves, s, &B.split);
             },
             2, &ms);
         if (st != LP_OK) return st;

@@ -89,12 +89,21 @@ def test_plan_counts_match_oracle_walk(l, N, m):
     assert lp.bbox_counts(l, N, m) == (br, ks, depth)
 
 
+def _tail_widths(N, m):
+    tree, cur = [], N
+    while cur > 1:
+        tree.append((cur // 2) * m)
+        cur = (cur + 1) // 2
+    return [2 * N, N, N * m] + tree  # validation ANDs, bitwiseAND, XOR tree
+
+
 @pytest.mark.parametrize("l,N,m", [(8, 1, 8), (16, 16, 32), (13, 8, 9), (32, 4, 3)])
-def test_level_widths_schedule(l, N, m):
-    """Gates are scheduled as late as their consumers allow: the depth and
-    gate counts are those of the circuit, and comparator bit i's XNOR shares
-    the level of the MUX of bit i-1 (the MUX of a two-bootstrap gate).  With
-    a power-of-two box count every box sits at the same depth."""
+def test_level_widths_schedule(monkeypatch, l, N, m):
+    """Late placement: gates as late as their consumers allow.  The depth
+    and gate counts are those of the circuit, and comparator bit i's XNOR
+    shares the level of the MUX of bit i-1 (the MUX of a two-bootstrap
+    gate).  With a power-of-two box count every box sits at the same depth."""
+    monkeypatch.setenv("LOCPIR_XNOR_EARLY", "0")
     w = lp.bbox_level_widths(l, N, m)
     br, _, depth = lp.bbox_counts(l, N, m)
     assert len(w) == depth and sum(w) == br and min(w) > 0
@@ -102,20 +111,45 @@ def test_level_widths_schedule(l, N, m):
     assert w[0] == per_bit  # XNOR of bit 0 only
     assert w[1:l] == [3 * per_bit] * (l - 1)  # MUX of bit i-1 (2 bootstraps) + XNOR of bit i
     assert w[l] == 2 * per_bit  # MUX of the MSB
-    assert w[l + 1:l + 4] == [2 * N, N, N * m]  # validation ANDs, bitwiseAND
-    tree, cur = [], N
-    while cur > 1:
-        tree.append((cur // 2) * m)
-        cur = (cur + 1) // 2
-    assert w[l + 4:] == tree
+    assert w[l + 1:] == _tail_widths(N, m)
+
+
+@pytest.mark.parametrize("l,N,m", [(8, 1, 8), (16, 16, 32), (13, 8, 9), (32, 4, 3)])
+def test_level_widths_early_placement(monkeypatch, l, N, m):
+    """Early placement: every XNOR at the first level (the level its inputs
+    allow), then one level of MUXes alone per bit; the same depth, counts
+    and tail."""
+    monkeypatch.setenv("LOCPIR_XNOR_EARLY", "1")
+    w = lp.bbox_level_widths(l, N, m)
+    br, _, depth = lp.bbox_counts(l, N, m)
+    assert len(w) == depth and sum(w) == br
+    per_bit = 4 * N
+    assert w[0] == l * per_bit
+    assert w[1:l + 1] == [2 * per_bit] * l
+    assert w[l + 1:] == _tail_widths(N, m)
+
+
+@pytest.mark.parametrize("l,N,early", [(16, 16, True), (16, 11, True), (2, 16, True), (16, 10, False),
+                                       (16, 4, False), (8, 1, False), (16, 17, False), (1, 16, False)])
+def test_automatic_placement_with_default_shapes(monkeypatch, l, N, early):
+    """Without a table, launches of at most 128 rotations split: a lone
+    query's XNORs go early exactly when its MUX levels (8N rotations) split
+    and the mixed levels (12N) would not; a one-bit query has no MUX level
+    to free."""
+    for v in ("LOCPIR_XNOR_EARLY", "LOCPIR_BR_WAVES"):
+        monkeypatch.delenv(v, raising=False)
+    lp.set_tune_table([])
+    w = lp.bbox_level_widths(l, N, 3)
+    assert (w[0] == l * 4 * N) == early or l == 1
 
 
 @pytest.mark.parametrize("l,N,m", [(13, 9, 9), (32, 5, 3), (16, 3, 32)])
-def test_level_widths_ragged_box_count(l, N, m):
+def test_level_widths_ragged_box_count(monkeypatch, l, N, m):
     """An odd box count carries a box's products past XOR rounds, and that
     box's comparators move later with them: the first level holds fewer
     XNORs, the total and the depth are unchanged, and no level is wider
     than all boxes' MUX and XNOR work together."""
+    monkeypatch.setenv("LOCPIR_XNOR_EARLY", "0")
     w = lp.bbox_level_widths(l, N, m)
     br, _, depth = lp.bbox_counts(l, N, m)
     assert len(w) == depth and sum(w) == br and min(w) > 0

@@ -31,6 +31,19 @@ def test_phase_split_by_level_and_busy_share():
     assert busy == pytest.approx(want)
 
 
+def test_rotation_launches_by_shape():
+    """Rotation records grouped by waves per bootstrap (one kernel each)."""
+    recs = records([8, 64], 2, waves=6) + records([512], 2, waves=3)
+    tot, busy, _ = bench.summarize_launches(recs, 3, 1)
+    by = tot["blind_rotate_by_shape"]
+    assert by[6] == {"launches": 4, "jobs": 2 * 72, "total_ms": 2 * (10.0 + 11.0)}
+    assert by[3] == {"launches": 2, "jobs": 1024, "total_ms": 20.0}
+    # a split job holds six SIMDs (three waves on each of two CUs)
+    want = (2 * (10 * 48 + 11 * 384) / 1024 + 2 * 10 * 1.0) / 62.0
+    assert busy == pytest.approx(want)
+    assert bench.SHAPE_KERNEL[6] == "blind_rotate_split_kernel"
+
+
 def test_missing_key_switch_record_keeps_levels_aligned():
     widths = [8, 8, 8, 8, 8]
     _, _, ph = bench.summarize_launches(records(widths, 2, skip_ks_at=1), len(widths), 1)

@@ -1,6 +1,6 @@
 """Schedule invariance: the same inputs give identical bits under every
-launch shape (waves per bootstrap, key-switch tile and ring-index split),
-and equal the oracle."""
+launch shape (waves per bootstrap, including the rotation split over two
+workgroups, key-switch tile and ring-index split), and equal the oracle."""
 import numpy as np
 import pytest
 
@@ -29,7 +29,7 @@ def inputs(okeys, octx):
     return c1, c2, exp
 
 
-@pytest.mark.parametrize("waves", ["1", "3"])
+@pytest.mark.parametrize("waves", ["1", "3", "6"])
 def test_blind_rotation_waves_per_bootstrap(monkeypatch, okeys, octx, dkey, waves):
     monkeypatch.setenv("LOCPIR_BR_WAVES", waves)
     ct = O.encrypt_bits(okeys, [1, 0, 1], seed=88)
@@ -38,7 +38,7 @@ def test_blind_rotation_waves_per_bootstrap(monkeypatch, okeys, octx, dkey, wave
         assert (acc[k] == octx.blind_rotate(ct[k], 20)).all(), k
 
 
-@pytest.mark.parametrize("waves", ["1", "3"])
+@pytest.mark.parametrize("waves", ["1", "3", "6"])
 def test_gate_waves_per_bootstrap(monkeypatch, dkey, inputs, waves):
     monkeypatch.setenv("LOCPIR_BR_WAVES", waves)
     monkeypatch.setenv("LOCPIR_KS_SPLIT", "1")

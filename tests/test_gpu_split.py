@@ -1,0 +1,124 @@
+"""Split blind rotation (br_waves 6: one bootstrap on two workgroups, each
+owning one accumulator component, trading forward transforms every step):
+bit-exact against the oracle for the accumulator after all n steps, for
+gates at one, ragged and maximal launch widths, and for whole queries whose
+narrow levels run split, with the exchange area reused launch after launch."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2407_19871_amd as lp
+from oracle import plain
+from paper_2407_19871_amd import workloads as W
+
+from gpu_common import as_u32, cuda_or_skip, device_key_from_oracle
+
+pytestmark = pytest.mark.gpu
+
+SPLIT_MAX = 128  # widest split launch
+
+
+@pytest.fixture(scope="module")
+def dkey(okeys):
+    cuda_or_skip()
+    return device_key_from_oracle(okeys)
+
+
+@pytest.fixture
+def split_table():
+    """Split rotations up to 128 jobs, one gadget level per wave above."""
+    old = lp.tune_table()
+    lp.set_tune_table([{"jobs": SPLIT_MAX, "br_waves": 6, "ks_tile": 4, "ks_split": 8},
+                       {"jobs": 1 << 22, "br_waves": 3, "ks_tile": 8, "ks_split": 8}])
+    yield
+    lp.set_tune_table(old)
+
+
+def test_accumulator_after_all_steps(monkeypatch, okeys, octx, dkey):
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+    ct = O.encrypt_bits(okeys, [1, 0, 1], seed=91)
+    acc = as_u32(lp.debug_blind_rotate(dkey, lp.to_device(ct), 630))
+    for k in range(3):
+        assert (acc[k] == octx.blind_rotate(ct[k], 630)).all(), k
+
+
+@pytest.mark.parametrize("cnt", [1, 13, 120])
+def test_gates_at_launch_widths(monkeypatch, okeys, octx, dkey, cnt):
+    """One pair; a ragged block (idle pairs in the last block of 16
+    tickets); nearly the widest launch."""
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+    a, b = W.random_bits(200 + cnt, cnt), W.random_bits(300 + cnt, cnt)
+    c1 = O.encrypt_bits(okeys, a, seed=400 + cnt)
+    c2 = O.encrypt_bits(okeys, b, seed=500 + cnt)
+    got = as_u32(lp.bootstrap_batch(dkey, "XNOR", lp.to_device(c1), lp.to_device(c2)))
+    exp, _ = octx.gate_batch("XNOR", c1, c2)
+    assert (got == exp).all()
+    d, _ = O.decrypt_bits(okeys, got)
+    assert (d == (1 - (a ^ b))).all()
+
+
+def test_mux_at_widest_split_launch(monkeypatch, okeys, octx, dkey):
+    """64 MUX gates are 128 rotations, the widest split launch."""
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+    cnt = SPLIT_MAX // 2
+    s, t, f = (W.random_bits(600 + k, cnt) for k in range(3))
+    cts = [O.encrypt_bits(okeys, v, seed=700 + k) for k, v in enumerate((s, t, f))]
+    got = as_u32(lp.bootstrap_batch(dkey, "MUX", *[lp.to_device(c) for c in cts]))
+    exp, _ = octx.gate_batch("MUX", *cts)
+    assert (got == exp).all()
+
+
+def test_wider_launch_falls_back(monkeypatch, okeys, octx, dkey):
+    """A forced split shape on more than 128 rotations runs one gadget level
+    per wave instead (and is still exact)."""
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+    assert lp.tune_pick(SPLIT_MAX)["br_waves"] == 6
+    assert lp.tune_pick(SPLIT_MAX + 1)["br_waves"] == 3
+    cnt = SPLIT_MAX + 3
+    a, b = W.random_bits(801, cnt), W.random_bits(802, cnt)
+    c1, c2 = O.encrypt_bits(okeys, a, seed=803), O.encrypt_bits(okeys, b, seed=804)
+    lp.profile_enable(True)
+    try:
+        got = as_u32(lp.bootstrap_batch(dkey, "AND", lp.to_device(c1), lp.to_device(c2)))
+        recs = lp.profile_collect_launches()
+    finally:
+        lp.profile_enable(False)
+    assert [r["shape"] for r in recs if r["name"] == "blind_rotate"] == [3]
+    exp, _ = octx.gate_batch("AND", c1, c2)
+    assert (got == exp).all()
+
+
+def _query_parts(okeys, q, seed):
+    xb, yb, bb, pb = q.plain_bits()
+    ct = O.encrypt_bits(okeys, np.concatenate([xb, yb, bb, pb]), seed=seed)
+    l, N = q.l, q.n_boxes
+    return (ct[:l], ct[l:2 * l], ct[2 * l:2 * l + 4 * l * N], ct[2 * l + 4 * l * N:])
+
+
+@pytest.mark.parametrize("graphs", ["1", "0"])
+def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_table, graphs):
+    """An 8-bit one-box query (12 levels, every one at most 32 rotations
+    wide, so all of them split), run twice: the exchange area is reused by
+    every level and every replay."""
+    monkeypatch.setenv("LOCPIR_GRAPHS", graphs)
+    q = W.random_query_u8(31, force_inside=True)
+    parts = _query_parts(okeys, q, seed=32)
+    l, N, m = q.l, q.n_boxes, q.m
+    assert max(lp.bbox_level_widths(l, N, m)) <= SPLIT_MAX
+    exp = octx.bbox_query(l, N, m, False, *parts)
+    lp.profile_enable(True)
+    try:
+        for _ in range(2):
+            res = as_u32(lp.eval_bbox_query(dkey, l, N, m, False, *[lp.to_device(v) for v in parts]))
+            assert (res == exp).all()
+        recs = lp.profile_collect_launches()
+    finally:
+        lp.profile_enable(False)
+    assert {r["shape"] for r in recs if r["name"] == "blind_rotate"} == {6}
+    d, _ = O.decrypt_bits(okeys, res)
+    assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, False)
+
+
+def test_no_stalled_waits(dkey):
+    """No split wait above ran out of polls."""
+    assert lp.split_stall_count() == 0

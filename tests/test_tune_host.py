@@ -21,9 +21,7 @@ def clean_table(monkeypatch):
 
 def test_defaults_without_table():
     assert lp.tune_table() == []
-    assert lp.tune_pick(1)["br_waves"] == 3
-    assert lp.tune_pick(512)["br_waves"] == 3
-    assert lp.tune_pick(513)["br_waves"] == 1
+    assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129, 512, 513)] == [6, 6, 3, 3, 1]
     assert [lp.tune_pick(j)["ks_tile"] for j in (1, 16, 256, 4096)] == [1, 4, 8, 16]
     # the default split grows until the key switch has >= 2048 blocks
     assert lp.tune_pick(1)["ks_split"] == 16
@@ -49,6 +47,18 @@ def test_environment_overrides_table(monkeypatch):
     assert g["ks_split"] == lp.tune_pick(1024, 630)["ks_split"]
     monkeypatch.setenv("LOCPIR_BR_WAVES", "2")  # invalid values are ignored
     assert lp.tune_pick(1024)["br_waves"] == 3
+
+
+def test_split_shape_applies_up_to_128_jobs(monkeypatch):
+    """A row of split rotations (6) serves launches of at most 128 jobs; a
+    wider launch that looks it up (the last row, or the environment) gets one
+    gadget level per wave (3)."""
+    lp.set_tune_table([{"jobs": 32, "br_waves": 1, "ks_tile": 4, "ks_split": 8},
+                       {"jobs": 200, "br_waves": 6, "ks_tile": 8, "ks_split": 8}])
+    got = [lp.tune_pick(j)["br_waves"] for j in (32, 33, 128, 129, 200, 5000)]
+    assert got == [1, 6, 6, 3, 3, 3]
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+    assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129)] == [6, 6, 3]
 
 
 @pytest.mark.parametrize("bad", [
