@@ -119,6 +119,47 @@ def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_table, gr
     assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, False)
 
 
+@pytest.fixture(scope="module")
+def placement_query(okeys, octx):
+    """9-bit signed coordinates against 11 boxes (1263 bootstraps) and the
+    oracle's result."""
+    q = W.random_query(41, 9, 11, 2, force_inside=True)
+    parts = _query_parts(okeys, q, seed=42)
+    return q, parts, octx.bbox_query(q.l, q.n_boxes, q.m, True, *parts)
+
+
+@pytest.mark.parametrize("early", ["0", "1", None])
+def test_query_xnor_placements(monkeypatch, okeys, dkey, placement_query, early):
+    """With 11 boxes the MUX levels (88 rotations) split and the mixed ones
+    (132) cannot, so the XNORs go early unless told otherwise; either
+    placement gives the oracle's bits, with the launch widths it announces."""
+    if early is None:
+        monkeypatch.delenv("LOCPIR_XNOR_EARLY", raising=False)
+    else:
+        monkeypatch.setenv("LOCPIR_XNOR_EARLY", early)
+    monkeypatch.delenv("LOCPIR_BR_WAVES", raising=False)
+    old = lp.tune_table()
+    lp.set_tune_table([])  # built-in shapes; also drops cached programs
+    try:
+        q, parts, exp = placement_query
+        l, N, m = q.l, q.n_boxes, q.m
+        widths = lp.bbox_level_widths(l, N, m)
+        assert (widths[0] == l * 4 * N) == (early != "0")
+        lp.profile_enable(True)
+        lp.profile_collect_launches()
+        try:
+            res = as_u32(lp.eval_bbox_query(dkey, l, N, m, True, *[lp.to_device(v) for v in parts]))
+            recs = lp.profile_collect_launches()
+        finally:
+            lp.profile_enable(False)
+    finally:
+        lp.set_tune_table(old)
+    assert [r["jobs"] for r in recs if r["name"] == "blind_rotate"] == widths
+    assert (res == exp).all()
+    d, _ = O.decrypt_bits(okeys, res)
+    assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, True)
+
+
 def test_no_stalled_waits(dkey):
     """No split wait above ran out of polls."""
     assert lp.split_stall_count() == 0
