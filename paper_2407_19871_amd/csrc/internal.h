@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/locpir.h"
@@ -78,8 +79,9 @@ struct Plan {
 // Cached plan of a shape (thread-safe); xnor_early places the comparators'
 // XNORs all at the first level instead of next to the MUX that uses them.
 std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_signed, bool xnor_early);
-// The placement a lone query of this shape gets on the current device.
-bool choose_xnor_early(uint32_t l, uint32_t N);
+// The XNOR placement a program of these query shapes gets on the current
+// device (one entry per query: l, N, m, signed).
+bool choose_xnor_early(const std::vector<std::tuple<uint32_t, uint32_t, uint32_t, int>>& shapes);
 // Key-switch tile for a fused launch with per-key job counts.
 int fused_ks_tile(const std::vector<size_t>& per_key, size_t total);
 
@@ -94,6 +96,9 @@ inline int env_int(const char* name, int dflt) {
 }
 int pick_ks_tile(size_t njobs);
 int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe);
+// Estimated rotation launch time (us) of njobs from the current device's
+// timed table; false when there is none.
+bool est_br_launch_us(size_t njobs, double* us);
 // Waves per bootstrap: 6 (split over two workgroups) up to kSplitMaxJobs,
 // 3 (one gadget level per wave) for other narrow launches, else 1.
 int pick_br_wpb(size_t njobs);

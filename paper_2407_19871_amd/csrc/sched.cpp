@@ -241,16 +241,42 @@ std::shared_ptr<const Plan> get_plan(uint32_t l, uint32_t N, uint32_t m, int is_
   return P;
 }
 
-// A single query's XNORs go early when that is what lets its MUX levels
-// (2 bootstraps per comparator, 4N comparators) run as split rotations,
-// which the mixed levels (3 per comparator) cannot; otherwise late.  On
-// MI355X a split launch takes about 0.73 of a one-level-per-wave one, and
-// the early level 1 (l XNORs per comparator) costs less than the l - 1
-// levels gain.  LOCPIR_XNOR_EARLY = 0 or 1 overrides.
-bool choose_xnor_early(uint32_t l, uint32_t N) {
+// XNOR placement of a program (one query, or many fused level by level).
+// With a timed shape table on the device: early when its levels' estimated
+// rotation launch times sum at least 2 % lower than late's (late keeps the
+// widest level, and so the extract buffer, smaller).  Without one: a
+// lone query goes early exactly when that lets its MUX levels (2
+// bootstraps per comparator, 4N comparators) run as split rotations, which
+// the mixed levels (3 per comparator) cannot -- on MI355X a split launch
+// takes about 0.73 of a one-level-per-wave one, more than paying for the
+// wider first level -- and fused queries stay late.  LOCPIR_XNOR_EARLY = 0
+// or 1 overrides.
+bool choose_xnor_early(const std::vector<std::tuple<uint32_t, uint32_t, uint32_t, int>>& shapes) {
   const int forced = env_int("LOCPIR_XNOR_EARLY", -1);
   if (forced == 0 || forced == 1) return forced == 1;
-  const size_t comparators = 4 * (size_t)N;
+  if (shapes.empty()) return false;
+  double cost[2] = {0.0, 0.0};
+  bool timed = true;
+  for (int early = 0; early < 2 && timed; ++early) {
+    std::vector<size_t> width;
+    for (const auto& q : shapes) {
+      auto P = get_plan(std::get<0>(q), std::get<1>(q), std::get<2>(q), std::get<3>(q), early == 1);
+      if (width.size() < P->br.size()) width.resize(P->br.size(), 0);
+      for (size_t L = 0; L < P->br.size(); ++L) width[L] += P->br[L].size();
+    }
+    for (size_t w : width) {
+      double us = 0.0;
+      if (w > 0 && !est_br_launch_us(w, &us)) {
+        timed = false;
+        break;
+      }
+      cost[early] += us;
+    }
+  }
+  if (timed) return cost[1] < 0.98 * cost[0];
+  if (shapes.size() != 1) return false;
+  const uint32_t l = std::get<0>(shapes[0]);
+  const size_t comparators = 4 * (size_t)std::get<1>(shapes[0]);
   return l >= 2 && pick_br_wpb(2 * comparators) == 6 && pick_br_wpb(3 * comparators) != 6;
 }
 
@@ -512,8 +538,10 @@ lp_status get_program(const std::vector<const lp_device_key*>& keys, const lp_bb
     *out = it->second;
     return LP_OK;
   }
-  // placement: chosen for a lone query; fused queries keep every level narrow
-  const bool early = keys.size() == 1 && choose_xnor_early(qs[0].l, qs[0].n_boxes);
+  std::vector<std::tuple<uint32_t, uint32_t, uint32_t, int>> shapes;
+  for (size_t k = 0; k < keys.size(); ++k)
+    shapes.emplace_back(qs[k].l, qs[k].n_boxes, qs[k].m, qs[k].is_signed ? 1 : 0);
+  const bool early = choose_xnor_early(shapes);
   std::vector<std::shared_ptr<const Plan>> plans;
   for (size_t k = 0; k < keys.size(); ++k)
     plans.push_back(get_plan(qs[k].l, qs[k].n_boxes, qs[k].m, qs[k].is_signed ? 1 : 0, early));
@@ -580,7 +608,7 @@ extern "C" lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t
                                           uint32_t* n_levels) {
   if (l == 0 || l > 64 || n_boxes == 0 || m == 0) return lp::fail(LP_EINVAL, "lp_bbox_level_widths: empty shape");
   if (!n_levels || (*n_levels > 0 && !widths)) return lp::fail(LP_EINVAL, "lp_bbox_level_widths: null argument");
-  auto P = lp::get_plan(l, n_boxes, m, 1, lp::choose_xnor_early(l, n_boxes));
+  auto P = lp::get_plan(l, n_boxes, m, 1, lp::choose_xnor_early({std::make_tuple(l, n_boxes, m, 1)}));
   const uint32_t depth = (uint32_t)P->levels();
   for (uint32_t k = 0; k < depth && k < *n_levels; ++k) widths[k] = (uint32_t)P->br[k].size();
   *n_levels = depth;

@@ -115,6 +115,19 @@ int pick_br_wpb(size_t njobs) {
   return default_br_wpb(njobs);
 }
 
+// Estimated duration (microseconds) of a rotation launch of njobs
+// bootstraps from the current device's timed table: the row's per-job time
+// times the jobs for one wave per bootstrap (throughput), or times the
+// row's bucket for the latency shapes (a launch below the bucket takes
+// about as long as the bucket).  False without a timed row.
+bool est_br_launch_us(size_t njobs, double* us) {
+  lp_tune_entry r;
+  if (njobs == 0 || !tuned_row(njobs, &r) || !(r.br_us > 0.f)) return false;
+  const int w = pick_br_wpb(njobs);
+  *us = (double)r.br_us * (double)(w == 1 ? njobs : std::max<size_t>(njobs, r.jobs));
+  return true;
+}
+
 }  // namespace lp
 
 using lp::fail;

@@ -143,6 +143,34 @@ def test_automatic_placement_with_default_shapes(monkeypatch, l, N, early):
     assert (w[0] == l * 4 * N) == early or l == 1
 
 
+# launch times per job as timed on MI355X (split up to 128, three waves up
+# to 768, one wave above)
+TIMED = [{"jobs": 1, "br_waves": 6, "ks_tile": 1, "ks_split": 16, "br_us": 11889.0},
+         {"jobs": 128, "br_waves": 6, "ks_tile": 4, "ks_split": 16, "br_us": 94.9},
+         {"jobs": 256, "br_waves": 3, "ks_tile": 8, "ks_split": 16, "br_us": 66.0},
+         {"jobs": 512, "br_waves": 3, "ks_tile": 8, "ks_split": 16, "br_us": 49.0},
+         {"jobs": 768, "br_waves": 3, "ks_tile": 4, "ks_split": 16, "br_us": 48.4},
+         {"jobs": 1024, "br_waves": 1, "ks_tile": 8, "ks_split": 8, "br_us": 39.4},
+         {"jobs": 2048, "br_waves": 1, "ks_tile": 8, "ks_split": 16, "br_us": 26.8},
+         {"jobs": 16384, "br_waves": 1, "ks_tile": 8, "ks_split": 16, "br_us": 24.1}]
+
+
+@pytest.mark.parametrize("l,N,early", [(16, 16, True), (16, 28, True), (16, 4, False), (8, 1, False)])
+def test_placement_from_timed_table(monkeypatch, l, N, early):
+    """With launch times in the table, the placement with the lower summed
+    estimate wins: 28 boxes go early although their MUX levels (224
+    rotations) do not split, since the mixed levels (336) would run two
+    bootstraps per CU; 4 boxes stay late, every level splitting either way."""
+    for v in ("LOCPIR_XNOR_EARLY", "LOCPIR_BR_WAVES"):
+        monkeypatch.delenv(v, raising=False)
+    lp.set_tune_table(TIMED)
+    try:
+        w = lp.bbox_level_widths(l, N, 9)
+    finally:
+        lp.set_tune_table([])
+    assert (w[0] == l * 4 * N) == early
+
+
 @pytest.mark.parametrize("l,N,m", [(13, 9, 9), (32, 5, 3), (16, 3, 32)])
 def test_level_widths_ragged_box_count(monkeypatch, l, N, m):
     """An odd box count carries a box's products past XOR rounds, and that
