@@ -233,11 +233,14 @@ lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_b
 /* Blind rotations per depth level of that circuit as the library schedules
  * a lone query of the shape on the calling thread's current device (signed
  * shape).  Only the comparators' XNORs have slack; they go either early
- * (all at the first level, then l levels of MUXes alone) when that lets the
- * MUX levels run as split rotations (br_waves 6, see lp_tune_entry) and a
- * level holding MUXes and XNORs together could not, or late (each next to
- * the MUX that uses it, as late as its consumers allow) otherwise; queries
- * fused by lp_eval_bbox_batch and the server use the late placement.  The
+ * (all at the first level, then l levels of MUXes alone) or late (each next
+ * to the MUX that uses it, as late as its consumers allow).  With a timed
+ * shape table (lp_autotune) a program, one query or many fused by
+ * lp_eval_bbox_batch, takes early when the summed launch times the table
+ * predicts are at least 2 % lower; without one, a lone query takes early
+ * exactly when that lets its MUX levels run as split rotations (br_waves
+ * 6, see lp_tune_entry) and a level holding MUXes and XNORs together could
+ * not, and fused queries take late.  The server always takes late.  The
  * environment variable LOCPIR_XNOR_EARLY = 0 or 1 overrides the choice.
  * The depth is the same either way.  widths: host array of *n_levels
  * entries on input; *n_levels receives the depth (entries beyond the array
