@@ -390,7 +390,9 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 //   1. D_c = X^a ACC_c - ACC_c, digits of level j -> forward NTT F_(c,j);
 //   2. store F_(c,j) in this role's exchange slot, then raise the wave's
 //      flag to the step count; wait for the partner's flag; load F_(1-c,j);
-//   3. P_(c,j) -> inverse NTT -> centred lift -> ACC_c += (LDS atomics).
+//   3. P_(c,j) into LDS; waves 0 and 1 sum the three levels in the NTT
+//      domain and invert the sum together (four lanes per row, ntt64.h),
+//      then add its centred lift to ACC_c.
 // Exchange data and flags use agent-scope relaxed atomics (coherent across
 // the CUs and XCDs of the device, no cache maintenance); a full vector
 // memory wait orders the data before the flag, and the data loads depend on
@@ -407,6 +409,7 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 // g_split_stalls, and the job's output is then undefined; the kernel still
 // exits.  The last workgroup to finish clears the tickets and flags.
 constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
+constexpr int T128_ROW = 36;  // u64 words per row of the two-wave transpose (bank spread)
 constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
 
 __device__ uint32_t g_split_stalls;
@@ -433,11 +436,16 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
     uint32_t* __restrict__ sync) {
   __shared__ uint32_t s_acc[RING_N];
   __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
+  __shared__ __align__(16) uint64_t s_part[3][RING_N];     // the levels' partials, NTT domain
+  __shared__ __align__(16) uint64_t s_t128[32 * T128_ROW];  // two-wave transpose
   __shared__ uint16_t s_abar[MAX_LWE + 4];
   __shared__ uint32_t s_ticket, s_last;
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  // two-wave inverse: row (or column) 16 wave + r, quad lane hq
+  const int r4 = lane >> 2, hq = lane & 3;
+  const uint64_t upper1 = (hq & 1) ? ~0ull : 0ull, upper2 = (hq & 2) ? ~0ull : 0ull;
   if (threadIdx.x == 0) s_ticket = atomicAdd(sync, 1u);
   __syncthreads();
   const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_ticket);
@@ -529,13 +537,44 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
 #pragma unroll
       for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
 #pragma unroll
-      for (int s = 0; s < 16; ++s) f[s] = gl_mul_sum(f[s], kown[s], g[s], koth[s]);
+      for (int s = 0; s < 16; ++s) s_part[wave][64 * s + 2 * l + h] = gl_mul_sum(f[s], kown[s], g[s], koth[s]);
+      __syncthreads();
 
-      // the level's partial is an exact integer polynomial (|coefficient| <
-      // 2^49), so lifting each partial and adding mod 2^32 is exact
-      ntt64_inv(f, buf, opaque(tw_i), lane);
+      // one inverse of the three levels' sum, on waves 0 and 1: each holds
+      // 16 rows at four lanes per row (the NTT-domain offset of position q of
+      // row k is 64 (q >> 1) + 2 k + (q & 1))
+      if (wave < 2) {
+        const int row = 16 * wave + r4;
+        uint64_t v[8];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) atomicAdd(&s_acc[l + 32 * (2 * s + h)], gl_lift_u32(f[s]));
+        for (int s = 0; s < 8; ++s) {
+          const int off = 128 * s + 64 * (hq >> 1) + 2 * row + (hq & 1);
+          v[s] = gl_add(gl_add(s_part[0][off], s_part[1][off]), s_part[2][off]);
+        }
+        inv128_p2(v, upper1, upper2, upper2);
+        {
+          const gmem_u64* t = as_global(opaque(tw_i)) + hq * 32 + row;
+          uint64_t w[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) w[s] = t[s * 128];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) v[s] = gl_mul(v[s], w[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) s_t128[row * T128_ROW + 4 * s + hq] = v[s];
+      }
+      __syncthreads();
+      if (wave < 2) {
+        const int col = 16 * wave + r4;
+        uint64_t v[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = s_t128[(4 * s + hq) * T128_ROW + col];
+        inv128_p1(v, upper1, upper2, upper2);
+        // the sum is an exact integer polynomial (|coefficient| < 2^50.6),
+        // so its centred lift reduced mod 2^32 is exact
+#pragma unroll
+        for (int s = 0; s < 8; ++s) s_acc[col + 32 * (4 * s + hq)] += gl_lift_u32(v[s]);
+      }
       ++done;
       __syncthreads();
     }

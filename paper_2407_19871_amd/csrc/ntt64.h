@@ -183,4 +183,83 @@ __device__ __forceinline__ void inv64_p1(uint64_t (&a)[16], int lane) {
   gs64_stage<16>(a, Z1<16>{});
 }
 
+// ---- inverse on two waves (four lanes per row) -------------------------------
+// The inverse transform of one polynomial spread over 128 lanes: wave w
+// (0, 1) holds rows 16 w .. 16 w + 15, lane 4 r + h of the wave holds the
+// eight positions q = 4 s + h (s = 0..7) of row 16 w + r.  Stages of
+// distance LEN >= 4 stay inside a lane, with per-block twiddles as above;
+// the distance-2 and distance-1 stages pair lanes h ^ 2 and h ^ 1 of a
+// row's quad (DPP quad permutations).  The distance-2 stage's block
+// (q / 4 = s) is uniform; the distance-1 stage's block (q / 2 = 2 s +
+// (h >> 1)) takes two values per slot, so both shifts are formed and each
+// lane keeps its own.  Between the passes the rows are transposed through
+// LDS across both waves; the output is, in lane 4 r + h of wave w, slot s,
+// coefficient j1 + 32 q with j1 = 16 w + r, q = 4 s + h.
+
+// The value held by lane ^ D of the quad (D = 1 or 2).
+template <int D>
+__device__ __forceinline__ uint64_t quad_xor(uint64_t v) {
+  constexpr int ctrl = D == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, ctrl, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), ctrl, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Gentleman-Sande stage of distance D in {1, 2} across the quad; FIRST:
+// the inputs may be lazy.  Masks: upper = ~0 in the upper lane of each
+// pair (h & D), second = ~0 in lanes h >= 2 (the second pair of the row).
+template <int D, bool FIRST, typename Zf>
+__device__ __forceinline__ void gs128_cross(uint64_t (&a)[8], Zf zf, uint64_t upper, uint64_t second) {
+  static_for<0, 8>([&](auto ss) {
+    constexpr int s = decltype(ss)::value;
+    const uint64_t self = a[s], other = quad_xor<D>(a[s]);
+    const uint64_t X = lane_select(upper, self, other), Y0 = lane_select(upper, other, self);
+    const uint64_t Y = FIRST ? gl_canon(Y0) : Y0;
+    const uint64_t sum = gl_canon(gl_add_r(X, Y));
+    const uint64_t dif = gl_sub_r(X, Y);
+    uint64_t up;
+    if constexpr (D == 1) {
+      constexpr int za = decltype(zf(std::integral_constant<int, 2 * s>{}))::value;
+      constexpr int zb = decltype(zf(std::integral_constant<int, 2 * s + 1>{}))::value;
+      up = lane_select(second, gl_mul_pow2_r<192 - za>(dif), gl_mul_pow2_r<192 - zb>(dif));
+    } else {
+      constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
+      up = gl_mul_pow2_r<192 - z>(dif);
+    }
+    a[s] = lane_select(upper, sum, up);
+  });
+}
+
+// In-lane Gentleman-Sande stage of distance LEN in {4, 8, 16}: slots s and
+// s + LEN / 4 within blocks of LEN / 2 slots; reduced inputs and outputs.
+template <int LEN, typename Zf>
+__device__ __forceinline__ void gs128_stage(uint64_t (&a)[8], Zf zf) {
+  static_for<0, 16 / LEN>([&](auto bb) {
+    constexpr int blk = decltype(bb)::value;
+    constexpr int z = decltype(zf(std::integral_constant<int, blk>{}))::value;
+    static_for<0, LEN / 4>([&](auto jj) {
+      constexpr int s0 = blk * (LEN / 2) + decltype(jj)::value, s1 = s0 + LEN / 4;
+      const uint64_t x = a[s0], y = a[s1];
+      a[s0] = gl_canon(gl_add_r(x, y));
+      a[s1] = gl_mul_pow2_r<192 - z>(gl_sub_r(x, y));
+    });
+  });
+}
+
+__device__ __forceinline__ void inv128_p2(uint64_t (&a)[8], uint64_t upper1, uint64_t upper2, uint64_t second) {
+  gs128_cross<1, true>(a, Z2<1>{}, upper1, second);
+  gs128_cross<2, false>(a, Z2<2>{}, upper2, second);
+  gs128_stage<4>(a, Z2<4>{});
+  gs128_stage<8>(a, Z2<8>{});
+  gs128_stage<16>(a, Z2<16>{});
+}
+
+__device__ __forceinline__ void inv128_p1(uint64_t (&a)[8], uint64_t upper1, uint64_t upper2, uint64_t second) {
+  gs128_cross<1, true>(a, Z1<1>{}, upper1, second);
+  gs128_cross<2, false>(a, Z1<2>{}, upper2, second);
+  gs128_stage<4>(a, Z1<4>{});
+  gs128_stage<8>(a, Z1<8>{});
+  gs128_stage<16>(a, Z1<16>{});
+}
+
 }  // namespace lp
