@@ -359,7 +359,9 @@ lp_status lp_split_stall_count(uint32_t* count);
  * the first row (rows sorted by `jobs`, ascending) with count <= jobs, or
  * the last row when count exceeds every bound.
  *   br_waves: waves cooperating on one blind rotation, 1 (throughput), 3
- *             (one gadget level per wave, latency) or 6 (the rotation split
+ *             (one gadget level per wave, latency), 4 (three level waves,
+ *             then the levels summed in the NTT domain and each component
+ *             inverted once on two waves; one rotation per CU) or 6 (the rotation split
  *             over two workgroups, normally two CUs, each owning one
  *             accumulator component and trading forward transforms with
  *             the other every step; lower latency again, for launches of at

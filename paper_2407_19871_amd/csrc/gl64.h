@@ -107,15 +107,22 @@ GL_INLINE uint64_t gl_sub_r(uint64_t a, uint64_t b) {
 // -y for reduced y: p - y = ~y + 2 - 2^32 (mod 2^64), again reduced.
 GL_INLINE uint64_t gl_neg_r(uint64_t y) { return ~y + 0xFFFFFFFF00000002ull; }
 
-// a b + c d mod p with one reduction.  The two 128-bit products sum to at
-// most 2^129; the carry into bit 128 stands for 2^128 = 2^96 2^32 = -2^32.
-GL_INLINE uint64_t gl_mul_sum(uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
-  uint64_t l1, h1, l2, h2, lo, hi;
-  gl_mul_wide(a, b, l1, h1);
+// a b + c d mod p with one reduction, a b given as its 128-bit product
+// (l1, h1).  The two 128-bit products sum to at most 2^129; the carry into
+// bit 128 stands for 2^128 = 2^96 2^32 = -2^32.
+GL_INLINE uint64_t gl_mul_sum_wide(uint64_t l1, uint64_t h1, uint64_t c, uint64_t d) {
+  uint64_t l2, h2, lo, hi;
   gl_mul_wide(c, d, l2, h2);
   const bool c1 = __builtin_add_overflow(l1, l2, &lo);
   const bool c2 = __builtin_add_overflow(h1, h2 + (c1 ? 1ull : 0ull), &hi);  // h2 <= 2^64 - 2
   return gl_sub_r(gl_reduce128(lo, hi), c2 ? 0x100000000ull : 0ull);
+}
+
+// a b + c d mod p with one reduction.
+GL_INLINE uint64_t gl_mul_sum(uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
+  uint64_t l1, h1;
+  gl_mul_wide(a, b, l1, h1);
+  return gl_mul_sum_wide(l1, h1, c, d);
 }
 
 // x * 2^S mod p for a compile-time S; the result is lazy for S mod 192 in

@@ -213,16 +213,27 @@ __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restri
 //   W = 3: wave w runs gadget level w and the inverse NTT of that level's
 //          partial product, and adds its lifted partial into the LDS
 //          accumulator with LDS atomics (latency mode for narrow circuit
-//          levels; 35 KB of LDS, so four bootstraps fit one CU).
+//          levels; 35 KB of LDS, so four bootstraps fit one CU);
+//   W = 4: waves 0-2 run the gadget levels as in W = 3 but leave their
+//          partial products in LDS; the levels' sum of each component is
+//          inverted once, by two waves at four lanes per row (ntt64.h),
+//          waves 0-1 for the mask and 2-3 for the body (latency mode, one
+//          bootstrap per CU: 102 KB of LDS).
 // The accumulator lives in LDS ([component][coefficient] u32); each level
 // re-reads it to form X^a ACC - ACC.
+constexpr int T128_ROW = 36;  // u64 words per row of a two-wave transpose (bank spread)
+
 template <int W>
 __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
+  constexpr int NL = W == 4 ? 3 : W;  // waves that run gadget levels
+  constexpr bool SUM = W == 4;        // levels summed in the NTT domain
   __shared__ uint32_t s_acc[2][RING_N];
-  __shared__ __align__(16) uint32_t s_tr[W][2][LDS_HALF];
+  __shared__ __align__(16) uint32_t s_tr[NL][2][LDS_HALF];
+  __shared__ __align__(16) uint64_t s_part[SUM ? 3 : 1][2][SUM ? RING_N : 2];
+  __shared__ __align__(16) uint64_t s_t128[2][SUM ? 32 * T128_ROW : 1];
   __shared__ uint16_t s_abar[MAX_LWE + 4];
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -231,7 +242,7 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
   if (job >= njobs) return;  // uniform over the block
 
   const BrJob J = jobs[job];
-  uint32_t* buf = s_tr[wave][h];
+  uint32_t* buf = s_tr[wave < NL ? wave : 0][h];
   uint32_t* acc = s_acc[h];
 
   // modulus switch of the combined input (0, cst) + c0 in0 + c1 in1
@@ -268,6 +279,79 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
   for (int i = 0; i < nsteps; ++i) {
     const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
     if (a == 0) continue;  // X^0 ACC - ACC = 0 decomposes to zero digits
+
+    if constexpr (SUM) {
+      const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+      const bool lvl = wave < NL;
+      uint64_t kpre[64];
+      int32_t dg[32];
+      if (lvl) {
+        // rows (h, j) and (1-h, j), component h, of level j = wave
+        const gmem_u64* ko = step_key + (size_t)((h * 3 + wave) * 2 + h) * RING_N + l * 2;
+        const gmem_u64* kt = step_key + (size_t)(((1 - h) * 3 + wave) * 2 + h) * RING_N + l * 2;
+#pragma unroll
+        for (int sp = 0; sp < 16; ++sp) {
+          kpre[4 * sp + 0] = ko[sp * 64];
+          kpre[4 * sp + 1] = ko[sp * 64 + 1];
+          kpre[4 * sp + 2] = kt[sp * 64];
+          kpre[4 * sp + 3] = kt[sp * 64 + 1];
+        }
+        const int sh = 25 - 7 * wave;
+#pragma unroll
+        for (int m = 0; m < 32; ++m) {
+          const uint32_t j = (uint32_t)(l + 32 * m);
+          const uint32_t e = (j - a) & 2047u;
+          const uint32_t v = acc[e & 1023u];
+          const uint32_t D = ((e & 1024u) ? (0u - v) : v) - acc[j];
+          dg[m] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+        }
+      }
+      __syncthreads();  // every wave has read ACC before any adds to it
+      if (lvl) {
+        uint64_t f[32];
+        ntt_fwd_digits(dg, f, buf, opaque(tw_f), l);
+        uint64_t* part = s_part[wave][h];
+#pragma unroll
+        for (int sp = 0; sp < 16; ++sp) {
+          const uint64_t g0 = from_other_half(f[2 * sp], lane), g1 = from_other_half(f[2 * sp + 1], lane);
+          part[sp * 64 + 2 * l] = gl_mul_sum(f[2 * sp], kpre[4 * sp], g0, kpre[4 * sp + 2]);
+          part[sp * 64 + 2 * l + 1] = gl_mul_sum(f[2 * sp + 1], kpre[4 * sp + 1], g1, kpre[4 * sp + 3]);
+        }
+      }
+      __syncthreads();
+      // component c = wave >> 1 on waves 2c and 2c + 1, rows 16 (wave & 1) + r
+      {
+        const int c = wave >> 1, r4 = lane >> 2, hq = lane & 3, row = 16 * (wave & 1) + r4;
+        const uint64_t upper1 = (hq & 1) ? ~0ull : 0ull, upper2 = (hq & 2) ? ~0ull : 0ull;
+        uint64_t v[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int off = 128 * s + 64 * (hq >> 1) + 2 * row + (hq & 1);
+          v[s] = gl_add(gl_add(s_part[0][c][off], s_part[1][c][off]), s_part[2][c][off]);
+        }
+        inv128_p2(v, upper1, upper2, upper2);
+        {
+          const gmem_u64* t = as_global(opaque(tw_i)) + hq * 32 + row;
+          uint64_t w[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) w[s] = t[s * 128];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) v[s] = gl_mul(v[s], w[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) s_t128[c][row * T128_ROW + 4 * s + hq] = v[s];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = s_t128[c][(4 * s + hq) * T128_ROW + row];
+        inv128_p1(v, upper1, upper2, upper2);
+        // the levels' sum is an exact integer polynomial (|coefficient| <
+        // 2^50.6), so its centred lift reduced mod 2^32 is exact
+#pragma unroll
+        for (int s = 0; s < 8; ++s) s_acc[c][row + 32 * (4 * s + hq)] += gl_lift_u32(v[s]);
+      }
+      __syncthreads();
+      continue;
+    }
 
     // BSK_i in the NTT domain: rows (p, j) = 3p + j, each with components q
     // = 0, 1.  Output component h of level j is
@@ -409,7 +493,6 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 // g_split_stalls, and the job's output is then undefined; the kernel still
 // exits.  The last workgroup to finish clears the tickets and flags.
 constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
-constexpr int T128_ROW = 36;  // u64 words per row of the two-wave transpose (bank spread)
 constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
 
 __device__ uint32_t g_split_stalls;
@@ -519,6 +602,14 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
       const size_t par = (size_t)(done & 1u) * 3 * RING_N;
 #pragma unroll
       for (int s = 0; s < 16; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
+      // this component's products while the stores drain and the partner's
+      // transform is on its way (the empty asm keeps them ahead of the wait)
+      uint64_t plo[16], phi[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        gl_mul_wide(f[s], kown[s], plo[s], phi[s]);
+        asm volatile("" : "+v"(plo[s]), "+v"(phi[s]));
+      }
       vm_wait_all();
       if (lane == 0) store_agent(my_flag, done + 1);
       if (!stalled) {
@@ -537,7 +628,7 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
 #pragma unroll
       for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
 #pragma unroll
-      for (int s = 0; s < 16; ++s) s_part[wave][64 * s + 2 * l + h] = gl_mul_sum(f[s], kown[s], g[s], koth[s]);
+      for (int s = 0; s < 16; ++s) s_part[wave][64 * s + 2 * l + h] = gl_mul_sum_wide(plo[s], phi[s], g[s], koth[s]);
       __syncthreads();
 
       // one inverse of the three levels' sum, on waves 0 and 1: each holds
@@ -801,6 +892,10 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       break;
     case 3:
       hipLaunchKernelGGL(blind_rotate_kernel<3>, dim3(njobs), dim3(192), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
+                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+      break;
+    case 4:
+      hipLaunchKernelGGL(blind_rotate_kernel<4>, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
     case 6: {

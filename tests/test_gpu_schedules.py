@@ -29,7 +29,7 @@ def inputs(okeys, octx):
     return c1, c2, exp
 
 
-@pytest.mark.parametrize("waves", ["1", "3", "6"])
+@pytest.mark.parametrize("waves", ["1", "3", "4", "6"])
 def test_blind_rotation_waves_per_bootstrap(monkeypatch, okeys, octx, dkey, waves):
     monkeypatch.setenv("LOCPIR_BR_WAVES", waves)
     ct = O.encrypt_bits(okeys, [1, 0, 1], seed=88)
@@ -38,7 +38,7 @@ def test_blind_rotation_waves_per_bootstrap(monkeypatch, okeys, octx, dkey, wave
         assert (acc[k] == octx.blind_rotate(ct[k], 20)).all(), k
 
 
-@pytest.mark.parametrize("waves", ["1", "3", "6"])
+@pytest.mark.parametrize("waves", ["1", "3", "4", "6"])
 def test_gate_waves_per_bootstrap(monkeypatch, dkey, inputs, waves):
     monkeypatch.setenv("LOCPIR_BR_WAVES", waves)
     monkeypatch.setenv("LOCPIR_KS_SPLIT", "1")
@@ -56,3 +56,20 @@ def test_keyswitch_shapes(monkeypatch, octx, dkey, tile, split):
     got = as_u32(lp.keyswitch_batch(dkey, lp.to_device(big)))
     for k in (0, 7, 20):
         assert (got[k] == octx.keyswitch(big[k])).all(), k
+
+
+@pytest.mark.parametrize("waves", ["1", "3", "4", "6"])
+def test_query_under_each_rotation_shape(monkeypatch, okeys, octx, dkey, waves):
+    """An 8-bit one-box query (107 bootstraps, 12 levels) with every level
+    forced to one rotation shape equals the oracle."""
+    from paper_2407_19871_amd import workloads as Wl
+    monkeypatch.setenv("LOCPIR_BR_WAVES", waves)
+    lp.set_tune_table(lp.tune_table())  # drops cached programs
+    q = Wl.random_query_u8(55, force_inside=True)
+    xb, yb, bb, pb = q.plain_bits()
+    ct = O.encrypt_bits(okeys, np.concatenate([xb, yb, bb, pb]), seed=56)
+    l, N, m = q.l, q.n_boxes, q.m
+    parts = (ct[:l], ct[l:2 * l], ct[2 * l:2 * l + 4 * l * N], ct[2 * l + 4 * l * N:])
+    got = as_u32(lp.eval_bbox_query(dkey, l, N, m, False, *[lp.to_device(v) for v in parts]))
+    lp.set_tune_table(lp.tune_table())
+    assert (got == octx.bbox_query(l, N, m, False, *parts)).all()
