@@ -27,7 +27,7 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
 constexpr int kSplitMaxJobs = 128;
 struct SplitArea {
   uint64_t* xbuf = nullptr;  // [job][role 2][step parity 2][level 3][1024] u64
-  uint32_t* sync = nullptr;  // tickets, finish count, then 8 flag words per job
+  uint32_t* sync = nullptr;  // 8 ticket counters, finish count, then 8 flag words per job
   int max_jobs = 0;
 };
 size_t split_xbuf_bytes(int max_jobs);

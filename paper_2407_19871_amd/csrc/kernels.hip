@@ -484,15 +484,19 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 // count: a role rewrites a slot only after the partner has raised its flag
 // for the following step, which it does after its loads of that slot.
 //
-// Pairing: each workgroup draws a ticket on arrival; tickets t and t ^ 8 of
-// a block of 16 form a pair (job 8 (t >> 4) + (t & 7), role (t >> 3) & 1),
-// so a workgroup only ever waits for one of the next 15 arrivals (no
-// co-residency assumption), and with round-robin dispatch over the eight
-// XCDs both halves of a pair usually share an L2.  Every wait is bounded:
+// Pairing: a workgroup draws a ticket on arrival from the counter of its
+// class x = blockIdx % 8 (the XCD that round-robin dispatch gives it);
+// tickets 2k and 2k + 1 of a class form a pair (job 8 k + x, role t & 1).
+// Arrival order is not launch order, so pairing by class rather than by
+// arrival keeps both halves on one XCD.  The grid is a multiple of 16, so
+// every class holds an even count and every ticket finds its partner; at
+// most one workgroup per class waits for a partner, so no co-residency is
+// assumed.  Every wait is bounded:
 // a partner missing for SPLIT_SPIN_LIMIT polls ends the wait, counts in
 // g_split_stalls, and the job's output is then undefined; the kernel still
 // exits.  The last workgroup to finish clears the tickets and flags.
 constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
+constexpr int SPLIT_DONE = 8;    // finish counter (words 0-7: ticket counters per class)
 constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
 
 __device__ uint32_t g_split_stalls;
@@ -529,11 +533,12 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
   // two-wave inverse: row (or column) 16 wave + r, quad lane hq
   const int r4 = lane >> 2, hq = lane & 3;
   const uint64_t upper1 = (hq & 1) ? ~0ull : 0ull, upper2 = (hq & 2) ? ~0ull : 0ull;
-  if (threadIdx.x == 0) s_ticket = atomicAdd(sync, 1u);
+  const int cls = (int)(blockIdx.x & 7u);
+  if (threadIdx.x == 0) s_ticket = atomicAdd(sync + cls, 1u);
   __syncthreads();
   const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_ticket);
-  const int job = (int)((t >> 4) * 8 + (t & 7));
-  const int c = (int)((t >> 3) & 1);
+  const int job = (int)(t >> 1) * 8 + cls;
+  const int c = (int)(t & 1u);
 
   if (job < njobs) {
     const BrJob J = jobs[job];
@@ -691,15 +696,12 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
   // launch on this area (every other one has finished using them)
   vm_wait_all();
   __syncthreads();
-  if (threadIdx.x == 0) s_last = atomicAdd(sync + 1, 1u) == gridDim.x - 1 ? 1u : 0u;
+  if (threadIdx.x == 0) s_last = atomicAdd(sync + SPLIT_DONE, 1u) == gridDim.x - 1 ? 1u : 0u;
   __syncthreads();
   if (s_last) {
     const int nflags = (int)(gridDim.x / 2) * 8;
     for (int k = threadIdx.x; k < nflags; k += 192) store_agent(sync + SPLIT_FLAGS + k, 0u);
-    if (threadIdx.x == 0) {
-      store_agent(sync, 0u);
-      store_agent(sync + 1, 0u);
-    }
+    if (threadIdx.x <= SPLIT_DONE) store_agent(sync + threadIdx.x, 0u);  // the 8 class counters and the finish count
   }
 }
 
