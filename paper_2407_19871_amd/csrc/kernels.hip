@@ -462,10 +462,10 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Split blind rotation: one bootstrap on two workgroups of three waves,
+// Split blind rotation: one bootstrap on two workgroups of four waves,
 // normally on two CUs of one XCD, for levels too narrow to fill the GPU.
 // Workgroup role c owns accumulator component c (0 = mask A, 1 = body B);
-// its wave j runs gadget level j with whole-wave transforms (ntt64.h).
+// its wave j < 3 runs gadget level j with whole-wave transforms (ntt64.h).
 // Output component c of level j needs the level-j transforms of both
 // components,
 //   P_(c,j) = NTT(d_(c,j)) BSK[(c,j)][c] + NTT(d_(1-c,j)) BSK[(1-c,j)][c],
@@ -474,8 +474,8 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
 //   1. D_c = X^a ACC_c - ACC_c, digits of level j -> forward NTT F_(c,j);
 //   2. store F_(c,j) in this role's exchange slot, then raise the wave's
 //      flag to the step count; wait for the partner's flag; load F_(1-c,j);
-//   3. P_(c,j) into LDS; waves 0 and 1 sum the three levels in the NTT
-//      domain and invert the sum together (four lanes per row, ntt64.h),
+//   3. P_(c,j) into LDS; all four waves sum the three levels in the NTT
+//      domain and invert the sum together (eight lanes per row, ntt64.h),
 //      then add its centred lift to ACC_c.
 // Exchange data and flags use agent-scope relaxed atomics (coherent across
 // the CUs and XCDs of the device, no cache maintenance); a full vector
@@ -516,7 +516,7 @@ __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
+__global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
@@ -530,9 +530,13 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
-  // two-wave inverse: row (or column) 16 wave + r, quad lane hq
-  const int r4 = lane >> 2, hq = lane & 3;
-  const uint64_t upper1 = (hq & 1) ? ~0ull : 0ull, upper2 = (hq & 2) ? ~0ull : 0ull;
+  const bool lvl = wave < 3;  // waves 0-2 run the gadget levels; all four invert
+  // four-wave inverse: row (or column) 8 wave + r8, lane h8 of the row's eight
+  const int r8 = lane >> 3, h8 = lane & 7, row = 8 * wave + r8;
+  const uint64_t upper1 = (h8 & 1) ? ~0ull : 0ull, upper2 = (h8 & 2) ? ~0ull : 0ull,
+                 upper4 = (h8 & 4) ? ~0ull : 0ull;
+  uint64_t w2[4], w1[4];
+  inv256_twiddles(h8, w2, w1);
   const int cls = (int)(blockIdx.x & 7u);
   if (threadIdx.x == 0) s_ticket = atomicAdd(sync + cls, 1u);
   __syncthreads();
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
 
   if (job < njobs) {
     const BrJob J = jobs[job];
-    uint32_t* buf = s_tr[wave];
+    uint32_t* buf = s_tr[lvl ? wave : 0];
     {
       auto operand = [&](uint32_t r) -> const uint32_t* {
         if (r == REF_NONE) return nullptr;
@@ -552,7 +556,7 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
       };
       const uint32_t* in0 = operand(J.in0);
       const uint32_t* in1 = operand(J.in1);
-      for (int k = threadIdx.x; k <= n_lwe; k += 192) {
+      for (int k = threadIdx.x; k <= n_lwe; k += 256) {
         uint32_t v = (k == n_lwe) ? J.cst : 0u;
         if (in0) v += (uint32_t)J.c0 * in0[k];
         if (in1) v += (uint32_t)J.c1 * in1[k];
@@ -562,16 +566,17 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
     __syncthreads();
     // ACC_0 = 0, ACC_1 = X^{-b} v (coefficient j: +1/8 if (j + b) mod 2N < N)
     const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
-    for (int j = threadIdx.x; j < RING_N; j += 192)
+    for (int j = threadIdx.x; j < RING_N; j += 256)
       s_acc[j] = c == 0 ? 0u : ((((uint32_t)j + bbar) & 2047u) < 1024u ? 0x20000000u : 0xE0000000u);
     __syncthreads();
 
     const gmem_u64* bsk = as_global(bsk_tab[J.key]);
     const int nsteps = steps < n_lwe ? steps : n_lwe;
-    uint64_t* my_x = xbuf + ((size_t)(job * 2 + c) * 6 + wave) * RING_N;
-    const uint64_t* peer_x = xbuf + ((size_t)(job * 2 + (1 - c)) * 6 + wave) * RING_N;
-    uint32_t* my_flag = sync + SPLIT_FLAGS + job * 8 + c * 4 + wave;
-    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * 8 + (1 - c) * 4 + wave;
+    const int lw = lvl ? wave : 0;  // wave 3 has no exchange slot (and uses none)
+    uint64_t* my_x = xbuf + ((size_t)(job * 2 + c) * 6 + lw) * RING_N;
+    const uint64_t* peer_x = xbuf + ((size_t)(job * 2 + (1 - c)) * 6 + lw) * RING_N;
+    uint32_t* my_flag = sync + SPLIT_FLAGS + job * 8 + c * 4 + lw;
+    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * 8 + (1 - c) * 4 + lw;
     const int sh = 25 - 7 * wave;
     uint32_t done = 0;  // executed steps, the same count in both roles
     bool stalled = false;
@@ -582,94 +587,94 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
 
       // key rows (c, j) and (1-c, j), component c, at this lane's offsets
       const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
-      const gmem_u64* ko = step_key + (size_t)((c * 3 + wave) * 2 + c) * RING_N + 2 * l + h;
-      const gmem_u64* kt = step_key + (size_t)(((1 - c) * 3 + wave) * 2 + c) * RING_N + 2 * l + h;
+      const gmem_u64* ko = step_key + (size_t)((c * 3 + lw) * 2 + c) * RING_N + 2 * l + h;
+      const gmem_u64* kt = step_key + (size_t)(((1 - c) * 3 + lw) * 2 + c) * RING_N + 2 * l + h;
       uint64_t kown[16], koth[16];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        kown[s] = ko[s * 64];
-        koth[s] = kt[s * 64];
-      }
-
       int32_t dg[16];
+      if (lvl) {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const uint32_t j = (uint32_t)(l + 32 * (2 * s + h));
-        const uint32_t e = (j - a) & 2047u;
-        const uint32_t v = s_acc[e & 1023u];
-        const uint32_t D = ((e & 1024u) ? (0u - v) : v) - s_acc[j];
-        dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+        for (int s = 0; s < 16; ++s) {
+          kown[s] = ko[s * 64];
+          koth[s] = kt[s * 64];
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const uint32_t j = (uint32_t)(l + 32 * (2 * s + h));
+          const uint32_t e = (j - a) & 2047u;
+          const uint32_t v = s_acc[e & 1023u];
+          const uint32_t D = ((e & 1024u) ? (0u - v) : v) - s_acc[j];
+          dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+        }
       }
       __syncthreads();  // every wave has read ACC_c before any adds to it
-      uint64_t f[16];
-      ntt64_fwd_digits(dg, f, buf, opaque(tw_f), lane);
+      if (lvl) {
+        uint64_t f[16];
+        ntt64_fwd_digits(dg, f, buf, opaque(tw_f), lane);
 
-      const size_t par = (size_t)(done & 1u) * 3 * RING_N;
+        const size_t par = (size_t)(done & 1u) * 3 * RING_N;
 #pragma unroll
-      for (int s = 0; s < 16; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
-      // this component's products while the stores drain and the partner's
-      // transform is on its way (the empty asm keeps them ahead of the wait)
-      uint64_t plo[16], phi[16];
+        for (int s = 0; s < 16; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
+        // this component's products while the stores drain and the partner's
+        // transform is on its way (the empty asm keeps them ahead of the wait)
+        uint64_t plo[16], phi[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        gl_mul_wide(f[s], kown[s], plo[s], phi[s]);
-        asm volatile("" : "+v"(plo[s]), "+v"(phi[s]));
-      }
-      vm_wait_all();
-      if (lane == 0) store_agent(my_flag, done + 1);
-      if (!stalled) {
-        int it = 0;
-        while (load_agent(peer_flag) < done + 1) {
-          if (++it == SPLIT_SPIN_LIMIT) break;
-          __builtin_amdgcn_s_sleep(1);
+        for (int s = 0; s < 16; ++s) {
+          gl_mul_wide(f[s], kown[s], plo[s], phi[s]);
+          asm volatile("" : "+v"(plo[s]), "+v"(phi[s]));
         }
-        if (it == SPLIT_SPIN_LIMIT) {
-          stalled = true;
-          if (lane == 0) atomicAdd(&g_split_stalls, 1u);
+        vm_wait_all();
+        if (lane == 0) store_agent(my_flag, done + 1);
+        if (!stalled) {
+          int it = 0;
+          while (load_agent(peer_flag) < done + 1) {
+            if (++it == SPLIT_SPIN_LIMIT) break;
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (it == SPLIT_SPIN_LIMIT) {
+            stalled = true;
+            if (lane == 0) atomicAdd(&g_split_stalls, 1u);
+          }
         }
+        vm_wait_all();
+        uint64_t g[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+          s_part[wave][64 * s + 2 * l + h] = gl_mul_sum_wide(plo[s], phi[s], g[s], koth[s]);
       }
-      vm_wait_all();
-      uint64_t g[16];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
-#pragma unroll
-      for (int s = 0; s < 16; ++s) s_part[wave][64 * s + 2 * l + h] = gl_mul_sum_wide(plo[s], phi[s], g[s], koth[s]);
       __syncthreads();
 
-      // one inverse of the three levels' sum, on waves 0 and 1: each holds
-      // 16 rows at four lanes per row (the NTT-domain offset of position q of
-      // row k is 64 (q >> 1) + 2 k + (q & 1))
-      if (wave < 2) {
-        const int row = 16 * wave + r4;
-        uint64_t v[8];
+      // one inverse of the three levels' sum, on all four waves: each holds
+      // eight rows at eight lanes per row (the NTT-domain offset of position
+      // q of row k is 64 (q >> 1) + 2 k + (q & 1))
+      {
+        uint64_t v[4];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int off = 128 * s + 64 * (hq >> 1) + 2 * row + (hq & 1);
+        for (int s = 0; s < 4; ++s) {
+          const int off = 256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1);
           v[s] = gl_add(gl_add(s_part[0][off], s_part[1][off]), s_part[2][off]);
         }
-        inv128_p2(v, upper1, upper2, upper2);
+        inv256_p2(v, upper1, upper2, upper4, w2);
         {
-          const gmem_u64* t = as_global(opaque(tw_i)) + hq * 32 + row;
-          uint64_t w[8];
+          const gmem_u64* t = as_global(opaque(tw_i)) + h8 * 32 + row;
+          uint64_t w[4];
 #pragma unroll
-          for (int s = 0; s < 8; ++s) w[s] = t[s * 128];
+          for (int s = 0; s < 4; ++s) w[s] = t[s * 256];
 #pragma unroll
-          for (int s = 0; s < 8; ++s) v[s] = gl_mul(v[s], w[s]);
+          for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], w[s]);
         }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) s_t128[row * T128_ROW + 4 * s + hq] = v[s];
-      }
-      __syncthreads();
-      if (wave < 2) {
-        const int col = 16 * wave + r4;
-        uint64_t v[8];
+        for (int s = 0; s < 4; ++s) s_t128[row * T128_ROW + 8 * s + h8] = v[s];
+        __syncthreads();
+        // column j1 = row of this lane, positions q = 8 s + h8
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v[s] = s_t128[(4 * s + hq) * T128_ROW + col];
-        inv128_p1(v, upper1, upper2, upper2);
+        for (int s = 0; s < 4; ++s) v[s] = s_t128[(8 * s + h8) * T128_ROW + row];
+        inv256_p1(v, upper1, upper2, upper4, w1);
         // the sum is an exact integer polynomial (|coefficient| < 2^50.6),
         // so its centred lift reduced mod 2^32 is exact
 #pragma unroll
-        for (int s = 0; s < 8; ++s) s_acc[col + 32 * (4 * s + hq)] += gl_lift_u32(v[s]);
+        for (int s = 0; s < 4; ++s) s_acc[row + 32 * (8 * s + h8)] += gl_lift_u32(v[s]);
       }
       ++done;
       __syncthreads();
@@ -677,12 +682,12 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
 
     if (raw_acc) {
       uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
-      for (int j = threadIdx.x; j < RING_N; j += 192) o[j] = s_acc[j];
+      for (int j = threadIdx.x; j < RING_N; j += 256) o[j] = s_acc[j];
     } else {
       // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
       uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
       if (c == 0) {
-        for (int j = threadIdx.x; j < RING_N; j += 192) {
+        for (int j = threadIdx.x; j < RING_N; j += 256) {
           if (j == 0) o[0] = s_acc[0];
           else o[RING_N - j] = 0u - s_acc[j];
         }
@@ -700,7 +705,7 @@ __global__ __launch_bounds__(192, 1) void blind_rotate_split_kernel(
   __syncthreads();
   if (s_last) {
     const int nflags = (int)(gridDim.x / 2) * 8;
-    for (int k = threadIdx.x; k < nflags; k += 192) store_agent(sync + SPLIT_FLAGS + k, 0u);
+    for (int k = threadIdx.x; k < nflags; k += 256) store_agent(sync + SPLIT_FLAGS + k, 0u);
     if (threadIdx.x <= SPLIT_DONE) store_agent(sync + threadIdx.x, 0u);  // the 8 class counters and the finish count
   }
 }
@@ -903,7 +908,7 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
     case 6: {
       if (!split || !split->xbuf || !split->sync || njobs > split->max_jobs) return hipErrorInvalidValue;
       const int grid = 16 * ((njobs + 7) / 8);
-      hipLaunchKernelGGL(blind_rotate_split_kernel, dim3(grid), dim3(192), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
+      hipLaunchKernelGGL(blind_rotate_split_kernel, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync);
       break;
     }

@@ -262,4 +262,113 @@ __device__ __forceinline__ void inv128_p1(uint64_t (&a)[8], uint64_t upper1, uin
   gs128_stage<16>(a, Z1<16>{});
 }
 
+// ---- inverse on four waves (eight lanes per row) -----------------------------
+// The same inverse over 256 lanes: wave w (0..3) holds rows 8 w .. 8 w + 7,
+// lane 8 r + h of the wave holds the four positions q = 8 s + h (s = 0..3)
+// of row 8 w + r.  Stages of distance 16 and 8 stay in the lane; distance
+// 4 pairs lanes h ^ 4 with a uniform block (q / 8 = s); distance 2 pairs
+// h ^ 2 with two blocks per slot (q / 4 = 2 s + (h >> 2)), both shifts
+// formed; distance 1 pairs h ^ 1 with four blocks per slot (q / 2 = 4 s +
+// (h >> 1)), so each lane multiplies by its own twiddle, computed once per
+// launch (gl_pow2).  Output, in lane 8 r + h of wave w, slot s: coefficient
+// j1 + 32 q with j1 = 8 w + r, q = 8 s + h.
+
+// The value held by lane ^ 4 of each group of eight: lanes h < 4 read
+// lane + 4 (DPP row_shl:4), lanes h >= 4 lane - 4 (row_shr:4); hi4 = ~0 in
+// lanes h >= 4.
+__device__ __forceinline__ uint32_t oct_xor4_u32(uint32_t x, bool hi4) {
+  const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0xF, false);
+  const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);
+  return hi4 ? dn : up;
+}
+__device__ __forceinline__ uint64_t oct_xor4(uint64_t v, bool hi4) {
+  return ((uint64_t)oct_xor4_u32((uint32_t)(v >> 32), hi4) << 32) | oct_xor4_u32((uint32_t)v, hi4);
+}
+
+// 2^e mod p, reduced, for a runtime e in [0, 192).
+__device__ __forceinline__ uint64_t gl_pow2(int e) {
+  uint64_t w = 1;
+  for (int k = 0; k < e; ++k) w = gl_add(w, w);
+  return gl_canon(w);
+}
+
+// Gentleman-Sande stage of distance D in {1, 2, 4} across the eight lanes
+// of a row; FIRST: the inputs may be lazy.  upper: ~0 in the upper lane of
+// each pair (h & D); hi4: ~0 in lanes h >= 4; w1: the lane's twiddles of
+// the distance-1 stage (one per slot).
+template <int D, bool FIRST, typename Zf>
+__device__ __forceinline__ void gs256_cross(uint64_t (&a)[4], Zf zf, uint64_t upper, uint64_t hi4,
+                                            const uint64_t (&w1)[4]) {
+  static_for<0, 4>([&](auto ss) {
+    constexpr int s = decltype(ss)::value;
+    uint64_t other;
+    if constexpr (D == 4) other = oct_xor4(a[s], hi4 != 0);
+    else other = quad_xor<D>(a[s]);
+    const uint64_t self = a[s];
+    const uint64_t X = lane_select(upper, self, other), Y0 = lane_select(upper, other, self);
+    const uint64_t Y = FIRST ? gl_canon(Y0) : Y0;
+    const uint64_t sum = gl_canon(gl_add_r(X, Y));
+    const uint64_t dif = gl_sub_r(X, Y);
+    uint64_t up;
+    if constexpr (D == 4) {
+      constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
+      up = gl_mul_pow2_r<192 - z>(dif);
+    } else if constexpr (D == 2) {
+      constexpr int za = decltype(zf(std::integral_constant<int, 2 * s>{}))::value;
+      constexpr int zb = decltype(zf(std::integral_constant<int, 2 * s + 1>{}))::value;
+      up = lane_select(hi4, gl_mul_pow2_r<192 - za>(dif), gl_mul_pow2_r<192 - zb>(dif));
+    } else {
+      up = gl_canon(gl_mul(dif, w1[s]));
+    }
+    a[s] = lane_select(upper, sum, up);
+  });
+}
+
+// In-lane stage of distance LEN in {8, 16}: slots s and s + LEN / 16 within
+// blocks of LEN / 4 slots.
+template <int LEN, typename Zf>
+__device__ __forceinline__ void gs256_stage(uint64_t (&a)[4], Zf zf) {
+  constexpr int span = LEN / 4;
+  static_for<0, 4 / span>([&](auto bb) {
+    constexpr int blk = decltype(bb)::value;
+    constexpr int z = decltype(zf(std::integral_constant<int, blk>{}))::value;
+    static_for<0, span / 2>([&](auto jj) {
+      constexpr int s0 = blk * span + decltype(jj)::value, s1 = s0 + span / 2;
+      const uint64_t x = a[s0], y = a[s1];
+      a[s0] = gl_canon(gl_add_r(x, y));
+      a[s1] = gl_mul_pow2_r<192 - z>(gl_sub_r(x, y));
+    });
+  });
+}
+
+// The lane's distance-1 twiddles of each pass: 2^(192 - z) for the block
+// 4 s + (h >> 1) of slot s (pass 2: z = 6 (brv5(b) >> 1); pass 1: z =
+// 3 brv5(16 + b)).
+__device__ __forceinline__ void inv256_twiddles(int h, uint64_t (&w2)[4], uint64_t (&w1)[4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int b = 4 * s + (h >> 1);
+    w2[s] = gl_pow2((192 - 6 * (brv5(b) >> 1)) % 192);
+    w1[s] = gl_pow2((192 - 3 * brv5(16 + b)) % 192);
+  }
+}
+
+__device__ __forceinline__ void inv256_p2(uint64_t (&a)[4], uint64_t upper1, uint64_t upper2, uint64_t upper4,
+                                          const uint64_t (&w2)[4]) {
+  gs256_cross<1, true>(a, Z2<1>{}, upper1, upper4, w2);
+  gs256_cross<2, false>(a, Z2<2>{}, upper2, upper4, w2);
+  gs256_cross<4, false>(a, Z2<4>{}, upper4, upper4, w2);
+  gs256_stage<8>(a, Z2<8>{});
+  gs256_stage<16>(a, Z2<16>{});
+}
+
+__device__ __forceinline__ void inv256_p1(uint64_t (&a)[4], uint64_t upper1, uint64_t upper2, uint64_t upper4,
+                                          const uint64_t (&w1)[4]) {
+  gs256_cross<1, true>(a, Z1<1>{}, upper1, upper4, w1);
+  gs256_cross<2, false>(a, Z1<2>{}, upper2, upper4, w1);
+  gs256_cross<4, false>(a, Z1<4>{}, upper4, upper4, w1);
+  gs256_stage<8>(a, Z1<8>{});
+  gs256_stage<16>(a, Z1<16>{});
+}
+
 }  // namespace lp

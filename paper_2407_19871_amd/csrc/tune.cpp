@@ -85,7 +85,7 @@ int default_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   return sp;
 }
 
-// MI355X, n = 630: split 10.0-10.4 ms per launch up to 128 rotations; four
+// MI355X, n = 630: split 9.0-9.4 ms per launch up to 128 rotations; four
 // waves 13.2 ms up to 256 (one rotation per CU); three waves 16.3 ms up to
 // 256 and 25 ms at 512 (two per CU); one wave beyond.
 int default_br_wpb(size_t njobs) {
