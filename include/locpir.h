@@ -350,7 +350,11 @@ lp_status lp_profile_collect_launches(lp_launch_record* recs, int* count);
  * current device's count of these events, since the library was loaded,
  * goes up by one per wave.  Writes that count to *count (synchronous: waits
  * for the device).  Pairing draws tickets on arrival, so the count stays 0
- * unless other work holds every CU for the whole bound. */
+ * unless other work holds every CU for the whole bound.  The environment
+ * variable LOCPIR_SPLIT_SPIN, when set to a smaller positive number of
+ * polls, lowers the bound for the launches made while it is set (a test of
+ * the give-up path; captured query graphs keep the bound they were captured
+ * with). */
 lp_status lp_split_stall_count(uint32_t* count);
 
 /* ---- launch-shape autotuning --------------------------------------------- */

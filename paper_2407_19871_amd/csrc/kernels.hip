@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
+
 #include "gl64.h"
 #include "jobs.h"
 #include "kernels.h"
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
-    uint32_t* __restrict__ sync) {
+    uint32_t* __restrict__ sync, int spin_limit) {
   __shared__ uint32_t s_acc[RING_N];
   __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
   __shared__ __align__(16) uint64_t s_part[3][RING_N];     // the levels' partials, NTT domain
@@ -627,10 +629,10 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
         if (!stalled) {
           int it = 0;
           while (load_agent(peer_flag) < done + 1) {
-            if (++it == SPLIT_SPIN_LIMIT) break;
+            if (++it >= spin_limit) break;
             __builtin_amdgcn_s_sleep(1);
           }
-          if (it == SPLIT_SPIN_LIMIT) {
+          if (it >= spin_limit) {
             stalled = true;
             if (lane == 0) atomicAdd(&g_split_stalls, 1u);
           }
@@ -887,6 +889,8 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
   return hipGetLastError();
 }
 
+int split_spin_limit();
+
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
                                int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
@@ -909,7 +913,8 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       if (!split || !split->xbuf || !split->sync || njobs > split->max_jobs) return hipErrorInvalidValue;
       const int grid = 16 * ((njobs + 7) / 8);
       hipLaunchKernelGGL(blind_rotate_split_kernel, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
-                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync);
+                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
+                         split_spin_limit());
       break;
     }
     default:
@@ -919,6 +924,15 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
 }
 
 static int split_jobs_padded(int max_jobs) { return (max_jobs + 7) / 8 * 8; }
+
+// Polls of a split wait before it gives up: SPLIT_SPIN_LIMIT, or a smaller
+// positive LOCPIR_SPLIT_SPIN (tests force the give-up path with it; every
+// wave still runs to the end).
+int split_spin_limit() {
+  const char* v = std::getenv("LOCPIR_SPLIT_SPIN");
+  const long x = (v && *v) ? std::atol(v) : 0;
+  return x > 0 && x < SPLIT_SPIN_LIMIT ? (int)x : SPLIT_SPIN_LIMIT;
+}
 size_t split_xbuf_bytes(int max_jobs) { return (size_t)split_jobs_padded(max_jobs) * 12 * RING_N * 8; }
 size_t split_sync_bytes(int max_jobs) { return (size_t)(SPLIT_FLAGS + split_jobs_padded(max_jobs) * 8) * 4; }
 

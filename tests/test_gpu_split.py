@@ -24,6 +24,13 @@ def dkey(okeys):
     return device_key_from_oracle(okeys)
 
 
+@pytest.fixture(scope="module")
+def stalls_before(dkey):
+    """The device's count of split waits that ran out of polls before the
+    tests of this module."""
+    return lp.split_stall_count()
+
+
 @pytest.fixture
 def split_table():
     """Split rotations up to 128 jobs, one gadget level per wave above."""
@@ -160,6 +167,27 @@ def test_query_xnor_placements(monkeypatch, okeys, dkey, placement_query, early)
     assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, True)
 
 
-def test_no_stalled_waits(dkey):
+def test_no_stalled_waits(dkey, stalls_before):
     """No split wait above ran out of polls."""
-    assert lp.split_stall_count() == 0
+    assert lp.split_stall_count() == stalls_before
+
+
+def test_give_up_path_is_bounded_and_leaves_the_area_clean(monkeypatch, okeys, octx, dkey, split_table):
+    """Forced from the host with a one-poll limit, split waits give up: the
+    kernel still finishes, the stalls are counted, and the next launches on
+    the same query program's exchange area (eager, so that each launch reads
+    the limit) are exact again."""
+    monkeypatch.setenv("LOCPIR_GRAPHS", "0")
+    q = W.random_query_u8(61, force_inside=True)
+    parts = _query_parts(okeys, q, seed=62)
+    l, N, m = q.l, q.n_boxes, q.m
+    args = [lp.to_device(v) for v in parts]
+    before = lp.split_stall_count()
+    monkeypatch.setenv("LOCPIR_SPLIT_SPIN", "1")
+    lp.eval_bbox_query(dkey, l, N, m, False, *args)
+    assert lp.split_stall_count() > before
+    monkeypatch.delenv("LOCPIR_SPLIT_SPIN")
+    after = lp.split_stall_count()
+    got = as_u32(lp.eval_bbox_query(dkey, l, N, m, False, *args))
+    assert (got == octx.bbox_query(l, N, m, False, *parts)).all()
+    assert lp.split_stall_count() == after
