@@ -365,7 +365,8 @@ lp_status lp_split_stall_count(uint32_t* count);
  *   br_waves: waves cooperating on one blind rotation, 1 (throughput), 3
  *             (one gadget level per wave, latency), 4 (three level waves,
  *             then the levels summed in the NTT domain and each component
- *             inverted once on two waves; one rotation per CU) or 6 (the rotation split
+ *             inverted once on two waves; one rotation per CU), 5 (the
+ *             same, sized for two rotations per CU) or 6 (the rotation split
  *             over two workgroups, normally two CUs, each owning one
  *             accumulator component and trading forward transforms with
  *             the other every step; lower latency again, for launches of at

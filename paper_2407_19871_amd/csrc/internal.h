@@ -100,8 +100,8 @@ int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe);
 // timed table; false when there is none.
 bool est_br_launch_us(size_t njobs, double* us);
 // Waves per bootstrap: 6 (split over two workgroups) up to kSplitMaxJobs,
-// 4 (levels summed, two-wave inverses) up to 256, 3 (one gadget level per
-// wave) up to 512, else 1.
+// 4 (levels summed, two-wave inverses) up to 256, 5 (the same, two per CU)
+// up to 768, else 1.
 int pick_br_wpb(size_t njobs);
 // Built-in defaults (no environment, no table).
 int default_ks_tile(size_t njobs);

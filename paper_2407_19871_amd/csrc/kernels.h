@@ -46,8 +46,9 @@ hipError_t split_stall_count(uint32_t* out);
 // jobs.  ex: extract buffer, N+1 words per slot (2N per slot when raw_acc).
 // waves_per_job: 1 (one wave per bootstrap), 3 (one wave per gadget level),
 // 4 (three level waves, the levels' NTT-domain sum inverted once per
-// component on two waves each) or 6 (split over two workgroups; needs
-// `split` with room for njobs).
+// component on two waves each; one bootstrap per CU), 5 (the same, two
+// bootstraps per CU) or 6 (split over two workgroups; needs `split` with
+// room for njobs).
 // d_pool_tab (may be null) resolves operands with base KEY_POOL_BASE to the
 // pool of the job's key.
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,

@@ -220,20 +220,26 @@ __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restri
 //          partial products in LDS; the levels' sum of each component is
 //          inverted once, by two waves at four lanes per row (ntt64.h),
 //          waves 0-1 for the mask and 2-3 for the body (latency mode, one
-//          bootstrap per CU: 102 KB of LDS).
+//          bootstrap per CU: 102 KB of LDS);
+//   W = 5: the same four waves sized for two bootstraps per CU: key rows
+//          loaded where they are used (at most 256 registers), and the
+//          forward transposes placed in the partials' space behind one
+//          more barrier per step (76 KB of LDS).
 // The accumulator lives in LDS ([component][coefficient] u32); each level
 // re-reads it to form X^a ACC - ACC.
 constexpr int T128_ROW = 36;  // u64 words per row of a two-wave transpose (bank spread)
 
 template <int W>
-__global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
+__global__ __launch_bounds__(64 * (W == 5 ? 4 : W), (W == 1 || W == 5) ? 2 : 1) void blind_rotate_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
-  constexpr int NL = W == 4 ? 3 : W;  // waves that run gadget levels
-  constexpr bool SUM = W == 4;        // levels summed in the NTT domain
+  constexpr int NW = W == 5 ? 4 : W;   // waves per bootstrap
+  constexpr int NL = W >= 4 ? 3 : W;   // waves that run gadget levels
+  constexpr bool SUM = W >= 4;         // levels summed in the NTT domain
+  constexpr bool DUAL = W == 5;        // two bootstraps per CU
   __shared__ uint32_t s_acc[2][RING_N];
-  __shared__ __align__(16) uint32_t s_tr[NL][2][LDS_HALF];
+  __shared__ __align__(16) uint32_t s_tr[DUAL ? 1 : NL][2][DUAL ? 4 : LDS_HALF];
   __shared__ __align__(16) uint64_t s_part[SUM ? 3 : 1][2][SUM ? RING_N : 2];
   __shared__ __align__(16) uint64_t s_t128[2][SUM ? 32 * T128_ROW : 1];
   __shared__ uint16_t s_abar[MAX_LWE + 4];
@@ -244,7 +250,8 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
   if (job >= njobs) return;  // uniform over the block
 
   const BrJob J = jobs[job];
-  uint32_t* buf = s_tr[wave < NL ? wave : 0][h];
+  const int lw = wave < NL ? wave : 0;  // level of this wave (any, for a wave without one)
+  uint32_t* buf = DUAL ? reinterpret_cast<uint32_t*>(&s_part[0][0][0]) + (lw * 2 + h) * LDS_HALF : s_tr[lw][h];
   uint32_t* acc = s_acc[h];
 
   // modulus switch of the combined input (0, cst) + c0 in0 + c1 in1
@@ -257,7 +264,7 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     };
     const uint32_t* in0 = operand(J.in0);
     const uint32_t* in1 = operand(J.in1);
-    for (int c = threadIdx.x; c <= n_lwe; c += 64 * W) {
+    for (int c = threadIdx.x; c <= n_lwe; c += 64 * NW) {
       uint32_t v = (c == n_lwe) ? J.cst : 0u;
       if (in0) v += (uint32_t)J.c0 * in0[c];
       if (in1) v += (uint32_t)J.c1 * in1[c];
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
   // ACC = (0, X^{-b} v), v = sum_j (1/8) X^j: coefficient j of X^{-b} v is
   // +1/8 when (j + b) mod 2N < N, else -1/8
   const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
-  for (int c = threadIdx.x; c < 2 * RING_N; c += 64 * W) {
+  for (int c = threadIdx.x; c < 2 * RING_N; c += 64 * NW) {
     const uint32_t j = (uint32_t)c & 1023u;
     s_acc[c >> 10][j] = c < RING_N ? 0u : ((((j + bbar) & 2047u) < 1024u) ? 0x20000000u : 0xE0000000u);
   }
@@ -285,18 +292,20 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
     if constexpr (SUM) {
       const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
       const bool lvl = wave < NL;
-      uint64_t kpre[64];
+      // rows (h, j) and (1-h, j), component h, of level j = wave
+      const gmem_u64* ko = step_key + (size_t)((h * 3 + lw) * 2 + h) * RING_N + l * 2;
+      const gmem_u64* kt = step_key + (size_t)(((1 - h) * 3 + lw) * 2 + h) * RING_N + l * 2;
+      uint64_t kpre[DUAL ? 1 : 64];
       int32_t dg[32];
       if (lvl) {
-        // rows (h, j) and (1-h, j), component h, of level j = wave
-        const gmem_u64* ko = step_key + (size_t)((h * 3 + wave) * 2 + h) * RING_N + l * 2;
-        const gmem_u64* kt = step_key + (size_t)(((1 - h) * 3 + wave) * 2 + h) * RING_N + l * 2;
+        if constexpr (!DUAL) {
 #pragma unroll
-        for (int sp = 0; sp < 16; ++sp) {
-          kpre[4 * sp + 0] = ko[sp * 64];
-          kpre[4 * sp + 1] = ko[sp * 64 + 1];
-          kpre[4 * sp + 2] = kt[sp * 64];
-          kpre[4 * sp + 3] = kt[sp * 64 + 1];
+          for (int sp = 0; sp < 16; ++sp) {
+            kpre[4 * sp + 0] = ko[sp * 64];
+            kpre[4 * sp + 1] = ko[sp * 64 + 1];
+            kpre[4 * sp + 2] = kt[sp * 64];
+            kpre[4 * sp + 3] = kt[sp * 64 + 1];
+          }
         }
         const int sh = 25 - 7 * wave;
 #pragma unroll
@@ -309,15 +318,28 @@ __global__ __launch_bounds__(64 * W, (W == 1 ? 2 : 1)) void blind_rotate_kernel(
         }
       }
       __syncthreads();  // every wave has read ACC before any adds to it
+      uint64_t f[32];
+      if (lvl) ntt_fwd_digits(dg, f, buf, opaque(tw_f), l);
+      if constexpr (DUAL) __syncthreads();  // the transposes are done before the partials take their space
       if (lvl) {
-        uint64_t f[32];
-        ntt_fwd_digits(dg, f, buf, opaque(tw_f), l);
         uint64_t* part = s_part[wave][h];
 #pragma unroll
         for (int sp = 0; sp < 16; ++sp) {
+          uint64_t k0, k1, k2, k3;
+          if constexpr (DUAL) {
+            k0 = ko[sp * 64];
+            k1 = ko[sp * 64 + 1];
+            k2 = kt[sp * 64];
+            k3 = kt[sp * 64 + 1];
+          } else {
+            k0 = kpre[4 * sp];
+            k1 = kpre[4 * sp + 1];
+            k2 = kpre[4 * sp + 2];
+            k3 = kpre[4 * sp + 3];
+          }
           const uint64_t g0 = from_other_half(f[2 * sp], lane), g1 = from_other_half(f[2 * sp + 1], lane);
-          part[sp * 64 + 2 * l] = gl_mul_sum(f[2 * sp], kpre[4 * sp], g0, kpre[4 * sp + 2]);
-          part[sp * 64 + 2 * l + 1] = gl_mul_sum(f[2 * sp + 1], kpre[4 * sp + 1], g1, kpre[4 * sp + 3]);
+          part[sp * 64 + 2 * l] = gl_mul_sum(f[2 * sp], k0, g0, k2);
+          part[sp * 64 + 2 * l + 1] = gl_mul_sum(f[2 * sp + 1], k1, g1, k3);
         }
       }
       __syncthreads();
@@ -907,6 +929,10 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       break;
     case 4:
       hipLaunchKernelGGL(blind_rotate_kernel<4>, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
+                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+      break;
+    case 5:
+      hipLaunchKernelGGL(blind_rotate_kernel<5>, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
     case 6: {
