@@ -175,16 +175,6 @@ __device__ __forceinline__ void ntt64_fwd_digits(const int32_t (&d)[16], uint64_
   fwd64_p2(f, lane);
 }
 
-// Inverse of ntt64_fwd_digits including the 1/1024 scaling.
-__device__ __forceinline__ void ntt64_inv(uint64_t (&f)[16], uint32_t* buf, const uint64_t* __restrict__ tw_i,
-                                          int lane) {
-  const int h = lane >> 5, l = lane & 31;
-  inv64_p2(f, lane);
-  twist64(f, tw_i, lane);
-  transpose64(f, buf, h, l);
-  inv64_p1(f, lane);
-}
-
 // Offset of (slot s, lane l) inside one NTT-domain polynomial.
 __device__ __forceinline__ int ntt_pos(int s, int l) { return (s >> 1) * 64 + l * 2 + (s & 1); }
 
