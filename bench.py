@@ -46,8 +46,8 @@ ALG_LANE_CYCLES_PER_BR = 630 * ((6 + 2) * 5120 * 40 + 12 * 1024 * 35)
 KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd/csrc/ntt32.h",
                   "paper_2407_19871_amd/csrc/ntt64.h", "paper_2407_19871_amd/csrc/gl64.h"]
 # blind-rotation kernel of each launch shape (waves per bootstrap)
-SHAPE_KERNEL = {1: "blind_rotate_kernel<1>", 3: "blind_rotate_kernel<3>", 4: "blind_rotate_kernel<4>",
-                5: "blind_rotate_kernel<5>", 6: "blind_rotate_split_kernel"}
+SHAPE_KERNEL = {1: "blind_rotate_kernel<1>", 2: "blind_rotate_pair_kernel", 3: "blind_rotate_kernel<3>",
+                4: "blind_rotate_kernel<4>", 5: "blind_rotate_kernel<5>", 6: "blind_rotate_split_kernel"}
 TUNE_BUCKETS = (1, 16, 32, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16384)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_bbox16x16_traffic.txt")
 VALU_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_valu_issue.txt")

@@ -362,8 +362,11 @@ lp_status lp_split_stall_count(uint32_t* count);
 /* One row of a device's launch-shape table.  A launch of `count` jobs uses
  * the first row (rows sorted by `jobs`, ascending) with count <= jobs, or
  * the last row when count exceeds every bound.
- *   br_waves: waves cooperating on one blind rotation, 1 (throughput), 3
- *             (one gadget level per wave, latency), 4 (three level waves,
+ *   br_waves: waves cooperating on one blind rotation, 1 (throughput), 2
+ *             (one accumulator component per wave, the two trading their
+ *             cross terms in the NTT domain; two waves per SIMD at four
+ *             rotations per CU), 3 (one gadget level per wave, latency), 4
+ *             (three level waves,
  *             then the levels summed in the NTT domain and each component
  *             inverted once on two waves; one rotation per CU), 5 (the
  *             same, sized for two rotations per CU) or 6 (the rotation split

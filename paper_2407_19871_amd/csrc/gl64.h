@@ -125,6 +125,16 @@ GL_INLINE uint64_t gl_mul_sum(uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
   return gl_mul_sum_wide(l1, h1, c, d);
 }
 
+// acc + a b mod p with one reduction: a product of two 64-bit values has
+// a high word of at most 2^64 - 2, so the carry of adding acc to the low
+// word fits in it.
+GL_INLINE uint64_t gl_mac(uint64_t acc, uint64_t a, uint64_t b) {
+  uint64_t lo, hi;
+  gl_mul_wide(a, b, lo, hi);
+  const bool c = __builtin_add_overflow(lo, acc, &lo);
+  return gl_reduce128(lo, hi + (c ? 1ull : 0ull));
+}
+
 // x * 2^S mod p for a compile-time S; the result is lazy for S mod 192 in
 // (0, 64) and reduced otherwise (see gl_mul_pow2_r).  2^96 = -1 folds S
 // into [0, 96) with a negation.

@@ -44,7 +44,8 @@ hipError_t split_stall_count(uint32_t* out);
 
 // Blind rotation + sample extraction (or raw accumulator output) of njobs
 // jobs.  ex: extract buffer, N+1 words per slot (2N per slot when raw_acc).
-// waves_per_job: 1 (one wave per bootstrap), 3 (one wave per gadget level),
+// waves_per_job: 1 (one wave per bootstrap), 2 (one wave per accumulator
+// component, two bootstraps per SIMD), 3 (one wave per gadget level),
 // 4 (three level waves, the levels' NTT-domain sum inverted once per
 // component on two waves each; one bootstrap per CU), 5 (the same, two
 // bootstraps per CU) or 6 (split over two workgroups; needs `split` with

@@ -175,6 +175,18 @@ __device__ __forceinline__ void ntt64_fwd_digits(const int32_t (&d)[16], uint64_
   fwd64_p2(f, lane);
 }
 
+// Inverse of ntt64_fwd_digits including the 1/1024 scaling: in, the value
+// at offset 64 s + 2 l + h of the NTT-domain layout in slot s of lane
+// (h, l) (lazy residues allowed); out, coefficient l + 32 (2s + h).
+__device__ __forceinline__ void ntt64_inv(uint64_t (&f)[16], uint32_t* buf, const uint64_t* __restrict__ tw_i,
+                                          int lane) {
+  const int h = lane >> 5, l = lane & 31;
+  inv64_p2(f, lane);
+  twist64(f, tw_i, lane);
+  transpose64(f, buf, h, l);
+  inv64_p1(f, lane);
+}
+
 // Offset of (slot s, lane l) inside one NTT-domain polynomial.
 __device__ __forceinline__ int ntt_pos(int s, int l) { return (s >> 1) * 64 + l * 2 + (s & 1); }
 
@@ -470,6 +482,165 @@ __global__ __launch_bounds__(64 * (W == 5 ? 4 : W), (W == 1 || W == 5) ? 2 : 1) 
         else o[RING_N - j] = 0u - acc[j];
       }
     } else if (l == 0) {
+      o[RING_N] = acc[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blind rotation on two waves per bootstrap, one accumulator component per
+// wave: wave c owns ACC_c (0 = mask A, 1 = body B) and runs whole-wave
+// transforms (ntt64.h).  Output component o of a step is the sum over both
+// input components c and the three gadget levels j of
+// NTT(d_(c,j)) BSK[(c,j)][o], so each step wave c
+//   1. forms D_c = X^a ACC_c - ACC_c, transforms the digits of every level
+//      and accumulates its terms of both outputs, Q_(c->c) and Q_(c->1-c);
+//   2. hands Q_(c->1-c) to the partner through LDS and adds the partner's
+//      Q_(1-c->c) to its own: the full output component c, an exact
+//      integer polynomial (|coefficient| < 2^50.6) in the NTT domain;
+//   3. inverts it and adds its centred lift mod 2^32 to ACC_c.
+// Every wave does a third of the forward transforms, half of the products
+// and one inverse, with no accumulator shared between waves.  Sized for two
+// waves per SIMD (four bootstraps per CU), the shape for levels of about
+// one bootstrap per SIMD, where one wave per bootstrap leaves a SIMD a
+// single wave to issue from.
+//
+// A wave's inbox (the partner's term) doubles as its transpose block
+// between reading it and the partner's next write: the partner writes only
+// after the first barrier of the next step, which this wave reaches after
+// its inverse and its next forward transforms.
+__global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
+    const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
+    const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
+    int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i) {
+  __shared__ uint32_t s_acc[2][RING_N];
+  __shared__ __align__(16) uint64_t s_in[2][RING_N];  // inbox of wave c
+  __shared__ __align__(16) uint64_t s_twf[RING_N];    // forward twist table
+  __shared__ uint16_t s_abar[MAX_LWE + 4];
+
+  const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  const int job = blockIdx.x;
+  if (job >= njobs) return;  // uniform over the block
+  for (int k = threadIdx.x; k < RING_N; k += 128) s_twf[k] = tw_f[k];
+
+  const BrJob J = jobs[job];
+  {
+    auto operand = [&](uint32_t r) -> const uint32_t* {
+      if (r == REF_NONE) return nullptr;
+      const uint32_t base = r >> REF_SHIFT;
+      const uint32_t* b = base == KEY_POOL_BASE ? pool_tab[J.key] : src.p[base];
+      return b + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
+    };
+    const uint32_t* in0 = operand(J.in0);
+    const uint32_t* in1 = operand(J.in1);
+    for (int k = threadIdx.x; k <= n_lwe; k += 128) {
+      uint32_t v = (k == n_lwe) ? J.cst : 0u;
+      if (in0) v += (uint32_t)J.c0 * in0[k];
+      if (in1) v += (uint32_t)J.c1 * in1[k];
+      s_abar[k] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
+    }
+  }
+  __syncthreads();
+
+  // ACC_0 = 0, ACC_1 = X^{-b} v (coefficient j: +1/8 if (j + b) mod 2N < N)
+  uint32_t* acc = s_acc[c];
+  const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
+  for (int j = lane; j < RING_N; j += 64)
+    acc[j] = c == 0 ? 0u : ((((uint32_t)j + bbar) & 2047u) < 1024u ? 0x20000000u : 0xE0000000u);
+  wave_fence();
+
+  uint64_t* inbox = s_in[c];
+  uint64_t* outbox = s_in[1 - c];
+  uint32_t* tbuf = reinterpret_cast<uint32_t*>(inbox);
+  const gmem_u64* bsk = as_global(bsk_tab[J.key]);
+  const int nsteps = steps < n_lwe ? steps : n_lwe;
+
+  for (int i = 0; i < nsteps; ++i) {
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
+    if (a == 0) continue;  // X^0 ACC - ACC = 0 decomposes to zero digits
+
+    const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+    const gmem_u64* twi = as_global(opaque(tw_i)) + lane;  // twist64's reads
+    uint64_t qo[16], qx[16];  // terms of output c and of output 1 - c
+    // gadget level j: rows (c, j) of BSK_i, components c and 1 - c, at this
+    // lane's offsets 64 s + 2 l + h
+    auto level = [&](int j, auto first) {
+      // the rows are loaded before the transform, whose LDS transposes
+      // order every memory access behind them
+      const gmem_u64* ko = step_key + (size_t)((c * 3 + j) * 2 + c) * RING_N + 2 * l + h;
+      const gmem_u64* kx = step_key + (size_t)((c * 3 + j) * 2 + (1 - c)) * RING_N + 2 * l + h;
+      uint64_t k0[16], k1[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        k0[s] = ko[s * 64];
+        k1[s] = kx[s * 64];
+      }
+      const int sh = 25 - 7 * j;
+      int32_t dg[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const uint32_t k = (uint32_t)(l + 32 * (2 * s + h));
+        const uint32_t e = (k - a) & 2047u;
+        const uint32_t v = acc[e & 1023u];
+        const uint32_t D = ((e & 1024u) ? (0u - v) : v) - acc[k];
+        dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+      }
+      uint64_t f[16];  // ntt64_fwd_digits with the twist factors at hand
+      fwd64_p1_digits(dg, f);
+      fwd64_p1_rest(f, lane);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
+      transpose64(f, tbuf, h, l);
+      fwd64_p2(f, lane);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        if constexpr (decltype(first)::value) {
+          qo[s] = gl_mul(f[s], k0[s]);
+          qx[s] = gl_mul(f[s], k1[s]);
+        } else {
+          qo[s] = gl_mac(qo[s], f[s], k0[s]);
+          qx[s] = gl_mac(qx[s], f[s], k1[s]);
+        }
+      }
+    };
+    level(0, std::true_type{});
+#pragma nounroll
+    for (int j = 1; j < 3; ++j) level(j, std::false_type{});
+
+    uint64_t w[16];  // inverse twist factors, loaded ahead of the barriers
+#pragma unroll
+    for (int s = 0; s < 16; ++s) w[s] = twi[s * 64];
+    __syncthreads();  // the partner is done with its inbox of the previous step
+#pragma unroll
+    for (int s = 0; s < 16; ++s) outbox[64 * s + lane] = qx[s];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) qo[s] = gl_add(qo[s], inbox[64 * s + lane]);
+    wave_fence();  // the inbox is read before it serves as the transpose block
+    // ntt64_inv with the twist factors at hand
+    inv64_p2(qo, lane);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) qo[s] = gl_mul(qo[s], w[s]);
+    transpose64(qo, tbuf, h, l);
+    inv64_p1(qo, lane);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc[l + 32 * (2 * s + h)] += gl_lift_u32(qo[s]);
+    wave_fence();
+  }
+
+  if (raw_acc) {
+    uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
+    for (int j = lane; j < RING_N; j += 64) o[j] = acc[j];
+  } else {
+    // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
+    uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
+    if (c == 0) {
+      for (int j = lane; j < RING_N; j += 64) {
+        if (j == 0) o[0] = acc[0];
+        else o[RING_N - j] = 0u - acc[j];
+      }
+    } else if (lane == 0) {
       o[RING_N] = acc[0];
     }
   }
@@ -911,6 +1082,10 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
   switch (waves_per_job) {
     case 1:
       hipLaunchKernelGGL(blind_rotate_kernel<1>, dim3(njobs), dim3(64), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
+                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
+      break;
+    case 2:
+      hipLaunchKernelGGL(blind_rotate_pair_kernel, dim3(njobs), dim3(128), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
     case 3:

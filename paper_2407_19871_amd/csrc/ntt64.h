@@ -16,12 +16,12 @@
 //             out lane (h, l), slot s = A(k), k = brv5(l) + 32 brv5(2s + h),
 //             which sits at offset 64 s + 2 l + h of the 32-lane layout
 //             (ntt_pos), so NTT-domain keys are shared by both layouts.
-// The inverses below (on two or four waves) are Gentleman-Sande stages that
-// undo the merged Cooley-Tukey stages in reverse order, (X, Y) -> (X + Y,
-// (X - Y) w^-1), with the same per-block twiddles; each pass leaves a
-// factor 32, both factors sit in the inverse twist table (the one of the
-// 32-lane transform), and the pass-1 stages also undo the negacyclic
-// factor, so there is no post-twist.
+// The inverses below (on one, two or four waves) are Gentleman-Sande
+// stages that undo the merged Cooley-Tukey stages in reverse order,
+// (X, Y) -> (X + Y, (X - Y) w^-1), with the same per-block twiddles; each
+// pass leaves a factor 32, both factors sit in the inverse twist table (the
+// one of the 32-lane transform), and the pass-1 stages also undo the
+// negacyclic factor, so there is no post-twist.
 #pragma once
 #include "ntt32.h"
 
@@ -128,6 +128,56 @@ __device__ __forceinline__ void fwd64_p2(uint64_t (&a)[16], int lane) {
   ct64_stage<4>(a, Z2<4>{});
   ct64_stage<2>(a, Z2<2>{});
   ct64_cross(a, Z2<1>{}, lane);
+}
+
+// ---- inverse on one wave: Gentleman-Sande ---------------------------------
+// Stages after the first take reduced inputs (every stage leaves its
+// outputs reduced: sums canonicalised, products by gl_mul_pow2_r), so the
+// sum and the difference need one correction each.
+template <int LEN, typename Zf>
+__device__ __forceinline__ void gs64_stage(uint64_t (&a)[16], Zf zf) {
+  static_for<0, 16 / LEN>([&](auto bb) {
+    constexpr int blk = decltype(bb)::value;
+    constexpr int z = decltype(zf(std::integral_constant<int, blk>{}))::value;
+    static_for<0, LEN / 2>([&](auto jj) {
+      constexpr int s0 = blk * LEN + decltype(jj)::value, s1 = s0 + LEN / 2;
+      const uint64_t x = a[s0], y = a[s1];
+      a[s0] = gl_canon(gl_add_r(x, y));
+      a[s1] = gl_mul_pow2_r<192 - z>(gl_sub_r(x, y));
+    });
+  });
+}
+
+// The first stage of a pass, across the two lanes of a column; its inputs
+// may be lazy, its outputs are reduced.
+template <typename Zf>
+__device__ __forceinline__ void gs64_cross(uint64_t (&a)[16], Zf zf, int lane) {
+  const uint64_t odd = lane >= 32 ? ~0ull : 0ull;
+  static_for<0, 16>([&](auto ss) {
+    constexpr int s = decltype(ss)::value;
+    constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
+    uint64_t x, y;
+    pair_values(a[s], x, y);
+    const uint64_t yr = gl_canon(y);
+    const uint64_t dif = gl_mul_pow2_r<192 - z>(gl_sub_r(x, yr));
+    a[s] = lane_select(odd, gl_canon(gl_add_r(x, yr)), dif);
+  });
+}
+
+__device__ __forceinline__ void inv64_p2(uint64_t (&a)[16], int lane) {
+  gs64_cross(a, Z2<1>{}, lane);
+  gs64_stage<2>(a, Z2<2>{});
+  gs64_stage<4>(a, Z2<4>{});
+  gs64_stage<8>(a, Z2<8>{});
+  gs64_stage<16>(a, Z2<16>{});
+}
+
+__device__ __forceinline__ void inv64_p1(uint64_t (&a)[16], int lane) {
+  gs64_cross(a, Z1<1>{}, lane);
+  gs64_stage<2>(a, Z1<2>{});
+  gs64_stage<4>(a, Z1<4>{});
+  gs64_stage<8>(a, Z1<8>{});
+  gs64_stage<16>(a, Z1<16>{});
 }
 
 // ---- inverse on two waves (four lanes per row) -------------------------------

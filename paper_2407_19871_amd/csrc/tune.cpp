@@ -2,7 +2,8 @@
 //
 // Two shapes decide how a level of gates runs: the number of waves that
 // cooperate on one blind rotation (1: independent bootstraps fill the GPU;
-// 3: one gadget level per wave, for levels too narrow to fill it; 4: the
+// 2: one accumulator component per wave, for levels of about one bootstrap
+// per SIMD; 3: one gadget level per wave, for narrower levels; 4: the
 // same with the levels summed in the NTT domain and one inverse per
 // component on two waves; 5: the same sized for two bootstraps per CU; 6:
 // the bootstrap split over two workgroups, one
@@ -27,7 +28,8 @@ std::map<int, std::vector<lp_tune_entry>> g_tune;  // device -> rows sorted by j
 
 constexpr uint32_t kMaxTuneJobs = 1u << 22;      // row bound
 constexpr uint32_t kMaxTuneBucket = 1u << 16;    // batch size the autotuner times
-const int kWaves[] = {1, 3, 4, 5, 6};
+const int kWaves[] = {1, 2, 3, 4, 5, 6};
+constexpr int kNumWaves = sizeof(kWaves) / sizeof(kWaves[0]);
 const int kTiles[] = {1, 4, 8, 16};
 const int kSplits[] = {1, 2, 4, 8, 16};
 
@@ -38,7 +40,7 @@ bool one_of(int v, const int* set, int n) {
 }
 
 bool row_ok(const lp_tune_entry& r) {
-  return r.jobs >= 1 && r.jobs <= kMaxTuneJobs && one_of(r.br_waves, kWaves, 5) && one_of(r.ks_tile, kTiles, 4) &&
+  return r.jobs >= 1 && r.jobs <= kMaxTuneJobs && one_of(r.br_waves, kWaves, kNumWaves) && one_of(r.ks_tile, kTiles, 4) &&
          one_of(r.ks_split, kSplits, 5);
 }
 
@@ -88,10 +90,16 @@ int default_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
 
 // MI355X, n = 630: split 9.0-9.4 ms per launch up to 128 rotations; four
 // waves 13.2 ms up to 256 (one rotation per CU); four waves two per CU
-// 19.8 ms at 384-512 and 29.7 ms at 768 (three waves: 24.8 and 37.1); one
-// wave from 1024 (38 ms, level with the two-per-CU four waves).
+// 19.8 ms at 384-512 and 29.7 ms at 768 (three waves: 24.8 and 37.1); two
+// waves, one per component, 36.5 ms at 1024 (one wave 38.2, four waves
+// 38.0); four waves again at 1280 (47.2 ms, one wave 54.5); one wave from
+// 1536 (54-55 ms up to 2048).
 int default_br_wpb(size_t njobs) {
-  return njobs <= (size_t)kSplitMaxJobs ? 6 : njobs <= 256 ? 4 : njobs <= 768 ? 5 : 1;
+  if (njobs <= (size_t)kSplitMaxJobs) return 6;
+  if (njobs <= 256) return 4;
+  if (njobs <= 768) return 5;
+  if (njobs <= 1024) return 2;
+  return njobs <= 1280 ? 5 : 1;
 }
 
 int pick_ks_tile(size_t njobs) {
@@ -117,7 +125,7 @@ int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
 int pick_br_wpb(size_t njobs) {
   auto fit = [&](int w) { return w == 6 && njobs > (size_t)kSplitMaxJobs ? 3 : w; };
   const int forced = env_int("LOCPIR_BR_WAVES", 0);
-  if (one_of(forced, kWaves, 5)) return fit(forced);
+  if (one_of(forced, kWaves, kNumWaves)) return fit(forced);
   lp_tune_entry r;
   if (tuned_row(njobs, &r)) return fit(r.br_waves);
   return default_br_wpb(njobs);

@@ -21,7 +21,8 @@ def clean_table(monkeypatch):
 
 def test_defaults_without_table():
     assert lp.tune_table() == []
-    assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129, 256, 257, 768, 769)] == [6, 6, 4, 4, 5, 5, 1]
+    assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129, 256, 257, 768, 769, 1024, 1025, 1280, 1281)] == \
+        [6, 6, 4, 4, 5, 5, 2, 2, 5, 5, 1]
     assert [lp.tune_pick(j)["ks_tile"] for j in (1, 16, 256, 4096)] == [1, 4, 8, 16]
     # the default split grows until the key switch has >= 2048 blocks
     assert lp.tune_pick(1)["ks_split"] == 16
@@ -45,7 +46,7 @@ def test_environment_overrides_table(monkeypatch):
     assert g["br_waves"] == 1 and g["ks_tile"] == 8
     # the row's split belongs to tile 16, so tile 8 takes the default rule
     assert g["ks_split"] == lp.tune_pick(1024, 630)["ks_split"]
-    monkeypatch.setenv("LOCPIR_BR_WAVES", "2")  # invalid values are ignored
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "7")  # invalid values are ignored
     assert lp.tune_pick(1024)["br_waves"] == 3
 
 
@@ -63,7 +64,8 @@ def test_split_shape_applies_up_to_128_jobs(monkeypatch):
 
 @pytest.mark.parametrize("bad", [
     {"jobs": 0, "br_waves": 1, "ks_tile": 4, "ks_split": 1},
-    {"jobs": 8, "br_waves": 2, "ks_tile": 4, "ks_split": 1},
+    {"jobs": 8, "br_waves": 7, "ks_tile": 4, "ks_split": 1},
+    {"jobs": 8, "br_waves": 0, "ks_tile": 4, "ks_split": 1},
     {"jobs": 8, "br_waves": 1, "ks_tile": 3, "ks_split": 1},
     {"jobs": 8, "br_waves": 1, "ks_tile": 4, "ks_split": 32},
     {"jobs": (1 << 22) + 1, "br_waves": 1, "ks_tile": 4, "ks_split": 1},
