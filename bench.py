@@ -204,11 +204,13 @@ def microbench(lp, torch, sk, dk, sizes=(1, 64, 1024, 16384)):
     return {"batched_nand_bootstraps_per_s": res, "one_per_launch_bootstraps_per_s": round(one, 1)}
 
 
-def serve_bench(requests_per_rate: int, seed: int = 5):
+def serve_bench(requests_per_rate: int, tick_cap: int = 0, seed: int = 5):
     """Serving: requests with their own keys (a pool of client keys, each
     uploaded and converted on the GPU per request), 16- or 32-bit signed
     coordinates, 1..256 boxes log-uniform, 32-bit payloads.  A burst measures
-    the saturated rate, then Poisson arrivals at 0.25/0.5/0.75/0.95 of it."""
+    the saturated rate, then Poisson arrivals at 0.25/0.5/0.75/0.95 of it.
+    tick_cap > 0 caps the blind rotations of a server tick; p50 is also
+    given for requests of at most 16 boxes and for larger ones."""
     import math
     import torch
     import paper_2407_19871_amd as lp
@@ -235,7 +237,7 @@ def serve_bench(requests_per_rate: int, seed: int = 5):
         return q, c, parts
 
     def run(reqs, arrivals):
-        srv = lp.Server(200 << 30)
+        srv = lp.Server(200 << 30, max_tick_rotations=tick_cap)
         t0 = time.perf_counter()
         tickets = []
         for (q, c, parts), at in zip(reqs, arrivals):
@@ -253,16 +255,20 @@ def serve_bench(requests_per_rate: int, seed: int = 5):
         stats = srv.stats()
         srv.close()
         n_br = sum(lp.bbox_counts(q.l, q.n_boxes, q.m)[0] for q, _, _ in reqs)
+        small = [x for x, (q, _, _) in zip(lats, reqs) if q.n_boxes <= 16]
+        large = [x for x, (q, _, _) in zip(lats, reqs) if q.n_boxes > 16]
+        p50 = lambda v: round(float(np.percentile(v, 50)) * 1e3, 1) if v else None
         return {"queries_per_s": round(len(reqs) / wall, 3), "bootstraps_per_s": round(n_br / wall, 1),
-                "p50_ms": round(float(np.percentile(lats, 50)) * 1e3, 1),
-                "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1),
-                "requests": len(reqs), "ticks": stats["ticks"], "correct": bool(ok)}
+                "p50_ms": p50(lats), "p99_ms": round(float(np.percentile(lats, 99)) * 1e3, 1),
+                "p50_ms_upto16_boxes": p50(small), "p50_ms_over16_boxes": p50(large),
+                "requests": len(reqs), "ticks": stats["ticks"], "widest_tick": stats["widest_tick"],
+                "correct": bool(ok)}
 
     burst = [make_request(i) for i in range(requests_per_rate)]
     sat = run(burst, [0.0] * len(burst))
     print(f"serve: burst done, {sat['queries_per_s']} queries/s", file=sys.stderr, flush=True)
     res = {"metric": "serving: p50/p99 latency and queries/s under Poisson arrivals on 1 MI355X",
-           "saturated": sat, "rates": []}
+           "tick_cap": tick_cap, "saturated": sat, "rates": []}
     for k, f in enumerate((0.25, 0.5, 0.75, 0.95)):
         reqs = [make_request(1000 * (k + 1) + i) for i in range(requests_per_rate)]
         lam = f * sat["queries_per_s"]
@@ -446,6 +452,8 @@ def main():
                     help="also run device copies of this many bytes (traffic calibration)")
     ap.add_argument("--serve", type=int, default=0,
                     help="serving benchmark with this many requests per arrival rate (separate JSON line)")
+    ap.add_argument("--tick-cap", type=int, default=0,
+                    help="with --serve: blind rotations per server tick at most (0 = whole levels)")
     ap.add_argument("--sweep", action="store_true",
                     help="the paper's Fig. 4a / Table 2 query shapes and a box-count sweep (separate JSON line)")
     ap.add_argument("--clients", type=int, default=0,
@@ -459,7 +467,7 @@ def main():
         sys.exit(2)
 
     if args.serve:
-        serve_bench(args.serve)
+        serve_bench(args.serve, args.tick_cap)
         return
     if args.clients:
         clients_bench(args.clients, args.steps, args.warmup)

@@ -258,6 +258,12 @@ lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t m, uint32_
  * n, ks_base_bit and ks_t; keys of the lambda 128 and lambda 80 sets are
  * served side by side in separate launches); requests that arrive meanwhile
  * join at the next tick.  stats.ticks counts fused launch pairs.
+ * max_tick_rotations > 0 caps the blind rotations of one tick: requests
+ * with less of their level left than an equal share run all of it, the
+ * others split the rest (at least one gate each), and a level that does not
+ * fit runs over several ticks; results are unchanged, and a wide request no
+ * longer stretches the ticks of every narrow one beside it.
+ * stats.widest_tick is the most rotations one fused launch has held.
  * A finished request's result is kept on the host until polled; its device
  * memory is released at once.  A failing request (allocation, upload) ends
  * alone; the others continue.  Latency is measured from submit to the end of
@@ -268,6 +274,7 @@ typedef struct {
   uint32_t max_inflight; /* admitted requests at once; 0 = bounded by the budget only */
   int32_t simulate;      /* 1: schedule without a GPU (results are zero); for tests   */
   uint64_t fail_ticket;  /* fault injection: this ticket's set-up fails (0 = none)    */
+  uint32_t max_tick_rotations; /* blind rotations per tick at most; 0 = a whole level */
 } lp_server_config;
 /* A query whose ciphertexts are in host memory (same layout as lp_bbox_query). */
 typedef struct {
@@ -282,6 +289,7 @@ typedef struct {
   uint64_t submitted, admitted, completed, failed, cancelled, ticks, fused_bootstraps;
   uint32_t pending, active;
   size_t bytes_in_use, peak_bytes;
+  uint64_t widest_tick;
 } lp_server_stats;
 lp_status lp_server_create(const lp_server_config* cfg, lp_server** out);
 /* Device bytes a request of this key and shape holds while admitted. */

@@ -61,7 +61,7 @@ DEFAULT_TUNE_BUCKETS = (1, 16, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_uint32), ("simulate", C.c_int32),
-                ("fail_ticket", C.c_uint64)]
+                ("fail_ticket", C.c_uint64), ("max_tick_rotations", C.c_uint32)]
 
 
 class HostQuery(C.Structure):
@@ -73,7 +73,7 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
                 ("failed", C.c_uint64), ("cancelled", C.c_uint64), ("ticks", C.c_uint64),
                 ("fused_bootstraps", C.c_uint64), ("pending", C.c_uint32), ("active", C.c_uint32),
-                ("bytes_in_use", C.c_size_t), ("peak_bytes", C.c_size_t)]
+                ("bytes_in_use", C.c_size_t), ("peak_bytes", C.c_size_t), ("widest_tick", C.c_uint64)]
 
 
 class BBoxQuery(C.Structure):
@@ -568,11 +568,13 @@ LP_ECANCELED = -7
 
 class Server:
     """Continuous-batching query server (lp_server_*).  Queries are host
-    arrays (x, y, bounds, payload) of uint32 ciphertexts."""
+    arrays (x, y, bounds, payload) of uint32 ciphertexts.  max_tick_rotations
+    caps the blind rotations of one tick (0: a whole level per request)."""
 
-    def __init__(self, hbm_budget: int, max_inflight: int = 0, simulate: bool = False, fail_ticket: int = 0):
+    def __init__(self, hbm_budget: int, max_inflight: int = 0, simulate: bool = False, fail_ticket: int = 0,
+                 max_tick_rotations: int = 0):
         self._keep = {}
-        cfg = ServerConfig(hbm_budget, max_inflight, 1 if simulate else 0, fail_ticket)
+        cfg = ServerConfig(hbm_budget, max_inflight, 1 if simulate else 0, fail_ticket, max_tick_rotations)
         h = C.c_void_p()
         _check(lib().lp_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

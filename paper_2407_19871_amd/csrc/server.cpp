@@ -12,6 +12,13 @@
 // requests already in flight.  A finished request's result is copied to the
 // host and its device memory released.
 //
+// With a per-tick rotation cap, a tick runs at most that many blind
+// rotations: requests with less of their level left than an equal share of
+// the cap run all of it, the others split the rest, and a request whose
+// level does not fit runs it over several ticks.  Gates within a level are
+// independent, so results do not change; the tick time is bounded, which
+// keeps a wide request from slowing every narrow one it shares ticks with.
+//
 // simulate = 1 runs the same admission and scheduling without touching a
 // GPU (results are zero), which lets the host logic be tested on a CPU.
 #include <hip/hip_runtime.h>
@@ -45,6 +52,7 @@ struct Request {
   lp_device_key* dk = nullptr;
   uint32_t* pool = nullptr;
   int level = 0;
+  size_t ks_pos = 0, br_pos = 0;  // jobs of the current level already run
   std::vector<uint32_t> out;
   lp_status status = LP_EAGAIN;
   bool cancel = false;
@@ -160,8 +168,59 @@ bool same_shape(const lp_params& a, const lp_params& b) {
   return a.n == b.n && a.ks_t == b.ks_t && a.ks_base_bit == b.ks_base_bit;
 }
 
-// One fused level over admitted requests of one shape.
-lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, uint64_t* n_br_out) {
+// A request's part of a tick: key switches [k0, k1) of its current level
+// and the rotations they read, [r0, r1).  The plan lists a level's
+// rotations in the order of the key switches that read them (two for a MUX,
+// one otherwise), and a rotation's output index is its place in the level,
+// so both ranges are contiguous.
+struct Chunk {
+  size_t k0, k1, r0, r1;
+};
+
+// Rotations per request under a cap (0 = none) by water-filling over the
+// rotations each has left in its level; every request gets at least one
+// key switch.  LP_EINVAL if a level breaks the order above.
+lp_status plan_chunks(const std::vector<std::shared_ptr<Request>>& act, uint32_t cap, std::vector<Chunk>* out) {
+  const size_t n = act.size();
+  std::vector<size_t> left(n), budget(n), order(n);
+  for (size_t k = 0; k < n; ++k) {
+    left[k] = act[k]->plan->br[act[k]->level].size() - act[k]->br_pos;
+    order[k] = k;
+  }
+  if (cap == 0) {
+    budget = left;
+  } else {
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return left[a] < left[b]; });
+    size_t rem = cap;
+    for (size_t i = 0; i < n; ++i) {
+      const size_t k = order[i];
+      budget[k] = std::min(left[k], std::max<size_t>(rem / (n - i), 1));
+      rem -= std::min(rem, budget[k]);
+    }
+  }
+  out->assign(n, Chunk{});
+  for (size_t k = 0; k < n; ++k) {
+    const Request& r = *act[k];
+    const std::vector<lp::KsJob>& ks = r.plan->ks[r.level];
+    Chunk c{r.ks_pos, r.ks_pos, r.br_pos, r.br_pos};
+    while (c.k1 < ks.size()) {
+      const lp::KsJob& j = ks[c.k1];
+      const size_t w = j.ex1 != lp::REF_NONE ? 2 : 1;
+      if (j.ex0 != c.r1 || (w == 2 && j.ex1 != c.r1 + 1))
+        return lp::fail(LP_EINVAL, "server: level %d of a plan is out of rotation order", r.level);
+      if (c.k1 > c.k0 && c.r1 - c.r0 + w > budget[k]) break;
+      c.r1 += w;
+      ++c.k1;
+    }
+    (*out)[k] = c;
+  }
+  return LP_OK;
+}
+
+// One fused tick over admitted requests of one shape: each request's chunk
+// of its current level.
+lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, const std::vector<Chunk>& ch,
+               uint64_t* n_br_out) {
   using lp::BrJob;
   using lp::KsJob;
   std::vector<BrJob> br;
@@ -172,26 +231,29 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, u
   uint32_t ex_cnt = 0;
   for (size_t k = 0; k < act.size(); ++k) {
     const lp::Plan& P = *act[k]->plan;
-    const int L = act[k]->level;
+    const Chunk& c = ch[k];
     ex_base[k] = ex_cnt;
-    for (BrJob j : P.br[L]) {
+    for (size_t q = c.r0; q < c.r1; ++q) {
+      BrJob j = P.br[act[k]->level][q];
       if (j.in0 != lp::REF_NONE) j.in0 = lp::make_ref(lp::KEY_POOL_BASE, j.in0 & lp::REF_INDEX_MASK);
       if (j.in1 != lp::REF_NONE) j.in1 = lp::make_ref(lp::KEY_POOL_BASE, j.in1 & lp::REF_INDEX_MASK);
-      j.out += ex_base[k];
+      j.out = j.out - (uint32_t)c.r0 + ex_base[k];
       j.key = (uint32_t)k;
       br.push_back(j);
     }
-    ex_cnt += (uint32_t)P.br[L].size();
-    per_key.push_back(P.ks[L].size());
-    ks_total += P.ks[L].size();
+    ex_cnt += (uint32_t)(c.r1 - c.r0);
+    per_key.push_back(c.k1 - c.k0);
+    ks_total += c.k1 - c.k0;
   }
   const int tile = lp::fused_ks_tile(per_key, ks_total);
   for (size_t k = 0; k < act.size(); ++k) {
     const lp::Plan& P = *act[k]->plan;
+    const Chunk& c = ch[k];
     size_t cnt = 0;
-    for (KsJob j : P.ks[act[k]->level]) {
-      j.ex0 += ex_base[k];
-      if (j.ex1 != lp::REF_NONE) j.ex1 += ex_base[k];
+    for (size_t q = c.k0; q < c.k1; ++q) {
+      KsJob j = P.ks[act[k]->level][q];
+      j.ex0 = j.ex0 - (uint32_t)c.r0 + ex_base[k];
+      if (j.ex1 != lp::REF_NONE) j.ex1 = j.ex1 - (uint32_t)c.r0 + ex_base[k];
       j.out = lp::make_ref(lp::KEY_POOL_BASE, j.out & lp::REF_INDEX_MASK);
       j.key = (uint32_t)k;
       ks.push_back(j);
@@ -331,19 +393,31 @@ void worker_main(lp_server* S) {
     uint64_t nbr = 0;
     std::vector<std::shared_ptr<Request>> done;
     std::vector<lp_status> done_st;
+    uint64_t widest = 0;
     for (auto& g : groups) {
       uint64_t n = 0;
-      const lp_status st = tick(S, g, &n);
+      std::vector<Chunk> ch;
+      lp_status st = plan_chunks(g, S->cfg.max_tick_rotations, &ch);
+      if (st == LP_OK) st = tick(S, g, ch, &n);
       nbr += n;
-      for (auto& r : g) {
-        if (st == LP_OK && ++r->level < r->plan->levels()) continue;
-        done.push_back(r);
-        done_st.push_back(st == LP_OK ? collect_output(S, *r) : st);
+      widest = std::max(widest, n);
+      for (size_t i = 0; i < g.size(); ++i) {
+        Request& r = *g[i];
+        if (st == LP_OK) {
+          r.ks_pos = ch[i].k1;
+          r.br_pos = ch[i].r1;
+          if (r.ks_pos < r.plan->ks[r.level].size()) continue;  // the level goes on next tick
+          r.ks_pos = r.br_pos = 0;
+          if (++r.level < r.plan->levels()) continue;
+        }
+        done.push_back(g[i]);
+        done_st.push_back(st == LP_OK ? collect_output(S, r) : st);
       }
     }
     std::lock_guard<std::mutex> lk(S->mu);
     S->st.ticks += groups.size();
     S->st.fused_bootstraps += nbr;
+    S->st.widest_tick = std::max(S->st.widest_tick, widest);
     for (size_t i = 0; i < done.size(); ++i) {
       release(S, *done[i]);
       finish_locked(S, *done[i], done_st[i]);

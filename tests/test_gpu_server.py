@@ -82,3 +82,31 @@ def test_server_mixed_parameter_sets():
         assert (got == alone).all(), k
         d, _ = bits_of(ok[owner[k]], got)
         assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, q.l, q.m, q.is_signed), k
+
+
+def test_server_tick_cap_leaves_results_unchanged():
+    """A rotation cap below the widest levels splits them over several
+    ticks (MUX pairs and key switches stay with their rotations): every
+    result is bit-identical to the query evaluated alone."""
+    cuda_or_skip()
+    p = lp.params_default()
+    okeys = O.keygen(71)
+    ck = lp.CloudKey.from_arrays(p, okeys.bsk, okeys.ksk)
+    qs = [W.random_query_u8(7, force_inside=True), W.random_query(72, 16, 3, 4, force_inside=True)]
+    parts = [enc(okeys, q, 950 + k) for k, q in enumerate(qs)]
+    cap = 25
+    srv = lp.Server(64 << 30, max_tick_rotations=cap)
+    tickets = [srv.submit(ck, q.l, q.n_boxes, q.m, q.is_signed, *parts[k]) for k, q in enumerate(qs)]
+    results = [srv.poll(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    assert all(r[0] == 0 for r in results)
+    assert stats["widest_tick"] <= cap
+    assert stats["ticks"] > max(lp.bbox_counts(q.l, q.n_boxes, q.m)[2] for q in qs)  # levels were split
+    dk = lp.DeviceKey(ck)
+    for k, q in enumerate(qs):
+        alone = lp.to_host(lp.eval_bbox_query(dk, q.l, q.n_boxes, q.m, q.is_signed,
+                                              *[lp.to_device(v) for v in parts[k]]))
+        assert (results[k][1] == alone).all(), k
+        d, _ = bits_of(okeys, results[k][1])
+        assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, q.l, q.m, q.is_signed), k

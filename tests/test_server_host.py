@@ -119,3 +119,56 @@ def test_mixed_parameter_sets_run_in_separate_launches(ck):
     s = srv.stats()
     assert s["ticks"] == 2 * depth and s["completed"] == 2 and s["bytes_in_use"] == 0
     srv.close()
+
+
+def _late_widths(monkeypatch, l, nb, m):
+    monkeypatch.setenv("LOCPIR_XNOR_EARLY", "0")  # the server's placement
+    return lp.bbox_level_widths(l, nb, m)
+
+
+@pytest.mark.parametrize("cap", [1, 7, 40])
+def test_tick_cap_bounds_every_launch(monkeypatch, ck, cap):
+    """A lone 16-box request under a rotation cap: no tick holds more than
+    the cap (a MUX's two rotations stay together, so a cap of 1 still runs
+    one gate), every level is split into enough ticks, and the request
+    completes."""
+    widths = _late_widths(monkeypatch, 16, 16, 8)
+    srv = lp.Server(1 << 40, simulate=True, max_tick_rotations=cap)
+    t = srv.submit(ck, *query(16, 16, 8))
+    assert srv.poll(t)[0] == 0
+    s = srv.stats()
+    srv.close()
+    assert s["widest_tick"] <= max(cap, 2)
+    assert s["ticks"] >= sum(-(-w // max(cap, 2)) for w in widths)
+    assert s["fused_bootstraps"] == sum(widths)
+    assert s["completed"] == 1 and s["bytes_in_use"] == 0
+
+
+def test_without_cap_a_tick_runs_whole_levels(monkeypatch, ck):
+    widths = _late_widths(monkeypatch, 16, 4, 8)
+    srv = lp.Server(1 << 40, simulate=True)
+    assert srv.poll(srv.submit(ck, *query(16, 4, 8)))[0] == 0
+    s = srv.stats()
+    srv.close()
+    assert s["ticks"] == len(widths) and s["widest_tick"] == max(widths)
+
+
+def test_tick_cap_lets_narrow_requests_finish_first(monkeypatch, ck):
+    """A one-box request beside a 64-box one under a cap of twice its widest
+    level: its levels fit its share, so it finishes before the wide one,
+    whose levels take several ticks each."""
+    small = _late_widths(monkeypatch, 16, 1, 4)
+    big = _late_widths(monkeypatch, 16, 64, 4)
+    cap = 2 * max(small)
+    srv = lp.Server(1 << 40, simulate=True, max_tick_rotations=cap)
+    tb = srv.submit(ck, *query(16, 64, 4))
+    ts = srv.submit(ck, *query(16, 1, 4))
+    st_s, _, lat_s = srv.poll(ts, wait=True)
+    st_b, _, lat_b = srv.poll(tb, wait=True)
+    s = srv.stats()
+    srv.close()
+    assert st_s == 0 and st_b == 0
+    assert s["widest_tick"] <= cap
+    assert s["fused_bootstraps"] == sum(small) + sum(big)
+    assert lat_s < lat_b
+    assert s["ticks"] >= sum(-(-w // cap) for w in big)
