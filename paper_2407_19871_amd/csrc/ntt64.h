@@ -43,6 +43,12 @@ __device__ __forceinline__ uint64_t lane_select(uint64_t mask, uint64_t x, uint6
   return (x & ~mask) | (y & mask);
 }
 
+// hi_lane ? -y : y for reduced y, again reduced: -y = ~y + (2 - 2^32)
+// (gl_neg_r), so the upper lanes flip y and add the constant.
+__device__ __forceinline__ uint64_t lane_negate(uint64_t mask, uint64_t y) {
+  return (y ^ mask) + (mask & 0xFFFFFFFF00000002ull);
+}
+
 // ---- pass 1, forward -------------------------------------------------------
 // Stages LEN = 16 and 8 on gadget digits, exact in int64 (see
 // fwd1_first_stages_digits): the groups (j, j+8, j+16, j+24) share a parity,
@@ -78,7 +84,9 @@ __device__ __forceinline__ void ct64_stage(uint64_t (&a)[16], Zf zf) {
   });
 }
 
-// The LEN = 1 stage across the two lanes of a column; Z(s) per slot.
+// The LEN = 1 stage across the two lanes of a column; Z(s) per slot.  The
+// lower lane keeps x_even + t, the upper one x_even - t, each with one
+// addition (of t or of -t).
 template <typename Zf>
 __device__ __forceinline__ void ct64_cross(uint64_t (&a)[16], Zf zf, int lane) {
   const uint64_t odd = lane >= 32 ? ~0ull : 0ull;
@@ -87,8 +95,7 @@ __device__ __forceinline__ void ct64_cross(uint64_t (&a)[16], Zf zf, int lane) {
     constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
     uint64_t xe, xo;
     pair_values(a[s], xe, xo);
-    const uint64_t t = gl_mul_pow2_r<z>(xo);
-    a[s] = lane_select(odd, gl_add_r(xe, t), gl_sub_r(xe, t));
+    a[s] = gl_add_r(xe, lane_negate(odd, gl_mul_pow2_r<z>(xo)));
   });
 }
 
@@ -149,7 +156,8 @@ __device__ __forceinline__ void gs64_stage(uint64_t (&a)[16], Zf zf) {
 }
 
 // The first stage of a pass, across the two lanes of a column; its inputs
-// may be lazy, its outputs are reduced.
+// may be lazy, its outputs are reduced.  The lower lane keeps X + Y, the
+// upper one (X - Y) w^-1, both from one addition (of Y or of -Y).
 template <typename Zf>
 __device__ __forceinline__ void gs64_cross(uint64_t (&a)[16], Zf zf, int lane) {
   const uint64_t odd = lane >= 32 ? ~0ull : 0ull;
@@ -158,9 +166,8 @@ __device__ __forceinline__ void gs64_cross(uint64_t (&a)[16], Zf zf, int lane) {
     constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
     uint64_t x, y;
     pair_values(a[s], x, y);
-    const uint64_t yr = gl_canon(y);
-    const uint64_t dif = gl_mul_pow2_r<192 - z>(gl_sub_r(x, yr));
-    a[s] = lane_select(odd, gl_canon(gl_add_r(x, yr)), dif);
+    const uint64_t v = gl_add_r(x, lane_negate(odd, gl_canon(y)));
+    a[s] = lane_select(odd, gl_canon(v), gl_mul_pow2_r<192 - z>(v));
   });
 }
 
