@@ -1,5 +1,7 @@
 """GPU parity of gate batches of the microbenchmark sizes (uniform random
-bits, NAND gates sharing one key) and of ragged sizes."""
+bits, NAND gates sharing one key) and of ragged sizes; with the built-in
+launch shapes 769 and 1024 run the two-wave rotation, the smaller sizes the
+split one."""
 import numpy as np
 import pytest
 
@@ -18,7 +20,7 @@ def dkey(okeys):
     return device_key_from_oracle(okeys)
 
 
-@pytest.mark.parametrize("B", [1, 64, 97, 1024])
+@pytest.mark.parametrize("B", [1, 64, 97, 769, 1024])
 def test_nand_batch_parity(okeys, octx, dkey, B):
     a = W.random_bits(1000 + B, B)
     b = W.random_bits(2000 + B, B)
