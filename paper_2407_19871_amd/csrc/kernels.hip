@@ -175,18 +175,6 @@ __device__ __forceinline__ void ntt64_fwd_digits(const int32_t (&d)[16], uint64_
   fwd64_p2(f, lane);
 }
 
-// Inverse of ntt64_fwd_digits including the 1/1024 scaling: in, the value
-// at offset 64 s + 2 l + h of the NTT-domain layout in slot s of lane
-// (h, l) (lazy residues allowed); out, coefficient l + 32 (2s + h).
-__device__ __forceinline__ void ntt64_inv(uint64_t (&f)[16], uint32_t* buf, const uint64_t* __restrict__ tw_i,
-                                          int lane) {
-  const int h = lane >> 5, l = lane & 31;
-  inv64_p2(f, lane);
-  twist64(f, tw_i, lane);
-  transpose64(f, buf, h, l);
-  inv64_p1(f, lane);
-}
-
 // Offset of (slot s, lane l) inside one NTT-domain polynomial.
 __device__ __forceinline__ int ntt_pos(int s, int l) { return (s >> 1) * 64 + l * 2 + (s & 1); }
 
@@ -618,7 +606,7 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
 #pragma unroll
     for (int s = 0; s < 16; ++s) qo[s] = gl_add(qo[s], inbox[64 * s + lane]);
     wave_fence();  // the inbox is read before it serves as the transpose block
-    // ntt64_inv with the twist factors at hand
+    // inverse of the forward transform (1/1024 included), twist factors at hand
     inv64_p2(qo, lane);
 #pragma unroll
     for (int s = 0; s < 16; ++s) qo[s] = gl_mul(qo[s], w[s]);
