@@ -237,7 +237,7 @@ def serve_bench(requests_per_rate: int, tick_cap: int = 0, seed: int = 5):
         return q, c, parts
 
     def run(reqs, arrivals):
-        srv = lp.Server(200 << 30, max_tick_rotations=tick_cap)
+        srv = lp.Server(200 << 30, max_tick_rotations="auto" if tick_cap < 0 else tick_cap)
         t0 = time.perf_counter()
         tickets = []
         for (q, c, parts), at in zip(reqs, arrivals):
@@ -453,7 +453,8 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="serving benchmark with this many requests per arrival rate (separate JSON line)")
     ap.add_argument("--tick-cap", type=int, default=0,
-                    help="with --serve: blind rotations per server tick at most (0 = whole levels)")
+                    help="with --serve: blind rotations per server tick at most (0 = whole levels, "
+                         "-1 = sized from the timed launch-shape table)")
     ap.add_argument("--sweep", action="store_true",
                     help="the paper's Fig. 4a / Table 2 query shapes and a box-count sweep (separate JSON line)")
     ap.add_argument("--clients", type=int, default=0,

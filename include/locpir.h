@@ -263,6 +263,9 @@ lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t m, uint32_
  * others split the rest (at least one gate each), and a level that does not
  * fit runs over several ticks; results are unchanged, and a wide request no
  * longer stretches the ticks of every narrow one beside it.
+ * LP_TICK_CAP_AUTO takes, at every tick, the narrowest launch width of the
+ * device's timed launch-shape table (lp_autotune) whose rotation time per
+ * job is within 15 % of the table's best, or 2048 without a timed table.
  * stats.widest_tick is the most rotations one fused launch has held.
  * A finished request's result is kept on the host until polled; its device
  * memory is released at once.  A failing request (allocation, upload) ends
@@ -276,6 +279,7 @@ typedef struct {
   uint64_t fail_ticket;  /* fault injection: this ticket's set-up fails (0 = none)    */
   uint32_t max_tick_rotations; /* blind rotations per tick at most; 0 = a whole level */
 } lp_server_config;
+#define LP_TICK_CAP_AUTO 0xFFFFFFFFu /* max_tick_rotations from the timed shape table */
 /* A query whose ciphertexts are in host memory (same layout as lp_bbox_query). */
 typedef struct {
   uint32_t l, n_boxes, m;

@@ -59,6 +59,9 @@ TUNE_MAX_ROWS = 32
 DEFAULT_TUNE_BUCKETS = (1, 16, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16384)
 
 
+TICK_CAP_AUTO = 0xFFFFFFFF  # LP_TICK_CAP_AUTO
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_inflight", C.c_uint32), ("simulate", C.c_int32),
                 ("fail_ticket", C.c_uint64), ("max_tick_rotations", C.c_uint32)]
@@ -569,12 +572,14 @@ LP_ECANCELED = -7
 class Server:
     """Continuous-batching query server (lp_server_*).  Queries are host
     arrays (x, y, bounds, payload) of uint32 ciphertexts.  max_tick_rotations
-    caps the blind rotations of one tick (0: a whole level per request)."""
+    caps the blind rotations of one tick (0: a whole level per request;
+    "auto": sized from the device's timed launch-shape table)."""
 
     def __init__(self, hbm_budget: int, max_inflight: int = 0, simulate: bool = False, fail_ticket: int = 0,
-                 max_tick_rotations: int = 0):
+                 max_tick_rotations: "int | str" = 0):
         self._keep = {}
-        cfg = ServerConfig(hbm_budget, max_inflight, 1 if simulate else 0, fail_ticket, max_tick_rotations)
+        cap = TICK_CAP_AUTO if max_tick_rotations == "auto" else int(max_tick_rotations)
+        cfg = ServerConfig(hbm_budget, max_inflight, 1 if simulate else 0, fail_ticket, cap)
         h = C.c_void_p()
         _check(lib().lp_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

@@ -99,9 +99,14 @@ int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe);
 // Estimated rotation launch time (us) of njobs from the current device's
 // timed table; false when there is none.
 bool est_br_launch_us(size_t njobs, double* us);
-// Waves per bootstrap: 6 (split over two workgroups) up to kSplitMaxJobs,
-// 4 (levels summed, two-wave inverses) up to 256, 5 (the same, two per CU)
-// up to 768, else 1.
+// The narrowest bucket of the current device's timed table whose rotation
+// time per job is within a factor 1 + tol of the table's best; 0 when the
+// table has no timed row.
+uint32_t throughput_knee(float tol);
+// Waves per bootstrap; the built-in rule: 6 (split over two workgroups) up
+// to kSplitMaxJobs, 4 (levels summed, two-wave inverses) up to 256, 5 (the
+// same, two per CU) up to 768, 2 (one accumulator component per wave) up to
+// 1024, 5 up to 1280, else 1.
 int pick_br_wpb(size_t njobs);
 // Built-in defaults (no environment, no table).
 int default_ks_tile(size_t njobs);

@@ -144,6 +144,20 @@ bool est_br_launch_us(size_t njobs, double* us) {
   return true;
 }
 
+uint32_t throughput_knee(float tol) {
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(dev);
+  if (it == g_tune.end()) return 0;
+  float best = 0.f;
+  for (const auto& r : it->second)
+    if (r.br_us > 0.f && (best == 0.f || r.br_us < best)) best = r.br_us;
+  if (best == 0.f) return 0;
+  for (const auto& r : it->second)  // sorted by jobs
+    if (r.br_us > 0.f && r.br_us <= best * (1.f + tol)) return r.jobs;
+  return 0;
+}
+
 }  // namespace lp
 
 using lp::fail;

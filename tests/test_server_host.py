@@ -172,3 +172,31 @@ def test_tick_cap_lets_narrow_requests_finish_first(monkeypatch, ck):
     assert s["fused_bootstraps"] == sum(small) + sum(big)
     assert lat_s < lat_b
     assert s["ticks"] >= sum(-(-w // cap) for w in big)
+
+
+TIMED_ROWS = [{"jobs": 128, "br_waves": 6, "ks_tile": 4, "ks_split": 16, "br_us": 94.9},
+              {"jobs": 1024, "br_waves": 2, "ks_tile": 8, "ks_split": 16, "br_us": 34.6},
+              {"jobs": 2048, "br_waves": 1, "ks_tile": 8, "ks_split": 16, "br_us": 27.0},
+              {"jobs": 4096, "br_waves": 1, "ks_tile": 8, "ks_split": 16, "br_us": 25.5},
+              {"jobs": 16384, "br_waves": 1, "ks_tile": 8, "ks_split": 16, "br_us": 24.1}]
+
+
+@pytest.mark.parametrize("rows,cap", [(None, 2048), (TIMED_ROWS, 2048), (TIMED_ROWS[:2], 1024)])
+def test_automatic_tick_cap(monkeypatch, ck, rows, cap):
+    """LP_TICK_CAP_AUTO: the narrowest timed width within 15 % of the best
+    rotation time per job (2048 for the measured MI355X table: 27.0 us
+    against 24.1; 1024 when the table stops there), 2048 without a timed
+    table; a 256-box request's widest levels are split to it."""
+    widths = _late_widths(monkeypatch, 16, 256, 4)
+    assert max(widths) > 2048
+    old = lp.tune_table()
+    lp.set_tune_table(rows or [])
+    try:
+        srv = lp.Server(1 << 40, simulate=True, max_tick_rotations="auto")
+        assert srv.poll(srv.submit(ck, *query(16, 256, 4)))[0] == 0
+        s = srv.stats()
+        srv.close()
+    finally:
+        lp.set_tune_table(old)
+    assert s["widest_tick"] == cap
+    assert s["fused_bootstraps"] == sum(widths)
