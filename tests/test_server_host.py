@@ -181,12 +181,16 @@ TIMED_ROWS = [{"jobs": 128, "br_waves": 6, "ks_tile": 4, "ks_split": 16, "br_us"
               {"jobs": 16384, "br_waves": 1, "ks_tile": 8, "ks_split": 16, "br_us": 24.1}]
 
 
-@pytest.mark.parametrize("rows,cap", [(None, 2048), (TIMED_ROWS, 2048), (TIMED_ROWS[:2], 1024)])
+UNTIMED_ROWS = [{k: v for k, v in r.items() if k != "br_us"} for r in TIMED_ROWS]
+
+
+@pytest.mark.parametrize("rows,cap", [(None, 2048), (UNTIMED_ROWS, 2048), (TIMED_ROWS, 2048), (TIMED_ROWS[:2], 1024)])
 def test_automatic_tick_cap(monkeypatch, ck, rows, cap):
     """LP_TICK_CAP_AUTO: the narrowest timed width within 15 % of the best
     rotation time per job (2048 for the measured MI355X table: 27.0 us
-    against 24.1; 1024 when the table stops there), 2048 without a timed
-    table; a 256-box request's widest levels are split to it."""
+    against 24.1; 1024 when the table stops there), 2048 without a table or
+    with rows installed untimed; a 256-box request's widest levels are split
+    to it."""
     widths = _late_widths(monkeypatch, 16, 256, 4)
     assert max(widths) > 2048
     old = lp.tune_table()
