@@ -554,8 +554,8 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
     // gadget level j: rows (c, j) of BSK_i, components c and 1 - c, at this
     // lane's offsets 64 s + 2 l + h
     auto level = [&](int j, auto first) {
-      // the rows are loaded before the transform, whose LDS transposes
-      // order every memory access behind them
+      // the rows are loaded before the transform: the compiler keeps loads
+      // where they are written, and after it they would be waited on at once
       const gmem_u64* ko = step_key + (size_t)((c * 3 + j) * 2 + c) * RING_N + 2 * l + h;
       const gmem_u64* kx = step_key + (size_t)((c * 3 + j) * 2 + (1 - c)) * RING_N + 2 * l + h;
       uint64_t k0[16], k1[16];
