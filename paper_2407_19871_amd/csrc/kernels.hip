@@ -310,17 +310,34 @@ __global__ __launch_bounds__(64 * (W == 5 ? 4 : W), (W == 1 || W == 5) ? 2 : 1) 
       __syncthreads();  // every wave has read ACC before any adds to it
       uint64_t f[32];
       if (lvl) ntt_fwd_digits(dg, f, buf, opaque(tw_f), l);
-      if constexpr (DUAL) __syncthreads();  // the transposes are done before the partials take their space
+      // DUAL: the key rows of a slot pair are requested KD pairs ahead of
+      // their products (the first KD before the barrier), in a ring of KD
+      constexpr int KD = 4;
+      uint64_t kr[DUAL ? KD : 1][4];
+      auto request = [&](int sp, uint64_t(&k)[4]) {
+        k[0] = ko[sp * 64];
+        k[1] = ko[sp * 64 + 1];
+        k[2] = kt[sp * 64];
+        k[3] = kt[sp * 64 + 1];
+      };
+      if constexpr (DUAL) {
+        if (lvl) {
+#pragma unroll
+          for (int sp = 0; sp < KD; ++sp) request(sp, kr[sp]);
+        }
+        __syncthreads();  // the transposes are done before the partials take their space
+      }
       if (lvl) {
         uint64_t* part = s_part[wave][h];
 #pragma unroll
         for (int sp = 0; sp < 16; ++sp) {
           uint64_t k0, k1, k2, k3;
           if constexpr (DUAL) {
-            k0 = ko[sp * 64];
-            k1 = ko[sp * 64 + 1];
-            k2 = kt[sp * 64];
-            k3 = kt[sp * 64 + 1];
+            k0 = kr[sp % KD][0];
+            k1 = kr[sp % KD][1];
+            k2 = kr[sp % KD][2];
+            k3 = kr[sp % KD][3];
+            if (sp + KD < 16) request(sp + KD, kr[sp % KD]);
           } else {
             k0 = kpre[4 * sp];
             k1 = kpre[4 * sp + 1];
