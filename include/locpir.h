@@ -79,7 +79,12 @@ const char* lp_last_error(void);
 const char* lp_version(void);
 
 /* Default parameters: n = 630, lwe_sigma = 2^-15, N = 1024, k = 1,
- * bg_bit = 7, l = 3, bk_sigma = 2^-25, ks_base_bit = 2, ks_t = 8. */
+ * bg_bit = 7, l = 3, bk_sigma = 2^-25, ks_base_bit = 2, ks_t = 8.  This is
+ * the paper's lambda 128 set (Sec. 5: TLWE dimension n = 630); the paper
+ * fixes no other parameter of it, so the noise widths, the ring, the gadget
+ * and the key-switching base are those of the standard TFHE gate
+ * bootstrapping set that Sec. 2.2 builds on (TFHE library 1.1, which the
+ * experiments of Sec. 5 use). */
 lp_status lp_params_default(lp_params* out);
 /* The paper's lambda 80 set (Sec. 5): n = 540, lwe_sigma = 2^-20.2; the
  * paper gives nothing else for it, so the ring, gadget and key-switching
@@ -135,37 +140,54 @@ lp_status lp_decrypt_bits(const lp_secret_key* sk, const uint32_t* ct, size_t cn
 
 /* ---- cloud side (device) ------------------------------------------------- */
 
-/* Upload PK to the current HIP device and transform the bootstrapping key to
- * the NTT domain there (about 62 MB of BSK plus 62 MB of KSK per key). */
+/* The cloud's copy of PK (KeyGen's bootstrapping key and key-switching key,
+ * Sec. 2.2), resident on the current HIP device: uploads both and transforms
+ * the bootstrapping key to the NTT domain there (about 62 MB of BSK plus
+ * 62 MB of KSK per key; lp_device_key_bytes gives the total).  ck stays
+ * owned by the caller and may be freed afterwards; *dk is owned by the
+ * caller and freed with lp_device_key_free.  Synchronous on stream.
+ * LP_EUNSUPPORTED for parameters the GPU kernels do not handle, LP_ENOMEM
+ * when the device allocation fails, LP_EDEVICE for other HIP failures. */
 lp_status lp_device_key_create(const lp_cloud_key* ck, void* stream, lp_device_key** dk);
 lp_status lp_device_key_bytes(const lp_device_key* dk, size_t* bytes);
 
-/* cnt gates of one kind on device ciphertexts: d_out[k] = gate(d_in0[k],
- * d_in1[k], d_in2[k]).  d_in1 is ignored for NOT/COPY; d_in2 is used by MUX
+/* EvalGate(ct1, ct2, PK) of Sec. 2.2 over a batch: the gate's linear
+ * pre-combination (HomAND = Bootstrap((0, -1/8) + ct1 + ct2), the other
+ * gates alike), then Bootstrap (blind rotation, sample extraction, key
+ * switching).  cnt gates of one kind on device ciphertexts:
+ * d_out[k] = gate(d_in0[k], d_in1[k], d_in2[k]).  d_in1 is ignored for NOT/COPY; d_in2 is used by MUX
  * only.  All arrays are cnt*(n+1) uint32 on the key's device.  Every
  * bootstrapped gate runs the blind rotation, sample extraction and key
  * switching (MUX: two blind rotations, one key switch).  d_out may be one of
  * the inputs (it is written by the key switch, after every input was read).
- * cnt = 0 is a no-op. */
+ * cnt = 0 is a no-op.  A batch of at most 128 blind rotations runs them
+ * split over two workgroups each (lp_split_stall_count); the call then waits
+ * for the stream and returns LP_EDEVICE if one of their bounded waits ran
+ * out (the outputs are then undefined). */
 lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
                              const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
                              uint32_t* d_out, void* stream);
 
-/* The same gates without the key switch: d_out_big[k] (N+1 words, LWE of
- * dimension N under the ring key S) is the sample that gate's key switch
- * takes: the sample extracted from the blind rotation of the gate's input
+/* EvalGate of Sec. 2.2 stopped before Bootstrap's final key switch:
+ * d_out_big[k] (N+1 words, LWE of dimension N under the ring key S) is the
+ * sample that gate's key switch takes: the sample extracted from the blind rotation of the gate's input
  * combination, or for MUX (0, 1/8) + u1 + u2 of its two rotations.
  * lp_keyswitch_batch of d_out_big equals lp_bootstrap_batch bit for bit.
  * d_out_big (cnt*(N+1) uint32) must not overlap the inputs: the rotations
  * write it while others still read theirs.  NOT and COPY do not bootstrap:
- * LP_EINVAL.  cnt = 0 is a no-op. */
+ * LP_EINVAL.  cnt = 0 is a no-op.  Split rotations are waited for and
+ * checked as in lp_bootstrap_batch. */
 lp_status lp_bootstrap_batch_noks(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
                                   const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
                                   uint32_t* d_out_big, void* stream);
 
-/* Key switching alone: d_in holds cnt extracted samples of N+1 words under
- * the ring key; d_out receives cnt samples of n+1 words under s.  d_out must
- * not overlap d_in. */
+/* Key switching alone, the last step of Bootstrap (Sec. 2.2: PK's key
+ * switching key brings the bootstrapped sample back under the TLWE key):
+ * d_in holds cnt extracted samples of N+1 words under the ring key; d_out
+ * receives cnt samples of n+1 words under s.  Both on the key's device, owned
+ * by the caller.  d_out must not overlap d_in.  Waits for the stream before
+ * returning (its job list is staged in host memory).  cnt = 0 is a no-op;
+ * LP_EINVAL for a null buffer or a batch above 2^28. */
 lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,
                              uint32_t* d_out, void* stream);
 
@@ -182,7 +204,10 @@ lp_status lp_keyswitch_batch(const lp_device_key* dk, const uint32_t* d_in, size
  * d_out receives m ciphertexts.  The circuit is cut into depth levels; each
  * level is one batched bootstrap launch plus one key-switch launch.
  * LP_EINVAL for l outside 1..64, n_boxes outside 1..65536, m outside
- * 1..4096 or a null input. */
+ * 1..4096 or a null input.  When some level runs split rotations (see
+ * lp_split_stall_count) the call waits for the stream at its end and
+ * returns LP_EDEVICE if one of their bounded waits ran out; d_out is then
+ * undefined.  Otherwise it returns without waiting. */
 typedef struct {
   uint32_t l, n_boxes, m;
   int32_t is_signed;
@@ -201,7 +226,9 @@ lp_status lp_eval_bbox_query(const lp_device_key* dk, const lp_bbox_query* q, ui
  * pool, one graph per level for the blind rotations and one for the key
  * switches) is cached per (stream, keys, query shapes) and replayed; calls
  * that share a stream and a program are serialised by the library.  Set the
- * environment variable LOCPIR_GRAPHS=0 to launch the kernels directly. */
+ * environment variable LOCPIR_GRAPHS=0 to launch the kernels directly.
+ * Split rotations are waited for and checked as in lp_eval_bbox_query (a
+ * give-up fails the whole call). */
 lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
                              uint32_t* const* d_outs, void* stream);
 
@@ -268,7 +295,8 @@ lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t m, uint32_
  * job is within 15 % of the table's best, or 2048 without a timed table.
  * stats.widest_tick is the most rotations one fused launch has held.
  * A finished request's result is kept on the host until polled; its device
- * memory is released at once.  A failing request (allocation, upload) ends
+ * memory is released at once.  A failing request (allocation, upload, or a
+ * split rotation of its gates whose bounded wait ran out: LP_EDEVICE) ends
  * alone; the others continue.  Latency is measured from submit to the end of
  * the result copy.  The server runs on the HIP device current at creation. */
 typedef struct lp_server lp_server;
@@ -302,6 +330,15 @@ lp_status lp_server_request_bytes(const lp_cloud_key* ck, const lp_bbox_query_ho
  * request ends.  LP_EBUDGET if it can never fit the budget, LP_EINVAL for a
  * malformed shape.  *ticket identifies the request. */
 lp_status lp_server_submit(lp_server* s, const lp_cloud_key* ck, const lp_bbox_query_host* q, uint64_t* ticket);
+/* The same request as the client sends it (Sec. 3: PK uploaded with the
+ * query): key_blob is PK as lp_cloud_key_serialize writes it, key_len its
+ * length in bytes.  The server deserializes it into a key of its own, which
+ * the request holds until it ends; the caller's blob may be freed when the
+ * call returns.  Latency is measured from the call's entry, so it includes
+ * the deserialization.  LP_EINVAL for a foreign, truncated or inconsistent
+ * blob (nothing is queued), otherwise as lp_server_submit. */
+lp_status lp_server_submit_blob(lp_server* s, const void* key_blob, size_t key_len, const lp_bbox_query_host* q,
+                                uint64_t* ticket);
 /* LP_EAGAIN while the request runs (wait = 0), or blocks until it ends
  * (wait != 0).  On LP_OK copies the m result ciphertexts to out (host,
  * may be NULL) and the latency in seconds; other statuses report how the
@@ -321,7 +358,8 @@ void lp_server_free(lp_server* s);
 lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint32_t* d_poly, size_t cnt,
                                   uint32_t* d_out, void* stream);
 /* Blind rotation of cnt LWE_n samples over their first `steps` key bits
- * (steps >= n: all); d_acc receives cnt accumulators of [2][N] uint32. */
+ * (steps >= n: all); d_acc receives cnt accumulators of [2][N] uint32.
+ * Synchronous; split rotations are checked as in lp_bootstrap_batch. */
 lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,
                                 uint32_t steps, uint32_t* d_acc, void* stream);
 
@@ -360,7 +398,10 @@ lp_status lp_profile_collect_launches(lp_launch_record* recs, int* count);
  * polling), so a partner that never arrives cannot hang the device.  Such a
  * wait ends the job's exchange, its output is then undefined, and the
  * current device's count of these events, since the library was loaded,
- * goes up by one per wave.  Writes that count to *count (synchronous: waits
+ * goes up by one per wave.  The call that launched the rotation learns of it
+ * too: lp_bootstrap_batch, lp_bootstrap_batch_noks, lp_debug_blind_rotate,
+ * lp_eval_bbox_query and lp_eval_bbox_batch return LP_EDEVICE, and the server
+ * fails the requests whose gates were affected.  Writes that count to *count (synchronous: waits
  * for the device).  Pairing draws tickets on arrival, so the count stays 0
  * unless other work holds every CU for the whole bound.  The environment
  * variable LOCPIR_SPLIT_SPIN, when set to a smaller positive number of

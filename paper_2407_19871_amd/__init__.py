@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import struct
 
 import numpy as np
 
@@ -141,6 +142,7 @@ def lib() -> C.CDLL:
         "lp_server_create": (i32, [C.POINTER(ServerConfig), C.POINTER(vp)]),
         "lp_server_request_bytes": (i32, [vp, C.POINTER(HostQuery), C.POINTER(sz)]),
         "lp_server_submit": (i32, [vp, vp, C.POINTER(HostQuery), C.POINTER(u64)]),
+        "lp_server_submit_blob": (i32, [vp, vp, sz, C.POINTER(HostQuery), C.POINTER(u64)]),
         "lp_server_poll": (i32, [vp, u64, i32, vp, C.POINTER(C.c_double)]),
         "lp_server_cancel": (i32, [vp, u64]),
         "lp_server_stats_get": (i32, [vp, C.POINTER(ServerStats)]),
@@ -612,6 +614,16 @@ class Server:
         t = C.c_uint64()
         _check(lib().lp_server_submit(self._h, ck._h, C.byref(q), C.byref(t)))
         self._keep[int(t.value)] = (ck, m, ck.params.n + 1)   # keep the key alive until done
+        return int(t.value)
+
+    def submit_blob(self, key_blob: bytes, l, n_boxes, m, is_signed, x, y, bounds, payload) -> int:
+        """The request as the client sends it: PK as a serialized blob
+        (CloudKey.serialize) that the server deserializes and owns."""
+        q, arrs = self._host_query(l, n_boxes, m, is_signed, x, y, bounds, payload)
+        t = C.c_uint64()
+        _check(lib().lp_server_submit_blob(self._h, key_blob, len(key_blob), C.byref(q), C.byref(t)))
+        n = struct.unpack_from("<I", key_blob, 8)[0]   # the header's LWE dimension
+        self._keep[int(t.value)] = (None, m, n + 1)
         return int(t.value)
 
     def poll(self, ticket: int, wait: bool = True):

@@ -54,6 +54,10 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Twiddle tables of the current device (uploaded once per device).
 lp_status device_twiddles(Twiddles* out);
 
+// LP_EDEVICE with a message naming `stalls` split-rotation waits that ran
+// out of polls (their jobs' outputs are undefined).
+lp_status split_stall_error(const char* who, uint32_t stalls);
+
 // Drops every cached query program that references dk.
 void sched_forget_key(const lp_device_key* dk);
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "jobs.h"
 
 namespace lp {
@@ -41,6 +43,12 @@ hipError_t split_area_free_async(SplitArea* a, hipStream_t s);
 // Waits of split launches that ran out of polls on this device since the
 // process started (0 unless a partner workgroup never arrived).
 hipError_t split_stall_count(uint32_t* out);
+// After every launch on the area that s has queued: waits (synchronously
+// for s) and reads the area's give-up record, the number of waits that ran
+// out since it was last taken and (jobs, may be null) the launch-relative
+// indices of the jobs they belong to, whose outputs are undefined; then
+// clears the record.
+hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* count, std::vector<int>* jobs);
 
 // Blind rotation + sample extraction (or raw accumulator output) of njobs
 // jobs.  ex: extract buffer, N+1 words per slot (2N per slot when raw_acc).

@@ -683,10 +683,14 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
 // most one workgroup per class waits for a partner, so no co-residency is
 // assumed.  Every wait is bounded:
 // a partner missing for SPLIT_SPIN_LIMIT polls ends the wait, counts in
-// g_split_stalls, and the job's output is then undefined; the kernel still
-// exits.  The last workgroup to finish clears the tickets and flags.
+// g_split_stalls and in the area's own status word, marks the job, and the
+// job's output is then undefined; the kernel still exits.  The last
+// workgroup to finish clears the tickets and flags; the status word and the
+// job marks stay until the host has read them (split_area_take_stalls), so
+// every call that launched the kernel can report a give-up as an error.
 constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
 constexpr int SPLIT_DONE = 8;    // finish counter (words 0-7: ticket counters per class)
+constexpr int SPLIT_STATUS = 9;  // waits of this area that ran out, until the host clears it
 constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
 
 __device__ uint32_t g_split_stalls;
@@ -710,7 +714,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
-    uint32_t* __restrict__ sync, int spin_limit) {
+    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit) {
   __shared__ uint32_t s_acc[RING_N];
   __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
   __shared__ __align__(16) uint64_t s_part[3][RING_N];     // the levels' partials, NTT domain
@@ -822,7 +826,11 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
           }
           if (it >= spin_limit) {
             stalled = true;
-            if (lane == 0) atomicAdd(&g_split_stalls, 1u);
+            if (lane == 0) {
+              atomicAdd(&g_split_stalls, 1u);
+              atomicAdd(sync + SPLIT_STATUS, 1u);
+              store_agent(marks + job, 1u);
+            }
           }
         }
         vm_wait_all();
@@ -1078,6 +1086,7 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
 }
 
 int split_spin_limit();
+static size_t split_marks_offset(int max_jobs);
 
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
@@ -1110,7 +1119,7 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       const int grid = 16 * ((njobs + 7) / 8);
       hipLaunchKernelGGL(blind_rotate_split_kernel, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
-                         split_spin_limit());
+                         split->sync + split_marks_offset(split->max_jobs), split_spin_limit());
       break;
     }
     default:
@@ -1130,7 +1139,38 @@ int split_spin_limit() {
   return x > 0 && x < SPLIT_SPIN_LIMIT ? (int)x : SPLIT_SPIN_LIMIT;
 }
 size_t split_xbuf_bytes(int max_jobs) { return (size_t)split_jobs_padded(max_jobs) * 12 * RING_N * 8; }
-size_t split_sync_bytes(int max_jobs) { return (size_t)(SPLIT_FLAGS + split_jobs_padded(max_jobs) * 8) * 4; }
+// sync area: 64 control words, 8 flag words per job, then one give-up mark per job
+static size_t split_marks_offset(int max_jobs) { return (size_t)SPLIT_FLAGS + split_jobs_padded(max_jobs) * 8; }
+size_t split_sync_bytes(int max_jobs) {
+  return (split_marks_offset(max_jobs) + split_jobs_padded(max_jobs)) * 4;
+}
+
+hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* count, std::vector<int>* jobs) {
+  if (!a || !count) return hipErrorInvalidValue;
+  *count = 0;
+  if (jobs) jobs->clear();
+  if (!a->sync) return hipSuccess;
+  uint32_t st = 0;
+  hipError_t e = hipMemcpyAsync(&st, a->sync + SPLIT_STATUS, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess || st == 0) return e;
+  const int padded = split_jobs_padded(a->max_jobs);
+  std::vector<uint32_t> marks(padded);
+  uint32_t* dm = a->sync + split_marks_offset(a->max_jobs);
+  e = hipMemcpyAsync(marks.data(), dm, (size_t)padded * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (jobs)
+    for (int j = 0; j < padded; ++j)
+      if (marks[j]) jobs->push_back(j);
+  // clear the status word and the marks for the next launch on this area
+  hipLaunchKernelGGL(split_area_clear_kernel, dim3(1), dim3(256), 0, s, a->sync + SPLIT_STATUS, 1);
+  hipLaunchKernelGGL(split_area_clear_kernel, dim3((padded + 255) / 256), dim3(256), 0, s, dm, padded);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  *count = st;
+  return e;
+}
 
 hipError_t split_area_alloc(SplitArea* a, int max_jobs) {
   if (!a || max_jobs < 1 || max_jobs > kSplitMaxJobs) return hipErrorInvalidValue;

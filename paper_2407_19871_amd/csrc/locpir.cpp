@@ -509,6 +509,12 @@ namespace {
 const char* kProfNames[lp::kProfKinds] = {"blind_rotate", "keyswitch"};
 }
 
+lp_status lp::split_stall_error(const char* who, uint32_t stalls) {
+  return fail(LP_EDEVICE,
+              "%s: %u split-rotation wait(s) ran out of polls (a partner workgroup did not arrive in time); "
+              "the affected outputs are undefined", who, stalls);
+}
+
 extern "C" lp_status lp_split_stall_count(uint32_t* count) {
   if (!count) return fail(LP_EINVAL, "lp_split_stall_count: null argument");
   LP_HIP_TRY(hipDeviceSynchronize());
@@ -708,11 +714,15 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
     // MUX: (0, 1/8) + u1 + u2, the sample its key switch would take
     e = lp::launch_lwe_pair_sum(ex, d_out, cnt, (int)N + 1, 0x20000000u, s);
   }
+  // split rotations: wait for the batch and read the area's give-up record
+  uint32_t stalls = 0;
+  if (e == hipSuccess && waves == 6) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
   hipError_t e2 = hipFreeAsync(scratch, s);
   const hipError_t e3 = lp::split_area_free_async(&split, s);
   if (e2 == hipSuccess) e2 = e3;
   if (e != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e2));
+  if (stalls) return lp::split_stall_error(who, stalls);
   return LP_OK;
 }
 }  // namespace
@@ -810,10 +820,13 @@ extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32
     e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, nullptr, (int)dk->P.n, st, 1, dk->tw, waves, s,
                                 &split);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  uint32_t stalls = 0;
+  if (e == hipSuccess && waves == 6) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
   hipError_t e2 = hipFreeAsync(dj, s);
   const hipError_t e3 = lp::split_area_free_async(&split, s);
   if (e2 == hipSuccess) e2 = e3;
   if (e != hipSuccess || e2 != hipSuccess) return fail(LP_EDEVICE, "lp_debug_blind_rotate: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  if (stalls) return lp::split_stall_error("lp_debug_blind_rotate", stalls);
   return LP_OK;
 }
 

@@ -511,6 +511,14 @@ lp_status run_program(Program& G, const lp_bbox_query* qs, uint32_t* const* d_ou
   src.p[0] = G.pool;
   for (size_t k = 0; k < G.keys.size(); ++k)
     LP_HIP_TRY(launch_gather(G.d_out_refs + G.out_off[k], (int)G.plans[k]->m, src, 0, d_outs[k], (int)G.n_lwe, s));
+  // a program with split rotations waits for its end and reads the
+  // exchange area's give-up record: a wait that ran out leaves its job's
+  // output undefined, so the whole call fails
+  if (G.split.sync) {
+    uint32_t stalls = 0;
+    LP_HIP_TRY(split_area_take_stalls(&G.split, s, &stalls, nullptr));
+    if (stalls) return split_stall_error("bounding-box query", stalls);
+  }
   return LP_OK;
 }
 

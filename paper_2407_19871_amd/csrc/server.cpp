@@ -31,6 +31,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -44,6 +45,7 @@ using Clock = std::chrono::steady_clock;
 struct Request {
   uint64_t ticket = 0;
   const lp_cloud_key* ck = nullptr;
+  std::unique_ptr<lp_cloud_key> own_ck;  // the key deserialized from a submitted blob
   uint32_t l = 0, N = 0, m = 0;
   int is_signed = 0;
   std::vector<uint32_t> inputs;  // n_inputs * (n+1) words
@@ -55,6 +57,7 @@ struct Request {
   size_t ks_pos = 0, br_pos = 0;  // jobs of the current level already run
   std::vector<uint32_t> out;
   lp_status status = LP_EAGAIN;
+  std::string err;  // why the request failed (the scheduler thread's last error)
   bool cancel = false;
   Clock::time_point t_submit;
   double latency = 0.0;
@@ -137,6 +140,7 @@ void release(lp_server* S, Request& r) {
 // Caller holds S->mu.
 void finish_locked(lp_server* S, Request& r, lp_status status) {
   r.status = status;
+  if (status != LP_OK && status != LP_ECANCELED && r.err.empty()) r.err = lp_last_error();
   r.latency = std::chrono::duration<double>(Clock::now() - r.t_submit).count();
   S->st.bytes_in_use -= r.bytes;
   if (status == LP_OK) S->st.completed++;
@@ -144,6 +148,10 @@ void finish_locked(lp_server* S, Request& r, lp_status status) {
   else S->st.failed++;
   r.inputs.clear();
   r.inputs.shrink_to_fit();
+  if (r.own_ck) {
+    r.ck = nullptr;
+    r.own_ck.reset();
+  }
   S->cv_done.notify_all();
 }
 
@@ -228,9 +236,10 @@ uint32_t tick_cap(uint32_t cfg) {
 }
 
 // One fused tick over admitted requests of one shape: each request's chunk
-// of its current level.
+// of its current level.  (*stalled)[k] counts the jobs of request k whose
+// split rotation gave up a wait in this tick (their outputs are undefined).
 lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, const std::vector<Chunk>& ch,
-               uint64_t* n_br_out) {
+               uint64_t* n_br_out, std::vector<uint32_t>* stalled) {
   using lp::BrJob;
   using lp::KsJob;
   std::vector<BrJob> br;
@@ -272,6 +281,7 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, c
     for (; cnt % tile; ++cnt) ks.push_back(KsJob{lp::REF_NONE, lp::REF_NONE, 0u, 0u, (uint32_t)k, {0, 0, 0}});
   }
   *n_br_out = br.size();
+  stalled->assign(act.size(), 0);
   if (S->cfg.simulate) {
     std::this_thread::sleep_for(std::chrono::microseconds(200));
     return LP_OK;
@@ -322,6 +332,14 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, c
   // the host job arrays must outlive every copy queued above, also on failure
   const hipError_t es = hipStreamSynchronize(S->stream);
   if (e == hipSuccess) e = es;
+  if (e == hipSuccess && waves == 6) {
+    // split waits that ran out: only the requests owning those jobs fail
+    uint32_t n_stalls = 0;
+    std::vector<int> jobs;
+    e = lp::split_area_take_stalls(&S->split, S->stream, &n_stalls, &jobs);
+    for (int j : jobs)
+      if (j < (int)br.size()) (*stalled)[br[j].key] += 1;
+  }
   if (e != hipSuccess) return lp::fail(LP_EDEVICE, "server tick: %s", hipGetErrorString(e));
   return LP_OK;
 }
@@ -407,12 +425,19 @@ void worker_main(lp_server* S) {
     for (auto& g : groups) {
       uint64_t n = 0;
       std::vector<Chunk> ch;
+      std::vector<uint32_t> stalled(g.size(), 0);
       lp_status st = plan_chunks(g, tick_cap(S->cfg.max_tick_rotations), &ch);
-      if (st == LP_OK) st = tick(S, g, ch, &n);
+      if (st == LP_OK) st = tick(S, g, ch, &n, &stalled);
       nbr += n;
       widest = std::max(widest, n);
       for (size_t i = 0; i < g.size(); ++i) {
         Request& r = *g[i];
+        if (st == LP_OK && stalled[i]) {
+          done.push_back(g[i]);
+          done_st.push_back(lp::split_stall_error("server request", stalled[i]));
+          r.err = lp_last_error();
+          continue;
+        }
         if (st == LP_OK) {
           r.ks_pos = ch[i].k1;
           r.br_pos = ch[i].r1;
@@ -422,6 +447,7 @@ void worker_main(lp_server* S) {
         }
         done.push_back(g[i]);
         done_st.push_back(st == LP_OK ? collect_output(S, r) : st);
+        if (done_st.back() != LP_OK) r.err = lp_last_error();
       }
     }
     std::lock_guard<std::mutex> lk(S->mu);
@@ -460,15 +486,16 @@ extern "C" lp_status lp_server_request_bytes(const lp_cloud_key* ck, const lp_bb
   return LP_OK;
 }
 
-extern "C" lp_status lp_server_submit(lp_server* S, const lp_cloud_key* ck, const lp_bbox_query_host* q,
-                                      uint64_t* ticket) {
-  if (!S || !ck || !ticket) return lp::fail(LP_EINVAL, "lp_server_submit: null argument");
-  lp_status st = check_host_query(q);
-  if (st != LP_OK) return st;
+namespace {
+// Queues a request under key ck (owned by the request when `owned` holds
+// it); t0 is the moment the request arrived.
+lp_status submit(lp_server* S, const char* who, const lp_cloud_key* ck, std::unique_ptr<lp_cloud_key> owned,
+                 const lp_bbox_query_host* q, uint64_t* ticket, Clock::time_point t0) {
   if (!S->cfg.simulate && (ck->P.N != 1024 || ck->P.l != 3 || ck->P.bg_bit != 7 || ck->P.n > 1024))
-    return lp::fail(LP_EUNSUPPORTED, "lp_server_submit: parameters the GPU kernels do not handle");
+    return lp::fail(LP_EUNSUPPORTED, "%s: parameters the GPU kernels do not handle", who);
   auto r = std::make_shared<Request>();
   r->ck = ck;
+  r->own_ck = std::move(owned);
   r->l = q->l;
   r->N = q->n_boxes;
   r->m = q->m;
@@ -476,8 +503,7 @@ extern "C" lp_status lp_server_submit(lp_server* S, const lp_cloud_key* ck, cons
   r->plan = lp::get_plan(r->l, r->N, r->m, r->is_signed, false);
   r->bytes = request_bytes(ck->P, *r->plan);
   if (r->bytes > S->cfg.hbm_budget)
-    return lp::fail(LP_EBUDGET, "lp_server_submit: request needs %zu bytes, budget is %zu", r->bytes,
-                    S->cfg.hbm_budget);
+    return lp::fail(LP_EBUDGET, "%s: request needs %zu bytes, budget is %zu", who, r->bytes, S->cfg.hbm_budget);
   const size_t w = ck->P.n + 1, l = q->l, N = q->n_boxes, m = q->m;
   r->inputs.resize((size_t)r->plan->n_inputs * w);
   uint32_t* p = r->inputs.data();
@@ -485,10 +511,10 @@ extern "C" lp_status lp_server_submit(lp_server* S, const lp_cloud_key* ck, cons
   std::memcpy(p + l * w, q->y, l * w * 4);
   std::memcpy(p + 2 * l * w, q->bounds, 4 * l * N * w * 4);
   std::memcpy(p + (2 * l + 4 * l * N) * w, q->payload, N * m * w * 4);
-  r->t_submit = Clock::now();
+  r->t_submit = t0;
   {
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->stop) return lp::fail(LP_EINVAL, "lp_server_submit: server is shutting down");
+    if (S->stop) return lp::fail(LP_EINVAL, "%s: server is shutting down", who);
     r->ticket = S->next_ticket++;
     S->all[r->ticket] = r;
     S->pending.push_back(r);
@@ -498,6 +524,29 @@ extern "C" lp_status lp_server_submit(lp_server* S, const lp_cloud_key* ck, cons
   S->cv_work.notify_one();
   *ticket = r->ticket;
   return LP_OK;
+}
+}  // namespace
+
+extern "C" lp_status lp_server_submit(lp_server* S, const lp_cloud_key* ck, const lp_bbox_query_host* q,
+                                      uint64_t* ticket) {
+  const Clock::time_point t0 = Clock::now();
+  if (!S || !ck || !ticket) return lp::fail(LP_EINVAL, "lp_server_submit: null argument");
+  lp_status st = check_host_query(q);
+  if (st != LP_OK) return st;
+  return submit(S, "lp_server_submit", ck, nullptr, q, ticket, t0);
+}
+
+extern "C" lp_status lp_server_submit_blob(lp_server* S, const void* key_blob, size_t key_len,
+                                           const lp_bbox_query_host* q, uint64_t* ticket) {
+  const Clock::time_point t0 = Clock::now();
+  if (!S || !key_blob || !ticket) return lp::fail(LP_EINVAL, "lp_server_submit_blob: null argument");
+  lp_status st = check_host_query(q);
+  if (st != LP_OK) return st;
+  lp_cloud_key* ck = nullptr;
+  st = lp_cloud_key_deserialize(key_blob, key_len, &ck);
+  if (st != LP_OK) return st;
+  std::unique_ptr<lp_cloud_key> own(ck);
+  return submit(S, "lp_server_submit_blob", ck, std::move(own), q, ticket, t0);
 }
 
 extern "C" lp_status lp_server_poll(lp_server* S, uint64_t ticket, int wait, uint32_t* out, double* latency_s) {
@@ -514,7 +563,9 @@ extern "C" lp_status lp_server_poll(lp_server* S, uint64_t ticket, int wait, uin
   const lp_status st = r->status;
   if (st == LP_OK && out) std::memcpy(out, r->out.data(), r->out.size() * 4);
   S->all.erase(ticket);
-  if (st != LP_OK) return lp::fail(st, "request %llu ended with status %d", (unsigned long long)ticket, (int)st);
+  if (st != LP_OK)
+    return lp::fail(st, "request %llu ended with status %d%s%s", (unsigned long long)ticket, (int)st,
+                    r->err.empty() ? "" : ": ", r->err.c_str());
   return LP_OK;
 }
 

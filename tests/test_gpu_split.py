@@ -172,11 +172,12 @@ def test_no_stalled_waits(dkey, stalls_before):
     assert lp.split_stall_count() == stalls_before
 
 
-def test_give_up_path_is_bounded_and_leaves_the_area_clean(monkeypatch, okeys, octx, dkey, split_table):
+def test_give_up_path_is_bounded_and_reported(monkeypatch, okeys, octx, dkey, split_table):
     """Forced from the host with a one-poll limit, split waits give up: the
-    kernel still finishes, the stalls are counted, and the next launches on
-    the same query program's exchange area (eager, so that each launch reads
-    the limit) are exact again."""
+    kernel still finishes, the stalls are counted, and the call that launched
+    them fails with LP_EDEVICE instead of returning an undefined result.  The
+    next launches on the same query program's exchange area (eager, so that
+    each launch reads the limit) are exact again, and so is a gate batch."""
     monkeypatch.setenv("LOCPIR_GRAPHS", "0")
     q = W.random_query_u8(61, force_inside=True)
     parts = _query_parts(okeys, q, seed=62)
@@ -184,10 +185,43 @@ def test_give_up_path_is_bounded_and_leaves_the_area_clean(monkeypatch, okeys, o
     args = [lp.to_device(v) for v in parts]
     before = lp.split_stall_count()
     monkeypatch.setenv("LOCPIR_SPLIT_SPIN", "1")
-    lp.eval_bbox_query(dkey, l, N, m, False, *args)
+    with pytest.raises(lp.LocpirError) as e:
+        lp.eval_bbox_query(dkey, l, N, m, False, *args)
+    assert e.value.code == -3 and "split-rotation" in str(e.value)
     assert lp.split_stall_count() > before
+    bits = np.array([0, 1, 1, 0, 1, 0, 0, 1], np.uint8)
+    c = O.encrypt_bits(okeys, bits, seed=63)
+    c1, c2 = lp.to_device(c[:4]), lp.to_device(c[4:])
+    with pytest.raises(lp.LocpirError) as e:
+        lp.bootstrap_batch(dkey, "NAND", c1, c2)
+    assert e.value.code == -3
     monkeypatch.delenv("LOCPIR_SPLIT_SPIN")
     after = lp.split_stall_count()
     got = as_u32(lp.eval_bbox_query(dkey, l, N, m, False, *args))
     assert (got == octx.bbox_query(l, N, m, False, *parts)).all()
+    exp, _ = octx.gate_batch("NAND", c[:4], c[4:])
+    assert (as_u32(lp.bootstrap_batch(dkey, "NAND", c1, c2)) == exp).all()
     assert lp.split_stall_count() == after
+
+
+def test_give_up_fails_the_server_request_only(monkeypatch, okeys, octx, split_table):
+    """The server under the same forced limit: the request whose split
+    rotations gave up ends with LP_EDEVICE and the server goes on; a server
+    without the limit returns the exact result of the same request."""
+    q = W.random_query_u8(64, force_inside=True)
+    parts = _query_parts(okeys, q, seed=65)
+    l, N, m = q.l, q.n_boxes, q.m
+    ck = lp.CloudKey.from_arrays(lp.params_default(), okeys.bsk, okeys.ksk)
+    monkeypatch.setenv("LOCPIR_SPLIT_SPIN", "1")
+    srv = lp.Server(8 << 30)
+    st, out, _ = srv.poll(srv.submit(ck, l, N, m, False, *parts))
+    stats = srv.stats()
+    srv.close()
+    monkeypatch.delenv("LOCPIR_SPLIT_SPIN")
+    assert st == -3 and out is None
+    assert stats["failed"] == 1 and stats["bytes_in_use"] == 0
+    srv = lp.Server(8 << 30)
+    st, out, _ = srv.poll(srv.submit(ck, l, N, m, False, *parts))
+    srv.close()
+    assert st == 0
+    assert (out == octx.bbox_query(l, N, m, False, *parts)).all()

@@ -204,3 +204,28 @@ def test_automatic_tick_cap(monkeypatch, ck, rows, cap):
         lp.set_tune_table(old)
     assert s["widest_tick"] == cap
     assert s["fused_bootstraps"] == sum(widths)
+
+
+def test_submit_blob_deserializes_and_owns_the_key(ck):
+    """The request as the client sends it (Sec. 3: PK uploaded as a blob):
+    the server deserializes the blob itself, the caller's bytes may go away
+    at once, and a foreign or truncated blob is refused without queueing."""
+    blob = ck.serialize()
+    srv = lp.Server(1 << 40, simulate=True)
+    t1 = srv.submit_blob(bytes(blob), *query(16, 2, 3))
+    t2 = srv.submit(ck, *query(8, 1, 2))
+    del blob
+    st, out, lat = srv.poll(t1)
+    assert st == 0 and out.shape == (3, 631) and lat >= 0
+    assert srv.poll(t2)[0] == 0
+    good = ck.serialize()
+    with pytest.raises(lp.LocpirError) as e:
+        srv.submit_blob(good[:-4], *query(8, 1, 2))       # truncated
+    assert e.value.code == -1
+    bad = bytearray(good)
+    bad[:4] = b"XXXX"                                    # foreign magic
+    with pytest.raises(lp.LocpirError):
+        srv.submit_blob(bytes(bad), *query(8, 1, 2))
+    s = srv.stats()
+    assert s["submitted"] == 2 and s["completed"] == 2 and s["bytes_in_use"] == 0
+    srv.close()
