@@ -168,6 +168,23 @@ lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32
                              const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
                              uint32_t* d_out, void* stream);
 
+/* lp_bootstrap_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same gates, kernels and outputs, but every working buffer
+ * (job lists, the extracted samples, the split-rotation area) lives in the
+ * library's static device scratch, a fixed array of 21 MiB that each GPU the
+ * library runs on holds until the process ends.  The call allocates no
+ * device memory and calls no allocating library routine.  cnt is at most
+ * 1024 gates per call (LP_EINVAL above, nothing launched).  Every call on
+ * one GPU shares that GPU's scratch: calls that overlap in time on one GPU
+ * (different streams or threads) race and must be serialised by the caller;
+ * calls in order on one stream are safe.  The split area's control words are
+ * cleared (by a fill kernel) at the start of each call that uses them.  Other
+ * arguments, errors and waiting behave as in lp_bootstrap_batch. */
+lp_status lp_bootstrap_batch_noalloc(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                                     const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
+                                     uint32_t* d_out, void* stream);
+
 /* EvalGate of Sec. 2.2 stopped before Bootstrap's final key switch:
  * d_out_big[k] (N+1 words, LWE of dimension N under the ring key S) is the
  * sample that gate's key switch takes: the sample extracted from the blind rotation of the gate's input
@@ -231,7 +248,6 @@ lp_status lp_eval_bbox_query(const lp_device_key* dk, const lp_bbox_query* q, ui
  * give-up fails the whole call). */
 lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
                              uint32_t* const* d_outs, void* stream);
-
 /* Preprocess (Algorithm 1), cloud side: the cloud encrypts its plaintext
  * service bits S_i[j] without the secret key by adding the trivial sample
  * (0, f(bit)) to one of the client's fresh samples of zero each:

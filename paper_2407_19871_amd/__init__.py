@@ -124,6 +124,7 @@ def lib() -> C.CDLL:
         "lp_device_key_bytes": (i32, [vp, C.POINTER(sz)]),
         "lp_bootstrap_batch": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
         "lp_bootstrap_batch_noks": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
+        "lp_bootstrap_batch_noalloc": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
         "lp_keyswitch_batch": (i32, [vp, vp, sz, vp, vp]),
         "lp_eval_bbox_query": (i32, [vp, C.POINTER(BBoxQuery), vp, vp]),
         "lp_eval_bbox_batch": (i32, [C.POINTER(vp), C.POINTER(BBoxQuery), sz, C.POINTER(vp), vp]),
@@ -370,6 +371,19 @@ def bootstrap_batch(dk: DeviceKey, gate: str, in0, in1=None, in2=None, out=None,
         out = torch.empty((cnt, dk.params.n + 1), dtype=torch.int32, device=in0.device)
     _check(lib().lp_bootstrap_batch(dk._h, GATES[gate], _dev_ptr(in0), _dev_ptr(in1), _dev_ptr(in2), cnt,
                                     _dev_ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def bootstrap_batch_noalloc(dk: DeviceKey, gate: str, in0, in1=None, in2=None, out=None, stream=None):
+    """bootstrap_batch with every working buffer in the library's static
+    device scratch (at most 1024 gates per call; calls overlapping on one GPU
+    race).  `out` may be preallocated so the call allocates nothing."""
+    torch = _torch()
+    cnt = in0.shape[0]
+    if out is None:
+        out = torch.empty((cnt, dk.params.n + 1), dtype=torch.int32, device=in0.device)
+    _check(lib().lp_bootstrap_batch_noalloc(dk._h, GATES[gate], _dev_ptr(in0), _dev_ptr(in1), _dev_ptr(in2), cnt,
+                                            _dev_ptr(out), _stream_ptr(stream)))
     return out
 
 

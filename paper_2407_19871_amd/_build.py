@@ -19,7 +19,7 @@ HIP_FLAGS = [
 def build(verbose: bool = False, extra=()) -> str:
     objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in ("kernels.hip", "lwe_ops.hip", "locpir.cpp", "sched.cpp", "server.cpp", "tune.cpp"):
+    for src in ("kernels.hip", "lwe_ops.hip", "scratch.hip", "locpir.cpp", "sched.cpp", "server.cpp", "tune.cpp"):
         obj = os.path.join(HERE, "_build", src + ".o")
         cmd = ["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):

@@ -40,6 +40,27 @@ void split_area_free(SplitArea* a);
 // Stream-ordered allocation (hipMallocAsync, cleared by a kernel) and release.
 hipError_t split_area_alloc_async(SplitArea* a, int max_jobs, hipStream_t s);
 hipError_t split_area_free_async(SplitArea* a, hipStream_t s);
+// Clears `words` 32-bit words with a fill kernel on stream s.
+hipError_t launch_clear_words(uint32_t* d, size_t words, hipStream_t s);
+
+// Static scratch of the gate-batch entry point that allocates nothing: a
+// fixed device array per GPU (csrc/scratch.hip) carved into a split area for
+// kNoAllocSplitJobs jobs, job descriptors and extract slots for at most
+// kNoAllocMaxGates gates (2 blind rotations each for MUX).
+constexpr int kNoAllocMaxGates = 1024;
+constexpr int kNoAllocSplitJobs = kSplitMaxJobs;
+constexpr int RING_N_MAX = 1024;
+constexpr size_t kNoAllocScratchBytes = size_t(21) << 20;
+struct NoAllocScratch {
+  SplitArea split;
+  BrJob* br = nullptr;
+  KsJob* ks = nullptr;
+  uint32_t* ex = nullptr;
+};
+// The current device's copy of the array, its address looked up on the
+// first call on that device and kept.
+hipError_t noalloc_scratch(NoAllocScratch* out);
+
 // Waits of split launches that ran out of polls on this device since the
 // process started (0 unless a partner workgroup never arrived).
 hipError_t split_stall_count(uint32_t* out);
@@ -47,7 +68,7 @@ hipError_t split_stall_count(uint32_t* out);
 // for s) and reads the area's give-up record, the number of waits that ran
 // out since it was last taken and (jobs, may be null) the launch-relative
 // indices of the jobs they belong to, whose outputs are undefined; then
-// clears the record.
+// clears the record.  With jobs null it allocates nothing.
 hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* count, std::vector<int>* jobs);
 
 // Blind rotation + sample extraction (or raw accumulator output) of njobs

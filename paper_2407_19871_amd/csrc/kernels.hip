@@ -1155,14 +1155,15 @@ hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* c
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess || st == 0) return e;
   const int padded = split_jobs_padded(a->max_jobs);
-  std::vector<uint32_t> marks(padded);
   uint32_t* dm = a->sync + split_marks_offset(a->max_jobs);
-  e = hipMemcpyAsync(marks.data(), dm, (size_t)padded * 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return e;
-  if (jobs)
+  if (jobs) {
+    std::vector<uint32_t> marks(padded);
+    e = hipMemcpyAsync(marks.data(), dm, (size_t)padded * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
     for (int j = 0; j < padded; ++j)
       if (marks[j]) jobs->push_back(j);
+  }
   // clear the status word and the marks for the next launch on this area
   hipLaunchKernelGGL(split_area_clear_kernel, dim3(1), dim3(256), 0, s, a->sync + SPLIT_STATUS, 1);
   hipLaunchKernelGGL(split_area_clear_kernel, dim3((padded + 255) / 256), dim3(256), 0, s, dm, padded);
@@ -1170,6 +1171,13 @@ hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* c
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   *count = st;
   return e;
+}
+
+hipError_t launch_clear_words(uint32_t* d, size_t words, hipStream_t s) {
+  if (words == 0) return hipSuccess;
+  if (!d || words > (size_t)INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_area_clear_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, d, (int)words);
+  return hipGetLastError();
 }
 
 hipError_t split_area_alloc(SplitArea* a, int max_jobs) {

@@ -660,10 +660,12 @@ namespace {
 // Gate bootstrapping of a batch: blind rotations (sample extraction
 // included) and, with_ks, the key switch into d_out (cnt * (n+1) words);
 // without it d_out receives the samples the key switch would take
-// (cnt * (N+1) words).
+// (cnt * (N+1) words).  Working memory (job lists, extract slots, the split
+// area) comes from the stream-ordered allocator, or from `pre` when given
+// (the static scratch: then nothing is allocated).
 lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
                           const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt, uint32_t* d_out, bool with_ks,
-                          void* stream) {
+                          void* stream, const lp::NoAllocScratch* pre = nullptr) {
   if (!dk) return fail(LP_EINVAL, "%s: null key", who);
   GateCombo gc;
   if (!gate_combo(gate, &gc)) return fail(LP_EINVAL, "%s: unknown gate %d", who, (int)gate);
@@ -673,6 +675,9 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   if (gc.nbr >= 1 && gate != LP_GATE_MUX && !d_in1) return fail(LP_EINVAL, "%s: gate needs d_in1", who);
   if (gate == LP_GATE_MUX && (!d_in1 || !d_in2)) return fail(LP_EINVAL, "%s: MUX needs three inputs", who);
   if (cnt > (size_t)(lp::REF_INDEX_MASK / 2)) return fail(LP_EINVAL, "%s: batch too large", who);
+  if (pre && cnt > (size_t)lp::kNoAllocMaxGates)
+    return fail(LP_EINVAL, "%s: %zu gates exceed the static scratch's maximum of %d per call", who, cnt,
+                lp::kNoAllocMaxGates);
   ScopedDevice sd(dk->device);
   hipStream_t s = as_stream(stream);
   const uint32_t n = dk->P.n, N = dk->P.N;
@@ -685,11 +690,27 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   const bool direct = !with_ks && gc.nbr == 1;
   const size_t ex_bytes = direct ? 0 : nbr * (N + 1) * 4, br_bytes = nbr * sizeof(BrJob),
                ks_bytes = cnt * sizeof(KsJob);
+  const int waves = pick_br_wpb(nbr);
   char* scratch = nullptr;
-  LP_HIP_TRY(hipMallocAsync((void**)&scratch, ex_bytes + br_bytes + ks_bytes + 512, s));
-  uint32_t* ex = direct ? d_out : reinterpret_cast<uint32_t*>(scratch);
-  BrJob* br = reinterpret_cast<BrJob*>(scratch + ((ex_bytes + 255) & ~size_t(255)));
-  KsJob* ks = reinterpret_cast<KsJob*>(reinterpret_cast<char*>(br) + ((br_bytes + 255) & ~size_t(255)));
+  uint32_t* ex = d_out;
+  BrJob* br = nullptr;
+  KsJob* ks = nullptr;
+  lp::SplitArea split;
+  if (pre) {
+    if (!direct) ex = pre->ex;
+    br = pre->br;
+    ks = pre->ks;
+    if (waves == 6) {
+      split = pre->split;
+      // the control words start at zero whatever an earlier call left
+      LP_HIP_TRY(lp::launch_clear_words(split.sync, lp::split_sync_bytes(split.max_jobs) / 4, s));
+    }
+  } else {
+    LP_HIP_TRY(hipMallocAsync((void**)&scratch, ex_bytes + br_bytes + ks_bytes + 512, s));
+    if (!direct) ex = reinterpret_cast<uint32_t*>(scratch);
+    br = reinterpret_cast<BrJob*>(scratch + ((ex_bytes + 255) & ~size_t(255)));
+    ks = reinterpret_cast<KsJob*>(reinterpret_cast<char*>(br) + ((br_bytes + 255) & ~size_t(255)));
+  }
   hipError_t e = lp::launch_make_batch_jobs(gc.nbr, gc.cst, gc.c0, gc.c1, d_in1 != nullptr, cnt, br, ks, s);
   lp::SrcBases src{};
   src.p[0] = d_in0;
@@ -697,9 +718,8 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   src.p[2] = d_in2;
   lp::DstBases dst{};
   dst.p[0] = d_out;
-  const int waves = pick_br_wpb(nbr);
-  lp::SplitArea split;  // stream-ordered, freed below
-  if (e == hipSuccess && waves == 6) e = lp::split_area_alloc_async(&split, (int)nbr, s);
+  // stream-ordered, freed below (the static scratch's area is kept)
+  if (e == hipSuccess && waves == 6 && !pre) e = lp::split_area_alloc_async(&split, (int)nbr, s);
   if (e == hipSuccess) {
     ProfScope ps(kProfBR, nbr, waves, s);
     e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, waves, s,
@@ -717,9 +737,12 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   // split rotations: wait for the batch and read the area's give-up record
   uint32_t stalls = 0;
   if (e == hipSuccess && waves == 6) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
-  hipError_t e2 = hipFreeAsync(scratch, s);
-  const hipError_t e3 = lp::split_area_free_async(&split, s);
-  if (e2 == hipSuccess) e2 = e3;
+  hipError_t e2 = hipSuccess;
+  if (!pre) {
+    e2 = hipFreeAsync(scratch, s);
+    const hipError_t e3 = lp::split_area_free_async(&split, s);
+    if (e2 == hipSuccess) e2 = e3;
+  }
   if (e != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(LP_EDEVICE, "%s: %s", who, hipGetErrorString(e2));
   if (stalls) return lp::split_stall_error(who, stalls);
@@ -737,6 +760,21 @@ extern "C" lp_status lp_bootstrap_batch_noks(const lp_device_key* dk, lp_gate ga
                                              const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
                                              uint32_t* d_out_big, void* stream) {
   return bootstrap_batch("lp_bootstrap_batch_noks", dk, gate, d_in0, d_in1, d_in2, cnt, d_out_big, false, stream);
+}
+
+extern "C" lp_status lp_bootstrap_batch_noalloc(const lp_device_key* dk, lp_gate gate, const uint32_t* d_in0,
+                                                const uint32_t* d_in1, const uint32_t* d_in2, size_t cnt,
+                                                uint32_t* d_out, void* stream) {
+  if (!dk) return fail(LP_EINVAL, "lp_bootstrap_batch_noalloc: null key");
+  if (cnt > (size_t)lp::kNoAllocMaxGates)
+    return fail(LP_EINVAL, "lp_bootstrap_batch_noalloc: %zu gates exceed the static scratch's maximum of %d per call",
+                cnt, lp::kNoAllocMaxGates);
+  ScopedDevice sd(dk->device);
+  lp::NoAllocScratch pre;
+  const hipError_t e = lp::noalloc_scratch(&pre);
+  if (e != hipSuccess)
+    return fail(LP_EDEVICE, "lp_bootstrap_batch_noalloc: static scratch lookup failed (%s)", hipGetErrorString(e));
+  return bootstrap_batch("lp_bootstrap_batch_noalloc", dk, gate, d_in0, d_in1, d_in2, cnt, d_out, true, stream, &pre);
 }
 
 extern "C" lp_status lp_preprocess(const lp_device_key* dk, const uint32_t* d_zero, const uint8_t* d_bits, size_t cnt,
