@@ -248,6 +248,17 @@ lp_status lp_eval_bbox_query(const lp_device_key* dk, const lp_bbox_query* q, ui
  * give-up fails the whole call). */
 lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
                              uint32_t* const* d_outs, void* stream);
+/* The one-time part of lp_eval_bbox_batch for the same keys, query shapes
+ * and stream, done ahead: compiles the circuit of Algorithms 2-5 for every
+ * query into depth levels, uploads the job lists, allocates the ciphertext
+ * pool and captures the per-level graphs, launching nothing.  The following
+ * lp_eval_bbox_batch with the same keys, shapes and stream finds the program
+ * cached (the cache keeps the 16 most recent programs).  Only the shapes and
+ * keys are read (input pointers must be non-null but are not dereferenced).
+ * Errors as lp_eval_bbox_batch. */
+lp_status lp_eval_bbox_prepare(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
+                               void* stream);
+
 /* Preprocess (Algorithm 1), cloud side: the cloud encrypts its plaintext
  * service bits S_i[j] without the secret key by adding the trivial sample
  * (0, f(bit)) to one of the client's fresh samples of zero each:
@@ -378,6 +389,39 @@ lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint32_t* d_pol
  * Synchronous; split rotations are checked as in lp_bootstrap_batch. */
 lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32_t* d_in, size_t cnt,
                                 uint32_t steps, uint32_t* d_acc, void* stream);
+
+/* The CMux external product of one blind-rotation step (Sec. 2.2, Bootstrap:
+ * ACC + ExtProd(BSK_i, X^a ACC - ACC)) computed on the int8 matrix cores, an
+ * exact alternative to the NTT: d_out[b] = sum over the 2l key rows r of
+ * dec_r(d_in[b]) * d_key_step[r] in Z[X]/(X^N + 1) mod 2^32, where dec_r is
+ * gadget digit j of component p (r = p l + j, signed digits in [-64, 64)).
+ * The key words are split into four balanced bytes and every negacyclic
+ * product is an int8 Toeplitz matrix product summed exactly in int32.
+ * d_key_step: [2l][2][N] uint32 (one step's rows in lp_cloud_key_export's
+ * bsk layout); d_in, d_out: cnt x [2][N] uint32 (TRLWE samples, mask then
+ * body); all on the current device, owned by the caller.  N = 1024, l = 3
+ * only; cnt <= 65536 (LP_EINVAL above).  Allocates stream-ordered scratch. */
+lp_status lp_debug_external_product_mfma(const uint32_t* d_key_step, const uint32_t* d_in, size_t cnt,
+                                         uint32_t* d_out, void* stream);
+
+/* Throughput of the field operations the blind rotation's external product
+ * (Sec. 2.2, Bootstrap) is built from, measured on the current device: each
+ * runs alone at full occupancy on every compute unit, on residues held in
+ * registers, in launches sized to about target_ms (0 < target_ms <= 1000).
+ * rates[LP_OPRATE_COUNT] receives operations per second on the whole device,
+ * ms (may be NULL) the timed launch of each.  The operations, in order:
+ *   0 forward-transform butterflies (the 1024-point transform's shift-twiddle
+ *     stages as the kernels run them: pass-1 stages 4, 2, 1 and pass 2);
+ *   1 inverse-transform butterflies (the cyclic inverse pass);
+ *   2 digit butterflies (the first two forward stages on gadget digits, int64);
+ *   3 general products mod p (the twists);
+ *   4 a*b + c*d mod p with one reduction (the key products);
+ *   5 additions of a reduced operand mod p (the sums over gadget levels);
+ *   6 32-bit integer additions (the full-rate reference).
+ * These price the rotation's operation count in the benchmark's roofline.
+ * Synchronous on stream; allocates a small device buffer. */
+#define LP_OPRATE_COUNT 7
+lp_status lp_debug_field_op_rates(double target_ms, double* rates, double* ms, void* stream);
 
 /* ---- profiling ----------------------------------------------------------- */
 

@@ -73,7 +73,9 @@ def lib():
     global _LIB
     if _LIB is not None:
         return _LIB
-    path = os.path.join(_HERE, "liboracle.so")
+    # LOCPIR_ORACLE_LIB names another build of the same C core (e.g. an
+    # address- and undefined-behaviour-sanitizer build)
+    path = os.environ.get("LOCPIR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
     if not os.path.exists(path):
         from .build import build
         build()

@@ -15,7 +15,9 @@ import struct
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liblocpir.so")
+# LOCPIR_LIB names another build of the same library (e.g. an address- and
+# undefined-behaviour-sanitizer build of the host code for CPU tests)
+_LIB_PATH = os.environ.get("LOCPIR_LIB") or os.path.join(_HERE, "liblocpir.so")
 _LIB = None
 
 GATES = {"NAND": 0, "AND": 1, "OR": 2, "XOR": 3, "XNOR": 4, "NOR": 5, "MUX": 6, "NOT": 7, "COPY": 8}
@@ -93,10 +95,12 @@ def lib() -> C.CDLL:
         raise LocpirError(-100, f"{_LIB_PATH} is not built (run __graft_entry__.build())")
     # torch ships its own HIP runtime with the same soname; loading torch
     # first makes liblocpir bind to that one runtime instead of a second copy
-    try:
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    # (a sanitizer build runs host-only tests and skips it)
+    if not os.environ.get("LOCPIR_NO_TORCH"):
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     L = C.CDLL(_LIB_PATH)
     vp, sz, u32, u64, i32 = C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint64, C.c_int32
     PP = C.POINTER(Params)
@@ -125,9 +129,12 @@ def lib() -> C.CDLL:
         "lp_bootstrap_batch": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
         "lp_bootstrap_batch_noks": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
         "lp_bootstrap_batch_noalloc": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
+        "lp_debug_field_op_rates": (i32, [C.c_double, vp, vp, vp]),
+        "lp_debug_external_product_mfma": (i32, [vp, vp, sz, vp, vp]),
         "lp_keyswitch_batch": (i32, [vp, vp, sz, vp, vp]),
         "lp_eval_bbox_query": (i32, [vp, C.POINTER(BBoxQuery), vp, vp]),
         "lp_eval_bbox_batch": (i32, [C.POINTER(vp), C.POINTER(BBoxQuery), sz, C.POINTER(vp), vp]),
+        "lp_eval_bbox_prepare": (i32, [C.POINTER(vp), C.POINTER(BBoxQuery), sz, vp]),
         "lp_bbox_counts": (i32, [u32, u32, u32, C.POINTER(u64), C.POINTER(u64), C.POINTER(u32)]),
         "lp_bbox_level_widths": (i32, [u32, u32, u32, C.POINTER(u32), C.POINTER(u32)]),
         "lp_debug_negacyclic_mul": (i32, [vp, vp, sz, vp, vp]),
@@ -459,6 +466,18 @@ def eval_bbox_batch(keys, queries, outs=None, stream=None):
     return outs
 
 
+def eval_bbox_prepare(keys, queries, stream=None):
+    """Compiles and caches the program eval_bbox_batch would run for these
+    keys and query shapes (graphs captured), launching nothing."""
+    nq = len(queries)
+    if len(keys) != nq:
+        raise LocpirError(-1, "one key per query")
+    qarr = (BBoxQuery * nq)(*[BBoxQuery(q[0], q[1], q[2], int(bool(q[3])), _dev_ptr(q[4]), _dev_ptr(q[5]),
+                                        _dev_ptr(q[6]), _dev_ptr(q[7])) for q in queries])
+    karr = (C.c_void_p * nq)(*[k._h for k in keys])
+    _check(lib().lp_eval_bbox_prepare(karr, qarr, nq, _stream_ptr(stream)))
+
+
 def debug_negacyclic_mul(digits, poly, out=None, stream=None):
     torch = _torch()
     cnt = digits.shape[0]
@@ -469,6 +488,18 @@ def debug_negacyclic_mul(digits, poly, out=None, stream=None):
     return out
 
 
+def debug_external_product_mfma(key_step, d, out=None, stream=None):
+    """ExtProd of one blind-rotation step on the int8 matrix cores: key_step
+    [2l][2][N] (device, Torus32), d [cnt][2N] TRLWE inputs (device)."""
+    torch = _torch()
+    cnt = d.shape[0]
+    if out is None:
+        out = torch.empty((cnt, 2048), dtype=torch.int32, device=d.device)
+    _check(lib().lp_debug_external_product_mfma(_dev_ptr(key_step), _dev_ptr(d), cnt, _dev_ptr(out),
+                                                _stream_ptr(stream)))
+    return out
+
+
 def debug_blind_rotate(dk: DeviceKey, ct, steps: int, out=None, stream=None):
     torch = _torch()
     cnt = ct.shape[0]
@@ -476,6 +507,19 @@ def debug_blind_rotate(dk: DeviceKey, ct, steps: int, out=None, stream=None):
         out = torch.empty((cnt, 2 * dk.params.N), dtype=torch.int32, device=ct.device)
     _check(lib().lp_debug_blind_rotate(dk._h, _dev_ptr(ct), cnt, steps, _dev_ptr(out), _stream_ptr(stream)))
     return out
+
+
+FIELD_OPS = ("fwd_butterfly", "inv_butterfly", "digit_butterfly", "mulmod", "mulsum", "add", "u32_add")
+
+
+def field_op_rates(target_ms: float = 4.0, stream=None) -> dict:
+    """Measured throughput (operations per second, whole device) of the field
+    operations the blind rotation is built from, each alone at full
+    occupancy; see lp_debug_field_op_rates."""
+    rates = (C.c_double * len(FIELD_OPS))()
+    ms = (C.c_double * len(FIELD_OPS))()
+    _check(lib().lp_debug_field_op_rates(float(target_ms), rates, ms, _stream_ptr(stream)))
+    return {k: {"per_s": float(rates[i]), "ms": float(ms[i])} for i, k in enumerate(FIELD_OPS)}
 
 
 # ------------------------------------------------------------------ profiling

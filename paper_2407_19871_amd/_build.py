@@ -16,10 +16,14 @@ HIP_FLAGS = [
 ]
 
 
+SOURCES = ("kernels.hip", "lwe_ops.hip", "scratch.hip", "oprate.hip", "extprod_mfma.hip", "locpir.cpp", "sched.cpp",
+           "server.cpp", "tune.cpp")
+
+
 def build(verbose: bool = False, extra=()) -> str:
     objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in ("kernels.hip", "lwe_ops.hip", "scratch.hip", "locpir.cpp", "sched.cpp", "server.cpp", "tune.cpp"):
+    for src in SOURCES:
         obj = os.path.join(HERE, "_build", src + ".o")
         cmd = ["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):

@@ -135,9 +135,10 @@ GL_INLINE uint64_t gl_mac(uint64_t acc, uint64_t a, uint64_t b) {
   return gl_reduce128(lo, hi + (c ? 1ull : 0ull));
 }
 
-// x * 2^S mod p for a compile-time S; the result is lazy for S mod 192 in
-// (0, 64) and reduced otherwise (see gl_mul_pow2_r).  2^96 = -1 folds S
-// into [0, 96) with a negation.
+// x * 2^S mod p for a compile-time S; for S mod 192 = 0 the result is x
+// itself, for S mod 192 in (0, 64) it is lazy, and for S mod 192 in
+// [64, 192) it is reduced (see gl_mul_pow2_r).  2^96 = -1 folds S into
+// [0, 96) with a negation.
 //   0 < s < 32:   x 2^s = w0 + 2^32 w1 + 2^64 w2 with w2 < 2^31, i.e.
 //                 (w1:w0) + EPS w2;
 //   32 <= s < 64: the three high words are reduced by gl_reduce128;

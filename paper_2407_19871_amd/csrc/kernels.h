@@ -108,6 +108,21 @@ hipError_t launch_lwe_scale(const uint32_t* d_in, uint32_t* d_out, size_t words,
 hipError_t launch_gather(const uint32_t* d_refs, int cnt, const SrcBases& src, uint32_t index_offset,
                          uint32_t* d_out, int n_lwe, hipStream_t s);
 
+// Field-operation throughput (csrc/oprate.hip): each operation alone at full
+// occupancy in a launch sized to about target_ms; rates[op] receives
+// operations per second on the whole device, ms[op] (may be null) the timed
+// launch.  Synchronous.
+enum { kOpFwd = 0, kOpInv = 1, kOpDigits = 2, kOpMul = 3, kOpMulSum = 4, kOpAdd = 5, kOpU32 = 6, kOpCount = 7 };
+hipError_t launch_op_rates(double target_ms, double* rates, double* ms, hipStream_t s);
+
+// The external product of one blind-rotation step on the int8 matrix cores
+// (csrc/extprod_mfma.hip): d_out[b] = sum_r dec_r(d_in[b]) * key[r] for cnt
+// TRLWE inputs [cnt][2][1024]; key: the step's 2l = 6 key rows [6][2][1024]
+// in Torus32 form.  scratch: xp_mfma_scratch_bytes(cnt) device bytes.
+size_t xp_mfma_scratch_bytes(int cnt);
+hipError_t launch_extprod_mfma(const uint32_t* d_key_step, const uint32_t* d_in, int cnt, uint32_t* d_out,
+                               void* scratch, hipStream_t s);
+
 // cnt exact negacyclic products (digits x NTT-domain polynomial) mod 2^32.
 hipError_t launch_debug_polymul(const int32_t* d_digits, const uint64_t* d_poly_ntt, uint32_t* d_out,
                                 int cnt, Twiddles tw, hipStream_t s);

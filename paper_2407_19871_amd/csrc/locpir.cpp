@@ -834,6 +834,29 @@ extern "C" lp_status lp_debug_negacyclic_mul(const int32_t* d_digits, const uint
   return LP_OK;
 }
 
+extern "C" lp_status lp_debug_external_product_mfma(const uint32_t* d_key_step, const uint32_t* d_in, size_t cnt,
+                                                    uint32_t* d_out, void* stream) {
+  if (cnt == 0) return LP_OK;
+  if (!d_key_step || !d_in || !d_out) return fail(LP_EINVAL, "lp_debug_external_product_mfma: null buffer");
+  if (cnt > 65536) return fail(LP_EINVAL, "lp_debug_external_product_mfma: at most 65536 inputs");
+  hipStream_t s = as_stream(stream);
+  void* scratch = nullptr;
+  LP_HIP_TRY(hipMallocAsync(&scratch, lp::xp_mfma_scratch_bytes((int)cnt), s));
+  hipError_t e = lp::launch_extprod_mfma(d_key_step, d_in, (int)cnt, d_out, scratch, s);
+  const hipError_t e2 = hipFreeAsync(scratch, s);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_debug_external_product_mfma: %s", hipGetErrorString(e));
+  return LP_OK;
+}
+
+extern "C" lp_status lp_debug_field_op_rates(double target_ms, double* rates, double* ms, void* stream) {
+  if (!rates) return fail(LP_EINVAL, "lp_debug_field_op_rates: null rates");
+  if (!(target_ms > 0.0) || target_ms > 1000.0) return fail(LP_EINVAL, "lp_debug_field_op_rates: target_ms outside (0, 1000]");
+  const hipError_t e = lp::launch_op_rates(target_ms, rates, ms, as_stream(stream));
+  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_debug_field_op_rates: %s", hipGetErrorString(e));
+  return LP_OK;
+}
+
 extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, uint32_t steps,
                                            uint32_t* d_acc, void* stream) {
   if (!dk) return fail(LP_EINVAL, "lp_debug_blind_rotate: null key");

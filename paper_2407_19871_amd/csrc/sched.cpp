@@ -473,6 +473,13 @@ lp_status capture_graphs(Program& G) {
   return LP_OK;
 }
 
+// Captures the program's graphs ahead of its first run (when graphs are on).
+lp_status prepare_program(Program& G) {
+  std::lock_guard<std::mutex> lk(G.mu);
+  if (env_int("LOCPIR_GRAPHS", 1) != 0 && !G.graphs_ready) return capture_graphs(G);
+  return LP_OK;
+}
+
 // Copies the queries' inputs into the pool, runs every level and gathers
 // each query's m outputs.
 lp_status run_program(Program& G, const lp_bbox_query* qs, uint32_t* const* d_outs, hipStream_t s) {
@@ -623,25 +630,52 @@ extern "C" lp_status lp_bbox_level_widths(uint32_t l, uint32_t n_boxes, uint32_t
   return LP_OK;
 }
 
-extern "C" lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
-                                        uint32_t* const* d_outs, void* stream) {
-  if (nq == 0) return LP_OK;
-  if (!keys || !queries || !d_outs) return lp::fail(LP_EINVAL, "lp_eval_bbox_batch: null argument");
-  std::vector<const lp_device_key*> ks(keys, keys + nq);
+namespace {
+// Validation shared by the batch call and its prepare step.
+lp_status check_batch(const char* who, const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
+                      uint32_t* const* d_outs, std::vector<const lp_device_key*>* ks) {
+  if (!keys || !queries) return lp::fail(LP_EINVAL, "%s: null argument", who);
+  ks->assign(keys, keys + nq);
   for (size_t k = 0; k < nq; ++k) {
-    if (!ks[k] || !d_outs[k]) return lp::fail(LP_EINVAL, "lp_eval_bbox_batch: null key or output %zu", k);
-    if (ks[k]->device != ks[0]->device || ks[k]->P.n != ks[0]->P.n || ks[k]->P.ks_t != ks[0]->P.ks_t ||
-        ks[k]->P.ks_base_bit != ks[0]->P.ks_base_bit)
-      return lp::fail(LP_EINVAL, "lp_eval_bbox_batch: keys differ in device or parameters");
+    if (!(*ks)[k]) return lp::fail(LP_EINVAL, "%s: null key %zu", who, k);
+    if (d_outs && !d_outs[k]) return lp::fail(LP_EINVAL, "%s: null output %zu", who, k);
+    const lp_device_key* a = (*ks)[k];
+    const lp_device_key* b = (*ks)[0];
+    if (a->device != b->device || a->P.n != b->P.n || a->P.ks_t != b->P.ks_t || a->P.ks_base_bit != b->P.ks_base_bit)
+      return lp::fail(LP_EINVAL, "%s: keys differ in device or parameters", who);
     lp_status st = lp::check_query(queries[k]);
     if (st != LP_OK) return st;
   }
+  return LP_OK;
+}
+}  // namespace
+
+extern "C" lp_status lp_eval_bbox_batch(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
+                                        uint32_t* const* d_outs, void* stream) {
+  if (nq == 0) return LP_OK;
+  if (!d_outs) return lp::fail(LP_EINVAL, "lp_eval_bbox_batch: null argument");
+  std::vector<const lp_device_key*> ks;
+  lp_status st = check_batch("lp_eval_bbox_batch", keys, queries, nq, d_outs, &ks);
+  if (st != LP_OK) return st;
   lp::ScopedDevice sd(ks[0]->device);
   hipStream_t s = lp::as_stream(stream);
   std::shared_ptr<lp::Program> G;
-  lp_status st = lp::get_program(ks, queries, s, &G);
+  st = lp::get_program(ks, queries, s, &G);
   if (st != LP_OK) return st;
   return lp::run_program(*G, queries, d_outs, s);
+}
+
+extern "C" lp_status lp_eval_bbox_prepare(const lp_device_key* const* keys, const lp_bbox_query* queries, size_t nq,
+                                          void* stream) {
+  if (nq == 0) return LP_OK;
+  std::vector<const lp_device_key*> ks;
+  lp_status st = check_batch("lp_eval_bbox_prepare", keys, queries, nq, nullptr, &ks);
+  if (st != LP_OK) return st;
+  lp::ScopedDevice sd(ks[0]->device);
+  std::shared_ptr<lp::Program> G;
+  st = lp::get_program(ks, queries, lp::as_stream(stream), &G);
+  if (st != LP_OK) return st;
+  return lp::prepare_program(*G);
 }
 
 extern "C" lp_status lp_eval_bbox_query(const lp_device_key* dk, const lp_bbox_query* q, uint32_t* d_out,

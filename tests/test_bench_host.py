@@ -57,3 +57,27 @@ def test_more_than_one_gpu_exits_with_a_message():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_op_prices_from_measured_rates():
+    """Each operation's price is the peak lane-op rate over its own measured
+    rate; the per-bootstrap count sums ops x price over the CMux steps."""
+    peak = bench.VALU_PEAK_TOPS * 1e12
+
+    class FakeLib:
+        @staticmethod
+        def field_op_rates(target_ms):
+            r = {"fwd_butterfly": peak / 20, "inv_butterfly": peak / 22, "digit_butterfly": peak / 5,
+                 "mulmod": peak / 25, "mulsum": peak / 40, "add": peak / 6, "u32_add": peak}
+            return {k: {"per_s": v, "ms": 4.0} for k, v in r.items()}
+
+    p = bench.op_prices(FakeLib(), n_steps=630)
+    price = {"fwd_butterfly": 20, "inv_butterfly": 22, "digit_butterfly": 5, "mulmod": 25, "mulsum": 40,
+             "add": 6, "u32_add": 1}
+    want = 630 * sum(bench.OPS_PER_STEP[k] * price[k] for k in price)
+    assert p["lane_cycles_per_bootstrap"] == pytest.approx(want)
+    assert p["u32_rate_vs_peak"] == pytest.approx(1.0)
+    # the per-step counts of the formulation: 6 forward and 2 inverse transforms of 1024 points
+    assert bench.OPS_PER_STEP["fwd_butterfly"] + bench.OPS_PER_STEP["digit_butterfly"] == 6 * 10 * 512
+    assert bench.OPS_PER_STEP["inv_butterfly"] == 2 * 10 * 512
+    assert bench.OPS_PER_STEP["mulmod"] == 8 * 1024

@@ -46,8 +46,9 @@ def test_mux_batch_ragged(okeys, octx, dkey):
 
 def test_nand_batch_full_size_sampled(okeys, octx, dkey):
     """The batched microbenchmark's largest launch (16384 NAND gates, one
-    shared key): every output decrypts to the truth table, and 32 sampled
-    outputs equal the oracle's gates bit for bit."""
+    shared key): every output decrypts to the truth table, and 512 sampled
+    outputs plus the first, the last and rows at power-of-two boundaries
+    equal the oracle's gates bit for bit."""
     B = 16384
     a = W.random_bits(5001, B)
     b = W.random_bits(5002, B)
@@ -57,7 +58,8 @@ def test_nand_batch_full_size_sampled(okeys, octx, dkey):
     d, ph = bits_of(okeys, got)
     assert (d == 1 - (a & b)).all()
     assert np.abs(np.abs(ph.astype(np.int64)) - 2**29).max() < 2**28
-    idx = np.random.default_rng(5005).choice(B, 32, replace=False)
+    idx = np.random.default_rng(5005).choice(B, 512, replace=False)
+    idx = np.unique(np.concatenate([idx, [0, 1, 63, 64, 1023, 1024, 8191, 8192, B - 1]]))
     exp, _ = octx.gate_batch("NAND", c1[idx], c2[idx])
     assert (got[idx] == exp).all()
 
