@@ -21,15 +21,19 @@ struct Twiddles {
 hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, Twiddles tw,
                              hipStream_t s);
 
-// Exchange area of split blind rotations (waves_per_job = 6: one bootstrap
-// on two workgroups that trade their forward transforms every step).  The
+// Split shapes: one bootstrap on two workgroups (4 waves each for 6, 8 for 7).
+inline bool is_split(int waves_per_job) { return waves_per_job == 6 || waves_per_job == 7; }
+
+// Exchange area of split blind rotations (waves_per_job = 6 or 7: one
+// bootstrap on two workgroups that trade their forward transforms every
+// step).  The
 // owner allocates it for at most max_jobs jobs per launch; the sync words
 // are zero before the first launch and every launch leaves them zero.  One
 // launch at a time may use an area.
 constexpr int kSplitMaxJobs = 128;
 struct SplitArea {
   uint64_t* xbuf = nullptr;  // [job][role 2][step parity 2][level 3][1024] u64
-  uint32_t* sync = nullptr;  // 8 ticket counters, finish count, then 8 flag words per job
+  uint32_t* sync = nullptr;  // 8 ticket counters, finish count, status; 16 flag words per job; give-up marks
   int max_jobs = 0;
 };
 size_t split_xbuf_bytes(int max_jobs);
@@ -77,14 +81,34 @@ hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* c
 // component, two bootstraps per SIMD), 3 (one wave per gadget level),
 // 4 (three level waves, the levels' NTT-domain sum inverted once per
 // component on two waves each; one bootstrap per CU), 5 (the same, two
-// bootstraps per CU) or 6 (split over two workgroups; needs `split` with
-// room for njobs).
+// bootstraps per CU), 6 (split over two workgroups of four waves; needs
+// `split` with room for njobs) or 7 (the same on eight waves per workgroup,
+// each level's forward transform on two).
 // d_pool_tab (may be null) resolves operands with base KEY_POOL_BASE to the
 // pool of the job's key.
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe,
                                int steps, int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
                                const SplitArea* split = nullptr);
+
+// The split rotation's profiling instantiation (waves_per_job 6 or 7, raw
+// accumulators into d_ex): every wave of every workgroup writes, at
+// d_prof + (block * waves per workgroup + wave) * kSplitPhaseWords, its
+// shader cycles in each of the kSplitPhaseWords - 2 phases of a step summed
+// over its executed steps, then that step count, then its XCD id plus 16
+// when the pair traded through that XCD's L2.  The phases: [0] digits and
+// key requests (eight waves: also pass 1 and the twist); [1] the barrier
+// after them; [2] the forward transform (eight waves: its pass 2); [3] the
+// stores of the transform and the own-component products; [4] the wait for
+// every outstanding memory access; [5] the flag and the wait for the
+// partner's; [6] loading the partner's transform and the products; [7] the
+// barrier after them; [8] the inverse's first pass and twist; [9] the
+// barrier inside the inverse; [10] its second pass and the accumulator
+// update; [11] the closing barrier.
+constexpr int kSplitPhaseWords = 14;
+hipError_t launch_split_profiled(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
+                                 const uint64_t* const* d_bsk_tab, int n_lwe, int steps, Twiddles tw,
+                                 int waves_per_job, const SplitArea* split, uint64_t* d_prof, hipStream_t s);
 
 // Key switching of njobs jobs (tiles of `tile` consecutive jobs share one
 // key; jobs with ex0 == REF_NONE are padding and skipped); the ring index is

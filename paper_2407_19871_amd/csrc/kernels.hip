@@ -692,6 +692,7 @@ constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
 constexpr int SPLIT_DONE = 8;    // finish counter (words 0-7: ticket counters per class)
 constexpr int SPLIT_STATUS = 9;  // waits of this area that ran out, until the host clears it
 constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
+constexpr int SPLIT_FLAGS_PER_JOB = 16;  // [role 2][wave 8]
 
 __device__ uint32_t g_split_stalls;
 
@@ -710,17 +711,89 @@ __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Accesses of an exchange between two workgroups on one XCD, through that
+// XCD's L2 (the coherence point of its CUs): stores write through to L2,
+// loads carry sc0 so that they miss the reading CU's L1.  Buffer resources
+// (raw, no stride) over the exchange slots and the sync words; the aux bit
+// 31 marks the accesses volatile, so polls stay in their loop.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t l2_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+constexpr int kL2Load = (int)0x80000001u;  // volatile, sc0
+constexpr int kL2Store = (int)0x80000000u;  // volatile
+__device__ __forceinline__ void st_l2(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t v) {
+  const u32x2 x = {(uint32_t)v, (uint32_t)(v >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, kL2Store);
+}
+__device__ __forceinline__ uint64_t ld_l2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kL2Load);
+  return ((uint64_t)x.y << 32) | x.x;
+}
+__device__ __forceinline__ void st_l2_u32(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, kL2Store);
+}
+__device__ __forceinline__ uint32_t ld_l2_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kL2Load);
+}
+// The XCD this wave runs on.
+__device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
+
+// Per-wave cycle counts of the phases of a split step (the profiling
+// instantiation only; the production one compiles none of it).  mark<K>()
+// adds the shader cycles since the previous mark to phase K; store() writes
+// phases 0..kPhases-1 and the executed-step count for this wave.
+// Scheduling barriers around each clock read keep the compiler from moving
+// work across a phase boundary (the profiling build schedules a little
+// differently for it).
+constexpr int kSplitPhases = 12;
+template <bool PROF>
+struct PhaseClock {
+  uint64_t t = 0;
+  uint64_t acc[kSplitPhases] = {};
+  __device__ __forceinline__ void start() {
+    if constexpr (PROF) {
+      __builtin_amdgcn_sched_barrier(0);
+      t = __builtin_amdgcn_s_memtime();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  template <int K>
+  __device__ __forceinline__ void mark() {
+    if constexpr (PROF) {
+      __builtin_amdgcn_sched_barrier(0);
+      const uint64_t n = __builtin_amdgcn_s_memtime();
+      __builtin_amdgcn_sched_barrier(0);
+      acc[K] += n - t;
+      t = n;
+    }
+  }
+  __device__ __forceinline__ void store(uint64_t* out, int lane, uint32_t done, uint32_t where) {
+    if constexpr (PROF) {
+      if (out && lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kSplitPhases; ++k) out[k] = acc[k];
+        out[kSplitPhases] = done;
+        out[kSplitPhases + 1] = where;
+      }
+    }
+  }
+};
+
+template <bool PROF>
 __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
-    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit) {
+    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, uint64_t* __restrict__ prof) {
   __shared__ uint32_t s_acc[RING_N];
   __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
   __shared__ __align__(16) uint64_t s_part[3][RING_N];     // the levels' partials, NTT domain
   __shared__ __align__(16) uint64_t s_t128[32 * T128_ROW];  // two-wave transpose
+  // both twist tables, read every step at LDS latency instead of L2's
+  __shared__ __align__(16) uint64_t s_twf[RING_N], s_twi[RING_N];
   __shared__ uint16_t s_abar[MAX_LWE + 4];
-  __shared__ uint32_t s_ticket, s_last;
+  __shared__ uint32_t s_ticket, s_last, s_local;
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
@@ -731,6 +804,10 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
                  upper4 = (h8 & 4) ? ~0ull : 0ull;
   uint64_t w2[4], w1[4];
   inv256_twiddles(h8, w2, w1);
+  for (int k = threadIdx.x; k < RING_N; k += 256) {
+    s_twf[k] = tw_f[k];
+    s_twi[k] = tw_i[k];
+  }
   const int cls = (int)(blockIdx.x & 7u);
   if (threadIdx.x == 0) s_ticket = atomicAdd(sync + cls, 1u);
   __syncthreads();
@@ -769,15 +846,35 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const int lw = lvl ? wave : 0;  // wave 3 has no exchange slot (and uses none)
     uint64_t* my_x = xbuf + ((size_t)(job * 2 + c) * 6 + lw) * RING_N;
     const uint64_t* peer_x = xbuf + ((size_t)(job * 2 + (1 - c)) * 6 + lw) * RING_N;
-    uint32_t* my_flag = sync + SPLIT_FLAGS + job * 8 + c * 4 + lw;
-    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * 8 + (1 - c) * 4 + lw;
+    uint32_t* my_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + lw;
+    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + lw;
     const int sh = 25 - 7 * wave;
     uint32_t done = 0;  // executed steps, the same count in both roles
     bool stalled = false;
+    PhaseClock<PROF> pc;
+    // Both halves on one XCD (the normal placement of the class pairing)
+    // trade through that XCD's L2; otherwise past it, as agent-scope
+    // accesses.  The halves learn it from each other's XCD id, published in
+    // their pair's spare flag word (bounded wait as for the transforms).
+    const uint32_t my_xcc = xcc_id();
+    if (threadIdx.x == 0) {
+      store_agent(sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + 7, my_xcc + 1);
+      const uint32_t* px = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + 7;
+      uint32_t v = 0;
+      for (int it = 0; it < spin_limit && (v = load_agent(px)) == 0; ++it) __builtin_amdgcn_s_sleep(1);
+      s_local = v == my_xcc + 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool local = __builtin_amdgcn_readfirstlane((int)s_local) != 0;
+    const __amdgpu_buffer_rsrc_t xr = l2_rsrc(xbuf, (gridDim.x / 2) * 12u * RING_N * 8u);
+    const __amdgpu_buffer_rsrc_t fr = l2_rsrc(sync, (SPLIT_FLAGS + (gridDim.x / 2) * SPLIT_FLAGS_PER_JOB) * 4u);
+    const uint32_t my_xo = (uint32_t)(my_x - xbuf) * 8u, peer_xo = (uint32_t)(peer_x - xbuf) * 8u;
+    const uint32_t my_fo = (uint32_t)(my_flag - sync) * 4u, peer_fo = (uint32_t)(peer_flag - sync) * 4u;
 
     for (int i = 0; i < nsteps; ++i) {
       const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
       if (a == 0) continue;  // X^0 ACC - ACC = 0: no digits, no exchange
+      pc.start();
 
       // key rows (c, j) and (1-c, j), component c, at this lane's offsets
       const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
@@ -800,14 +897,27 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
           dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
         }
       }
+      pc.template mark<0>();
       __syncthreads();  // every wave has read ACC_c before any adds to it
+      pc.template mark<1>();
       if (lvl) {
-        uint64_t f[16];
-        ntt64_fwd_digits(dg, f, buf, opaque(tw_f), lane);
+        uint64_t f[16];  // ntt64_fwd_digits with the twist factors from LDS
+        fwd64_p1_digits(dg, f);
+        fwd64_p1_rest(f, lane);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
+        transpose64(f, buf, h, l);
+        fwd64_p2(f, lane);
+        pc.template mark<2>();
 
         const size_t par = (size_t)(done & 1u) * 3 * RING_N;
+        if (local) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
+          for (int s = 0; s < 16; ++s) st_l2(xr, my_xo + (uint32_t)(par + s * 64 + lane) * 8u, f[s]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
+        }
         // this component's products while the stores drain and the partner's
         // transform is on its way (the empty asm keeps them ahead of the wait)
         uint64_t plo[16], phi[16];
@@ -816,11 +926,16 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
           gl_mul_wide(f[s], kown[s], plo[s], phi[s]);
           asm volatile("" : "+v"(plo[s]), "+v"(phi[s]));
         }
+        pc.template mark<3>();
         vm_wait_all();
-        if (lane == 0) store_agent(my_flag, done + 1);
+        pc.template mark<4>();
+        if (lane == 0) {
+          if (local) st_l2_u32(fr, my_fo, done + 1);
+          else store_agent(my_flag, done + 1);
+        }
         if (!stalled) {
           int it = 0;
-          while (load_agent(peer_flag) < done + 1) {
+          while ((local ? ld_l2_u32(fr, peer_fo) : load_agent(peer_flag)) < done + 1) {
             if (++it >= spin_limit) break;
             __builtin_amdgcn_s_sleep(1);
           }
@@ -833,15 +948,23 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
             }
           }
         }
+        pc.template mark<5>();
         vm_wait_all();
         uint64_t g[16];
+        if (local) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
+          for (int s = 0; s < 16; ++s) g[s] = ld_l2(xr, peer_xo + (uint32_t)(par + s * 64 + lane) * 8u);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
+        }
 #pragma unroll
         for (int s = 0; s < 16; ++s)
           s_part[wave][64 * s + 2 * l + h] = gl_mul_sum_wide(plo[s], phi[s], g[s], koth[s]);
+        pc.template mark<6>();
       }
       __syncthreads();
+      pc.template mark<7>();
 
       // one inverse of the three levels' sum, on all four waves: each holds
       // eight rows at eight lanes per row (the NTT-domain offset of position
@@ -854,17 +977,13 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
           v[s] = gl_add(gl_add(s_part[0][off], s_part[1][off]), s_part[2][off]);
         }
         inv256_p2(v, upper1, upper2, upper4, w2);
-        {
-          const gmem_u64* t = as_global(opaque(tw_i)) + h8 * 32 + row;
-          uint64_t w[4];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) w[s] = t[s * 256];
-#pragma unroll
-          for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], w[s]);
-        }
+        for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], s_twi[h8 * 32 + row + s * 256]);
 #pragma unroll
         for (int s = 0; s < 4; ++s) s_t128[row * T128_ROW + 8 * s + h8] = v[s];
+        pc.template mark<8>();
         __syncthreads();
+        pc.template mark<9>();
         // column j1 = row of this lane, positions q = 8 s + h8
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = s_t128[(8 * s + h8) * T128_ROW + row];
@@ -874,9 +993,13 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
 #pragma unroll
         for (int s = 0; s < 4; ++s) s_acc[row + 32 * (8 * s + h8)] += gl_lift_u32(v[s]);
       }
+      pc.template mark<10>();
       ++done;
       __syncthreads();
+      pc.template mark<11>();
     }
+    pc.store(prof ? prof + ((size_t)blockIdx.x * 4 + wave) * kSplitPhaseWords : nullptr, lane, done,
+             my_xcc | (local ? 16u : 0u));
 
     if (raw_acc) {
       uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
@@ -902,8 +1025,253 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
   if (threadIdx.x == 0) s_last = atomicAdd(sync + SPLIT_DONE, 1u) == gridDim.x - 1 ? 1u : 0u;
   __syncthreads();
   if (s_last) {
-    const int nflags = (int)(gridDim.x / 2) * 8;
+    const int nflags = (int)(gridDim.x / 2) * SPLIT_FLAGS_PER_JOB;
     for (int k = threadIdx.x; k < nflags; k += 256) store_agent(sync + SPLIT_FLAGS + k, 0u);
+    if (threadIdx.x <= SPLIT_DONE) store_agent(sync + threadIdx.x, 0u);  // the 8 class counters and the finish count
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split blind rotation on eight waves per workgroup (two per SIMD): the
+// pairing, the exchange protocol, the bounded waits and the give-up record
+// of blind_rotate_split_kernel, with each gadget level's forward transform
+// spread over two waves (the 128-lane layout of ntt64.h, four lanes per
+// row), so that two waves share every SIMD while the transforms run.
+// Waves 0-5: level j = wave / 2, half k = wave % 2; each publishes its half
+// of F_(c,j) (4 KB) under a flag of its own and loads the partner's same
+// half.  Waves 0-3 invert the levels' sum as before; waves 6 and 7 only
+// keep the barriers.
+template <bool PROF>
+__global__ __launch_bounds__(512, 1) void blind_rotate_split8_kernel(
+    const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
+    const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
+    int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
+    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, uint64_t* __restrict__ prof) {
+  __shared__ uint32_t s_acc[RING_N];
+  __shared__ __align__(16) uint64_t s_fwd[3][32 * T128_ROW];  // each level's two-wave transpose
+  __shared__ __align__(16) uint64_t s_part[3][RING_N];       // the levels' partials, NTT domain
+  __shared__ __align__(16) uint64_t s_t128[32 * T128_ROW];    // the inverse's transpose
+  __shared__ uint16_t s_abar[MAX_LWE + 4];
+  __shared__ uint32_t s_ticket, s_last;
+
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const bool lvl = wave < 6;  // waves 0-5 run the gadget levels (two per level)
+  const bool inv = wave < 4;  // waves 0-3 invert
+  const int lj = lvl ? wave >> 1 : 0, lk = wave & 1;
+  // two-wave forward: lane 4 r4 + hq holds column (then row) 16 lk + r4,
+  // positions 4 s + hq
+  const int r4 = lane >> 2, hq = lane & 3, col = 16 * lk + r4;
+  const uint64_t fu1 = (hq & 1) ? ~0ull : 0ull, fu2 = (hq & 2) ? ~0ull : 0ull;
+  // four-wave inverse: row (or column) 8 wave + r8, lane h8 of the row's eight
+  const int r8 = lane >> 3, h8 = lane & 7, row = 8 * (wave & 3) + r8;
+  const uint64_t upper1 = (h8 & 1) ? ~0ull : 0ull, upper2 = (h8 & 2) ? ~0ull : 0ull,
+                 upper4 = (h8 & 4) ? ~0ull : 0ull;
+  uint64_t w2[4], w1[4];
+  inv256_twiddles(h8, w2, w1);
+  const int cls = (int)(blockIdx.x & 7u);
+  if (threadIdx.x == 0) s_ticket = atomicAdd(sync + cls, 1u);
+  __syncthreads();
+  const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_ticket);
+  const int job = (int)(t >> 1) * 8 + cls;
+  const int c = (int)(t & 1u);
+
+  if (job < njobs) {
+    const BrJob J = jobs[job];
+    {
+      auto operand = [&](uint32_t r) -> const uint32_t* {
+        if (r == REF_NONE) return nullptr;
+        const uint32_t base = r >> REF_SHIFT;
+        const uint32_t* b = base == KEY_POOL_BASE ? pool_tab[J.key] : src.p[base];
+        return b + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
+      };
+      const uint32_t* in0 = operand(J.in0);
+      const uint32_t* in1 = operand(J.in1);
+      for (int k = threadIdx.x; k <= n_lwe; k += 512) {
+        uint32_t v = (k == n_lwe) ? J.cst : 0u;
+        if (in0) v += (uint32_t)J.c0 * in0[k];
+        if (in1) v += (uint32_t)J.c1 * in1[k];
+        s_abar[k] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
+      }
+    }
+    __syncthreads();
+    // ACC_0 = 0, ACC_1 = X^{-b} v (coefficient j: +1/8 if (j + b) mod 2N < N)
+    const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
+    for (int j = threadIdx.x; j < RING_N; j += 512)
+      s_acc[j] = c == 0 ? 0u : ((((uint32_t)j + bbar) & 2047u) < 1024u ? 0x20000000u : 0xE0000000u);
+    __syncthreads();
+
+    const gmem_u64* bsk = as_global(bsk_tab[J.key]);
+    const int nsteps = steps < n_lwe ? steps : n_lwe;
+    const int lw = lvl ? wave : 0;  // waves 6 and 7 have no exchange slot (and use none)
+    // this wave's half of its level's 1024 values: [half][slot][lane]
+    uint64_t* my_x = xbuf + ((size_t)(job * 2 + c) * 6 + lj) * RING_N + lk * 512;
+    const uint64_t* peer_x = xbuf + ((size_t)(job * 2 + (1 - c)) * 6 + lj) * RING_N + lk * 512;
+    uint32_t* my_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + lw;
+    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + lw;
+    const int sh = 25 - 7 * lj;
+    // NTT-domain offset of slot s after pass 2: row 16 lk + r4, position 4 s + hq
+    auto key_off = [&](int s) { return 128 * s + 64 * (hq >> 1) + 2 * col + (hq & 1); };
+    uint32_t done = 0;  // executed steps, the same count in both roles
+    bool stalled = false;
+    PhaseClock<PROF> pc;
+
+    for (int i = 0; i < nsteps; ++i) {
+      const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
+      if (a == 0) continue;  // X^0 ACC - ACC = 0: no digits, no exchange
+      pc.start();
+
+      // key rows (c, j) and (1-c, j), component c, at this lane's offsets
+      const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
+      const gmem_u64* ko = step_key + (size_t)((c * 3 + lj) * 2 + c) * RING_N;
+      const gmem_u64* kt = step_key + (size_t)(((1 - c) * 3 + lj) * 2 + c) * RING_N;
+      uint64_t kown[8], koth[8];
+      uint64_t f[8];
+      if (lvl) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          kown[s] = ko[key_off(s)];
+          koth[s] = kt[key_off(s)];
+        }
+        int32_t dg[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const uint32_t j = (uint32_t)(col + 32 * (4 * s + hq));
+          const uint32_t e = (j - a) & 2047u;
+          const uint32_t v = s_acc[e & 1023u];
+          const uint32_t D = ((e & 1024u) ? (0u - v) : v) - s_acc[j];
+          dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+        }
+        fwd128_p1_digits(dg, f);
+        fwd128_p1_rest(f, fu1, fu2, fu2);
+        // twist by psi^((2 ka + 1) j1) for position q = 4 s + hq (ka slot) of
+        // column j1, then to the level's transpose block, element (q, j1)
+        const gmem_u64* tw = as_global(opaque(tw_f)) + hq * 32 + col;
+        uint64_t w[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) w[s] = tw[s * 128];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) s_fwd[lj][(4 * s + hq) * T128_ROW + col] = gl_mul(f[s], w[s]);
+      }
+      pc.template mark<0>();
+      __syncthreads();  // both halves of every level are in their transpose blocks; every wave has read ACC_c
+      pc.template mark<1>();
+      if (lvl) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) f[s] = s_fwd[lj][col * T128_ROW + 4 * s + hq];
+        fwd128_p2(f, fu1, fu2, fu2);
+        pc.template mark<2>();
+
+        const size_t par = (size_t)(done & 1u) * 3 * RING_N;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
+        // this component's products while the stores drain and the partner's
+        // half is on its way (the empty asm keeps them ahead of the wait)
+        uint64_t plo[8], phi[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          gl_mul_wide(f[s], kown[s], plo[s], phi[s]);
+          asm volatile("" : "+v"(plo[s]), "+v"(phi[s]));
+        }
+        pc.template mark<3>();
+        vm_wait_all();
+        pc.template mark<4>();
+        if (lane == 0) store_agent(my_flag, done + 1);
+        if (!stalled) {
+          int it = 0;
+          while (load_agent(peer_flag) < done + 1) {
+            if (++it >= spin_limit) break;
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (it >= spin_limit) {
+            stalled = true;
+            if (lane == 0) {
+              atomicAdd(&g_split_stalls, 1u);
+              atomicAdd(sync + SPLIT_STATUS, 1u);
+              store_agent(marks + job, 1u);
+            }
+          }
+        }
+        pc.template mark<5>();
+        vm_wait_all();
+        uint64_t g[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) s_part[lj][key_off(s)] = gl_mul_sum_wide(plo[s], phi[s], g[s], koth[s]);
+        pc.template mark<6>();
+      }
+      __syncthreads();
+      pc.template mark<7>();
+
+      // one inverse of the three levels' sum on waves 0-3: each holds eight
+      // rows at eight lanes per row (the NTT-domain offset of position q of
+      // row k is 64 (q >> 1) + 2 k + (q & 1))
+      uint64_t v[4];
+      if (inv) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int off = 256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1);
+          v[s] = gl_add(gl_add(s_part[0][off], s_part[1][off]), s_part[2][off]);
+        }
+        inv256_p2(v, upper1, upper2, upper4, w2);
+        {
+          const gmem_u64* tt = as_global(opaque(tw_i)) + h8 * 32 + row;
+          uint64_t w[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) w[s] = tt[s * 256];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], w[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) s_t128[row * T128_ROW + 8 * s + h8] = v[s];
+      }
+      pc.template mark<8>();
+      __syncthreads();
+      pc.template mark<9>();
+      if (inv) {
+        // column j1 = row of this lane, positions q = 8 s + h8
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = s_t128[(8 * s + h8) * T128_ROW + row];
+        inv256_p1(v, upper1, upper2, upper4, w1);
+        // the sum is an exact integer polynomial (|coefficient| < 2^50.6),
+        // so its centred lift reduced mod 2^32 is exact
+#pragma unroll
+        for (int s = 0; s < 4; ++s) s_acc[row + 32 * (8 * s + h8)] += gl_lift_u32(v[s]);
+      }
+      pc.template mark<10>();
+      ++done;
+      __syncthreads();
+      pc.template mark<11>();
+    }
+    pc.store(prof ? prof + ((size_t)blockIdx.x * 8 + wave) * kSplitPhaseWords : nullptr, lane, done, xcc_id());
+
+    if (raw_acc) {
+      uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
+      for (int j = threadIdx.x; j < RING_N; j += 512) o[j] = s_acc[j];
+    } else {
+      // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
+      uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
+      if (c == 0) {
+        for (int j = threadIdx.x; j < RING_N; j += 512) {
+          if (j == 0) o[0] = s_acc[0];
+          else o[RING_N - j] = 0u - s_acc[j];
+        }
+      } else if (threadIdx.x == 0) {
+        o[RING_N] = s_acc[0];
+      }
+    }
+  }
+
+  // the last workgroup to finish clears the tickets and flags for the next
+  // launch on this area (every other one has finished using them)
+  vm_wait_all();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(sync + SPLIT_DONE, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (s_last) {
+    const int nflags = (int)(gridDim.x / 2) * SPLIT_FLAGS_PER_JOB;
+    for (int k = threadIdx.x; k < nflags; k += 512) store_agent(sync + SPLIT_FLAGS + k, 0u);
     if (threadIdx.x <= SPLIT_DONE) store_agent(sync + threadIdx.x, 0u);  // the 8 class counters and the finish count
   }
 }
@@ -1114,17 +1482,41 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       hipLaunchKernelGGL(blind_rotate_kernel<5>, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
-    case 6: {
+    case 6:
+    case 7: {
       if (!split || !split->xbuf || !split->sync || njobs > split->max_jobs) return hipErrorInvalidValue;
       const int grid = 16 * ((njobs + 7) / 8);
-      hipLaunchKernelGGL(blind_rotate_split_kernel, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
-                         d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
-                         split->sync + split_marks_offset(split->max_jobs), split_spin_limit());
+      if (waves_per_job == 6)
+        hipLaunchKernelGGL(blind_rotate_split_kernel<false>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
+                           d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
+                           split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), nullptr);
+      else
+        hipLaunchKernelGGL(blind_rotate_split8_kernel<false>, dim3(grid), dim3(512), 0, s, d_jobs, njobs, src, d_ex,
+                           d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
+                           split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), nullptr);
       break;
     }
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_split_profiled(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
+                                 const uint64_t* const* d_bsk_tab, int n_lwe, int steps, Twiddles tw,
+                                 int waves_per_job, const SplitArea* split, uint64_t* d_prof, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  if (!is_split(waves_per_job) || !split || !split->xbuf || !split->sync || njobs > split->max_jobs || !d_prof)
+    return hipErrorInvalidValue;
+  const int grid = 16 * ((njobs + 7) / 8);
+  if (waves_per_job == 6)
+    hipLaunchKernelGGL(blind_rotate_split_kernel<true>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
+                       d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
+                       split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), d_prof);
+  else
+    hipLaunchKernelGGL(blind_rotate_split8_kernel<true>, dim3(grid), dim3(512), 0, s, d_jobs, njobs, src, d_ex,
+                       d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
+                       split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), d_prof);
   return hipGetLastError();
 }
 
@@ -1139,8 +1531,10 @@ int split_spin_limit() {
   return x > 0 && x < SPLIT_SPIN_LIMIT ? (int)x : SPLIT_SPIN_LIMIT;
 }
 size_t split_xbuf_bytes(int max_jobs) { return (size_t)split_jobs_padded(max_jobs) * 12 * RING_N * 8; }
-// sync area: 64 control words, 8 flag words per job, then one give-up mark per job
-static size_t split_marks_offset(int max_jobs) { return (size_t)SPLIT_FLAGS + split_jobs_padded(max_jobs) * 8; }
+// sync area: 64 control words, 16 flag words per job, then one give-up mark per job
+static size_t split_marks_offset(int max_jobs) {
+  return (size_t)SPLIT_FLAGS + (size_t)split_jobs_padded(max_jobs) * SPLIT_FLAGS_PER_JOB;
+}
 size_t split_sync_bytes(int max_jobs) {
   return (split_marks_offset(max_jobs) + split_jobs_padded(max_jobs)) * 4;
 }

@@ -700,7 +700,7 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
     if (!direct) ex = pre->ex;
     br = pre->br;
     ks = pre->ks;
-    if (waves == 6) {
+    if (lp::is_split(waves)) {
       split = pre->split;
       // the control words start at zero whatever an earlier call left
       LP_HIP_TRY(lp::launch_clear_words(split.sync, lp::split_sync_bytes(split.max_jobs) / 4, s));
@@ -719,7 +719,7 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   lp::DstBases dst{};
   dst.p[0] = d_out;
   // stream-ordered, freed below (the static scratch's area is kept)
-  if (e == hipSuccess && waves == 6 && !pre) e = lp::split_area_alloc_async(&split, (int)nbr, s);
+  if (e == hipSuccess && lp::is_split(waves) && !pre) e = lp::split_area_alloc_async(&split, (int)nbr, s);
   if (e == hipSuccess) {
     ProfScope ps(kProfBR, nbr, waves, s);
     e = lp::launch_blind_rotate(br, (int)nbr, src, ex, dk->bsk_tab, nullptr, (int)n, (int)n, 0, dk->tw, waves, s,
@@ -736,7 +736,7 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   }
   // split rotations: wait for the batch and read the area's give-up record
   uint32_t stalls = 0;
-  if (e == hipSuccess && waves == 6) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
+  if (e == hipSuccess && lp::is_split(waves)) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
   hipError_t e2 = hipSuccess;
   if (!pre) {
     e2 = hipFreeAsync(scratch, s);
@@ -857,6 +857,75 @@ extern "C" lp_status lp_debug_field_op_rates(double target_ms, double* rates, do
   return LP_OK;
 }
 
+extern "C" lp_status lp_debug_split_profile(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, int waves,
+                                           double* cycles, double* ms, double* local_share, void* stream) {
+  if (!dk || !d_in || !cycles) return fail(LP_EINVAL, "lp_debug_split_profile: null argument");
+  if (cnt == 0 || cnt > (size_t)lp::kSplitMaxJobs)
+    return fail(LP_EINVAL, "lp_debug_split_profile: 1..%d rotations", lp::kSplitMaxJobs);
+  if (!lp::is_split(waves)) return fail(LP_EINVAL, "lp_debug_split_profile: waves must be 6 or 7");
+  ScopedDevice sd(dk->device);
+  hipStream_t s = as_stream(stream);
+  const int N = (int)dk->P.N, wpw = waves == 6 ? 4 : 8;
+  const int grid = 16 * (((int)cnt + 7) / 8);
+  const size_t pwords = (size_t)grid * wpw * lp::kSplitPhaseWords;
+  std::vector<BrJob> jobs(cnt);
+  for (size_t k = 0; k < cnt; ++k)
+    jobs[k] = BrJob{lp::make_ref(0, (uint32_t)k), lp::REF_NONE, 1, 0, 0u, (uint32_t)k, 0u, 0u};
+  BrJob* dj = nullptr;
+  uint32_t* dacc = nullptr;
+  uint64_t* dprof = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  LP_HIP_TRY(hipMallocAsync((void**)&dj, cnt * sizeof(BrJob), s));
+  hipError_t e = hipMallocAsync((void**)&dacc, cnt * 2 * N * 4, s);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&dprof, pwords * 8, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dj, jobs.data(), cnt * sizeof(BrJob), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = lp::launch_clear_words(reinterpret_cast<uint32_t*>(dprof), pwords * 2, s);
+  lp::SplitArea split;
+  if (e == hipSuccess) e = lp::split_area_alloc_async(&split, (int)cnt, s);
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  lp::SrcBases src{};
+  src.p[0] = d_in;
+  if (e == hipSuccess) e = hipEventRecord(t0, s);
+  if (e == hipSuccess)
+    e = lp::launch_split_profiled(dj, (int)cnt, src, dacc, dk->bsk_tab, (int)dk->P.n, (int)dk->P.n, dk->tw, waves,
+                                  &split, dprof, s);
+  if (e == hipSuccess) e = hipEventRecord(t1, s);
+  std::vector<uint64_t> prof(pwords);
+  if (e == hipSuccess) e = hipMemcpyAsync(prof.data(), dprof, pwords * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, t0, t1);
+  uint32_t stalls = 0;
+  if (e == hipSuccess) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)lp::split_area_free_async(&split, s);
+  (void)hipFreeAsync(dprof, s);
+  (void)hipFreeAsync(dacc, s);
+  (void)hipFreeAsync(dj, s);
+  if (e != hipSuccess) return fail(LP_EDEVICE, "lp_debug_split_profile: %s", hipGetErrorString(e));
+  if (stalls) return lp::split_stall_error("lp_debug_split_profile", stalls);
+  constexpr int P = lp::kSplitPhaseWords - 2;
+  int busy = 0, local = 0;
+  for (int w = 0; w < wpw; ++w) {
+    double steps = 0.0, sum[P] = {};
+    for (int b = 0; b < grid; ++b) {
+      const uint64_t* r = prof.data() + ((size_t)b * wpw + w) * lp::kSplitPhaseWords;
+      steps += (double)r[P];
+      for (int k = 0; k < P; ++k) sum[k] += (double)r[k];
+      if (w == 0 && r[P] > 0) {
+        ++busy;
+        local += (r[P + 1] & 16u) ? 1 : 0;
+      }
+    }
+    for (int k = 0; k < P; ++k) cycles[w * P + k] = steps > 0 ? sum[k] / steps : 0.0;
+  }
+  if (ms) *ms = f;
+  if (local_share) *local_share = busy ? (double)local / busy : 0.0;
+  return LP_OK;
+}
+
 extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, uint32_t steps,
                                            uint32_t* d_acc, void* stream) {
   if (!dk) return fail(LP_EINVAL, "lp_debug_blind_rotate: null key");
@@ -876,13 +945,13 @@ extern "C" lp_status lp_debug_blind_rotate(const lp_device_key* dk, const uint32
   const int st = (int)std::min<uint32_t>(steps, dk->P.n);
   const int waves = pick_br_wpb(cnt);
   lp::SplitArea split;
-  if (e == hipSuccess && waves == 6) e = lp::split_area_alloc_async(&split, (int)cnt, s);
+  if (e == hipSuccess && lp::is_split(waves)) e = lp::split_area_alloc_async(&split, (int)cnt, s);
   if (e == hipSuccess)
     e = lp::launch_blind_rotate(dj, (int)cnt, src, d_acc, dk->bsk_tab, nullptr, (int)dk->P.n, st, 1, dk->tw, waves, s,
                                 &split);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   uint32_t stalls = 0;
-  if (e == hipSuccess && waves == 6) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
+  if (e == hipSuccess && lp::is_split(waves)) e = lp::split_area_take_stalls(&split, s, &stalls, nullptr);
   hipError_t e2 = hipFreeAsync(dj, s);
   const hipError_t e3 = lp::split_area_free_async(&split, s);
   if (e2 == hipSuccess) e2 = e3;

@@ -277,7 +277,7 @@ bool choose_xnor_early(const std::vector<std::tuple<uint32_t, uint32_t, uint32_t
   if (shapes.size() != 1) return false;
   const uint32_t l = std::get<0>(shapes[0]);
   const size_t comparators = 4 * (size_t)std::get<1>(shapes[0]);
-  return l >= 2 && pick_br_wpb(2 * comparators) == 6 && pick_br_wpb(3 * comparators) != 6;
+  return l >= 2 && is_split(pick_br_wpb(2 * comparators)) && !is_split(pick_br_wpb(3 * comparators));
 }
 
 namespace {
@@ -428,7 +428,7 @@ lp_status build_program(const std::vector<const lp_device_key*>& keys,
   LP_HIP_TRY(hipMemcpy(G->d_out_refs, out_refs.data(), out_refs.size() * 4, hipMemcpyHostToDevice));
   int split_jobs = 0;
   for (int L = 0; L < depth; ++L)
-    if (G->br_waves[L] == 6) split_jobs = std::max(split_jobs, G->br_cnt[L]);
+    if (is_split(G->br_waves[L])) split_jobs = std::max(split_jobs, G->br_cnt[L]);
   if (split_jobs > 0) LP_HIP_TRY(split_area_alloc(&G->split, split_jobs));
   *out = G;
   return LP_OK;

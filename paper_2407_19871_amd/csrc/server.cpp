@@ -310,7 +310,7 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, c
   lp::DstBases dst{};
   const lp::Twiddles tw = act[0]->dk->tw;
   const int waves = lp::pick_br_wpb(br.size());
-  if (e == hipSuccess && waves == 6 && S->split.max_jobs < (int)br.size()) {
+  if (e == hipSuccess && lp::is_split(waves) && S->split.max_jobs < (int)br.size()) {
     // ticks run one at a time, so the previous area is idle once the stream is
     e = hipStreamSynchronize(S->stream);
     if (e == hipSuccess) {
@@ -332,7 +332,7 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, c
   // the host job arrays must outlive every copy queued above, also on failure
   const hipError_t es = hipStreamSynchronize(S->stream);
   if (e == hipSuccess) e = es;
-  if (e == hipSuccess && waves == 6) {
+  if (e == hipSuccess && lp::is_split(waves)) {
     // split waits that ran out: only the requests owning those jobs fail
     uint32_t n_stalls = 0;
     std::vector<int> jobs;

@@ -28,7 +28,7 @@ std::map<int, std::vector<lp_tune_entry>> g_tune;  // device -> rows sorted by j
 
 constexpr uint32_t kMaxTuneJobs = 1u << 22;      // row bound
 constexpr uint32_t kMaxTuneBucket = 1u << 16;    // batch size the autotuner times
-const int kWaves[] = {1, 2, 3, 4, 5, 6};
+const int kWaves[] = {1, 2, 3, 4, 5, 6, 7};
 constexpr int kNumWaves = sizeof(kWaves) / sizeof(kWaves[0]);
 const int kTiles[] = {1, 4, 8, 16};
 const int kSplits[] = {1, 2, 4, 8, 16};
@@ -123,7 +123,7 @@ int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
 // A split shape (6) applies up to kSplitMaxJobs jobs; a wider launch that
 // looks it up (the table's last row, or a forced shape) takes 3 instead.
 int pick_br_wpb(size_t njobs) {
-  auto fit = [&](int w) { return w == 6 && njobs > (size_t)kSplitMaxJobs ? 3 : w; };
+  auto fit = [&](int w) { return is_split(w) && njobs > (size_t)kSplitMaxJobs ? 3 : w; };
   const int forced = env_int("LOCPIR_BR_WAVES", 0);
   if (one_of(forced, kWaves, kNumWaves)) return fit(forced);
   lp_tune_entry r;
@@ -285,7 +285,7 @@ extern "C" lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket
     r.jobs = jobs;
     float best = -1.f;
     for (int W : lp::kWaves) {
-      if (W == 6 && jobs > (uint32_t)lp::kSplitMaxJobs) continue;
+      if (lp::is_split(W) && jobs > (uint32_t)lp::kSplitMaxJobs) continue;
       float ms = 0.f;
       lp_status st = time(
           [&] {

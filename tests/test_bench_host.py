@@ -42,7 +42,7 @@ def test_rotation_launches_by_shape():
     want = (2 * (10 * 48 + 11 * 384) / 1024 + 2 * 10 * 1.0) / 62.0
     assert busy == pytest.approx(want)
     assert bench.SHAPE_KERNEL[6] == "blind_rotate_split_kernel"
-    assert set(bench.SHAPE_KERNEL) == {1, 2, 3, 4, 5, 6}  # every shape the library launches
+    assert set(bench.SHAPE_KERNEL) == {1, 2, 3, 4, 5, 6, 7}  # every shape the library launches
 
 
 def test_missing_key_switch_record_keeps_levels_aligned():

@@ -1,8 +1,11 @@
-"""Split blind rotation (br_waves 6: one bootstrap on two workgroups, each
-owning one accumulator component, trading forward transforms every step):
-bit-exact against the oracle for the accumulator after all n steps, for
-gates at one, ragged and maximal launch widths, and for whole queries whose
-narrow levels run split, with the exchange area reused launch after launch."""
+"""Split blind rotation (br_waves 6: one bootstrap on two workgroups of four
+waves, each owning one accumulator component, trading forward transforms
+every step; br_waves 7: the same on eight waves per workgroup, each gadget
+level's forward transform on two waves): bit-exact against the oracle for
+the accumulator after all n steps, for gates at one, ragged and maximal
+launch widths, and for whole queries whose narrow levels run split, with the
+exchange area reused launch after launch; a forced give-up fails the call
+that launched it, for both shapes."""
 import numpy as np
 import pytest
 
@@ -31,18 +34,24 @@ def stalls_before(dkey):
     return lp.split_stall_count()
 
 
+@pytest.fixture(params=[6, 7])
+def split_w(request):
+    """The split shape under test: four or eight waves per workgroup."""
+    return request.param
+
+
 @pytest.fixture
-def split_table():
+def split_table(split_w):
     """Split rotations up to 128 jobs, one gadget level per wave above."""
     old = lp.tune_table()
-    lp.set_tune_table([{"jobs": SPLIT_MAX, "br_waves": 6, "ks_tile": 4, "ks_split": 8},
+    lp.set_tune_table([{"jobs": SPLIT_MAX, "br_waves": split_w, "ks_tile": 4, "ks_split": 8},
                        {"jobs": 1 << 22, "br_waves": 3, "ks_tile": 8, "ks_split": 8}])
     yield
     lp.set_tune_table(old)
 
 
-def test_accumulator_after_all_steps(monkeypatch, okeys, octx, dkey):
-    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+def test_accumulator_after_all_steps(monkeypatch, okeys, octx, dkey, split_w):
+    monkeypatch.setenv("LOCPIR_BR_WAVES", str(split_w))
     ct = O.encrypt_bits(okeys, [1, 0, 1], seed=91)
     acc = as_u32(lp.debug_blind_rotate(dkey, lp.to_device(ct), 630))
     for k in range(3):
@@ -50,10 +59,10 @@ def test_accumulator_after_all_steps(monkeypatch, okeys, octx, dkey):
 
 
 @pytest.mark.parametrize("cnt", [1, 13, 120])
-def test_gates_at_launch_widths(monkeypatch, okeys, octx, dkey, cnt):
+def test_gates_at_launch_widths(monkeypatch, okeys, octx, dkey, split_w, cnt):
     """One pair; a ragged block (idle pairs in the last block of 16
     tickets); nearly the widest launch."""
-    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+    monkeypatch.setenv("LOCPIR_BR_WAVES", str(split_w))
     a, b = W.random_bits(200 + cnt, cnt), W.random_bits(300 + cnt, cnt)
     c1 = O.encrypt_bits(okeys, a, seed=400 + cnt)
     c2 = O.encrypt_bits(okeys, b, seed=500 + cnt)
@@ -64,9 +73,9 @@ def test_gates_at_launch_widths(monkeypatch, okeys, octx, dkey, cnt):
     assert (d == (1 - (a ^ b))).all()
 
 
-def test_mux_at_widest_split_launch(monkeypatch, okeys, octx, dkey):
+def test_mux_at_widest_split_launch(monkeypatch, okeys, octx, dkey, split_w):
     """64 MUX gates are 128 rotations, the widest split launch."""
-    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
+    monkeypatch.setenv("LOCPIR_BR_WAVES", str(split_w))
     cnt = SPLIT_MAX // 2
     s, t, f = (W.random_bits(600 + k, cnt) for k in range(3))
     cts = [O.encrypt_bits(okeys, v, seed=700 + k) for k, v in enumerate((s, t, f))]
@@ -75,11 +84,11 @@ def test_mux_at_widest_split_launch(monkeypatch, okeys, octx, dkey):
     assert (got == exp).all()
 
 
-def test_wider_launch_falls_back(monkeypatch, okeys, octx, dkey):
+def test_wider_launch_falls_back(monkeypatch, okeys, octx, dkey, split_w):
     """A forced split shape on more than 128 rotations runs one gadget level
     per wave instead (and is still exact)."""
-    monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
-    assert lp.tune_pick(SPLIT_MAX)["br_waves"] == 6
+    monkeypatch.setenv("LOCPIR_BR_WAVES", str(split_w))
+    assert lp.tune_pick(SPLIT_MAX)["br_waves"] == split_w
     assert lp.tune_pick(SPLIT_MAX + 1)["br_waves"] == 3
     cnt = SPLIT_MAX + 3
     a, b = W.random_bits(801, cnt), W.random_bits(802, cnt)
@@ -103,7 +112,7 @@ def _query_parts(okeys, q, seed):
 
 
 @pytest.mark.parametrize("graphs", ["1", "0"])
-def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_table, graphs):
+def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_w, split_table, graphs):
     """An 8-bit one-box query (12 levels, every one at most 32 rotations
     wide, so all of them split), run twice: the exchange area is reused by
     every level and every replay."""
@@ -121,7 +130,7 @@ def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_table, gr
         recs = lp.profile_collect_launches()
     finally:
         lp.profile_enable(False)
-    assert {r["shape"] for r in recs if r["name"] == "blind_rotate"} == {6}
+    assert {r["shape"] for r in recs if r["name"] == "blind_rotate"} == {split_w}
     d, _ = O.decrypt_bits(okeys, res)
     assert W.from_bits(d) == plain.predicate(q.x, q.y, q.boxes, q.payloads, l, m, False)
 
