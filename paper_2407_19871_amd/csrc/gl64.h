@@ -125,6 +125,23 @@ GL_INLINE uint64_t gl_mul_sum(uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
   return gl_mul_sum_wide(l1, h1, c, d);
 }
 
+// a b + c d + e f mod p with one reduction.  The three 128-bit products sum
+// below 3 2^128: each high word is at most 2^64 - 2, so a low-word carry
+// fits in it, and at most two carries leave bit 127, each standing for
+// 2^128 = -2^32.
+GL_INLINE uint64_t gl_mul_sum3(uint64_t a, uint64_t b, uint64_t c, uint64_t d, uint64_t e, uint64_t f) {
+  uint64_t l1, h1, l2, h2, l3, h3, lo, t, hi;
+  gl_mul_wide(a, b, l1, h1);
+  gl_mul_wide(c, d, l2, h2);
+  gl_mul_wide(e, f, l3, h3);
+  const bool c1 = __builtin_add_overflow(l1, l2, &lo);
+  const bool c2 = __builtin_add_overflow(lo, l3, &lo);
+  const bool o1 = __builtin_add_overflow(h1, h2 + (c1 ? 1ull : 0ull), &t);
+  const bool o2 = __builtin_add_overflow(t, h3 + (c2 ? 1ull : 0ull), &hi);
+  const uint64_t top = (uint64_t)o1 + (uint64_t)o2;
+  return gl_sub_r(gl_reduce128(lo, hi), top << 32);
+}
+
 // acc + a b mod p with one reduction: a product of two 64-bit values has
 // a high word of at most 2^64 - 2, so the carry of adding acc to the low
 // word fits in it.

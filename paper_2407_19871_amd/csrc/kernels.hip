@@ -712,28 +712,32 @@ __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
 }
 
 // Accesses of an exchange between two workgroups on one XCD, through that
-// XCD's L2 (the coherence point of its CUs): stores write through to L2,
-// loads carry sc0 so that they miss the reading CU's L1.  Buffer resources
-// (raw, no stride) over the exchange slots and the sync words; the aux bit
-// 31 marks the accesses volatile, so polls stay in their loop.
+// XCD's L2 (the coherence point of its CUs): stores write through to L2;
+// loads carry sc1 (device scope), so that they miss the reading CU's L1 and
+// are served by the L2.  Buffer resources (raw, no stride) over the
+// exchange slots and the sync words.  No access is volatile: the compiler
+// would complete each volatile access before the next one (and widen it to
+// system scope).  Order comes from an explicit wait for the data stores
+// before the flag store, a compiler memory barrier in every poll iteration
+// (so the flag is read anew) and one after the poll.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t l2_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
 }
-constexpr int kL2Load = (int)0x80000001u;  // volatile, sc0
-constexpr int kL2Store = (int)0x80000000u;  // volatile
+constexpr int kL2Load = 0x10;  // sc1
 __device__ __forceinline__ void st_l2(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t v) {
   const u32x2 x = {(uint32_t)v, (uint32_t)(v >> 32)};
-  __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, kL2Store);
+  __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
 }
 __device__ __forceinline__ uint64_t ld_l2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kL2Load);
   return ((uint64_t)x.y << 32) | x.x;
 }
 __device__ __forceinline__ void st_l2_u32(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v) {
-  __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, kL2Store);
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
 }
 __device__ __forceinline__ uint32_t ld_l2_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  asm volatile("" ::: "memory");
   return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kL2Load);
 }
 // The XCD this wave runs on.
@@ -843,11 +847,12 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
 
     const gmem_u64* bsk = as_global(bsk_tab[J.key]);
     const int nsteps = steps < n_lwe ? steps : n_lwe;
-    const int lw = lvl ? wave : 0;  // wave 3 has no exchange slot (and uses none)
-    uint64_t* my_x = xbuf + ((size_t)(job * 2 + c) * 6 + lw) * RING_N;
-    const uint64_t* peer_x = xbuf + ((size_t)(job * 2 + (1 - c)) * 6 + lw) * RING_N;
-    uint32_t* my_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + lw;
-    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + lw;
+    // wave w trades with the partner's wave w: the partner's component of the
+    // key products at the NTT-domain offsets both waves' inverses read
+    uint64_t* my_x = xbuf + (size_t)(job * 2 + c) * 6 * RING_N;
+    const uint64_t* peer_x = xbuf + (size_t)(job * 2 + (1 - c)) * 6 * RING_N;
+    uint32_t* my_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + wave;
+    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + wave;
     const int sh = 25 - 7 * wave;
     uint32_t done = 0;  // executed steps, the same count in both roles
     bool stalled = false;
@@ -855,7 +860,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     // Both halves on one XCD (the normal placement of the class pairing)
     // trade through that XCD's L2; otherwise past it, as agent-scope
     // accesses.  The halves learn it from each other's XCD id, published in
-    // their pair's spare flag word (bounded wait as for the transforms).
+    // their pair's spare flag word (bounded wait as for the products).
     const uint32_t my_xcc = xcc_id();
     if (threadIdx.x == 0) {
       store_agent(sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + 7, my_xcc + 1);
@@ -870,24 +875,30 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const __amdgpu_buffer_rsrc_t fr = l2_rsrc(sync, (SPLIT_FLAGS + (gridDim.x / 2) * SPLIT_FLAGS_PER_JOB) * 4u);
     const uint32_t my_xo = (uint32_t)(my_x - xbuf) * 8u, peer_xo = (uint32_t)(peer_x - xbuf) * 8u;
     const uint32_t my_fo = (uint32_t)(my_flag - sync) * 4u, peer_fo = (uint32_t)(peer_flag - sync) * 4u;
+    // this lane's four inverse positions (row `row`, q = 8 s + h8) and their
+    // NTT-domain offsets 64 (q >> 1) + 2 row + (q & 1)
+    int off[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) off[s] = 256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1);
 
     for (int i = 0; i < nsteps; ++i) {
       const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
       if (a == 0) continue;  // X^0 ACC - ACC = 0: no digits, no exchange
       pc.start();
 
-      // key rows (c, j) and (1-c, j), component c, at this lane's offsets
+      // the step's key rows (c, j), both components, at this lane's offsets:
+      // component c for this half's sum, 1 - c for the partner's
       const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
-      const gmem_u64* ko = step_key + (size_t)((c * 3 + lw) * 2 + c) * RING_N + 2 * l + h;
-      const gmem_u64* kt = step_key + (size_t)(((1 - c) * 3 + lw) * 2 + c) * RING_N + 2 * l + h;
-      uint64_t kown[16], koth[16];
+      uint64_t kc[3][4], ko[3][4];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          kc[j][s] = step_key[(size_t)((c * 3 + j) * 2 + c) * RING_N + off[s]];
+          ko[j][s] = step_key[(size_t)((c * 3 + j) * 2 + (1 - c)) * RING_N + off[s]];
+        }
       int32_t dg[16];
       if (lvl) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          kown[s] = ko[s * 64];
-          koth[s] = kt[s * 64];
-        }
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const uint32_t j = (uint32_t)(l + 32 * (2 * s + h));
@@ -908,74 +919,69 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
         for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
         transpose64(f, buf, h, l);
         fwd64_p2(f, lane);
-        pc.template mark<2>();
-
-        const size_t par = (size_t)(done & 1u) * 3 * RING_N;
-        if (local) {
 #pragma unroll
-          for (int s = 0; s < 16; ++s) st_l2(xr, my_xo + (uint32_t)(par + s * 64 + lane) * 8u, f[s]);
-        } else {
-#pragma unroll
-          for (int s = 0; s < 16; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
-        }
-        // this component's products while the stores drain and the partner's
-        // transform is on its way (the empty asm keeps them ahead of the wait)
-        uint64_t plo[16], phi[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          gl_mul_wide(f[s], kown[s], plo[s], phi[s]);
-          asm volatile("" : "+v"(plo[s]), "+v"(phi[s]));
-        }
-        pc.template mark<3>();
-        vm_wait_all();
-        pc.template mark<4>();
-        if (lane == 0) {
-          if (local) st_l2_u32(fr, my_fo, done + 1);
-          else store_agent(my_flag, done + 1);
-        }
-        if (!stalled) {
-          int it = 0;
-          while ((local ? ld_l2_u32(fr, peer_fo) : load_agent(peer_flag)) < done + 1) {
-            if (++it >= spin_limit) break;
-            __builtin_amdgcn_s_sleep(1);
-          }
-          if (it >= spin_limit) {
-            stalled = true;
-            if (lane == 0) {
-              atomicAdd(&g_split_stalls, 1u);
-              atomicAdd(sync + SPLIT_STATUS, 1u);
-              store_agent(marks + job, 1u);
-            }
-          }
-        }
-        pc.template mark<5>();
-        vm_wait_all();
-        uint64_t g[16];
-        if (local) {
-#pragma unroll
-          for (int s = 0; s < 16; ++s) g[s] = ld_l2(xr, peer_xo + (uint32_t)(par + s * 64 + lane) * 8u);
-        } else {
-#pragma unroll
-          for (int s = 0; s < 16; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
-        }
-#pragma unroll
-        for (int s = 0; s < 16; ++s)
-          s_part[wave][64 * s + 2 * l + h] = gl_mul_sum_wide(plo[s], phi[s], g[s], koth[s]);
-        pc.template mark<6>();
+        for (int s = 0; s < 16; ++s) s_part[wave][64 * s + 2 * l + h] = f[s];
       }
+      pc.template mark<2>();
       __syncthreads();
+      pc.template mark<3>();
+
+      // both components' products, summed over the levels with one reduction
+      uint64_t own[4], oth[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const uint64_t F0 = s_part[0][off[s]], F1 = s_part[1][off[s]], F2 = s_part[2][off[s]];
+        oth[s] = gl_mul_sum3(F0, ko[0][s], F1, ko[1][s], F2, ko[2][s]);
+        own[s] = gl_mul_sum3(F0, kc[0][s], F1, kc[1][s], F2, kc[2][s]);
+      }
+      const uint32_t par = (done & 1u) * RING_N;
+      const uint32_t slot = par + 64 * wave + lane;  // + 256 s
+      if (local) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) st_l2(xr, my_xo + (slot + 256 * s) * 8u, oth[s]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) store_agent(my_x + slot + 256 * s, oth[s]);
+      }
+      pc.template mark<4>();
+      vm_wait_all();
+      if (lane == 0) {
+        if (local) st_l2_u32(fr, my_fo, done + 1);
+        else store_agent(my_flag, done + 1);
+      }
+      pc.template mark<5>();
+      if (!stalled) {
+        int it = 0;
+        while ((local ? ld_l2_u32(fr, peer_fo) : load_agent(peer_flag)) < done + 1) {
+          if (++it >= spin_limit) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (it >= spin_limit) {
+          stalled = true;
+          if (lane == 0) {
+            atomicAdd(&g_split_stalls, 1u);
+            atomicAdd(sync + SPLIT_STATUS, 1u);
+            store_agent(marks + job, 1u);
+          }
+        }
+      }
+      asm volatile("" ::: "memory");  // the partner's products are read after its flag
+      pc.template mark<6>();
+      uint64_t v[4];
+      if (local) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = ld_l2(xr, peer_xo + (slot + 256 * s) * 8u);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = load_agent(peer_x + slot + 256 * s);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[s] = gl_add(own[s], v[s]);
       pc.template mark<7>();
 
-      // one inverse of the three levels' sum, on all four waves: each holds
-      // eight rows at eight lanes per row (the NTT-domain offset of position
-      // q of row k is 64 (q >> 1) + 2 k + (q & 1))
+      // one inverse of the sum on all four waves: each holds eight rows at
+      // eight lanes per row
       {
-        uint64_t v[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int off = 256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1);
-          v[s] = gl_add(gl_add(s_part[0][off], s_part[1][off]), s_part[2][off]);
-        }
         inv256_p2(v, upper1, upper2, upper4, w2);
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], s_twi[h8 * 32 + row + s * 256]);

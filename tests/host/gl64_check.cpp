@@ -107,6 +107,15 @@ int main() {
       expect_mod("gl_mul_sum", a, b, gl_mul_sum(a, b, c, d), want_ms);
       expect_mod("gl_mul_sum_wide", a, b, gl_mul_sum_wide(lo, hi, c, d), want_ms);
       expect_mod("gl_mac", a, b, gl_mac(c, a, b), modp((u128)modp(c) + modp((u128)modp(a) * modp(b))));
+      const uint64_t e = xs[(i * 5 + j * 17 + 3) % xs.size()], f = xs[(i * 13 + j * 7 + 2) % xs.size()];
+      expect_mod("gl_mul_sum3", a, b, gl_mul_sum3(a, b, c, d, e, f),
+                 modp((u128)want_ms + modp((u128)modp(e) * modp(f))));
+    }
+  // three maximal products carry twice out of bit 127
+  for (uint64_t a : std::vector<uint64_t>{0xFFFFFFFFFFFFFFFFull, 0xFFFFFFFFFFFFFFFEull, P, P - 1})
+    for (uint64_t b : std::vector<uint64_t>{0xFFFFFFFFFFFFFFFFull, 0xFFFFFFFFFFFFFFFEull, P + 1}) {
+      const uint64_t want = modp((u128)modp((u128)modp(a) * modp(b)) * 3);
+      expect_mod("gl_mul_sum3 (carries)", a, b, gl_mul_sum3(a, b, a, b, a, b), want);
     }
   for (uint64_t a : xs)
     for (size_t j = 0; j < red.size(); j += (j < edge.size() ? 1 : 7)) {
