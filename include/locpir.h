@@ -172,7 +172,7 @@ lp_status lp_bootstrap_batch(const lp_device_key* dk, lp_gate gate, const uint32
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same gates, kernels and outputs, but every working buffer
  * (job lists, the extracted samples, the split-rotation area) lives in the
- * library's static device scratch, a fixed array of 21 MiB that each GPU the
+ * library's static device scratch, a fixed array of 13 MiB that each GPU the
  * library runs on holds until the process ends.  The call allocates no
  * device memory and calls no allocating library routine.  cnt is at most
  * 1024 gates per call (LP_EINVAL above, nothing launched).  Every call on
@@ -423,25 +423,23 @@ lp_status lp_debug_external_product_mfma(const uint32_t* d_key_step, const uint3
 #define LP_OPRATE_COUNT 7
 lp_status lp_debug_field_op_rates(double target_ms, double* rates, double* ms, void* stream);
 
-/* Where a split blind rotation's time goes (br_waves 6 or 7): the blind
+/* Where a split blind rotation's time goes (br_waves 6): the blind
  * rotation of cnt (1..128) LWE_n samples d_in (device, cnt*(n+1) words) in
  * the shape's profiling build, which reads the shader clock at the phase
- * boundaries of every step.  cycles (host, 8 x 12 doubles) receives, per
- * wave index of a workgroup (4 or 8) and phase, the clock cycles per
- * executed step averaged over the launch's workgroups: [0] digits and key
- * requests (with pass 1 and the twist on eight waves), [1] the barrier after
- * them, [2] the forward transform (its pass 2 on eight waves), [3] storing
- * the transform and the own-component products, [4] the wait for every
- * outstanding memory access, [5] the flag and the wait for the partner's,
- * [6] loading the partner's transform and the products, [7] the barrier
- * after them, [8] the inverse's first pass and twist, [9] the barrier inside
- * the inverse, [10] its second pass and the accumulator update, [11] the
- * closing barrier.  ms (may be NULL) receives
- * the launch's duration; local_share (may be NULL) the share of the busy
- * workgroups whose pair traded through their XCD's L2 (both halves on one
- * XCD) rather than past it.  Synchronous; allocates its working memory. */
+ * boundaries of every step.  waves must be 6.  cycles (host, 4 x 12
+ * doubles) receives, per wave index of a workgroup and phase, the clock
+ * cycles per executed step averaged over the launch's workgroups: [0]
+ * digits and key requests, [1] the barrier after them, [2] the forward
+ * transform and its copy to LDS, [3] the barrier after it, [4] the
+ * partner component's key products and their stores, [5] the wait for
+ * those stores and the flag, [6] the wait for the partner's flag, [7]
+ * loading the partner's products, this half's own and the sum, [8] the inverse's first pass
+ * and twist, [9] the barrier inside the inverse, [10] its second pass and
+ * the accumulator update, [11] the closing barrier.  ms (may be NULL)
+ * receives the launch's duration.  Synchronous; allocates its working
+ * memory. */
 lp_status lp_debug_split_profile(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, int waves,
-                                 double* cycles, double* ms, double* local_share, void* stream);
+                                 double* cycles, double* ms, void* stream);
 
 /* ---- profiling ----------------------------------------------------------- */
 
@@ -504,12 +502,10 @@ lp_status lp_split_stall_count(uint32_t* count);
  *             inverted once on two waves; one rotation per CU), 5 (the
  *             same, sized for two rotations per CU) or 6 (the rotation split
  *             over two workgroups, normally two CUs, each owning one
- *             accumulator component and trading forward transforms with
- *             the other every step; lower latency again, for launches of at
- *             most 128 rotations -- a wider launch that looks up 6 runs 3)
- *             or 7 (the same split with eight waves per workgroup, each
- *             gadget level's forward transform on two waves; the same
- *             limit);
+ *             accumulator component and trading its key products for the
+ *             other component with the other every step; lower latency
+ *             again, for launches of at most 128 rotations -- a wider
+ *             launch that looks up 6 runs 3);
  *   ks_tile:  key switches per wave tile, 1, 4, 8 or 16;
  *   ks_split: ranges the ring index of a key switch is split into (partial
  *             sums added atomically), 1, 2, 4, 8 or 16;

@@ -131,7 +131,7 @@ def lib() -> C.CDLL:
         "lp_bootstrap_batch_noalloc": (i32, [vp, i32, vp, vp, vp, sz, vp, vp]),
         "lp_debug_field_op_rates": (i32, [C.c_double, vp, vp, vp]),
         "lp_debug_external_product_mfma": (i32, [vp, vp, sz, vp, vp]),
-        "lp_debug_split_profile": (i32, [vp, vp, sz, i32, vp, vp, vp, vp]),
+        "lp_debug_split_profile": (i32, [vp, vp, sz, i32, vp, vp, vp]),
         "lp_keyswitch_batch": (i32, [vp, vp, sz, vp, vp]),
         "lp_eval_bbox_query": (i32, [vp, C.POINTER(BBoxQuery), vp, vp]),
         "lp_eval_bbox_batch": (i32, [C.POINTER(vp), C.POINTER(BBoxQuery), sz, C.POINTER(vp), vp]),
@@ -501,21 +501,20 @@ def debug_external_product_mfma(key_step, d, out=None, stream=None):
     return out
 
 
-SPLIT_PHASES = ("digits", "barrier_a", "forward", "store_products", "drain", "flag_wait", "fetch_products",
-                "barrier_b", "inverse_1", "barrier_inv", "inverse_2", "barrier_c")
+SPLIT_PHASES = ("digits", "barrier_a", "forward", "barrier_f", "partner_products", "drain_flag", "wait_partner",
+                "fetch_own_sum", "inverse_1", "barrier_inv", "inverse_2", "barrier_c")
 
 
-def debug_split_profile(dk: DeviceKey, ct, waves: int, stream=None) -> dict:
+def debug_split_profile(dk: DeviceKey, ct, waves: int = 6, stream=None) -> dict:
     """Clock cycles per executed step of each phase, per wave index of a
     split workgroup (lp_debug_split_profile), and the launch time."""
-    cyc = (C.c_double * (8 * len(SPLIT_PHASES)))()
-    ms, local = C.c_double(), C.c_double()
-    _check(lib().lp_debug_split_profile(dk._h, _dev_ptr(ct), ct.shape[0], waves, cyc, C.byref(ms), C.byref(local),
+    cyc = (C.c_double * (4 * len(SPLIT_PHASES)))()
+    ms = C.c_double()
+    _check(lib().lp_debug_split_profile(dk._h, _dev_ptr(ct), ct.shape[0], waves, cyc, C.byref(ms),
                                         _stream_ptr(stream)))
-    wpw = 4 if waves == 6 else 8
-    return {"ms": float(ms.value), "l2_local_share": float(local.value),
+    return {"ms": float(ms.value),
             "waves": [{k: round(cyc[w * len(SPLIT_PHASES) + i], 1) for i, k in enumerate(SPLIT_PHASES)}
-                      for w in range(wpw)]}
+                      for w in range(4)]}
 
 
 def debug_blind_rotate(dk: DeviceKey, ct, steps: int, out=None, stream=None):

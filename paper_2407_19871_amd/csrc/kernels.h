@@ -21,18 +21,19 @@ struct Twiddles {
 hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, Twiddles tw,
                              hipStream_t s);
 
-// Split shapes: one bootstrap on two workgroups (4 waves each for 6, 8 for 7).
-inline bool is_split(int waves_per_job) { return waves_per_job == 6 || waves_per_job == 7; }
+// Split shape: one bootstrap on two workgroups of four waves.
+inline bool is_split(int waves_per_job) { return waves_per_job == 6; }
 
-// Exchange area of split blind rotations (waves_per_job = 6 or 7: one
-// bootstrap on two workgroups that trade their forward transforms every
-// step).  The
-// owner allocates it for at most max_jobs jobs per launch; the sync words
-// are zero before the first launch and every launch leaves them zero.  One
-// launch at a time may use an area.
+// Exchange area of split blind rotations (waves_per_job = 6: one bootstrap
+// on two workgroups, one per accumulator component, that trade their key
+// products for the other component every step).  The owner allocates it
+// for at most max_jobs jobs per launch; the sync words are zero before the
+// first launch, and every launch leaves its counters and XCD-id words zero
+// (the step flags are cleared by the launch that uses them, at its start).
+// One launch at a time may use an area.
 constexpr int kSplitMaxJobs = 128;
 struct SplitArea {
-  uint64_t* xbuf = nullptr;  // [job][role 2][step parity 2][level 3][1024] u64
+  uint64_t* xbuf = nullptr;  // [job][role 2][step parity 2][1024] u64
   uint32_t* sync = nullptr;  // 8 ticket counters, finish count, status; 16 flag words per job; give-up marks
   int max_jobs = 0;
 };
@@ -54,7 +55,7 @@ hipError_t launch_clear_words(uint32_t* d, size_t words, hipStream_t s);
 constexpr int kNoAllocMaxGates = 1024;
 constexpr int kNoAllocSplitJobs = kSplitMaxJobs;
 constexpr int RING_N_MAX = 1024;
-constexpr size_t kNoAllocScratchBytes = size_t(21) << 20;
+constexpr size_t kNoAllocScratchBytes = size_t(13) << 20;
 struct NoAllocScratch {
   SplitArea split;
   BrJob* br = nullptr;
@@ -82,8 +83,7 @@ hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* c
 // 4 (three level waves, the levels' NTT-domain sum inverted once per
 // component on two waves each; one bootstrap per CU), 5 (the same, two
 // bootstraps per CU), 6 (split over two workgroups of four waves; needs
-// `split` with room for njobs) or 7 (the same on eight waves per workgroup,
-// each level's forward transform on two).
+// `split` with room for njobs).
 // d_pool_tab (may be null) resolves operands with base KEY_POOL_BASE to the
 // pool of the job's key.
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
@@ -91,21 +91,19 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
                                int steps, int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
                                const SplitArea* split = nullptr);
 
-// The split rotation's profiling instantiation (waves_per_job 6 or 7, raw
+// The split rotation's profiling instantiation (waves_per_job 6, raw
 // accumulators into d_ex): every wave of every workgroup writes, at
-// d_prof + (block * waves per workgroup + wave) * kSplitPhaseWords, its
-// shader cycles in each of the kSplitPhaseWords - 2 phases of a step summed
-// over its executed steps, then that step count, then its XCD id plus 16
-// when the pair traded through that XCD's L2.  The phases: [0] digits and
-// key requests (eight waves: also pass 1 and the twist); [1] the barrier
-// after them; [2] the forward transform (eight waves: its pass 2); [3] the
-// stores of the transform and the own-component products; [4] the wait for
-// every outstanding memory access; [5] the flag and the wait for the
-// partner's; [6] loading the partner's transform and the products; [7] the
-// barrier after them; [8] the inverse's first pass and twist; [9] the
-// barrier inside the inverse; [10] its second pass and the accumulator
-// update; [11] the closing barrier.
-constexpr int kSplitPhaseWords = 14;
+// d_prof + (block * 4 + wave) * kSplitPhaseWords, its shader cycles in each
+// of the kSplitPhaseWords - 1 phases of a step summed over its executed
+// steps, then that step count.  The phases: [0] digits and key requests;
+// [1] the barrier after them; [2] the forward transform and its copy to
+// LDS; [3] the barrier after it; [4] the partner component's key products
+// and their stores; [5] the wait for those stores and the flag; [6] the
+// wait for the partner's flag; [7] loading the partner's products, this
+// half's own and the sum; [8] the inverse's first pass and twist; [9] the barrier inside
+// the inverse; [10] its second pass and the accumulator update; [11] the
+// closing barrier.
+constexpr int kSplitPhaseWords = 13;
 hipError_t launch_split_profiled(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                  const uint64_t* const* d_bsk_tab, int n_lwe, int steps, Twiddles tw,
                                  int waves_per_job, const SplitArea* split, uint64_t* d_prof, hipStream_t s);

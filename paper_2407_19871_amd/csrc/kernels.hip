@@ -655,22 +655,27 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
 // Split blind rotation: one bootstrap on two workgroups of four waves,
 // normally on two CUs of one XCD, for levels too narrow to fill the GPU.
 // Workgroup role c owns accumulator component c (0 = mask A, 1 = body B);
-// its wave j < 3 runs gadget level j with whole-wave transforms (ntt64.h).
-// Output component c of level j needs the level-j transforms of both
+// its wave j < 3 runs the forward transform of gadget level j (whole-wave
+// transforms, ntt64.h).  Output component c needs the digits of both
 // components,
-//   P_(c,j) = NTT(d_(c,j)) BSK[(c,j)][c] + NTT(d_(1-c,j)) BSK[(1-c,j)][c],
-// so every step each wave publishes its forward transform and reads its
-// partner wave's through L2:
-//   1. D_c = X^a ACC_c - ACC_c, digits of level j -> forward NTT F_(c,j);
-//   2. store F_(c,j) in this role's exchange slot, then raise the wave's
-//      flag to the step count; wait for the partner's flag; load F_(1-c,j);
-//   3. P_(c,j) into LDS; all four waves sum the three levels in the NTT
-//      domain and invert the sum together (eight lanes per row, ntt64.h),
-//      then add its centred lift to ACC_c.
-// Exchange data and flags use agent-scope relaxed atomics (coherent across
-// the CUs and XCDs of the device, no cache maintenance); a full vector
-// memory wait orders the data before the flag, and the data loads depend on
-// the observed flag.  Slots alternate by the parity of the executed-step
+//   S_c = sum_j NTT(d_(c,j)) BSK[(c,j)][c] + sum_j NTT(d_(1-c,j)) BSK[(1-c,j)][c],
+// so every step each role forms its own half of S_c and the half of
+// S_(1-c) its digits contribute, and trades the latter with its partner:
+//   1. D_c = X^a ACC_c - ACC_c, digits of level j -> forward NTT F_(c,j)
+//      on wave j, copied to LDS;
+//   2. all four waves, each at the 256 NTT-domain positions its part of
+//      the inverse reads (eight lanes per row, ntt64.h): the two sums over
+//      the levels, sum_j F_(c,j) BSK[(c,j)][c] and sum_j F_(c,j)
+//      BSK[(c,j)][1-c], one reduction each;
+//   3. wave w stores the second sum in its slot of this role's exchange
+//      area, raises its flag to the step count, waits for the partner
+//      wave w's flag and loads the partner's sum for these positions;
+//   4. the four waves invert S_c together and add its centred lift to ACC_c.
+// When both halves run on one XCD, exchange data and flags go through that
+// XCD's L2 (plain stores, device-scope loads); otherwise they are
+// agent-scope relaxed atomics.  Either way a full vector memory wait orders
+// the data before the flag, and the data loads follow the observed flag.
+// Slots alternate by the parity of the executed-step
 // count: a role rewrites a slot only after the partner has raised its flag
 // for the following step, which it does after its loads of that slot.
 //
@@ -684,15 +689,16 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
 // assumed.  Every wait is bounded:
 // a partner missing for SPLIT_SPIN_LIMIT polls ends the wait, counts in
 // g_split_stalls and in the area's own status word, marks the job, and the
-// job's output is then undefined; the kernel still exits.  The last
-// workgroup to finish clears the tickets and flags; the status word and the
+// job's output is then undefined; the kernel still exits.  Each half
+// clears its step flags when it starts, and the last workgroup to finish
+// clears the tickets and the XCD-id words; the status word and the
 // job marks stay until the host has read them (split_area_take_stalls), so
 // every call that launched the kernel can report a give-up as an error.
 constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
 constexpr int SPLIT_DONE = 8;    // finish counter (words 0-7: ticket counters per class)
 constexpr int SPLIT_STATUS = 9;  // waits of this area that ran out, until the host clears it
 constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
-constexpr int SPLIT_FLAGS_PER_JOB = 16;  // [role 2][wave 8]
+constexpr int SPLIT_FLAGS_PER_JOB = 16;  // [role 2][8]: the four waves' step flags, then the XCD id in word 7
 
 __device__ uint32_t g_split_stalls;
 
@@ -712,14 +718,23 @@ __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
 }
 
 // Accesses of an exchange between two workgroups on one XCD, through that
-// XCD's L2 (the coherence point of its CUs): stores write through to L2;
-// loads carry sc1 (device scope), so that they miss the reading CU's L1 and
-// are served by the L2.  Buffer resources (raw, no stride) over the
-// exchange slots and the sync words.  No access is volatile: the compiler
-// would complete each volatile access before the next one (and widen it to
-// system scope).  Order comes from an explicit wait for the data stores
-// before the flag store, a compiler memory barrier in every poll iteration
-// (so the flag is read anew) and one after the poll.
+// XCD's L2 (the coherence point of its CUs): plain stores, which write
+// through the CU's L1 into the L2; loads with sc1 (device scope), which miss
+// the reading CU's L1 and are served by the L2.  Agent-scope stores would
+// write through to memory and reach the partner several times later.
+// Buffer resources (raw, no stride) over the exchange slots and the sync
+// words.  No access is volatile: the compiler would complete each volatile
+// access before the next one (and widen it to system scope).  Order comes
+// from an explicit wait for the data stores before the flag store, a
+// compiler memory barrier in every poll iteration (so the flag is read
+// anew) and one after the poll.
+//
+// Such plain stores may leave the lines dirty in that L2 until the kernel
+// ends, when every L2 writes its dirty bytes back.  So no word an exchange
+// writes this way may be written from another XCD during the same launch:
+// each workgroup clears its own step flags at its start (before it announces
+// itself to its partner) rather than the last workgroup clearing all of
+// them at the end.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t l2_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
@@ -772,13 +787,12 @@ struct PhaseClock {
       t = n;
     }
   }
-  __device__ __forceinline__ void store(uint64_t* out, int lane, uint32_t done, uint32_t where) {
+  __device__ __forceinline__ void store(uint64_t* out, int lane, uint32_t done) {
     if constexpr (PROF) {
       if (out && lane == 0) {
 #pragma unroll
         for (int k = 0; k < kSplitPhases; ++k) out[k] = acc[k];
         out[kSplitPhases] = done;
-        out[kSplitPhases + 1] = where;
       }
     }
   }
@@ -849,8 +863,8 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const int nsteps = steps < n_lwe ? steps : n_lwe;
     // wave w trades with the partner's wave w: the partner's component of the
     // key products at the NTT-domain offsets both waves' inverses read
-    uint64_t* my_x = xbuf + (size_t)(job * 2 + c) * 6 * RING_N;
-    const uint64_t* peer_x = xbuf + (size_t)(job * 2 + (1 - c)) * 6 * RING_N;
+    uint64_t* my_x = xbuf + (size_t)(job * 2 + c) * 2 * RING_N;
+    const uint64_t* peer_x = xbuf + (size_t)(job * 2 + (1 - c)) * 2 * RING_N;
     uint32_t* my_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + wave;
     const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + wave;
     const int sh = 25 - 7 * wave;
@@ -859,11 +873,16 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     PhaseClock<PROF> pc;
     // Both halves on one XCD (the normal placement of the class pairing)
     // trade through that XCD's L2; otherwise past it, as agent-scope
-    // accesses.  The halves learn it from each other's XCD id, published in
-    // their pair's spare flag word (bounded wait as for the products).
+    // accesses.  Each half clears its own step flags, then publishes its XCD
+    // id in its spare flag word 7; the partner reads its flags only after
+    // that word (bounded wait as for the products).  Word 7 is only ever
+    // accessed at agent scope, and the last workgroup clears it.
     const uint32_t my_xcc = xcc_id();
     if (threadIdx.x == 0) {
-      store_agent(sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + 7, my_xcc + 1);
+      uint32_t* mine = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8;
+      for (int w = 0; w < 4; ++w) store_agent(mine + w, 0u);
+      vm_wait_all();
+      store_agent(mine + 7, my_xcc + 1);
       const uint32_t* px = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + 7;
       uint32_t v = 0;
       for (int it = 0; it < spin_limit && (v = load_agent(px)) == 0; ++it) __builtin_amdgcn_s_sleep(1);
@@ -871,7 +890,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     }
     __syncthreads();
     const bool local = __builtin_amdgcn_readfirstlane((int)s_local) != 0;
-    const __amdgpu_buffer_rsrc_t xr = l2_rsrc(xbuf, (gridDim.x / 2) * 12u * RING_N * 8u);
+    const __amdgpu_buffer_rsrc_t xr = l2_rsrc(xbuf, (gridDim.x / 2) * 4u * RING_N * 8u);
     const __amdgpu_buffer_rsrc_t fr = l2_rsrc(sync, (SPLIT_FLAGS + (gridDim.x / 2) * SPLIT_FLAGS_PER_JOB) * 4u);
     const uint32_t my_xo = (uint32_t)(my_x - xbuf) * 8u, peer_xo = (uint32_t)(peer_x - xbuf) * 8u;
     const uint32_t my_fo = (uint32_t)(my_flag - sync) * 4u, peer_fo = (uint32_t)(peer_flag - sync) * 4u;
@@ -926,13 +945,15 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       __syncthreads();
       pc.template mark<3>();
 
-      // both components' products, summed over the levels with one reduction
-      uint64_t own[4], oth[4];
+      // the partner's component of the products, summed over the levels
+      // with one reduction, goes out first; this half's own follows while
+      // the partner's is on its way
+      uint64_t F[3][4], oth[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const uint64_t F0 = s_part[0][off[s]], F1 = s_part[1][off[s]], F2 = s_part[2][off[s]];
-        oth[s] = gl_mul_sum3(F0, ko[0][s], F1, ko[1][s], F2, ko[2][s]);
-        own[s] = gl_mul_sum3(F0, kc[0][s], F1, kc[1][s], F2, kc[2][s]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) F[j][s] = s_part[j][off[s]];
+        oth[s] = gl_mul_sum3(F[0][s], ko[0][s], F[1][s], ko[1][s], F[2][s], ko[2][s]);
       }
       const uint32_t par = (done & 1u) * RING_N;
       const uint32_t slot = par + 64 * wave + lane;  // + 256 s
@@ -975,6 +996,13 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = load_agent(peer_x + slot + 256 * s);
       }
+      uint64_t own[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) own[s] = gl_mul_sum3(F[0][s], kc[0][s], F[1][s], kc[1][s], F[2][s], kc[2][s]);
+      // every own product before the first wait for the partner's (ordered
+      // empty asm statements that the sums depend on)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) asm volatile("" : "+v"(own[s]));
 #pragma unroll
       for (int s = 0; s < 4; ++s) v[s] = gl_add(own[s], v[s]);
       pc.template mark<7>();
@@ -1004,8 +1032,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       __syncthreads();
       pc.template mark<11>();
     }
-    pc.store(prof ? prof + ((size_t)blockIdx.x * 4 + wave) * kSplitPhaseWords : nullptr, lane, done,
-             my_xcc | (local ? 16u : 0u));
+    pc.store(prof ? prof + ((size_t)blockIdx.x * 4 + wave) * kSplitPhaseWords : nullptr, lane, done);
 
     if (raw_acc) {
       uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
@@ -1024,260 +1051,16 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     }
   }
 
-  // the last workgroup to finish clears the tickets and flags for the next
-  // launch on this area (every other one has finished using them)
+  // the last workgroup to finish clears the tickets and the XCD-id words
+  // for the next launch on this area (every other one has finished using
+  // them); the step flags are their owners' to clear
   vm_wait_all();
   __syncthreads();
   if (threadIdx.x == 0) s_last = atomicAdd(sync + SPLIT_DONE, 1u) == gridDim.x - 1 ? 1u : 0u;
   __syncthreads();
   if (s_last) {
-    const int nflags = (int)(gridDim.x / 2) * SPLIT_FLAGS_PER_JOB;
-    for (int k = threadIdx.x; k < nflags; k += 256) store_agent(sync + SPLIT_FLAGS + k, 0u);
-    if (threadIdx.x <= SPLIT_DONE) store_agent(sync + threadIdx.x, 0u);  // the 8 class counters and the finish count
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Split blind rotation on eight waves per workgroup (two per SIMD): the
-// pairing, the exchange protocol, the bounded waits and the give-up record
-// of blind_rotate_split_kernel, with each gadget level's forward transform
-// spread over two waves (the 128-lane layout of ntt64.h, four lanes per
-// row), so that two waves share every SIMD while the transforms run.
-// Waves 0-5: level j = wave / 2, half k = wave % 2; each publishes its half
-// of F_(c,j) (4 KB) under a flag of its own and loads the partner's same
-// half.  Waves 0-3 invert the levels' sum as before; waves 6 and 7 only
-// keep the barriers.
-template <bool PROF>
-__global__ __launch_bounds__(512, 1) void blind_rotate_split8_kernel(
-    const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
-    const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
-    int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
-    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, uint64_t* __restrict__ prof) {
-  __shared__ uint32_t s_acc[RING_N];
-  __shared__ __align__(16) uint64_t s_fwd[3][32 * T128_ROW];  // each level's two-wave transpose
-  __shared__ __align__(16) uint64_t s_part[3][RING_N];       // the levels' partials, NTT domain
-  __shared__ __align__(16) uint64_t s_t128[32 * T128_ROW];    // the inverse's transpose
-  __shared__ uint16_t s_abar[MAX_LWE + 4];
-  __shared__ uint32_t s_ticket, s_last;
-
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
-  const bool lvl = wave < 6;  // waves 0-5 run the gadget levels (two per level)
-  const bool inv = wave < 4;  // waves 0-3 invert
-  const int lj = lvl ? wave >> 1 : 0, lk = wave & 1;
-  // two-wave forward: lane 4 r4 + hq holds column (then row) 16 lk + r4,
-  // positions 4 s + hq
-  const int r4 = lane >> 2, hq = lane & 3, col = 16 * lk + r4;
-  const uint64_t fu1 = (hq & 1) ? ~0ull : 0ull, fu2 = (hq & 2) ? ~0ull : 0ull;
-  // four-wave inverse: row (or column) 8 wave + r8, lane h8 of the row's eight
-  const int r8 = lane >> 3, h8 = lane & 7, row = 8 * (wave & 3) + r8;
-  const uint64_t upper1 = (h8 & 1) ? ~0ull : 0ull, upper2 = (h8 & 2) ? ~0ull : 0ull,
-                 upper4 = (h8 & 4) ? ~0ull : 0ull;
-  uint64_t w2[4], w1[4];
-  inv256_twiddles(h8, w2, w1);
-  const int cls = (int)(blockIdx.x & 7u);
-  if (threadIdx.x == 0) s_ticket = atomicAdd(sync + cls, 1u);
-  __syncthreads();
-  const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_ticket);
-  const int job = (int)(t >> 1) * 8 + cls;
-  const int c = (int)(t & 1u);
-
-  if (job < njobs) {
-    const BrJob J = jobs[job];
-    {
-      auto operand = [&](uint32_t r) -> const uint32_t* {
-        if (r == REF_NONE) return nullptr;
-        const uint32_t base = r >> REF_SHIFT;
-        const uint32_t* b = base == KEY_POOL_BASE ? pool_tab[J.key] : src.p[base];
-        return b + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
-      };
-      const uint32_t* in0 = operand(J.in0);
-      const uint32_t* in1 = operand(J.in1);
-      for (int k = threadIdx.x; k <= n_lwe; k += 512) {
-        uint32_t v = (k == n_lwe) ? J.cst : 0u;
-        if (in0) v += (uint32_t)J.c0 * in0[k];
-        if (in1) v += (uint32_t)J.c1 * in1[k];
-        s_abar[k] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
-      }
-    }
-    __syncthreads();
-    // ACC_0 = 0, ACC_1 = X^{-b} v (coefficient j: +1/8 if (j + b) mod 2N < N)
-    const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
-    for (int j = threadIdx.x; j < RING_N; j += 512)
-      s_acc[j] = c == 0 ? 0u : ((((uint32_t)j + bbar) & 2047u) < 1024u ? 0x20000000u : 0xE0000000u);
-    __syncthreads();
-
-    const gmem_u64* bsk = as_global(bsk_tab[J.key]);
-    const int nsteps = steps < n_lwe ? steps : n_lwe;
-    const int lw = lvl ? wave : 0;  // waves 6 and 7 have no exchange slot (and use none)
-    // this wave's half of its level's 1024 values: [half][slot][lane]
-    uint64_t* my_x = xbuf + ((size_t)(job * 2 + c) * 6 + lj) * RING_N + lk * 512;
-    const uint64_t* peer_x = xbuf + ((size_t)(job * 2 + (1 - c)) * 6 + lj) * RING_N + lk * 512;
-    uint32_t* my_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + lw;
-    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + lw;
-    const int sh = 25 - 7 * lj;
-    // NTT-domain offset of slot s after pass 2: row 16 lk + r4, position 4 s + hq
-    auto key_off = [&](int s) { return 128 * s + 64 * (hq >> 1) + 2 * col + (hq & 1); };
-    uint32_t done = 0;  // executed steps, the same count in both roles
-    bool stalled = false;
-    PhaseClock<PROF> pc;
-
-    for (int i = 0; i < nsteps; ++i) {
-      const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
-      if (a == 0) continue;  // X^0 ACC - ACC = 0: no digits, no exchange
-      pc.start();
-
-      // key rows (c, j) and (1-c, j), component c, at this lane's offsets
-      const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
-      const gmem_u64* ko = step_key + (size_t)((c * 3 + lj) * 2 + c) * RING_N;
-      const gmem_u64* kt = step_key + (size_t)(((1 - c) * 3 + lj) * 2 + c) * RING_N;
-      uint64_t kown[8], koth[8];
-      uint64_t f[8];
-      if (lvl) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          kown[s] = ko[key_off(s)];
-          koth[s] = kt[key_off(s)];
-        }
-        int32_t dg[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const uint32_t j = (uint32_t)(col + 32 * (4 * s + hq));
-          const uint32_t e = (j - a) & 2047u;
-          const uint32_t v = s_acc[e & 1023u];
-          const uint32_t D = ((e & 1024u) ? (0u - v) : v) - s_acc[j];
-          dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
-        }
-        fwd128_p1_digits(dg, f);
-        fwd128_p1_rest(f, fu1, fu2, fu2);
-        // twist by psi^((2 ka + 1) j1) for position q = 4 s + hq (ka slot) of
-        // column j1, then to the level's transpose block, element (q, j1)
-        const gmem_u64* tw = as_global(opaque(tw_f)) + hq * 32 + col;
-        uint64_t w[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) w[s] = tw[s * 128];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) s_fwd[lj][(4 * s + hq) * T128_ROW + col] = gl_mul(f[s], w[s]);
-      }
-      pc.template mark<0>();
-      __syncthreads();  // both halves of every level are in their transpose blocks; every wave has read ACC_c
-      pc.template mark<1>();
-      if (lvl) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) f[s] = s_fwd[lj][col * T128_ROW + 4 * s + hq];
-        fwd128_p2(f, fu1, fu2, fu2);
-        pc.template mark<2>();
-
-        const size_t par = (size_t)(done & 1u) * 3 * RING_N;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) store_agent(my_x + par + s * 64 + lane, f[s]);
-        // this component's products while the stores drain and the partner's
-        // half is on its way (the empty asm keeps them ahead of the wait)
-        uint64_t plo[8], phi[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          gl_mul_wide(f[s], kown[s], plo[s], phi[s]);
-          asm volatile("" : "+v"(plo[s]), "+v"(phi[s]));
-        }
-        pc.template mark<3>();
-        vm_wait_all();
-        pc.template mark<4>();
-        if (lane == 0) store_agent(my_flag, done + 1);
-        if (!stalled) {
-          int it = 0;
-          while (load_agent(peer_flag) < done + 1) {
-            if (++it >= spin_limit) break;
-            __builtin_amdgcn_s_sleep(1);
-          }
-          if (it >= spin_limit) {
-            stalled = true;
-            if (lane == 0) {
-              atomicAdd(&g_split_stalls, 1u);
-              atomicAdd(sync + SPLIT_STATUS, 1u);
-              store_agent(marks + job, 1u);
-            }
-          }
-        }
-        pc.template mark<5>();
-        vm_wait_all();
-        uint64_t g[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) g[s] = load_agent(peer_x + par + s * 64 + lane);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) s_part[lj][key_off(s)] = gl_mul_sum_wide(plo[s], phi[s], g[s], koth[s]);
-        pc.template mark<6>();
-      }
-      __syncthreads();
-      pc.template mark<7>();
-
-      // one inverse of the three levels' sum on waves 0-3: each holds eight
-      // rows at eight lanes per row (the NTT-domain offset of position q of
-      // row k is 64 (q >> 1) + 2 k + (q & 1))
-      uint64_t v[4];
-      if (inv) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int off = 256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1);
-          v[s] = gl_add(gl_add(s_part[0][off], s_part[1][off]), s_part[2][off]);
-        }
-        inv256_p2(v, upper1, upper2, upper4, w2);
-        {
-          const gmem_u64* tt = as_global(opaque(tw_i)) + h8 * 32 + row;
-          uint64_t w[4];
-#pragma unroll
-          for (int s = 0; s < 4; ++s) w[s] = tt[s * 256];
-#pragma unroll
-          for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], w[s]);
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) s_t128[row * T128_ROW + 8 * s + h8] = v[s];
-      }
-      pc.template mark<8>();
-      __syncthreads();
-      pc.template mark<9>();
-      if (inv) {
-        // column j1 = row of this lane, positions q = 8 s + h8
-#pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = s_t128[(8 * s + h8) * T128_ROW + row];
-        inv256_p1(v, upper1, upper2, upper4, w1);
-        // the sum is an exact integer polynomial (|coefficient| < 2^50.6),
-        // so its centred lift reduced mod 2^32 is exact
-#pragma unroll
-        for (int s = 0; s < 4; ++s) s_acc[row + 32 * (8 * s + h8)] += gl_lift_u32(v[s]);
-      }
-      pc.template mark<10>();
-      ++done;
-      __syncthreads();
-      pc.template mark<11>();
-    }
-    pc.store(prof ? prof + ((size_t)blockIdx.x * 8 + wave) * kSplitPhaseWords : nullptr, lane, done, xcc_id());
-
-    if (raw_acc) {
-      uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
-      for (int j = threadIdx.x; j < RING_N; j += 512) o[j] = s_acc[j];
-    } else {
-      // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
-      uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
-      if (c == 0) {
-        for (int j = threadIdx.x; j < RING_N; j += 512) {
-          if (j == 0) o[0] = s_acc[0];
-          else o[RING_N - j] = 0u - s_acc[j];
-        }
-      } else if (threadIdx.x == 0) {
-        o[RING_N] = s_acc[0];
-      }
-    }
-  }
-
-  // the last workgroup to finish clears the tickets and flags for the next
-  // launch on this area (every other one has finished using them)
-  vm_wait_all();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = atomicAdd(sync + SPLIT_DONE, 1u) == gridDim.x - 1 ? 1u : 0u;
-  __syncthreads();
-  if (s_last) {
-    const int nflags = (int)(gridDim.x / 2) * SPLIT_FLAGS_PER_JOB;
-    for (int k = threadIdx.x; k < nflags; k += 512) store_agent(sync + SPLIT_FLAGS + k, 0u);
+    const int nroles = (int)gridDim.x;  // two roles per job slot
+    for (int k = threadIdx.x; k < nroles; k += 256) store_agent(sync + SPLIT_FLAGS + k * 8 + 7, 0u);
     if (threadIdx.x <= SPLIT_DONE) store_agent(sync + threadIdx.x, 0u);  // the 8 class counters and the finish count
   }
 }
@@ -1488,18 +1271,12 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       hipLaunchKernelGGL(blind_rotate_kernel<5>, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
-    case 6:
-    case 7: {
+    case 6: {
       if (!split || !split->xbuf || !split->sync || njobs > split->max_jobs) return hipErrorInvalidValue;
       const int grid = 16 * ((njobs + 7) / 8);
-      if (waves_per_job == 6)
-        hipLaunchKernelGGL(blind_rotate_split_kernel<false>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
-                           d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
-                           split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), nullptr);
-      else
-        hipLaunchKernelGGL(blind_rotate_split8_kernel<false>, dim3(grid), dim3(512), 0, s, d_jobs, njobs, src, d_ex,
-                           d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
-                           split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), nullptr);
+      hipLaunchKernelGGL(blind_rotate_split_kernel<false>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
+                         d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
+                         split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), nullptr);
       break;
     }
     default:
@@ -1515,14 +1292,9 @@ hipError_t launch_split_profiled(const BrJob* d_jobs, int njobs, const SrcBases&
   if (!is_split(waves_per_job) || !split || !split->xbuf || !split->sync || njobs > split->max_jobs || !d_prof)
     return hipErrorInvalidValue;
   const int grid = 16 * ((njobs + 7) / 8);
-  if (waves_per_job == 6)
-    hipLaunchKernelGGL(blind_rotate_split_kernel<true>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
-                       d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
-                       split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), d_prof);
-  else
-    hipLaunchKernelGGL(blind_rotate_split8_kernel<true>, dim3(grid), dim3(512), 0, s, d_jobs, njobs, src, d_ex,
-                       d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
-                       split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), d_prof);
+  hipLaunchKernelGGL(blind_rotate_split_kernel<true>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
+                     d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
+                     split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), d_prof);
   return hipGetLastError();
 }
 
@@ -1536,7 +1308,7 @@ int split_spin_limit() {
   const long x = (v && *v) ? std::atol(v) : 0;
   return x > 0 && x < SPLIT_SPIN_LIMIT ? (int)x : SPLIT_SPIN_LIMIT;
 }
-size_t split_xbuf_bytes(int max_jobs) { return (size_t)split_jobs_padded(max_jobs) * 12 * RING_N * 8; }
+size_t split_xbuf_bytes(int max_jobs) { return (size_t)split_jobs_padded(max_jobs) * 4 * RING_N * 8; }
 // sync area: 64 control words, 16 flag words per job, then one give-up mark per job
 static size_t split_marks_offset(int max_jobs) {
   return (size_t)SPLIT_FLAGS + (size_t)split_jobs_padded(max_jobs) * SPLIT_FLAGS_PER_JOB;

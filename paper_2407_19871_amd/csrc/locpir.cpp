@@ -858,14 +858,14 @@ extern "C" lp_status lp_debug_field_op_rates(double target_ms, double* rates, do
 }
 
 extern "C" lp_status lp_debug_split_profile(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, int waves,
-                                           double* cycles, double* ms, double* local_share, void* stream) {
+                                           double* cycles, double* ms, void* stream) {
   if (!dk || !d_in || !cycles) return fail(LP_EINVAL, "lp_debug_split_profile: null argument");
   if (cnt == 0 || cnt > (size_t)lp::kSplitMaxJobs)
     return fail(LP_EINVAL, "lp_debug_split_profile: 1..%d rotations", lp::kSplitMaxJobs);
-  if (!lp::is_split(waves)) return fail(LP_EINVAL, "lp_debug_split_profile: waves must be 6 or 7");
+  if (!lp::is_split(waves)) return fail(LP_EINVAL, "lp_debug_split_profile: waves must be 6");
   ScopedDevice sd(dk->device);
   hipStream_t s = as_stream(stream);
-  const int N = (int)dk->P.N, wpw = waves == 6 ? 4 : 8;
+  const int N = (int)dk->P.N, wpw = 4;
   const int grid = 16 * (((int)cnt + 7) / 8);
   const size_t pwords = (size_t)grid * wpw * lp::kSplitPhaseWords;
   std::vector<BrJob> jobs(cnt);
@@ -906,23 +906,17 @@ extern "C" lp_status lp_debug_split_profile(const lp_device_key* dk, const uint3
   (void)hipFreeAsync(dj, s);
   if (e != hipSuccess) return fail(LP_EDEVICE, "lp_debug_split_profile: %s", hipGetErrorString(e));
   if (stalls) return lp::split_stall_error("lp_debug_split_profile", stalls);
-  constexpr int P = lp::kSplitPhaseWords - 2;
-  int busy = 0, local = 0;
+  constexpr int P = lp::kSplitPhaseWords - 1;
   for (int w = 0; w < wpw; ++w) {
     double steps = 0.0, sum[P] = {};
     for (int b = 0; b < grid; ++b) {
       const uint64_t* r = prof.data() + ((size_t)b * wpw + w) * lp::kSplitPhaseWords;
       steps += (double)r[P];
       for (int k = 0; k < P; ++k) sum[k] += (double)r[k];
-      if (w == 0 && r[P] > 0) {
-        ++busy;
-        local += (r[P + 1] & 16u) ? 1 : 0;
-      }
     }
     for (int k = 0; k < P; ++k) cycles[w * P + k] = steps > 0 ? sum[k] / steps : 0.0;
   }
   if (ms) *ms = f;
-  if (local_share) *local_share = busy ? (double)local / busy : 0.0;
   return LP_OK;
 }
 

@@ -266,97 +266,6 @@ __device__ __forceinline__ void inv128_p1(uint64_t (&a)[8], uint64_t upper1, uin
   gs128_stage<16>(a, Z1<16>{});
 }
 
-// ---- forward on two waves (four lanes per row) -------------------------------
-// The forward transform of one polynomial over 128 lanes, in the lane
-// arrangement of the two-wave inverse.  Pass 1 runs on columns: wave w (0,
-// 1) holds columns 16 w .. 16 w + 15, lane 4 r + h of the wave the eight
-// positions q = 4 s + h (s = 0..7) of column 16 w + r, i.e. coefficients
-// 16 w + r + 32 q.  Pass 2 runs on rows in the same arrangement after the
-// kernel's transpose through LDS (wave w then holds rows 16 w .. 16 w + 15).
-// Stages of distance 16, 8 and 4 stay in the lane (slot distances 4, 2, 1),
-// with per-block shifts as in the one-wave transform; distances 2 and 1
-// pair lanes h ^ 2 and h ^ 1 of the quad.  The distance-2 stage's block
-// (q / 4 = s) is uniform; the distance-1 stage's (q / 2 = 2 s + (h >> 1))
-// takes two values per slot, so both shifts are formed and each lane keeps
-// its own.  Output: slot s of lane 4 r + h of wave w holds the value at row
-// 16 w + r, position q = 4 s + h, which sits at offset 64 (q >> 1) +
-// 2 (16 w + r) + (q & 1) of the NTT-domain key layout.
-
-// Pass 1's first two stages (distances 16 and 8) on gadget digits, exact in
-// int64 as in fwd1_first_stages_digits: each group (q, q + 8, q + 16, q + 24)
-// is slots (i, i + 2, i + 4, i + 6) of one lane, i = 0, 1.
-__device__ __forceinline__ void fwd128_p1_digits(const int32_t (&d)[8], uint64_t (&a)[8]) {
-  static_for<0, 2>([&](auto ii) {
-    constexpr int i = decltype(ii)::value;
-    const int64_t d0 = d[i], d1 = d[i + 2], d2 = d[i + 4], d3 = d[i + 6];
-    const int64_t s0 = d0 + d2 * (1ll << 48), s1 = d0 - d2 * (1ll << 48);
-    const int64_t p = d1 * (1ll << 24) + d3 * ((1ll << 40) - (1ll << 8));
-    const int64_t q = d1 * ((1ll << 40) - (1ll << 8)) + d3 * (1ll << 24);
-    a[i] = gl_from_i64(s0 + p);
-    a[i + 2] = gl_from_i64(s0 - p);
-    a[i + 4] = gl_from_i64(s1 + q);
-    a[i + 6] = gl_from_i64(s1 - q);
-  });
-}
-
-// In-lane Cooley-Tukey stage of distance LEN in {16, 8, 4}: slots s and
-// s + LEN / 4 within blocks of LEN / 2 slots; Z(blk) gives the block's shift.
-template <int LEN, typename Zf>
-__device__ __forceinline__ void ct128_stage(uint64_t (&a)[8], Zf zf) {
-  static_for<0, 16 / LEN>([&](auto bb) {
-    constexpr int blk = decltype(bb)::value;
-    constexpr int z = decltype(zf(std::integral_constant<int, blk>{}))::value;
-    static_for<0, LEN / 4>([&](auto jj) {
-      constexpr int s0 = blk * (LEN / 2) + decltype(jj)::value, s1 = s0 + LEN / 4;
-      const uint64_t t = gl_mul_pow2_r<z>(a[s1]);
-      a[s1] = gl_sub_r(a[s0], t);
-      a[s0] = gl_add_r(a[s0], t);
-    });
-  });
-}
-
-// Cooley-Tukey stage of distance D in {1, 2} across the quad: both lanes of
-// a pair form t = w * (the upper position's value), reduced; the lower lane
-// keeps x + t, the upper x - t, each with one addition (of t or of -t).
-// upper: ~0 in the upper lane of each pair (h & D); second: ~0 in lanes
-// h >= 2 (the distance-1 stage's second block of the slot).
-template <int D, typename Zf>
-__device__ __forceinline__ void ct128_cross(uint64_t (&a)[8], Zf zf, uint64_t upper, uint64_t second) {
-  static_for<0, 8>([&](auto ss) {
-    constexpr int s = decltype(ss)::value;
-    const uint64_t self = a[s], other = quad_xor<D>(a[s]);
-    const uint64_t X = lane_select(upper, self, other), Y = lane_select(upper, other, self);
-    uint64_t t;
-    if constexpr (D == 1) {
-      constexpr int za = decltype(zf(std::integral_constant<int, 2 * s>{}))::value;
-      constexpr int zb = decltype(zf(std::integral_constant<int, 2 * s + 1>{}))::value;
-      t = lane_select(second, gl_mul_pow2_r<za>(Y), gl_mul_pow2_r<zb>(Y));
-    } else {
-      constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
-      t = gl_mul_pow2_r<z>(Y);
-    }
-    a[s] = gl_add_r(X, lane_negate(upper, t));
-  });
-}
-
-// Pass 1 after the digit stages (distances 4, 2, 1), natural order in, the
-// value for ka = brv5(q) at position q out.
-__device__ __forceinline__ void fwd128_p1_rest(uint64_t (&a)[8], uint64_t upper1, uint64_t upper2, uint64_t second) {
-  ct128_stage<4>(a, Z1<4>{});
-  ct128_cross<2>(a, Z1<2>{}, upper2, second);
-  ct128_cross<1>(a, Z1<1>{}, upper1, second);
-}
-
-// Pass 2 (cyclic, root omega = 2^6), natural order in, kb = brv5(q) at
-// position q out.
-__device__ __forceinline__ void fwd128_p2(uint64_t (&a)[8], uint64_t upper1, uint64_t upper2, uint64_t second) {
-  ct128_stage<16>(a, Z2<16>{});
-  ct128_stage<8>(a, Z2<8>{});
-  ct128_stage<4>(a, Z2<4>{});
-  ct128_cross<2>(a, Z2<2>{}, upper2, second);
-  ct128_cross<1>(a, Z2<1>{}, upper1, second);
-}
-
 // ---- inverse on four waves (eight lanes per row) -----------------------------
 // The same inverse over 256 lanes: wave w (0..3) holds rows 8 w .. 8 w + 7,
 // lane 8 r + h of the wave holds the four positions q = 8 s + h (s = 0..3)

@@ -28,7 +28,7 @@ std::map<int, std::vector<lp_tune_entry>> g_tune;  // device -> rows sorted by j
 
 constexpr uint32_t kMaxTuneJobs = 1u << 22;      // row bound
 constexpr uint32_t kMaxTuneBucket = 1u << 16;    // batch size the autotuner times
-const int kWaves[] = {1, 2, 3, 4, 5, 6, 7};
+const int kWaves[] = {1, 2, 3, 4, 5, 6};
 constexpr int kNumWaves = sizeof(kWaves) / sizeof(kWaves[0]);
 const int kTiles[] = {1, 4, 8, 16};
 const int kSplits[] = {1, 2, 4, 8, 16};

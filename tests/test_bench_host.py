@@ -38,11 +38,11 @@ def test_rotation_launches_by_shape():
     by = tot["blind_rotate_by_shape"]
     assert by[6] == {"launches": 4, "jobs": 2 * 72, "total_ms": 2 * (10.0 + 11.0)}
     assert by[3] == {"launches": 2, "jobs": 1024, "total_ms": 20.0}
-    # a split job holds six SIMDs (three waves on each of two CUs)
-    want = (2 * (10 * 48 + 11 * 384) / 1024 + 2 * 10 * 1.0) / 62.0
+    # a split job holds eight SIMDs (four waves on each of two CUs)
+    want = (2 * (10 * 64 + 11 * 512) / 1024 + 2 * 10 * 1.0) / 62.0
     assert busy == pytest.approx(want)
     assert bench.SHAPE_KERNEL[6] == "blind_rotate_split_kernel"
-    assert set(bench.SHAPE_KERNEL) == {1, 2, 3, 4, 5, 6, 7}  # every shape the library launches
+    assert set(bench.SHAPE_KERNEL) == {1, 2, 3, 4, 5, 6}  # every shape the library launches
 
 
 def test_missing_key_switch_record_keeps_levels_aligned():

@@ -1,11 +1,10 @@
 """Split blind rotation (br_waves 6: one bootstrap on two workgroups of four
-waves, each owning one accumulator component, trading forward transforms
-every step; br_waves 7: the same on eight waves per workgroup, each gadget
-level's forward transform on two waves): bit-exact against the oracle for
-the accumulator after all n steps, for gates at one, ragged and maximal
-launch widths, and for whole queries whose narrow levels run split, with the
+waves, each owning one accumulator component and trading its key products
+for the other component every step): bit-exact against the oracle for the
+accumulator after all n steps, for gates at one, ragged and maximal launch
+widths, and for whole queries whose narrow levels run split, with the
 exchange area reused launch after launch; a forced give-up fails the call
-that launched it, for both shapes."""
+that launched it."""
 import numpy as np
 import pytest
 
@@ -34,10 +33,10 @@ def stalls_before(dkey):
     return lp.split_stall_count()
 
 
-@pytest.fixture(params=[6, 7])
-def split_w(request):
-    """The split shape under test: four or eight waves per workgroup."""
-    return request.param
+@pytest.fixture
+def split_w():
+    """The split shape under test."""
+    return 6
 
 
 @pytest.fixture
@@ -234,3 +233,20 @@ def test_give_up_fails_the_server_request_only(monkeypatch, okeys, octx, split_t
     srv.close()
     assert st == 0
     assert (out == octx.bbox_query(l, N, m, False, *parts)).all()
+
+
+def test_split_profile_reports_every_phase(okeys, dkey):
+    """The profiling build of the split rotation: every wave reports every
+    phase; the level waves spend their forward transform where the fourth
+    wave waits, and all four meet at the barriers, so their step totals
+    agree."""
+    ct = lp.to_device(O.encrypt_bits(okeys, [1, 0, 1, 1, 0, 0, 1, 0], seed=5))
+    r = lp.debug_split_profile(dkey, ct)
+    assert r["ms"] > 0
+    assert len(r["waves"]) == 4
+    for w in r["waves"]:
+        assert set(w) == set(lp.SPLIT_PHASES) and all(v >= 0 for v in w.values())
+    assert r["waves"][0]["forward"] > 10 * r["waves"][3]["forward"]
+    assert r["waves"][3]["barrier_f"] > 10 * r["waves"][0]["barrier_f"]
+    sums = [sum(w.values()) for w in r["waves"]]
+    assert max(sums) < 1.05 * min(sums)

@@ -60,13 +60,11 @@ def test_split_shape_applies_up_to_128_jobs(monkeypatch):
     assert got == [1, 6, 6, 3, 3, 3]
     monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
     assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129)] == [6, 6, 3]
-    monkeypatch.setenv("LOCPIR_BR_WAVES", "7")
-    assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129)] == [7, 7, 3]
 
 
 @pytest.mark.parametrize("bad", [
     {"jobs": 0, "br_waves": 1, "ks_tile": 4, "ks_split": 1},
-    {"jobs": 8, "br_waves": 8, "ks_tile": 4, "ks_split": 1},
+    {"jobs": 8, "br_waves": 7, "ks_tile": 4, "ks_split": 1},
     {"jobs": 8, "br_waves": 0, "ks_tile": 4, "ks_split": 1},
     {"jobs": 8, "br_waves": 1, "ks_tile": 3, "ks_split": 1},
     {"jobs": 8, "br_waves": 1, "ks_tile": 4, "ks_split": 32},
