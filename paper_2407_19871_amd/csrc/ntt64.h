@@ -212,25 +212,26 @@ __device__ __forceinline__ uint64_t quad_xor(uint64_t v) {
 // Gentleman-Sande stage of distance D in {1, 2} across the quad; FIRST:
 // the inputs may be lazy.  Masks: upper = ~0 in the upper lane of each
 // pair (h & D), second = ~0 in lanes h >= 2 (the second pair of the row).
+// Each lane forms only its own output from one addition: the partner's
+// value plus this lane's own, negated in the upper lane, i.e. X + Y in the
+// lower lane and X - Y in the upper one, which then takes the twiddle.
 template <int D, bool FIRST, typename Zf>
 __device__ __forceinline__ void gs128_cross(uint64_t (&a)[8], Zf zf, uint64_t upper, uint64_t second) {
   static_for<0, 8>([&](auto ss) {
     constexpr int s = decltype(ss)::value;
-    const uint64_t self = a[s], other = quad_xor<D>(a[s]);
-    const uint64_t X = lane_select(upper, self, other), Y0 = lane_select(upper, other, self);
-    const uint64_t Y = FIRST ? gl_canon(Y0) : Y0;
-    const uint64_t sum = gl_canon(gl_add_r(X, Y));
-    const uint64_t dif = gl_sub_r(X, Y);
+    const uint64_t other = quad_xor<D>(a[s]);
+    const uint64_t self = FIRST ? gl_canon(a[s]) : a[s];
+    const uint64_t v = gl_add_r(other, lane_negate(upper, self));
     uint64_t up;
     if constexpr (D == 1) {
       constexpr int za = decltype(zf(std::integral_constant<int, 2 * s>{}))::value;
       constexpr int zb = decltype(zf(std::integral_constant<int, 2 * s + 1>{}))::value;
-      up = lane_select(second, gl_mul_pow2_r<192 - za>(dif), gl_mul_pow2_r<192 - zb>(dif));
+      up = lane_select(second, gl_mul_pow2_r<192 - za>(v), gl_mul_pow2_r<192 - zb>(v));
     } else {
       constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
-      up = gl_mul_pow2_r<192 - z>(dif);
+      up = gl_mul_pow2_r<192 - z>(v);
     }
-    a[s] = lane_select(upper, sum, up);
+    a[s] = lane_select(upper, gl_canon(v), up);
   });
 }
 
@@ -299,7 +300,9 @@ __device__ __forceinline__ uint64_t gl_pow2(int e) {
 // Gentleman-Sande stage of distance D in {1, 2, 4} across the eight lanes
 // of a row; FIRST: the inputs may be lazy.  upper: ~0 in the upper lane of
 // each pair (h & D); hi4: ~0 in lanes h >= 4; w1: the lane's twiddles of
-// the distance-1 stage (one per slot).
+// the distance-1 stage (one per slot, 1 in the lower lanes).  As in
+// gs128_cross, each lane forms only its own output: the partner's value
+// plus its own, negated in the upper lane, then the upper lane's twiddle.
 template <int D, bool FIRST, typename Zf>
 __device__ __forceinline__ void gs256_cross(uint64_t (&a)[4], Zf zf, uint64_t upper, uint64_t hi4,
                                             const uint64_t (&w1)[4]) {
@@ -308,23 +311,18 @@ __device__ __forceinline__ void gs256_cross(uint64_t (&a)[4], Zf zf, uint64_t up
     uint64_t other;
     if constexpr (D == 4) other = oct_xor4(a[s], hi4 != 0);
     else other = quad_xor<D>(a[s]);
-    const uint64_t self = a[s];
-    const uint64_t X = lane_select(upper, self, other), Y0 = lane_select(upper, other, self);
-    const uint64_t Y = FIRST ? gl_canon(Y0) : Y0;
-    const uint64_t sum = gl_canon(gl_add_r(X, Y));
-    const uint64_t dif = gl_sub_r(X, Y);
-    uint64_t up;
+    const uint64_t self = FIRST ? gl_canon(a[s]) : a[s];
+    const uint64_t v = gl_add_r(other, lane_negate(upper, self));
     if constexpr (D == 4) {
       constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
-      up = gl_mul_pow2_r<192 - z>(dif);
+      a[s] = lane_select(upper, gl_canon(v), gl_mul_pow2_r<192 - z>(v));
     } else if constexpr (D == 2) {
       constexpr int za = decltype(zf(std::integral_constant<int, 2 * s>{}))::value;
       constexpr int zb = decltype(zf(std::integral_constant<int, 2 * s + 1>{}))::value;
-      up = lane_select(hi4, gl_mul_pow2_r<192 - za>(dif), gl_mul_pow2_r<192 - zb>(dif));
+      a[s] = lane_select(upper, gl_canon(v), lane_select(hi4, gl_mul_pow2_r<192 - za>(v), gl_mul_pow2_r<192 - zb>(v)));
     } else {
-      up = gl_canon(gl_mul(dif, w1[s]));
+      a[s] = gl_canon(gl_mul(v, w1[s]));
     }
-    a[s] = lane_select(upper, sum, up);
   });
 }
 
@@ -345,15 +343,16 @@ __device__ __forceinline__ void gs256_stage(uint64_t (&a)[4], Zf zf) {
   });
 }
 
-// The lane's distance-1 twiddles of each pass: 2^(192 - z) for the block
-// 4 s + (h >> 1) of slot s (pass 2: z = 6 (brv5(b) >> 1); pass 1: z =
-// 3 brv5(16 + b)).
+// The lane's distance-1 twiddles of each pass: in the upper lane of a pair
+// (h odd) 2^(192 - z) for the block 4 s + (h >> 1) of slot s (pass 2: z =
+// 6 (brv5(b) >> 1); pass 1: z = 3 brv5(16 + b)); 1 in the lower lane, which
+// keeps the sum.
 __device__ __forceinline__ void inv256_twiddles(int h, uint64_t (&w2)[4], uint64_t (&w1)[4]) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int b = 4 * s + (h >> 1);
-    w2[s] = gl_pow2((192 - 6 * (brv5(b) >> 1)) % 192);
-    w1[s] = gl_pow2((192 - 3 * brv5(16 + b)) % 192);
+    w2[s] = (h & 1) ? gl_pow2((192 - 6 * (brv5(b) >> 1)) % 192) : 1ull;
+    w1[s] = (h & 1) ? gl_pow2((192 - 3 * brv5(16 + b)) % 192) : 1ull;
   }
 }
 
