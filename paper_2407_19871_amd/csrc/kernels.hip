@@ -758,6 +758,14 @@ __device__ __forceinline__ uint32_t ld_l2_u32(__amdgpu_buffer_rsrc_t r, uint32_t
 // The XCD this wave runs on.
 __device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
 
+// Rows of NTT-domain values in LDS with eight spare words after every 64:
+// offset o sits at o + 8 (o >> 6).  The split rotation reads them at the
+// inverse's positions (lane 8 r + h of wave w: 64 (h >> 1) + 16 w + 2 r +
+// (h & 1) + 256 s), where plain rows put four lanes of each half-wave on
+// one bank pair; the padding moves (h >> 1) onto banks 8 apart.
+constexpr int KROW = RING_N + RING_N / 8;
+__device__ __forceinline__ int kpad(int o) { return o + 8 * (o >> 6); }
+
 // Per-wave cycle counts of the phases of a split step (the profiling
 // instantiation only; the production one compiles none of it).  mark<K>()
 // adds the shader cycles since the previous mark to phase K; store() writes
@@ -806,7 +814,12 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, uint64_t* __restrict__ prof) {
   __shared__ uint32_t s_acc[RING_N];
   __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
-  __shared__ __align__(16) uint64_t s_part[3][RING_N];     // the levels' partials, NTT domain
+  // the levels' forward transforms and the step's key rows (c, j), both
+  // output components, NTT domain, rows padded (kpad) for conflict-free
+  // reads at the inverse's positions
+  __shared__ __align__(16) uint64_t s_part[3][KROW];
+  __shared__ __align__(16) uint64_t s_key[6][KROW];
+  __shared__ uint32_t s_D[RING_N];                          // X^a ACC_c - ACC_c
   __shared__ __align__(16) uint64_t s_t128[32 * T128_ROW];  // two-wave transpose
   // both twist tables, read every step at LDS latency instead of L2's
   __shared__ __align__(16) uint64_t s_twf[RING_N], s_twi[RING_N];
@@ -894,43 +907,37 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const __amdgpu_buffer_rsrc_t fr = l2_rsrc(sync, (SPLIT_FLAGS + (gridDim.x / 2) * SPLIT_FLAGS_PER_JOB) * 4u);
     const uint32_t my_xo = (uint32_t)(my_x - xbuf) * 8u, peer_xo = (uint32_t)(peer_x - xbuf) * 8u;
     const uint32_t my_fo = (uint32_t)(my_flag - sync) * 4u, peer_fo = (uint32_t)(peer_flag - sync) * 4u;
-    // this lane's four inverse positions (row `row`, q = 8 s + h8) and their
-    // NTT-domain offsets 64 (q >> 1) + 2 row + (q & 1)
-    int off[4];
+    // this lane's four inverse positions (row `row`, q = 8 s + h8): their
+    // NTT-domain offsets 64 (q >> 1) + 2 row + (q & 1) in the padded rows
+    int po[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) off[s] = 256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1);
+    for (int s = 0; s < 4; ++s) po[s] = kpad(256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1));
 
     for (int i = 0; i < nsteps; ++i) {
       const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
       if (a == 0) continue;  // X^0 ACC - ACC = 0: no digits, no exchange
       pc.start();
 
-      // the step's key rows (c, j), both components, at this lane's offsets:
-      // component c for this half's sum, 1 - c for the partner's
-      const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
-      uint64_t kc[3][4], ko[3][4];
+      // D = X^a ACC_c - ACC_c (coefficient k: ACC_c[(k - a) mod 2N] with the
+      // negacyclic sign, minus ACC_c[k]), four coefficients per thread
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          kc[j][s] = step_key[(size_t)((c * 3 + j) * 2 + c) * RING_N + off[s]];
-          ko[j][s] = step_key[(size_t)((c * 3 + j) * 2 + (1 - c)) * RING_N + off[s]];
-        }
-      int32_t dg[16];
-      if (lvl) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const uint32_t j = (uint32_t)(l + 32 * (2 * s + h));
-          const uint32_t e = (j - a) & 2047u;
-          const uint32_t v = s_acc[e & 1023u];
-          const uint32_t D = ((e & 1024u) ? (0u - v) : v) - s_acc[j];
-          dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
-        }
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t k = threadIdx.x + 256u * q;
+        const uint32_t e = (k - a) & 2047u;
+        const uint32_t v = s_acc[e & 1023u];
+        s_D[k] = ((e & 1024u) ? (0u - v) : v) - s_acc[k];
       }
       pc.template mark<0>();
-      __syncthreads();  // every wave has read ACC_c before any adds to it
+      __syncthreads();  // D is complete, and every wave has read ACC_c before any adds to it
       pc.template mark<1>();
+      const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
       if (lvl) {
+        int32_t dg[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const uint32_t D = s_D[l + 32 * (2 * s + h)];
+          dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
+        }
         uint64_t f[16];  // ntt64_fwd_digits with the twist factors from LDS
         fwd64_p1_digits(dg, f);
         fwd64_p1_rest(f, lane);
@@ -939,7 +946,20 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
         transpose64(f, buf, h, l);
         fwd64_p2(f, lane);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) s_part[wave][64 * s + 2 * l + h] = f[s];
+        for (int s = 0; s < 16; ++s) s_part[wave][kpad(64 * s + 2 * l + h)] = f[s];
+      } else {
+        // meanwhile the fourth wave stages the step's key rows (c, j) in
+        // LDS: row 2 j + 0 for output component c, 2 j + 1 for 1 - c
+#pragma unroll 1
+        for (int r = 0; r < 6; ++r) {
+          const int j = r >> 1, comp = (r & 1) ? 1 - c : c;
+          const gmem_u64* src_row = step_key + (size_t)((c * 3 + j) * 2 + comp) * RING_N;
+          uint64_t t[16];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) t[k] = src_row[lane + 64 * k];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) s_key[r][kpad(lane + 64 * k)] = t[k];
+        }
       }
       pc.template mark<2>();
       __syncthreads();
@@ -952,8 +972,8 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) F[j][s] = s_part[j][off[s]];
-        oth[s] = gl_mul_sum3(F[0][s], ko[0][s], F[1][s], ko[1][s], F[2][s], ko[2][s]);
+        for (int j = 0; j < 3; ++j) F[j][s] = s_part[j][po[s]];
+        oth[s] = gl_mul_sum3(F[0][s], s_key[1][po[s]], F[1][s], s_key[3][po[s]], F[2][s], s_key[5][po[s]]);
       }
       const uint32_t par = (done & 1u) * RING_N;
       const uint32_t slot = par + 64 * wave + lane;  // + 256 s
@@ -998,7 +1018,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       }
       uint64_t own[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) own[s] = gl_mul_sum3(F[0][s], kc[0][s], F[1][s], kc[1][s], F[2][s], kc[2][s]);
+      for (int s = 0; s < 4; ++s) own[s] = gl_mul_sum3(F[0][s], s_key[0][po[s]], F[1][s], s_key[2][po[s]], F[2][s], s_key[4][po[s]]);
       // every own product before the first wait for the partner's (ordered
       // empty asm statements that the sums depend on)
 #pragma unroll

@@ -237,16 +237,16 @@ def test_give_up_fails_the_server_request_only(monkeypatch, okeys, octx, split_t
 
 def test_split_profile_reports_every_phase(okeys, dkey):
     """The profiling build of the split rotation: every wave reports every
-    phase; the level waves spend their forward transform where the fourth
-    wave waits, and all four meet at the barriers, so their step totals
-    agree."""
+    phase; the fourth wave stages the step's key while the level waves run
+    their forward transforms, which take longer, so it then waits for them;
+    all four meet at the barriers, so their step totals agree."""
     ct = lp.to_device(O.encrypt_bits(okeys, [1, 0, 1, 1, 0, 0, 1, 0], seed=5))
     r = lp.debug_split_profile(dkey, ct)
     assert r["ms"] > 0
     assert len(r["waves"]) == 4
     for w in r["waves"]:
         assert set(w) == set(lp.SPLIT_PHASES) and all(v >= 0 for v in w.values())
-    assert r["waves"][0]["forward"] > 10 * r["waves"][3]["forward"]
+    assert r["waves"][0]["forward"] > r["waves"][3]["forward"] > 0
     assert r["waves"][3]["barrier_f"] > 10 * r["waves"][0]["barrier_f"]
     sums = [sum(w.values()) for w in r["waves"]]
     assert max(sums) < 1.05 * min(sums)
