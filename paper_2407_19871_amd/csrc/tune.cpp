@@ -88,10 +88,10 @@ int default_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   return sp;
 }
 
-// MI355X, n = 630: split 9.0-9.4 ms per launch up to 128 rotations; four
-// waves 13.2 ms up to 256 (one rotation per CU); four waves two per CU
-// 19.8 ms at 384-512 and 29.7 ms at 768 (three waves: 24.8 and 37.1); two
-// waves, one per component, 36.5 ms at 1024 (one wave 38.2, four waves
+// MI355X, n = 630: split 7.0-7.2 ms per launch up to 128 rotations; four
+// waves 13.1 ms up to 256 (one rotation per CU); four waves two per CU
+// 19.5 ms at 384-512 and 29.7 ms at 768 (three waves: 24.8 and 37.1); two
+// waves, one per component, 34.8 ms at 1024 (one wave 38.2, four waves
 // 38.0); four waves again at 1280 (47.2 ms, one wave 54.5); one wave from
 // 1536 (54-55 ms up to 2048).
 int default_br_wpb(size_t njobs) {
