@@ -250,3 +250,16 @@ def test_split_profile_reports_every_phase(okeys, dkey):
     assert r["waves"][3]["barrier_f"] > 10 * r["waves"][0]["barrier_f"]
     sums = [sum(w.values()) for w in r["waves"]]
     assert max(sums) < 1.05 * min(sums)
+
+
+def test_area_reused_across_launch_widths(okeys, octx, dkey, split_table):
+    """One exchange area (the allocation-free entry's static one) serves split
+    launches of different widths back to back, each bit-exact against the
+    oracle: no exchange word or step flag of one launch leaks into the next,
+    whichever XCDs its pairs ran on."""
+    for k, cnt in enumerate((128, 37, 128, 1, 64, 128)):
+        bits = [W.random_bits(9100 + 10 * k + i, cnt) for i in range(2)]
+        c1, c2 = (O.encrypt_bits(okeys, b, seed=9200 + 10 * k + i) for i, b in enumerate(bits))
+        got = as_u32(lp.bootstrap_batch_noalloc(dkey, "NAND", lp.to_device(c1), lp.to_device(c2)))
+        exp, _ = octx.gate_batch("NAND", c1, c2)
+        assert (got == exp).all(), cnt
