@@ -65,8 +65,10 @@ OPS_PER_STEP = {
     "u32_add": 2048 + 3 * 6144 + 2 * 2048,
 }
 N_STEPS = 630
-KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd/csrc/ntt32.h",
-                  "paper_2407_19871_amd/csrc/ntt64.h", "paper_2407_19871_amd/csrc/gl64.h"]
+KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd/csrc/split.hip",
+                  "paper_2407_19871_amd/csrc/kernel_util.h", "paper_2407_19871_amd/csrc/ntt32.h",
+                  "paper_2407_19871_amd/csrc/ntt64.h", "paper_2407_19871_amd/csrc/gl64.h",
+                  "paper_2407_19871_amd/_build.py"]
 # blind-rotation kernel of each launch shape (waves per bootstrap)
 SHAPE_KERNEL = {1: "blind_rotate_kernel<1>", 2: "blind_rotate_pair_kernel", 3: "blind_rotate_kernel<3>",
                 4: "blind_rotate_kernel<4>", 5: "blind_rotate_kernel<5>", 6: "blind_rotate_split_kernel"}

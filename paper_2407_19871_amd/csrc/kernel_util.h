@@ -1,0 +1,84 @@
+// Device helpers shared by the blind-rotation kernels (kernels.hip) and the
+// split rotation (split.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lp {
+
+constexpr int RING_N = 1024;
+constexpr int ROW = 33;             // padded LDS row (32-bit words) of a 32 x 32 transpose
+constexpr int LDS_HALF = 32 * ROW;  // words per half-wave transpose block
+constexpr int MAX_LWE = 1024;
+
+// Orders this wave's LDS accesses (DS operations of one wave execute in
+// program order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Hides a (uniform) pointer's value from the optimizer so that loads
+// through it stay inside the loop that uses them: hoisting the 64 twiddle
+// loads out of the step loop would pin 128 VGPRs for the whole kernel.
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// The value held by lane ^ 32.
+__device__ __forceinline__ uint64_t from_other_half(uint64_t v, int lane) {
+  const int addr = (lane ^ 32) << 2;
+  uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The bootstrapping key as a global-address-space pointer: the key table
+// yields a generic pointer, and loads through it would otherwise be FLAT
+// loads that also count against the LDS wait counter.
+typedef __attribute__((address_space(1))) const uint64_t gmem_u64;
+__device__ __forceinline__ const gmem_u64* as_global(const uint64_t* p) {
+  return (const gmem_u64*)(const void*)p;
+}
+
+// ---- whole-wave transforms (layout of ntt64.h) ------------------------------
+// 32 x 32 transpose of one polynomial held by a whole wave: on entry lane
+// (h, l) slot s holds element (l, 2s + h) of the matrix; on exit element
+// (2s + h, l).  Two 32-bit passes through a 32 x 33 word block.
+__device__ __forceinline__ void transpose64(uint64_t (&a)[16], uint32_t* buf, int h, int l) {
+  uint32_t lo[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)a[s];
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) lo[s] = buf[(2 * s + h) * ROW + l];
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)(a[s] >> 32);
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) a[s] = ((uint64_t)buf[(2 * s + h) * ROW + l] << 32) | lo[s];
+  wave_fence();
+}
+
+constexpr int T128_ROW = 36;  // u64 words per row of a two-wave transpose (bank spread)
+
+
+__device__ __forceinline__ void vm_wait_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace lp

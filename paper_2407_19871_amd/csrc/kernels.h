@@ -91,6 +91,12 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
                                int steps, int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
                                const SplitArea* split = nullptr);
 
+// The split rotation's launch (waves_per_job 6), in split.hip; `split`
+// must have room for njobs.
+hipError_t launch_split(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
+                        const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
+                        int raw_acc, Twiddles tw, const SplitArea* split, hipStream_t s);
+
 // The split rotation's profiling instantiation (waves_per_job 6, raw
 // accumulators into d_ex): every wave of every workgroup writes, at
 // d_prof + (block * 4 + wave) * kSplitPhaseWords, its shader cycles in each

@@ -24,48 +24,12 @@
 
 #include "gl64.h"
 #include "jobs.h"
+#include "kernel_util.h"
 #include "kernels.h"
 #include "ntt32.h"
 #include "ntt64.h"
 
 namespace lp {
-
-constexpr int RING_N = 1024;
-constexpr int ROW = 33;             // padded LDS row (32-bit words) of a 32 x 32 transpose
-constexpr int LDS_HALF = 32 * ROW;  // words per half-wave transpose block
-constexpr int MAX_LWE = 1024;
-
-// Orders this wave's LDS accesses (DS operations of one wave execute in
-// program order; this keeps the compiler from moving them).
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Hides a (uniform) pointer's value from the optimizer so that loads
-// through it stay inside the loop that uses them: hoisting the 64 twiddle
-// loads out of the step loop would pin 128 VGPRs for the whole kernel.
-template <typename T>
-__device__ __forceinline__ const T* opaque(const T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-
-// The value held by lane ^ 32.
-__device__ __forceinline__ uint64_t from_other_half(uint64_t v, int lane) {
-  const int addr = (lane ^ 32) << 2;
-  uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// The bootstrapping key as a global-address-space pointer: the key table
-// yields a generic pointer, and loads through it would otherwise be FLAT
-// loads that also count against the LDS wait counter.
-typedef __attribute__((address_space(1))) const uint64_t gmem_u64;
-__device__ __forceinline__ const gmem_u64* as_global(const uint64_t* p) {
-  return (const gmem_u64*)(const void*)p;
-}
 
 // 32 x 32 transpose through a half-wave LDS block of 32 x 33 words, in two
 // 32-bit passes (low words, then high words): on entry lane l holds row l
@@ -128,26 +92,6 @@ __device__ __forceinline__ void ntt_inv(uint64_t (&f)[32], uint32_t* buf, const 
   twist(f, tw_i, l);
   transpose32(f, buf, l);
   inv1(f);
-}
-
-// ---- whole-wave transforms (layout of ntt64.h) ------------------------------
-// 32 x 32 transpose of one polynomial held by a whole wave: on entry lane
-// (h, l) slot s holds element (l, 2s + h) of the matrix; on exit element
-// (2s + h, l).  Two 32-bit passes through a 32 x 33 word block.
-__device__ __forceinline__ void transpose64(uint64_t (&a)[16], uint32_t* buf, int h, int l) {
-  uint32_t lo[16];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)a[s];
-  wave_fence();
-#pragma unroll
-  for (int s = 0; s < 16; ++s) lo[s] = buf[(2 * s + h) * ROW + l];
-  wave_fence();
-#pragma unroll
-  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)(a[s] >> 32);
-  wave_fence();
-#pragma unroll
-  for (int s = 0; s < 16; ++s) a[s] = ((uint64_t)buf[(2 * s + h) * ROW + l] << 32) | lo[s];
-  wave_fence();
 }
 
 // Slot s of lane (h, l) times tw[(2s + h) * 32 + l] (the 32-lane tables,
@@ -217,8 +161,6 @@ __global__ __launch_bounds__(64) void bsk_to_ntt_kernel(const uint32_t* __restri
 //          more barrier per step (76 KB of LDS).
 // The accumulator lives in LDS ([component][coefficient] u32); each level
 // re-reads it to form X^a ACC - ACC.
-constexpr int T128_ROW = 36;  // u64 words per row of a two-wave transpose (bank spread)
-
 template <int W>
 __global__ __launch_bounds__(64 * (W == 5 ? 4 : W), (W == 1 || W == 5) ? 2 : 1) void blind_rotate_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
@@ -651,452 +593,6 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
   }
 }
 
-// ---------------------------------------------------------------------------
-// Split blind rotation: one bootstrap on two workgroups of four waves,
-// normally on two CUs of one XCD, for levels too narrow to fill the GPU.
-// Workgroup role c owns accumulator component c (0 = mask A, 1 = body B);
-// its wave j < 3 runs the forward transform of gadget level j (whole-wave
-// transforms, ntt64.h).  Output component c needs the digits of both
-// components,
-//   S_c = sum_j NTT(d_(c,j)) BSK[(c,j)][c] + sum_j NTT(d_(1-c,j)) BSK[(1-c,j)][c],
-// so every step each role forms its own half of S_c and the half of
-// S_(1-c) its digits contribute, and trades the latter with its partner:
-//   1. D_c = X^a ACC_c - ACC_c, digits of level j -> forward NTT F_(c,j)
-//      on wave j, copied to LDS;
-//   2. all four waves, each at the 256 NTT-domain positions its part of
-//      the inverse reads (eight lanes per row, ntt64.h): the two sums over
-//      the levels, sum_j F_(c,j) BSK[(c,j)][c] and sum_j F_(c,j)
-//      BSK[(c,j)][1-c], one reduction each;
-//   3. wave w stores the second sum in its slot of this role's exchange
-//      area, raises its flag to the step count, waits for the partner
-//      wave w's flag and loads the partner's sum for these positions;
-//   4. the four waves invert S_c together and add its centred lift to ACC_c.
-// When both halves run on one XCD, exchange data and flags go through that
-// XCD's L2 (plain stores, device-scope loads); otherwise they are
-// agent-scope relaxed atomics.  Either way a full vector memory wait orders
-// the data before the flag, and the data loads follow the observed flag.
-// Slots alternate by the parity of the executed-step
-// count: a role rewrites a slot only after the partner has raised its flag
-// for the following step, which it does after its loads of that slot.
-//
-// Pairing: a workgroup draws a ticket on arrival from the counter of its
-// class x = blockIdx % 8 (the XCD that round-robin dispatch gives it);
-// tickets 2k and 2k + 1 of a class form a pair (job 8 k + x, role t & 1).
-// Arrival order is not launch order, so pairing by class rather than by
-// arrival keeps both halves on one XCD.  The grid is a multiple of 16, so
-// every class holds an even count and every ticket finds its partner; at
-// most one workgroup per class waits for a partner, so no co-residency is
-// assumed.  Every wait is bounded:
-// a partner missing for SPLIT_SPIN_LIMIT polls ends the wait, counts in
-// g_split_stalls and in the area's own status word, marks the job, and the
-// job's output is then undefined; the kernel still exits.  Each half
-// clears its step flags when it starts, and the last workgroup to finish
-// clears the tickets and the XCD-id words; the status word and the
-// job marks stay until the host has read them (split_area_take_stalls), so
-// every call that launched the kernel can report a give-up as an error.
-constexpr int SPLIT_SPIN_LIMIT = 1 << 22;
-constexpr int SPLIT_DONE = 8;    // finish counter (words 0-7: ticket counters per class)
-constexpr int SPLIT_STATUS = 9;  // waits of this area that ran out, until the host clears it
-constexpr int SPLIT_FLAGS = 64;  // first flag word of the sync area
-constexpr int SPLIT_FLAGS_PER_JOB = 16;  // [role 2][8]: the four waves' step flags, then the XCD id in word 7
-
-__device__ uint32_t g_split_stalls;
-
-__device__ __forceinline__ void vm_wait_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
-__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t load_agent(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Accesses of an exchange between two workgroups on one XCD, through that
-// XCD's L2 (the coherence point of its CUs): plain stores, which write
-// through the CU's L1 into the L2; loads with sc1 (device scope), which miss
-// the reading CU's L1 and are served by the L2.  Agent-scope stores would
-// write through to memory and reach the partner several times later.
-// Buffer resources (raw, no stride) over the exchange slots and the sync
-// words.  No access is volatile: the compiler would complete each volatile
-// access before the next one (and widen it to system scope).  Order comes
-// from an explicit wait for the data stores before the flag store, a
-// compiler memory barrier in every poll iteration (so the flag is read
-// anew) and one after the poll.
-//
-// Such plain stores may leave the lines dirty in that L2 until the kernel
-// ends, when every L2 writes its dirty bytes back.  So no word an exchange
-// writes this way may be written from another XCD during the same launch:
-// each workgroup clears its own step flags at its start (before it announces
-// itself to its partner) rather than the last workgroup clearing all of
-// them at the end.
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t l2_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
-}
-constexpr int kL2Load = 0x10;  // sc1
-__device__ __forceinline__ void st_l2(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t v) {
-  const u32x2 x = {(uint32_t)v, (uint32_t)(v >> 32)};
-  __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
-}
-__device__ __forceinline__ uint64_t ld_l2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kL2Load);
-  return ((uint64_t)x.y << 32) | x.x;
-}
-__device__ __forceinline__ void st_l2_u32(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v) {
-  __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
-}
-__device__ __forceinline__ uint32_t ld_l2_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  asm volatile("" ::: "memory");
-  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kL2Load);
-}
-// The XCD this wave runs on.
-__device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
-
-// Rows of NTT-domain values in LDS with eight spare words after every 64:
-// offset o sits at o + 8 (o >> 6).  The split rotation reads them at the
-// inverse's positions (lane 8 r + h of wave w: 64 (h >> 1) + 16 w + 2 r +
-// (h & 1) + 256 s), where plain rows put four lanes of each half-wave on
-// one bank pair; the padding moves (h >> 1) onto banks 8 apart.
-constexpr int KROW = RING_N + RING_N / 8;
-__device__ __forceinline__ int kpad(int o) { return o + 8 * (o >> 6); }
-
-// Per-wave cycle counts of the phases of a split step (the profiling
-// instantiation only; the production one compiles none of it).  mark<K>()
-// adds the shader cycles since the previous mark to phase K; store() writes
-// phases 0..kPhases-1 and the executed-step count for this wave.
-// Scheduling barriers around each clock read keep the compiler from moving
-// work across a phase boundary (the profiling build schedules a little
-// differently for it).
-constexpr int kSplitPhases = 12;
-template <bool PROF>
-struct PhaseClock {
-  uint64_t t = 0;
-  uint64_t acc[kSplitPhases] = {};
-  __device__ __forceinline__ void start() {
-    if constexpr (PROF) {
-      __builtin_amdgcn_sched_barrier(0);
-      t = __builtin_amdgcn_s_memtime();
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  template <int K>
-  __device__ __forceinline__ void mark() {
-    if constexpr (PROF) {
-      __builtin_amdgcn_sched_barrier(0);
-      const uint64_t n = __builtin_amdgcn_s_memtime();
-      __builtin_amdgcn_sched_barrier(0);
-      acc[K] += n - t;
-      t = n;
-    }
-  }
-  __device__ __forceinline__ void store(uint64_t* out, int lane, uint32_t done) {
-    if constexpr (PROF) {
-      if (out && lane == 0) {
-#pragma unroll
-        for (int k = 0; k < kSplitPhases; ++k) out[k] = acc[k];
-        out[kSplitPhases] = done;
-      }
-    }
-  }
-};
-
-template <bool PROF>
-__global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
-    const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
-    const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
-    int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
-    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, uint64_t* __restrict__ prof) {
-  __shared__ uint32_t s_acc[RING_N];
-  __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
-  // the levels' forward transforms and the step's key rows (c, j), both
-  // output components, NTT domain, rows padded (kpad) for conflict-free
-  // reads at the inverse's positions
-  __shared__ __align__(16) uint64_t s_part[3][KROW];
-  __shared__ __align__(16) uint64_t s_key[6][KROW];
-  __shared__ uint32_t s_D[RING_N];                          // X^a ACC_c - ACC_c
-  __shared__ __align__(16) uint64_t s_t128[32 * T128_ROW];  // two-wave transpose
-  // both twist tables, read every step at LDS latency instead of L2's
-  __shared__ __align__(16) uint64_t s_twf[RING_N], s_twi[RING_N];
-  __shared__ uint16_t s_abar[MAX_LWE + 4];
-  __shared__ uint32_t s_ticket, s_last, s_local;
-
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
-  const bool lvl = wave < 3;  // waves 0-2 run the gadget levels; all four invert
-  // four-wave inverse: row (or column) 8 wave + r8, lane h8 of the row's eight
-  const int r8 = lane >> 3, h8 = lane & 7, row = 8 * wave + r8;
-  const uint64_t upper1 = (h8 & 1) ? ~0ull : 0ull, upper2 = (h8 & 2) ? ~0ull : 0ull,
-                 upper4 = (h8 & 4) ? ~0ull : 0ull;
-  uint64_t w2[4], w1[4];
-  inv256_twiddles(h8, w2, w1);
-  for (int k = threadIdx.x; k < RING_N; k += 256) {
-    s_twf[k] = tw_f[k];
-    s_twi[k] = tw_i[k];
-  }
-  const int cls = (int)(blockIdx.x & 7u);
-  if (threadIdx.x == 0) s_ticket = atomicAdd(sync + cls, 1u);
-  __syncthreads();
-  const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_ticket);
-  const int job = (int)(t >> 1) * 8 + cls;
-  const int c = (int)(t & 1u);
-
-  if (job < njobs) {
-    const BrJob J = jobs[job];
-    uint32_t* buf = s_tr[lvl ? wave : 0];
-    {
-      auto operand = [&](uint32_t r) -> const uint32_t* {
-        if (r == REF_NONE) return nullptr;
-        const uint32_t base = r >> REF_SHIFT;
-        const uint32_t* b = base == KEY_POOL_BASE ? pool_tab[J.key] : src.p[base];
-        return b + (size_t)(r & REF_INDEX_MASK) * (n_lwe + 1);
-      };
-      const uint32_t* in0 = operand(J.in0);
-      const uint32_t* in1 = operand(J.in1);
-      for (int k = threadIdx.x; k <= n_lwe; k += 256) {
-        uint32_t v = (k == n_lwe) ? J.cst : 0u;
-        if (in0) v += (uint32_t)J.c0 * in0[k];
-        if (in1) v += (uint32_t)J.c1 * in1[k];
-        s_abar[k] = (uint16_t)(((v + (1u << 20)) >> 21) & 2047u);
-      }
-    }
-    __syncthreads();
-    // ACC_0 = 0, ACC_1 = X^{-b} v (coefficient j: +1/8 if (j + b) mod 2N < N)
-    const uint32_t bbar = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[n_lwe]);
-    for (int j = threadIdx.x; j < RING_N; j += 256)
-      s_acc[j] = c == 0 ? 0u : ((((uint32_t)j + bbar) & 2047u) < 1024u ? 0x20000000u : 0xE0000000u);
-    __syncthreads();
-
-    const gmem_u64* bsk = as_global(bsk_tab[J.key]);
-    const int nsteps = steps < n_lwe ? steps : n_lwe;
-    // wave w trades with the partner's wave w: the partner's component of the
-    // key products at the NTT-domain offsets both waves' inverses read
-    uint64_t* my_x = xbuf + (size_t)(job * 2 + c) * 2 * RING_N;
-    const uint64_t* peer_x = xbuf + (size_t)(job * 2 + (1 - c)) * 2 * RING_N;
-    uint32_t* my_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8 + wave;
-    const uint32_t* peer_flag = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + wave;
-    const int sh = 25 - 7 * wave;
-    uint32_t done = 0;  // executed steps, the same count in both roles
-    bool stalled = false;
-    PhaseClock<PROF> pc;
-    // Both halves on one XCD (the normal placement of the class pairing)
-    // trade through that XCD's L2; otherwise past it, as agent-scope
-    // accesses.  Each half clears its own step flags, then publishes its XCD
-    // id in its spare flag word 7; the partner reads its flags only after
-    // that word (bounded wait as for the products).  Word 7 is only ever
-    // accessed at agent scope, and the last workgroup clears it.
-    const uint32_t my_xcc = xcc_id();
-    if (threadIdx.x == 0) {
-      uint32_t* mine = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + c * 8;
-      for (int w = 0; w < 4; ++w) store_agent(mine + w, 0u);
-      vm_wait_all();
-      store_agent(mine + 7, my_xcc + 1);
-      const uint32_t* px = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + 7;
-      uint32_t v = 0;
-      for (int it = 0; it < spin_limit && (v = load_agent(px)) == 0; ++it) __builtin_amdgcn_s_sleep(1);
-      s_local = v == my_xcc + 1 ? 1u : 0u;
-    }
-    __syncthreads();
-    const bool local = __builtin_amdgcn_readfirstlane((int)s_local) != 0;
-    const __amdgpu_buffer_rsrc_t xr = l2_rsrc(xbuf, (gridDim.x / 2) * 4u * RING_N * 8u);
-    const __amdgpu_buffer_rsrc_t fr = l2_rsrc(sync, (SPLIT_FLAGS + (gridDim.x / 2) * SPLIT_FLAGS_PER_JOB) * 4u);
-    const uint32_t my_xo = (uint32_t)(my_x - xbuf) * 8u, peer_xo = (uint32_t)(peer_x - xbuf) * 8u;
-    const uint32_t my_fo = (uint32_t)(my_flag - sync) * 4u, peer_fo = (uint32_t)(peer_flag - sync) * 4u;
-    // this lane's four inverse positions (row `row`, q = 8 s + h8): their
-    // NTT-domain offsets 64 (q >> 1) + 2 row + (q & 1) in the padded rows
-    int po[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) po[s] = kpad(256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1));
-
-    for (int i = 0; i < nsteps; ++i) {
-      const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
-      if (a == 0) continue;  // X^0 ACC - ACC = 0: no digits, no exchange
-      pc.start();
-
-      // D = X^a ACC_c - ACC_c (coefficient k: ACC_c[(k - a) mod 2N] with the
-      // negacyclic sign, minus ACC_c[k]), four coefficients per thread
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t k = threadIdx.x + 256u * q;
-        const uint32_t e = (k - a) & 2047u;
-        const uint32_t v = s_acc[e & 1023u];
-        s_D[k] = ((e & 1024u) ? (0u - v) : v) - s_acc[k];
-      }
-      pc.template mark<0>();
-      __syncthreads();  // D is complete, and every wave has read ACC_c before any adds to it
-      pc.template mark<1>();
-      const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
-      if (lvl) {
-        int32_t dg[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const uint32_t D = s_D[l + 32 * (2 * s + h)];
-          dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
-        }
-        uint64_t f[16];  // ntt64_fwd_digits with the twist factors from LDS
-        fwd64_p1_digits(dg, f);
-        fwd64_p1_rest(f, lane);
-#pragma unroll
-        for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
-        transpose64(f, buf, h, l);
-        fwd64_p2(f, lane);
-#pragma unroll
-        for (int s = 0; s < 16; ++s) s_part[wave][kpad(64 * s + 2 * l + h)] = f[s];
-      } else {
-        // meanwhile the fourth wave stages the step's key rows (c, j) in
-        // LDS: row 2 j + 0 for output component c, 2 j + 1 for 1 - c
-#pragma unroll 1
-        for (int r = 0; r < 6; ++r) {
-          const int j = r >> 1, comp = (r & 1) ? 1 - c : c;
-          const gmem_u64* src_row = step_key + (size_t)((c * 3 + j) * 2 + comp) * RING_N;
-          uint64_t t[16];
-#pragma unroll
-          for (int k = 0; k < 16; ++k) t[k] = src_row[lane + 64 * k];
-#pragma unroll
-          for (int k = 0; k < 16; ++k) s_key[r][kpad(lane + 64 * k)] = t[k];
-        }
-      }
-      pc.template mark<2>();
-      __syncthreads();
-      pc.template mark<3>();
-
-      // the partner's component of the products, summed over the levels
-      // with one reduction, goes out first; this half's own follows while
-      // the partner's is on its way
-      uint64_t F[3][4], oth[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) F[j][s] = s_part[j][po[s]];
-        oth[s] = gl_mul_sum3(F[0][s], s_key[1][po[s]], F[1][s], s_key[3][po[s]], F[2][s], s_key[5][po[s]]);
-      }
-      const uint32_t par = (done & 1u) * RING_N;
-      const uint32_t slot = par + 64 * wave + lane;  // + 256 s
-      if (local) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) st_l2(xr, my_xo + (slot + 256 * s) * 8u, oth[s]);
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) store_agent(my_x + slot + 256 * s, oth[s]);
-      }
-      pc.template mark<4>();
-      vm_wait_all();
-      if (lane == 0) {
-        if (local) st_l2_u32(fr, my_fo, done + 1);
-        else store_agent(my_flag, done + 1);
-      }
-      pc.template mark<5>();
-      if (!stalled) {
-        int it = 0;
-        while ((local ? ld_l2_u32(fr, peer_fo) : load_agent(peer_flag)) < done + 1) {
-          if (++it >= spin_limit) break;
-          __builtin_amdgcn_s_sleep(1);
-        }
-        if (it >= spin_limit) {
-          stalled = true;
-          if (lane == 0) {
-            atomicAdd(&g_split_stalls, 1u);
-            atomicAdd(sync + SPLIT_STATUS, 1u);
-            store_agent(marks + job, 1u);
-          }
-        }
-      }
-      asm volatile("" ::: "memory");  // the partner's products are read after its flag
-      pc.template mark<6>();
-      uint64_t v[4];
-      if (local) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = ld_l2(xr, peer_xo + (slot + 256 * s) * 8u);
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = load_agent(peer_x + slot + 256 * s);
-      }
-      uint64_t own[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) own[s] = gl_mul_sum3(F[0][s], s_key[0][po[s]], F[1][s], s_key[2][po[s]], F[2][s], s_key[4][po[s]]);
-      // every own product before the first wait for the partner's (ordered
-      // empty asm statements that the sums depend on)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) asm volatile("" : "+v"(own[s]));
-#pragma unroll
-      for (int s = 0; s < 4; ++s) v[s] = gl_add(own[s], v[s]);
-      pc.template mark<7>();
-
-      // one inverse of the sum on all four waves: each holds eight rows at
-      // eight lanes per row
-      {
-        inv256_p2(v, upper1, upper2, upper4, w2);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], s_twi[h8 * 32 + row + s * 256]);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) s_t128[row * T128_ROW + 8 * s + h8] = v[s];
-        pc.template mark<8>();
-        __syncthreads();
-        pc.template mark<9>();
-        // column j1 = row of this lane, positions q = 8 s + h8
-#pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = s_t128[(8 * s + h8) * T128_ROW + row];
-        inv256_p1(v, upper1, upper2, upper4, w1);
-        // the sum is an exact integer polynomial (|coefficient| < 2^50.6),
-        // so its centred lift reduced mod 2^32 is exact
-#pragma unroll
-        for (int s = 0; s < 4; ++s) s_acc[row + 32 * (8 * s + h8)] += gl_lift_u32(v[s]);
-      }
-      pc.template mark<10>();
-      ++done;
-      __syncthreads();
-      pc.template mark<11>();
-    }
-    pc.store(prof ? prof + ((size_t)blockIdx.x * 4 + wave) * kSplitPhaseWords : nullptr, lane, done);
-
-    if (raw_acc) {
-      uint32_t* o = ex_out + (size_t)J.out * (2 * RING_N) + c * RING_N;
-      for (int j = threadIdx.x; j < RING_N; j += 256) o[j] = s_acc[j];
-    } else {
-      // sample extraction at coefficient 0: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0
-      uint32_t* o = ex_out + (size_t)J.out * (RING_N + 1);
-      if (c == 0) {
-        for (int j = threadIdx.x; j < RING_N; j += 256) {
-          if (j == 0) o[0] = s_acc[0];
-          else o[RING_N - j] = 0u - s_acc[j];
-        }
-      } else if (threadIdx.x == 0) {
-        o[RING_N] = s_acc[0];
-      }
-    }
-  }
-
-  // the last workgroup to finish clears the tickets and the XCD-id words
-  // for the next launch on this area (every other one has finished using
-  // them); the step flags are their owners' to clear
-  vm_wait_all();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = atomicAdd(sync + SPLIT_DONE, 1u) == gridDim.x - 1 ? 1u : 0u;
-  __syncthreads();
-  if (s_last) {
-    const int nroles = (int)gridDim.x;  // two roles per job slot
-    for (int k = threadIdx.x; k < nroles; k += 256) store_agent(sync + SPLIT_FLAGS + k * 8 + 7, 0u);
-    if (threadIdx.x <= SPLIT_DONE) store_agent(sync + threadIdx.x, 0u);  // the 8 class counters and the finish count
-  }
-}
-
-__global__ void split_area_clear_kernel(uint32_t* sync, int words) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < words) sync[k] = 0u;
-}
-
-// ---------------------------------------------------------------------------
-// Key switching: a tile of T jobs x 64 output columns per wave.  For every
-// (i, j) the wave reads the base-1 KSK rows of that digit position once and
-// each job of the tile subtracts the row its digit selects.  With
-// gridDim.z > 1 the ring index i is split into gridDim.z ranges; each block
-// subtracts its partial sum atomically from an output that ks_init_kernel
-// set to (0, b') (u32 wrap-around addition is exact and order-free).
 template <int T, int BB>
 __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__ jobs, int njobs,
                                                        const uint32_t* __restrict__ ex, DstBases dst,
@@ -1262,9 +758,6 @@ hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, 
   return hipGetLastError();
 }
 
-int split_spin_limit();
-static size_t split_marks_offset(int max_jobs);
-
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                                const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
                                int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
@@ -1291,141 +784,12 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
       hipLaunchKernelGGL(blind_rotate_kernel<5>, dim3(njobs), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab,
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
-    case 6: {
-      if (!split || !split->xbuf || !split->sync || njobs > split->max_jobs) return hipErrorInvalidValue;
-      const int grid = 16 * ((njobs + 7) / 8);
-      hipLaunchKernelGGL(blind_rotate_split_kernel<false>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
-                         d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
-                         split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), nullptr);
-      break;
-    }
+    case 6:
+      return launch_split(d_jobs, njobs, src, d_ex, d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw, split, s);
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
-}
-
-hipError_t launch_split_profiled(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
-                                 const uint64_t* const* d_bsk_tab, int n_lwe, int steps, Twiddles tw,
-                                 int waves_per_job, const SplitArea* split, uint64_t* d_prof, hipStream_t s) {
-  if (njobs <= 0) return hipSuccess;
-  if (!is_split(waves_per_job) || !split || !split->xbuf || !split->sync || njobs > split->max_jobs || !d_prof)
-    return hipErrorInvalidValue;
-  const int grid = 16 * ((njobs + 7) / 8);
-  hipLaunchKernelGGL(blind_rotate_split_kernel<true>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
-                     d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
-                     split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), d_prof);
-  return hipGetLastError();
-}
-
-static int split_jobs_padded(int max_jobs) { return (max_jobs + 7) / 8 * 8; }
-
-// Polls of a split wait before it gives up: SPLIT_SPIN_LIMIT, or a smaller
-// positive LOCPIR_SPLIT_SPIN (tests force the give-up path with it; every
-// wave still runs to the end).
-int split_spin_limit() {
-  const char* v = std::getenv("LOCPIR_SPLIT_SPIN");
-  const long x = (v && *v) ? std::atol(v) : 0;
-  return x > 0 && x < SPLIT_SPIN_LIMIT ? (int)x : SPLIT_SPIN_LIMIT;
-}
-size_t split_xbuf_bytes(int max_jobs) { return (size_t)split_jobs_padded(max_jobs) * 4 * RING_N * 8; }
-// sync area: 64 control words, 16 flag words per job, then one give-up mark per job
-static size_t split_marks_offset(int max_jobs) {
-  return (size_t)SPLIT_FLAGS + (size_t)split_jobs_padded(max_jobs) * SPLIT_FLAGS_PER_JOB;
-}
-size_t split_sync_bytes(int max_jobs) {
-  return (split_marks_offset(max_jobs) + split_jobs_padded(max_jobs)) * 4;
-}
-
-hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* count, std::vector<int>* jobs) {
-  if (!a || !count) return hipErrorInvalidValue;
-  *count = 0;
-  if (jobs) jobs->clear();
-  if (!a->sync) return hipSuccess;
-  uint32_t st = 0;
-  hipError_t e = hipMemcpyAsync(&st, a->sync + SPLIT_STATUS, 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess || st == 0) return e;
-  const int padded = split_jobs_padded(a->max_jobs);
-  uint32_t* dm = a->sync + split_marks_offset(a->max_jobs);
-  if (jobs) {
-    std::vector<uint32_t> marks(padded);
-    e = hipMemcpyAsync(marks.data(), dm, (size_t)padded * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    for (int j = 0; j < padded; ++j)
-      if (marks[j]) jobs->push_back(j);
-  }
-  // clear the status word and the marks for the next launch on this area
-  hipLaunchKernelGGL(split_area_clear_kernel, dim3(1), dim3(256), 0, s, a->sync + SPLIT_STATUS, 1);
-  hipLaunchKernelGGL(split_area_clear_kernel, dim3((padded + 255) / 256), dim3(256), 0, s, dm, padded);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  *count = st;
-  return e;
-}
-
-hipError_t launch_clear_words(uint32_t* d, size_t words, hipStream_t s) {
-  if (words == 0) return hipSuccess;
-  if (!d || words > (size_t)INT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(split_area_clear_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, d, (int)words);
-  return hipGetLastError();
-}
-
-hipError_t split_area_alloc(SplitArea* a, int max_jobs) {
-  if (!a || max_jobs < 1 || max_jobs > kSplitMaxJobs) return hipErrorInvalidValue;
-  *a = SplitArea{};
-  hipError_t e = hipMalloc((void**)&a->xbuf, split_xbuf_bytes(max_jobs));
-  if (e == hipSuccess) e = hipMalloc((void**)&a->sync, split_sync_bytes(max_jobs));
-  if (e == hipSuccess) e = hipMemset(a->sync, 0, split_sync_bytes(max_jobs));
-  if (e != hipSuccess) {
-    split_area_free(a);
-    return e;
-  }
-  a->max_jobs = max_jobs;
-  return hipSuccess;
-}
-
-void split_area_free(SplitArea* a) {
-  if (!a) return;
-  if (a->xbuf) (void)hipFree(a->xbuf);
-  if (a->sync) (void)hipFree(a->sync);
-  *a = SplitArea{};
-}
-
-hipError_t split_area_alloc_async(SplitArea* a, int max_jobs, hipStream_t s) {
-  if (!a || max_jobs < 1 || max_jobs > kSplitMaxJobs) return hipErrorInvalidValue;
-  *a = SplitArea{};
-  hipError_t e = hipMallocAsync((void**)&a->xbuf, split_xbuf_bytes(max_jobs), s);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&a->sync, split_sync_bytes(max_jobs), s);
-  if (e == hipSuccess) {
-    const int words = (int)(split_sync_bytes(max_jobs) / 4);
-    hipLaunchKernelGGL(split_area_clear_kernel, dim3((words + 255) / 256), dim3(256), 0, s, a->sync, words);
-    e = hipGetLastError();
-  }
-  if (e != hipSuccess) {
-    (void)split_area_free_async(a, s);
-    return e;
-  }
-  a->max_jobs = max_jobs;
-  return hipSuccess;
-}
-
-hipError_t split_area_free_async(SplitArea* a, hipStream_t s) {
-  if (!a) return hipSuccess;
-  hipError_t e = hipSuccess;
-  if (a->xbuf) e = hipFreeAsync(a->xbuf, s);
-  if (a->sync) {
-    const hipError_t e2 = hipFreeAsync(a->sync, s);
-    if (e == hipSuccess) e = e2;
-  }
-  *a = SplitArea{};
-  return e;
-}
-
-hipError_t split_stall_count(uint32_t* out) {
-  if (!out) return hipErrorInvalidValue;
-  return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_split_stalls), sizeof(uint32_t), 0, hipMemcpyDeviceToHost);
 }
 
 template <int T>
