@@ -163,7 +163,8 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
-    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, uint64_t* __restrict__ prof) {
+    uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, int allow_l2,
+    uint64_t* __restrict__ prof) {
   __shared__ uint32_t s_acc[RING_N];
   __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
   // the levels' forward transforms and the step's key rows (c, j), both
@@ -237,8 +238,8 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     bool stalled = false;
     PhaseClock<PROF> pc;
     // Both halves on one XCD (the normal placement of the class pairing)
-    // trade through that XCD's L2; otherwise past it, as agent-scope
-    // accesses.  Each half clears its own step flags, then publishes its XCD
+    // trade through that XCD's L2, unless the launch forbids it (allow_l2 =
+    // 0); otherwise past it, as agent-scope accesses.  Each half clears its own step flags, then publishes its XCD
     // id in its spare flag word 7; the partner reads its flags only after
     // that word (bounded wait as for the products).  Word 7 is only ever
     // accessed at agent scope, and the last workgroup clears it.
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       const uint32_t* px = sync + SPLIT_FLAGS + job * SPLIT_FLAGS_PER_JOB + (1 - c) * 8 + 7;
       uint32_t v = 0;
       for (int it = 0; it < spin_limit && (v = load_agent(px)) == 0; ++it) __builtin_amdgcn_s_sleep(1);
-      s_local = v == my_xcc + 1 ? 1u : 0u;
+      s_local = allow_l2 && v == my_xcc + 1 ? 1u : 0u;
     }
     __syncthreads();
     const bool local = __builtin_amdgcn_readfirstlane((int)s_local) != 0;
@@ -450,6 +451,7 @@ __global__ void split_area_clear_kernel(uint32_t* sync, int words) {
 // subtracts its partial sum atomically from an output that ks_init_kernel
 // set to (0, b') (u32 wrap-around addition is exact and order-free).
 int split_spin_limit();
+static int split_allow_l2();
 static int split_jobs_padded(int max_jobs) { return (max_jobs + 7) / 8 * 8; }
 // sync area: 64 control words, 16 flag words per job, then one give-up mark per job
 static size_t split_marks_offset(int max_jobs) {
@@ -464,7 +466,8 @@ hipError_t launch_split(const BrJob* d_jobs, int njobs, const SrcBases& src, uin
   const int grid = 16 * ((njobs + 7) / 8);
   hipLaunchKernelGGL(blind_rotate_split_kernel<false>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
                      d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
-                     split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), nullptr);
+                     split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), split_allow_l2(),
+                     nullptr);
   return hipGetLastError();
 }
 
@@ -477,13 +480,22 @@ hipError_t launch_split_profiled(const BrJob* d_jobs, int njobs, const SrcBases&
   const int grid = 16 * ((njobs + 7) / 8);
   hipLaunchKernelGGL(blind_rotate_split_kernel<true>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
                      d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
-                     split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), d_prof);
+                     split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), split_allow_l2(),
+                     d_prof);
   return hipGetLastError();
 }
 
 // Polls of a split wait before it gives up: SPLIT_SPIN_LIMIT, or a smaller
 // positive LOCPIR_SPLIT_SPIN (tests force the give-up path with it; every
 // wave still runs to the end).
+// Whether pairs on one XCD may trade through its L2: 1, or 0 when
+// LOCPIR_SPLIT_AGENT=1 makes every pair trade at agent scope, as pairs on
+// two XCDs do (tests cover that path with it).
+static int split_allow_l2() {
+  const char* v = std::getenv("LOCPIR_SPLIT_AGENT");
+  return (v && v[0] == '1') ? 0 : 1;
+}
+
 int split_spin_limit() {
   const char* v = std::getenv("LOCPIR_SPLIT_SPIN");
   const long x = (v && *v) ? std::atol(v) : 0;

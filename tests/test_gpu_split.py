@@ -263,3 +263,23 @@ def test_area_reused_across_launch_widths(okeys, octx, dkey, split_table):
         got = as_u32(lp.bootstrap_batch_noalloc(dkey, "NAND", lp.to_device(c1), lp.to_device(c2)))
         exp, _ = octx.gate_batch("NAND", c1, c2)
         assert (got == exp).all(), cnt
+
+
+def test_agent_scope_exchange(monkeypatch, okeys, octx, dkey, split_table):
+    """Pairs whose halves run on two XCDs trade at agent scope instead of
+    through one XCD's L2.  Dispatch normally puts both halves on one XCD, so
+    LOCPIR_SPLIT_AGENT=1 forces that path on every pair: gates at two widths
+    and a whole query, run twice on one exchange area, stay bit-exact."""
+    monkeypatch.setenv("LOCPIR_SPLIT_AGENT", "1")
+    for cnt in (128, 37):
+        a, b = W.random_bits(9300 + cnt, cnt), W.random_bits(9400 + cnt, cnt)
+        c1, c2 = O.encrypt_bits(okeys, a, seed=9500 + cnt), O.encrypt_bits(okeys, b, seed=9600 + cnt)
+        got = as_u32(lp.bootstrap_batch(dkey, "NAND", lp.to_device(c1), lp.to_device(c2)))
+        exp, _ = octx.gate_batch("NAND", c1, c2)
+        assert (got == exp).all(), cnt
+    q = W.random_query_u8(33, force_inside=True)
+    parts = _query_parts(okeys, q, seed=34)
+    exp = octx.bbox_query(q.l, q.n_boxes, q.m, False, *parts)
+    for _ in range(2):
+        res = as_u32(lp.eval_bbox_query(dkey, q.l, q.n_boxes, q.m, False, *[lp.to_device(v) for v in parts]))
+        assert (res == exp).all()
