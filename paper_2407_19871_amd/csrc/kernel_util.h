@@ -63,6 +63,26 @@ __device__ __forceinline__ void transpose64(uint64_t (&a)[16], uint32_t* buf, in
   wave_fence();
 }
 
+// transpose64 from the pair layout of ntt64.h: on entry register r of lane
+// (h, l) holds element (l, 16h + 2(r & 7) + (r >> 3)); on exit slot s holds
+// element (2s + h, l), as for transpose64.
+__device__ __forceinline__ void transpose64_pairs(uint64_t (&a)[16], uint32_t* buf, int h, int l) {
+  uint32_t lo[16];
+  uint32_t* wr = buf + l * ROW + 16 * h;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) wr[2 * (r & 7) + (r >> 3)] = (uint32_t)a[r];
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) lo[s] = buf[(2 * s + h) * ROW + l];
+  wave_fence();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) wr[2 * (r & 7) + (r >> 3)] = (uint32_t)(a[r] >> 32);
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) a[s] = ((uint64_t)buf[(2 * s + h) * ROW + l] << 32) | lo[s];
+  wave_fence();
+}
+
 constexpr int T128_ROW = 36;  // u64 words per row of a two-wave transpose (bank spread)
 
 

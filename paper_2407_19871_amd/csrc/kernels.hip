@@ -94,31 +94,6 @@ __device__ __forceinline__ void ntt_inv(uint64_t (&f)[32], uint32_t* buf, const 
   inv1(f);
 }
 
-// Slot s of lane (h, l) times tw[(2s + h) * 32 + l] (the 32-lane tables,
-// position 2s + h standing for the 32-lane slot); for each slot the wave
-// reads 64 consecutive entries.
-__device__ __forceinline__ void twist64(uint64_t (&f)[16], const uint64_t* __restrict__ tw, int lane) {
-  const gmem_u64* t = as_global(tw) + lane;
-  uint64_t w[16];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) w[s] = t[s * 64];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], w[s]);
-}
-
-// Forward transform of gadget digits: in, slot s of lane (h, l) holds
-// coefficient l + 32 (2s + h); out, the value at offset 64 s + 2 l + h of
-// the NTT-domain key layout.
-__device__ __forceinline__ void ntt64_fwd_digits(const int32_t (&d)[16], uint64_t (&f)[16], uint32_t* buf,
-                                                 const uint64_t* __restrict__ tw_f, int lane) {
-  const int h = lane >> 5, l = lane & 31;
-  fwd64_p1_digits(d, f);
-  fwd64_p1_rest(f, lane);
-  twist64(f, tw_f, lane);
-  transpose64(f, buf, h, l);
-  fwd64_p2(f, lane);
-}
-
 // Offset of (slot s, lane l) inside one NTT-domain polynomial.
 __device__ __forceinline__ int ntt_pos(int s, int l) { return (s >> 1) * 64 + l * 2 + (s & 1); }
 
@@ -467,9 +442,12 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
 
   const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  const uint32_t h6 = 6u * (uint32_t)h;  // the lane's extra shift in a paired distance-1 stage
   const int job = blockIdx.x;
   if (job >= njobs) return;  // uniform over the block
-  for (int k = threadIdx.x; k < RING_N; k += 128) s_twf[k] = tw_f[k];
+  // entry 64 r + lane: the factor of register r of that lane in the pair
+  // layout that the forward's first pass leaves
+  for (int k = threadIdx.x; k < RING_N; k += 128) s_twf[k] = tw_f[pair_pos(k >> 6, (k >> 5) & 1) * 32 + (k & 31)];
 
   const BrJob J = jobs[job];
   {
@@ -533,13 +511,17 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
         const uint32_t D = ((e & 1024u) ? (0u - v) : v) - acc[k];
         dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
       }
-      uint64_t f[16];  // ntt64_fwd_digits with the twist factors at hand
+      // forward transform: both passes end in the paired distance-1 stage;
+      // the second is swapped back to the interleaved layout of the key rows
+      // and of the inverse
+      uint64_t f[16];
       fwd64_p1_digits(dg, f);
-      fwd64_p1_rest(f, lane);
+      fwd64_p1_rest_pairs(f, h6);
 #pragma unroll
       for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
-      transpose64(f, tbuf, h, l);
-      fwd64_p2(f, lane);
+      transpose64_pairs(f, tbuf, h, l);
+      fwd64_p2_pairs(f, h6);
+      pairs_to_interleaved(f);
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         if constexpr (decltype(first)::value) {

@@ -99,6 +99,85 @@ __device__ __forceinline__ void ct64_cross(uint64_t (&a)[16], Zf zf, int lane) {
   });
 }
 
+// ---- the distance-1 stage on slot pairs --------------------------------------
+// v_permlane32_swap of two different registers trades the upper half-wave of
+// `a` for the lower half-wave of `b`.  For the slots (s, s + 8) that leaves
+// every lane with both values of one column pair: the lower lane gets
+// (position 2s, position 2s + 1) of its column, the upper lane (2s + 16,
+// 2s + 17).  Applied again, it restores the interleaved layout.
+__device__ __forceinline__ void swap_halves(uint64_t& a, uint64_t& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+  a = ((uint64_t)hi[0] << 32) | lo[0];
+  b = ((uint64_t)hi[1] << 32) | lo[1];
+}
+
+// x * 2^S mod p, reduced to [0, p], for a shift S held per lane and known to
+// lie in [LO, HI] (the two lanes of a slot pair shift by z and z + 6).  The
+// forms are those of gl_mul_pow2 with the shift counts in registers; a
+// 64-bit shift uses its count modulo 64, so no count may reach 64:
+//   HI < 32:        x 2^S = low + 2^64 w2, w2 = x >> (64 - S) < 2^31 (for
+//                   LO = 0, w2 = (x >> 1) >> (63 - S), which is 0 at S = 0);
+//   1 <= LO, HI < 64: the 128-bit product (x << S, x >> (64 - S)) reduced;
+//   64 < LO:        -xh + w EPS with c = 96 - S in [1, 31], xh = x >> c,
+//                   w = low32(x) << (S - 64), as in gl_mul_pow2;
+//   LO < 64 <= HI:  y = x 2^(S - 32) as (lo, hi), then x 2^S = lo 2^32 +
+//                   hi 2^96 = lo 2^32 - hi with hi < 2^63.
+template <int LO, int HI>
+GL_INLINE uint64_t gl_mul_pow2_lane(uint64_t x, uint32_t S) {
+  static_assert(0 <= LO && LO <= HI && HI < 96, "shift range");
+  if constexpr (HI < 32) {
+    const uint64_t low = x << S;
+    const uint64_t w2 = LO == 0 ? (x >> 1) >> (63 - S) : x >> (64 - S);
+    const uint64_t t = (w2 << 32) - w2;  // EPS w2 < 2^63
+    uint64_t r;
+    const bool c = __builtin_add_overflow(low, t, &r);
+    return gl_canon(r + (c ? GL_EPS : 0ull));
+  } else if constexpr (HI < 64) {
+    static_assert(LO >= 1, "shift range");
+    return gl_canon(gl_reduce128(x << S, x >> (64 - S)));
+  } else if constexpr (LO > 64) {
+    const uint64_t xh = x >> (96 - S);
+    const uint32_t w = (uint32_t)x << (S - 64);
+    return gl_sub_r(((uint64_t)w << 32) - w, xh);
+  } else {
+    static_assert(LO > 32, "shift range");
+    const uint64_t lo = x << (S - 32), hi = x >> (96 - S);
+    return gl_canon(gl_sub_r(gl_reduce128(lo << 32, lo >> 32), hi));
+  }
+}
+
+// Position within its column (pass 1) or row (pass 2) of register r of a
+// lane in half h after a paired distance-1 stage ("pair layout").
+__device__ __host__ constexpr int pair_pos(int r, int h) { return 16 * h + 2 * (r & 7) + (r >> 3); }
+
+// The forward LEN = 1 stage on the slot pairs (s, s + 8).  After
+// swap_halves, every lane runs one whole butterfly: the lower lane that of
+// slot s, the upper lane that of slot s + 8, whose twiddle is 2^6 times slot
+// s's (the block's brv5 grows by 2 in both passes), so the lane shifts by
+// z(s) + 6h.  Output in the pair layout (pair_pos).  Against ct64_cross,
+// each lane forms half the twiddle products and needs no register copies.
+template <typename Zf>
+__device__ __forceinline__ void ct64_cross_pairs(uint64_t (&a)[16], Zf zf, uint32_t h6) {
+  static_for<0, 8>([&](auto ss) {
+    constexpr int s = decltype(ss)::value;
+    constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
+    static_assert(decltype(zf(std::integral_constant<int, s + 8>{}))::value == z + 6, "pair twiddles");
+    swap_halves(a[s], a[s + 8]);
+    const uint64_t t = gl_mul_pow2_lane<z, z + 6>(a[s + 8], (uint32_t)z + h6);
+    a[s + 8] = gl_sub_r(a[s], t);
+    a[s] = gl_add_r(a[s], t);
+  });
+}
+
+// Back from the pair layout to the interleaved one.
+__device__ __forceinline__ void pairs_to_interleaved(uint64_t (&a)[16]) {
+  static_for<0, 8>([&](auto ss) {
+    constexpr int s = decltype(ss)::value;
+    swap_halves(a[s], a[s + 8]);
+  });
+}
+
 template <int K>
 struct IC {
   static constexpr int value = K;
@@ -135,6 +214,22 @@ __device__ __forceinline__ void fwd64_p2(uint64_t (&a)[16], int lane) {
   ct64_stage<4>(a, Z2<4>{});
   ct64_stage<2>(a, Z2<2>{});
   ct64_cross(a, Z2<1>{}, lane);
+}
+
+// The same passes ending in the paired distance-1 stage: output in the pair
+// layout, h6 = 6 (lane >> 5).
+__device__ __forceinline__ void fwd64_p1_rest_pairs(uint64_t (&a)[16], uint32_t h6) {
+  ct64_stage<4>(a, Z1<4>{});
+  ct64_stage<2>(a, Z1<2>{});
+  ct64_cross_pairs(a, Z1<1>{}, h6);
+}
+
+__device__ __forceinline__ void fwd64_p2_pairs(uint64_t (&a)[16], uint32_t h6) {
+  ct64_stage<16>(a, Z2<16>{});
+  ct64_stage<8>(a, Z2<8>{});
+  ct64_stage<4>(a, Z2<4>{});
+  ct64_stage<2>(a, Z2<2>{});
+  ct64_cross_pairs(a, Z2<1>{}, h6);
 }
 
 // ---- inverse on one wave: Gentleman-Sande ---------------------------------

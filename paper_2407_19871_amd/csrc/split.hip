@@ -181,6 +181,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  const uint32_t h6 = 6u * (uint32_t)h;  // the lane's extra shift in a paired distance-1 stage
   const bool lvl = wave < 3;  // waves 0-2 run the gadget levels; all four invert
   // four-wave inverse: row (or column) 8 wave + r8, lane h8 of the row's eight
   const int r8 = lane >> 3, h8 = lane & 7, row = 8 * wave + r8;
@@ -189,7 +190,9 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
   uint64_t w2[4], w1[4];
   inv256_twiddles(h8, w2, w1);
   for (int k = threadIdx.x; k < RING_N; k += 256) {
-    s_twf[k] = tw_f[k];
+    // forward entry 64 r + lane: the factor of register r of that lane in
+    // the pair layout that the forward's first pass leaves
+    s_twf[k] = tw_f[pair_pos(k >> 6, (k >> 5) & 1) * 32 + (k & 31)];
     s_twi[k] = tw_i[k];
   }
   const int cls = (int)(blockIdx.x & 7u);
@@ -291,15 +294,18 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
           const uint32_t D = s_D[l + 32 * (2 * s + h)];
           dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
         }
-        uint64_t f[16];  // ntt64_fwd_digits with the twist factors from LDS
+        // forward transform, both passes ending in the paired distance-1
+        // stage; register r then holds row l, position q = pair_pos(r, h),
+        // whose NTT-domain offset is 64 (q >> 1) + 2 l + (q & 1)
+        uint64_t f[16];
         fwd64_p1_digits(dg, f);
-        fwd64_p1_rest(f, lane);
+        fwd64_p1_rest_pairs(f, h6);
 #pragma unroll
         for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
-        transpose64(f, buf, h, l);
-        fwd64_p2(f, lane);
+        transpose64_pairs(f, buf, h, l);
+        fwd64_p2_pairs(f, h6);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) s_part[wave][kpad(64 * s + 2 * l + h)] = f[s];
+        for (int r = 0; r < 16; ++r) s_part[wave][kpad(512 * h + 64 * (r & 7) + 2 * l + (r >> 3))] = f[r];
       } else {
         // meanwhile the fourth wave stages the step's key rows (c, j) in
         // LDS: row 2 j + 0 for output component c, 2 j + 1 for 1 - c

@@ -7,8 +7,10 @@
 //   update_dpp quad_perm [1,0,3,2] / [2,3,0,1]: lane L reads lane
 //     (L & ~3) + perm[L & 3]; row_shl:4 / row_shr:4: lane L reads L + 4 /
 //     L - 4 within its row of 16 lanes, else keeps `old`;
-//   permlane32_swap(x, x): every lane gets (x of lane L & 31, x of lane
-//     (L & 31) + 32).
+//   permlane32_swap(a, b): the upper half-wave of a trades places with the
+//     lower half-wave of b, so lane L < 32 gets (a of L, a of L + 32) and
+//     lane L >= 32 gets (b of L - 32, b of L); with a = b every lane gets
+//     (x of lane L & 31, x of lane (L & 31) + 32).
 // Each pass (the forward passes on the 64-lane layout, the inverse passes
 // on all three) is compared with its definition over Z_p, p = 2^64 -
 // 2^32 + 1, for every lane layout the kernels use (64 lanes: lane (h, l) holds row l,
@@ -36,7 +38,7 @@
 namespace emu {
 struct Wave {
   std::barrier<> bar{64};
-  uint32_t buf[64];
+  uint32_t buf[64], buf2[64];
 };
 thread_local int lane = 0;
 thread_local Wave* wave = nullptr;
@@ -59,17 +61,19 @@ inline int update_dpp(int old, int src, int ctrl) {
   std::printf("unmodelled DPP control 0x%x\n", ctrl);
   std::exit(2);
 }
-inline std::array<uint32_t, 2> permlane32_swap(uint32_t x) {
-  wave->buf[lane] = x;
+inline std::array<uint32_t, 2> permlane32_swap(uint32_t a, uint32_t b) {
+  wave->buf[lane] = a;
+  wave->buf2[lane] = b;
   wave->bar.arrive_and_wait();
-  const std::array<uint32_t, 2> r{wave->buf[lane & 31], wave->buf[(lane & 31) + 32]};
+  const std::array<uint32_t, 2> r = lane < 32 ? std::array<uint32_t, 2>{wave->buf[lane], wave->buf[lane + 32]}
+                                              : std::array<uint32_t, 2>{wave->buf2[lane - 32], wave->buf2[lane]};
   wave->bar.arrive_and_wait();
   return r;
 }
 }  // namespace emu
 
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) emu::update_dpp((old), (src), (ctrl))
-#define __builtin_amdgcn_permlane32_swap(a, b, fi, bc) emu::permlane32_swap((a))
+#define __builtin_amdgcn_permlane32_swap(a, b, fi, bc) emu::permlane32_swap((a), (b))
 
 #include "ntt64.h"
 
@@ -183,8 +187,36 @@ static uint64_t ref_inv1(const std::array<uint64_t, 32>& x, int j) {
   return s;
 }
 
+// gl_mul_pow2_lane<LO, HI> at both of its shifts, on edge and random
+// operands: congruent to x 2^S and reduced (at most p), which the paired
+// butterflies' one-correction sum and difference rely on.
+template <int LO, int HI>
+static void check_lane_shift() {
+  const uint64_t edge[] = {0, 1, 2, 0xFFFFFFFFull, 0x100000000ull, P - 1, P, P + 1, 0x7FFFFFFFFFFFFFFFull,
+                           0x8000000000000000ull, 0xFFFFFFFEFFFFFFFFull, 0xFFFFFFFFFFFFFFFEull, 0xFFFFFFFFFFFFFFFFull};
+  for (int S : {LO, HI}) {
+    for (int i = 0; i < 13 + 4000; ++i) {
+      const uint64_t x = i < 13 ? edge[i] : rnd();
+      const uint64_t got = lp::gl_mul_pow2_lane<LO, HI>(x, (uint32_t)S);
+      ++checks;
+      if (got > P || got % P != mulp(x, powp(2, S))) {
+        std::printf("MISMATCH gl_mul_pow2_lane<%d, %d> S %d x %016llx: got %016llx\n", LO, HI, S,
+                    (unsigned long long)x, (unsigned long long)got);
+        std::exit(1);
+      }
+    }
+  }
+}
+
 int main() {
   using namespace lp;
+  // the slot pairs' shifts: pass 1 z = 3 brv5(16 + s), pass 2 z = 6 (brv5(s) >> 1), s < 8
+  static_for<0, 8>([&](auto ss) {
+    constexpr int s = decltype(ss)::value;
+    constexpr int z1 = 3 * brv5(16 + s), z2 = 6 * (brv5(s) >> 1);
+    check_lane_shift<z1, z1 + 6>();
+    check_lane_shift<z2, z2 + 6>();
+  });
   const Layout L64{2}, L128{4}, L256{8};
   for (int kind = 0; kind < 4; ++kind) {
     // ---- 64 lanes: forward passes (pass 1 from gadget digits) and inverses
@@ -209,11 +241,37 @@ int main() {
         for (int s = 0; s < 16; ++s) out[l][2 * s + h] = gl_canon(a[s]);
       });
       check("fwd64 pass 1 (digits)", L64, dres, out, ref_fwd1);
+      // the paired distance-1 stage: output in the pair layout
+      out.assign(32, {});
+      run_wave([&](int Ln) {
+        const int h = Ln >> 5, l = Ln & 31;
+        int32_t d[16];
+        uint64_t a[16];
+        for (int s = 0; s < 16; ++s) d[s] = (int32_t)(int64_t)dig[l][2 * s + h];
+        fwd64_p1_digits(d, a);
+        fwd64_p1_rest_pairs(a, 6u * (uint32_t)h);
+        for (int r = 0; r < 16; ++r) out[l][pair_pos(r, h)] = gl_canon(a[r]);
+      });
+      check("fwd64 pass 1 (digits, pair layout)", L64, dres, out, ref_fwd1);
     }
     auto in = inputs(32, kind);
     std::vector<std::array<uint64_t, 32>> out;
     run_layout<16>(L64, in, out, [](uint64_t(&a)[16], int Ln) { fwd64_p2(a, Ln); });
     check("fwd64 pass 2", L64, in, out, ref_fwd2);
+    out.assign(32, {});
+    run_wave([&](int Ln) {
+      const int h = Ln >> 5, l = Ln & 31;
+      uint64_t a[16];
+      for (int s = 0; s < 16; ++s) a[s] = in[l][2 * s + h];
+      fwd64_p2_pairs(a, 6u * (uint32_t)h);
+      for (int r = 0; r < 16; ++r) out[l][pair_pos(r, h)] = gl_canon(a[r]);
+    });
+    check("fwd64 pass 2 (pair layout)", L64, in, out, ref_fwd2);
+    run_layout<16>(L64, in, out, [](uint64_t(&a)[16], int Ln) {
+      fwd64_p2_pairs(a, 6u * (uint32_t)(Ln >> 5));
+      pairs_to_interleaved(a);
+    });
+    check("fwd64 pass 2 (pair layout, back to interleaved)", L64, in, out, ref_fwd2);
     run_layout<16>(L64, in, out, [](uint64_t(&a)[16], int Ln) { inv64_p2(a, Ln); });
     check("inv64 pass 2", L64, in, out, ref_inv2);
     run_layout<16>(L64, in, out, [](uint64_t(&a)[16], int Ln) { inv64_p1(a, Ln); });
