@@ -363,110 +363,129 @@ __device__ __forceinline__ void inv128_p1(uint64_t (&a)[8], uint64_t upper1, uin
 }
 
 // ---- inverse on four waves (eight lanes per row) -----------------------------
-// The same inverse over 256 lanes: wave w (0..3) holds rows 8 w .. 8 w + 7,
-// lane 8 r + h of the wave holds the four positions q = 8 s + h (s = 0..3)
-// of row 8 w + r.  Stages of distance 16 and 8 stay in the lane; distance
-// 4 pairs lanes h ^ 4 with a uniform block (q / 8 = s); distance 2 pairs
-// h ^ 2 with two blocks per slot (q / 4 = 2 s + (h >> 2)), both shifts
-// formed; distance 1 pairs h ^ 1 with four blocks per slot (q / 2 = 4 s +
-// (h >> 1)), so each lane multiplies by its own twiddle, computed once per
-// launch (gl_pow2).  Output, in lane 8 r + h of wave w, slot s: coefficient
-// j1 + 32 q with j1 = 8 w + r, q = 8 s + h.
+// The inverse over 256 lanes: wave w (0..3) holds rows 8 w .. 8 w + 7, and
+// lane 8 r + h of the wave holds four positions of row 8 w + r.  The input
+// layout puts the two low position bits in registers: register s holds
+// q = 4 h + s.  The distance-1 and -2 stages then run inside the lane.
+// Each of the distance-4, -8 and -16 stages first trades one register of
+// each pair with the partner lane h ^ 1, h ^ 2, h ^ 4, which moves the
+// stage's position bit (a lane bit until then) into a register and sends a
+// position bit that is already done (bits 0, 1, 2) out to the lane; every
+// lane then runs whole butterflies.  The upper lane of a traded pair holds
+// Y - X where the butterfly needs X - Y, so its twiddle carries a minus
+// sign.  Output: register s holds q = h + 8 (s >> 1) + 16 (s & 1).
 
-// The value held by lane ^ 4 of each group of eight: lanes h < 4 read
-// lane + 4 (DPP row_shl:4), lanes h >= 4 lane - 4 (row_shr:4); hi4 = ~0 in
-// lanes h >= 4.
-__device__ __forceinline__ uint32_t oct_xor4_u32(uint32_t x, bool hi4) {
-  const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0xF, false);
-  const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);
-  return hi4 ? dn : up;
-}
-__device__ __forceinline__ uint64_t oct_xor4(uint64_t v, bool hi4) {
-  return ((uint64_t)oct_xor4_u32((uint32_t)(v >> 32), hi4) << 32) | oct_xor4_u32((uint32_t)v, hi4);
+// Exponent z of the forward stage of distance LEN at block b (as Z1 and Z2,
+// for a block known at run time); the inverse multiplies by 2^(192 - z).
+__device__ __host__ constexpr int z_fwd(int pass, int len, int b) {
+  return pass == 1 ? 3 * brv5(32 / (2 * len) + b)
+                   : 6 * len * (brv5(b) >> (len == 16 ? 5 : len == 8 ? 4 : len == 4 ? 3 : len == 2 ? 2 : 1));
 }
 
 // 2^e mod p, reduced, for a runtime e in [0, 192).
-__device__ __forceinline__ uint64_t gl_pow2(int e) {
+__device__ __host__ inline uint64_t gl_pow2(int e) {
   uint64_t w = 1;
   for (int k = 0; k < e; ++k) w = gl_add(w, w);
   return gl_canon(w);
 }
 
-// Gentleman-Sande stage of distance D in {1, 2, 4} across the eight lanes
-// of a row; FIRST: the inputs may be lazy.  upper: ~0 in the upper lane of
-// each pair (h & D); hi4: ~0 in lanes h >= 4; w1: the lane's twiddles of
-// the distance-1 stage (one per slot, 1 in the lower lanes).  As in
-// gs128_cross, each lane forms only its own output: the partner's value
-// plus its own, negated in the upper lane, then the upper lane's twiddle.
-template <int D, bool FIRST, typename Zf>
-__device__ __forceinline__ void gs256_cross(uint64_t (&a)[4], Zf zf, uint64_t upper, uint64_t hi4,
-                                            const uint64_t (&w1)[4]) {
-  static_for<0, 4>([&](auto ss) {
-    constexpr int s = decltype(ss)::value;
-    uint64_t other;
-    if constexpr (D == 4) other = oct_xor4(a[s], hi4 != 0);
-    else other = quad_xor<D>(a[s]);
-    const uint64_t self = FIRST ? gl_canon(a[s]) : a[s];
-    const uint64_t v = gl_add_r(other, lane_negate(upper, self));
-    if constexpr (D == 4) {
-      constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
-      a[s] = lane_select(upper, gl_canon(v), gl_mul_pow2_r<192 - z>(v));
-    } else if constexpr (D == 2) {
-      constexpr int za = decltype(zf(std::integral_constant<int, 2 * s>{}))::value;
-      constexpr int zb = decltype(zf(std::integral_constant<int, 2 * s + 1>{}))::value;
-      a[s] = lane_select(upper, gl_canon(v), lane_select(hi4, gl_mul_pow2_r<192 - za>(v), gl_mul_pow2_r<192 - zb>(v)));
+// The lane's twiddles for one pass (1 or 2) of the four-wave inverse, h =
+// lane & 7: w[0], w[1] distance 1 (blocks 2h, 2h + 1), w[2] distance 2
+// (block h), w[3] distance 4 (block h >> 1, negated in lanes with h & 1),
+// w[4] distance 8 (block h >> 2, negated in lanes with h & 2).  Distance 16
+// has block 0 in both passes.
+__device__ __host__ inline void inv256_twiddles(int pass, int h, uint64_t (&w)[5]) {
+  auto tw = [&](int len, int b) { return gl_pow2((192 - z_fwd(pass, len, b)) % 192); };
+  w[0] = tw(1, 2 * h);
+  w[1] = tw(1, 2 * h + 1);
+  w[2] = tw(2, h);
+  w[3] = (h & 1) ? gl_neg_r(tw(4, h >> 1)) : tw(4, h >> 1);
+  w[4] = (h & 2) ? gl_neg_r(tw(8, h >> 2)) : tw(8, h >> 2);
+}
+
+// In-lane Gentleman-Sande butterfly, reduced inputs and outputs:
+// (x, y) -> (x + y, (x - y) w).
+__device__ __forceinline__ void gs_bf(uint64_t& x, uint64_t& y, uint64_t w) {
+  const uint64_t d = gl_sub_r(x, y);
+  x = gl_canon(gl_add_r(x, y));
+  y = gl_canon(gl_mul(d, w));
+}
+
+// Trade within the pair (a, b) with the partner lane, `upper` = ~0 in the
+// lane whose traded bit is set: the lower lane keeps a and receives the
+// partner's a, the upper lane receives the partner's b and keeps b.  Returns
+// k (kept) and r (received); the butterfly's X, Y are (k, r) in the lower
+// lane and (r, k) in the upper one, so X + Y = k + r and X - Y = +-(k - r).
+template <int D>
+__device__ __forceinline__ void quad_trade(uint64_t a, uint64_t b, uint64_t upper, uint64_t& k, uint64_t& r) {
+  r = quad_xor<D>(lane_select(upper, b, a));
+  k = lane_select(upper, a, b);
+}
+
+// The same with the lane h ^ 4 of the group of eight: lanes h < 4 (DPP banks
+// 0 and 2 of a row) read lane + 4's a, lanes h >= 4 (banks 1 and 3) lane -
+// 4's b, each DPP writing only its own banks.
+__device__ __forceinline__ uint32_t oct_trade_u32(uint32_t a, uint32_t b) {
+  const int from_lower = __builtin_amdgcn_update_dpp(0, (int)b, 0x114, 0xF, 0xA, false);  // row_shr:4
+  return (uint32_t)__builtin_amdgcn_update_dpp(from_lower, (int)a, 0x104, 0xF, 0x5, false);  // row_shl:4
+}
+__device__ __forceinline__ void oct_trade(uint64_t a, uint64_t b, uint64_t upper, uint64_t& k, uint64_t& r) {
+  r = ((uint64_t)oct_trade_u32((uint32_t)(a >> 32), (uint32_t)(b >> 32)) << 32) |
+      oct_trade_u32((uint32_t)a, (uint32_t)b);
+  k = lane_select(upper, a, b);
+}
+
+// One pass; FIRST inputs may be lazy (the distance-1 stage reduces them).
+// u4 = ~0 in lanes h >= 4; w from inv256_twiddles of this pass.
+template <int PASS>
+__device__ __forceinline__ void inv256_pass(uint64_t (&a)[4], uint64_t u1, uint64_t u2, uint64_t u4,
+                                            const uint64_t (&w)[5]) {
+  // distance 1: (q, q + 1) = registers (2j, 2j + 1), lazy inputs
+  static_for<0, 2>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    const uint64_t x = a[2 * j], y = gl_canon(a[2 * j + 1]);
+    a[2 * j] = gl_canon(gl_add_r(x, y));
+    a[2 * j + 1] = gl_canon(gl_mul(gl_sub_r(x, y), w[j]));
+  });
+  // distance 2: registers (j, j + 2)
+  gs_bf(a[0], a[2], w[2]);
+  gs_bf(a[1], a[3], w[2]);
+  // distance 4: trade with h ^ 1 on the pairs (0, 1), (2, 3); bit 2 then
+  // sits in register bit 0
+  static_for<0, 2>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    uint64_t k, r;
+    quad_trade<1>(a[2 * j], a[2 * j + 1], u1, k, r);
+    a[2 * j] = k;
+    a[2 * j + 1] = r;
+    gs_bf(a[2 * j], a[2 * j + 1], w[3]);
+  });
+  // distance 8: trade with h ^ 2 on the pairs (0, 2), (1, 3); bit 3 then
+  // sits in register bit 1
+  static_for<0, 2>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    uint64_t k, r;
+    quad_trade<2>(a[j], a[j + 2], u2, k, r);
+    a[j] = k;
+    a[j + 2] = r;
+    gs_bf(a[j], a[j + 2], w[4]);
+  });
+  // distance 16: trade with h ^ 4 on the pairs (0, 1), (2, 3); block 0:
+  // twiddle 1 in pass 2, 2^(192 - 48) = -2^48 in pass 1, times the trade's
+  // sign (-1 in the upper lanes)
+  static_for<0, 2>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    uint64_t k, r;
+    oct_trade(a[2 * j], a[2 * j + 1], u4, k, r);
+    const uint64_t d = gl_sub_r(k, r);
+    a[2 * j] = gl_canon(gl_add_r(k, r));
+    if constexpr (PASS == 2) {
+      a[2 * j + 1] = lane_negate(u4, d);
     } else {
-      a[s] = gl_canon(gl_mul(v, w1[s]));
+      static_assert(z_fwd(1, 16, 0) == 48, "pass-1 distance-16 twiddle");
+      a[2 * j + 1] = lane_negate(~u4, gl_mul_pow2_r<48>(d));
     }
   });
-}
-
-// In-lane stage of distance LEN in {8, 16}: slots s and s + LEN / 16 within
-// blocks of LEN / 4 slots.
-template <int LEN, typename Zf>
-__device__ __forceinline__ void gs256_stage(uint64_t (&a)[4], Zf zf) {
-  constexpr int span = LEN / 4;
-  static_for<0, 4 / span>([&](auto bb) {
-    constexpr int blk = decltype(bb)::value;
-    constexpr int z = decltype(zf(std::integral_constant<int, blk>{}))::value;
-    static_for<0, span / 2>([&](auto jj) {
-      constexpr int s0 = blk * span + decltype(jj)::value, s1 = s0 + span / 2;
-      const uint64_t x = a[s0], y = a[s1];
-      a[s0] = gl_canon(gl_add_r(x, y));
-      a[s1] = gl_mul_pow2_r<192 - z>(gl_sub_r(x, y));
-    });
-  });
-}
-
-// The lane's distance-1 twiddles of each pass: in the upper lane of a pair
-// (h odd) 2^(192 - z) for the block 4 s + (h >> 1) of slot s (pass 2: z =
-// 6 (brv5(b) >> 1); pass 1: z = 3 brv5(16 + b)); 1 in the lower lane, which
-// keeps the sum.
-__device__ __forceinline__ void inv256_twiddles(int h, uint64_t (&w2)[4], uint64_t (&w1)[4]) {
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int b = 4 * s + (h >> 1);
-    w2[s] = (h & 1) ? gl_pow2((192 - 6 * (brv5(b) >> 1)) % 192) : 1ull;
-    w1[s] = (h & 1) ? gl_pow2((192 - 3 * brv5(16 + b)) % 192) : 1ull;
-  }
-}
-
-__device__ __forceinline__ void inv256_p2(uint64_t (&a)[4], uint64_t upper1, uint64_t upper2, uint64_t upper4,
-                                          const uint64_t (&w2)[4]) {
-  gs256_cross<1, true>(a, Z2<1>{}, upper1, upper4, w2);
-  gs256_cross<2, false>(a, Z2<2>{}, upper2, upper4, w2);
-  gs256_cross<4, false>(a, Z2<4>{}, upper4, upper4, w2);
-  gs256_stage<8>(a, Z2<8>{});
-  gs256_stage<16>(a, Z2<16>{});
-}
-
-__device__ __forceinline__ void inv256_p1(uint64_t (&a)[4], uint64_t upper1, uint64_t upper2, uint64_t upper4,
-                                          const uint64_t (&w1)[4]) {
-  gs256_cross<1, true>(a, Z1<1>{}, upper1, upper4, w1);
-  gs256_cross<2, false>(a, Z1<2>{}, upper2, upper4, w1);
-  gs256_cross<4, false>(a, Z1<4>{}, upper4, upper4, w1);
-  gs256_stage<8>(a, Z1<8>{});
-  gs256_stage<16>(a, Z1<16>{});
 }
 
 }  // namespace lp

@@ -187,8 +187,9 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
   const int r8 = lane >> 3, h8 = lane & 7, row = 8 * wave + r8;
   const uint64_t upper1 = (h8 & 1) ? ~0ull : 0ull, upper2 = (h8 & 2) ? ~0ull : 0ull,
                  upper4 = (h8 & 4) ? ~0ull : 0ull;
-  uint64_t w2[4], w1[4];
-  inv256_twiddles(h8, w2, w1);
+  uint64_t tw2[5], tw1[5];  // the lane's inverse twiddles of passes 2 and 1
+  inv256_twiddles(2, h8, tw2);
+  inv256_twiddles(1, h8, tw1);
   for (int k = threadIdx.x; k < RING_N; k += 256) {
     // forward entry 64 r + lane: the factor of register r of that lane in
     // the pair layout that the forward's first pass leaves
@@ -263,11 +264,11 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const __amdgpu_buffer_rsrc_t fr = l2_rsrc(sync, (SPLIT_FLAGS + (gridDim.x / 2) * SPLIT_FLAGS_PER_JOB) * 4u);
     const uint32_t my_xo = (uint32_t)(my_x - xbuf) * 8u, peer_xo = (uint32_t)(peer_x - xbuf) * 8u;
     const uint32_t my_fo = (uint32_t)(my_flag - sync) * 4u, peer_fo = (uint32_t)(peer_flag - sync) * 4u;
-    // this lane's four inverse positions (row `row`, q = 8 s + h8): their
+    // this lane's four inverse positions (row `row`, q = 4 h8 + s): their
     // NTT-domain offsets 64 (q >> 1) + 2 row + (q & 1) in the padded rows
     int po[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) po[s] = kpad(256 * s + 64 * (h8 >> 1) + 2 * row + (h8 & 1));
+    for (int s = 0; s < 4; ++s) po[s] = kpad(128 * h8 + 64 * (s >> 1) + 2 * row + (s & 1));
 
     for (int i = 0; i < nsteps; ++i) {
       const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
@@ -387,24 +388,26 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       pc.template mark<7>();
 
       // one inverse of the sum on all four waves: each holds eight rows at
-      // eight lanes per row
+      // eight lanes per row; each pass leaves register s at position
+      // h8 + 8 (s >> 1) + 16 (s & 1)
       {
-        inv256_p2(v, upper1, upper2, upper4, w2);
+        inv256_pass<2>(v, upper1, upper2, upper4, tw2);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = gl_mul(v[s], s_twi[h8 * 32 + row + s * 256]);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) s_t128[row * T128_ROW + 8 * s + h8] = v[s];
+        for (int s = 0; s < 4; ++s) {
+          const int j = h8 + 8 * (s >> 1) + 16 * (s & 1);
+          s_t128[row * T128_ROW + j] = gl_mul(v[s], s_twi[j * 32 + row]);
+        }
         pc.template mark<8>();
         __syncthreads();
         pc.template mark<9>();
-        // column j1 = row of this lane, positions q = 8 s + h8
+        // column j1 = row of this lane, positions q = 4 h8 + s
 #pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = s_t128[(8 * s + h8) * T128_ROW + row];
-        inv256_p1(v, upper1, upper2, upper4, w1);
+        for (int s = 0; s < 4; ++s) v[s] = s_t128[(4 * h8 + s) * T128_ROW + row];
+        inv256_pass<1>(v, upper1, upper2, upper4, tw1);
         // the sum is an exact integer polynomial (|coefficient| < 2^50.6),
         // so its centred lift reduced mod 2^32 is exact
 #pragma unroll
-        for (int s = 0; s < 4; ++s) s_acc[row + 32 * (8 * s + h8)] += gl_lift_u32(v[s]);
+        for (int s = 0; s < 4; ++s) s_acc[row + 32 * (h8 + 8 * (s >> 1) + 16 * (s & 1))] += gl_lift_u32(v[s]);
       }
       pc.template mark<10>();
       ++done;

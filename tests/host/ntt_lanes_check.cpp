@@ -6,7 +6,8 @@
 // exchange):
 //   update_dpp quad_perm [1,0,3,2] / [2,3,0,1]: lane L reads lane
 //     (L & ~3) + perm[L & 3]; row_shl:4 / row_shr:4: lane L reads L + 4 /
-//     L - 4 within its row of 16 lanes, else keeps `old`;
+//     L - 4 within its row of 16 lanes, else keeps `old`; a lane whose bank
+//     (four lanes of a row, (L & 15) >> 2) is clear in bank_mask keeps `old`;
 //   permlane32_swap(a, b): the upper half-wave of a trades places with the
 //     lower half-wave of b, so lane L < 32 gets (a of L, a of L + 32) and
 //     lane L >= 32 gets (b of L - 32, b of L); with a = b every lane gets
@@ -15,7 +16,8 @@
 // on all three) is compared with its definition over Z_p, p = 2^64 -
 // 2^32 + 1, for every lane layout the kernels use (64 lanes: lane (h, l) holds row l,
 // positions 2s + h; 128: lane 4r + h holds row r, positions 4s + h; 256:
-// lane 8r + h holds row r, positions 8s + h), on random and lazy inputs
+// lane 8r + h holds row r, positions 4h + s on entry and h + 8 (s >> 1) +
+// 16 (s & 1) on exit), on random and lazy inputs
 // (values at or above p, 2^64 - 1) and on digits at their extremes:
 //   forward pass 1: out[P] = sum_j a[j] rho^(j (2 brv5(P) + 1)), rho = 2^3
 //   forward pass 2: out[P] = sum_j c[j] omega^(brv5(P) j),       omega = 2^6
@@ -50,14 +52,15 @@ inline uint32_t exchange(uint32_t v, int src_lane, bool valid, uint32_t old) {
   wave->bar.arrive_and_wait();
   return r;
 }
-inline int update_dpp(int old, int src, int ctrl) {
+inline int update_dpp(int old, int src, int ctrl, int bank_mask) {
   const int L = lane;
+  const bool on = (bank_mask >> ((L & 15) >> 2)) & 1;
   if (ctrl == 0xB1 || ctrl == 0x4E) {
     const int perm[4] = {ctrl == 0xB1 ? 1 : 2, ctrl == 0xB1 ? 0 : 3, ctrl == 0xB1 ? 3 : 0, ctrl == 0xB1 ? 2 : 1};
-    return (int)exchange((uint32_t)src, (L & ~3) + perm[L & 3], true, (uint32_t)old);
+    return (int)exchange((uint32_t)src, (L & ~3) + perm[L & 3], on, (uint32_t)old);
   }
-  if (ctrl == 0x104) return (int)exchange((uint32_t)src, L + 4, (L & 15) + 4 < 16, (uint32_t)old);
-  if (ctrl == 0x114) return (int)exchange((uint32_t)src, L - 4, (L & 15) >= 4, (uint32_t)old);
+  if (ctrl == 0x104) return (int)exchange((uint32_t)src, L + 4, on && (L & 15) + 4 < 16, (uint32_t)old);
+  if (ctrl == 0x114) return (int)exchange((uint32_t)src, L - 4, on && (L & 15) >= 4, (uint32_t)old);
   std::printf("unmodelled DPP control 0x%x\n", ctrl);
   std::exit(2);
 }
@@ -72,7 +75,7 @@ inline std::array<uint32_t, 2> permlane32_swap(uint32_t a, uint32_t b) {
 }
 }  // namespace emu
 
-#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) emu::update_dpp((old), (src), (ctrl))
+#define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) emu::update_dpp((old), (src), (ctrl), (bm))
 #define __builtin_amdgcn_permlane32_swap(a, b, fi, bc) emu::permlane32_swap((a), (b))
 
 #include "ntt64.h"
@@ -295,28 +298,27 @@ int main() {
       inv128_p1(a, u1, u2, u2);
     });
     check("inv128 pass 1", L128, in128, out, ref_inv1);
-    // ---- 256 lanes (one of the four waves: 8 rows at eight lanes per row)
+    // ---- 256 lanes (one of the four waves: 8 rows at eight lanes per row);
+    // in: lane 8r + h, register s holds q = 4h + s; out: q = h + 8 (s >> 1)
+    // + 16 (s & 1)
     auto in256 = inputs(8, kind);
-    auto b256 = [](int Ln, uint64_t& u1, uint64_t& u2, uint64_t& u4) {
-      const int h8 = Ln & 7;
-      u1 = (h8 & 1) ? ~0ull : 0ull;
-      u2 = (h8 & 2) ? ~0ull : 0ull;
-      u4 = (h8 & 4) ? ~0ull : 0ull;
-    };
-    run_layout<4>(L256, in256, out, [&](uint64_t(&a)[4], int Ln) {
-      uint64_t u1, u2, u4, w2[4], w1[4];
-      b256(Ln, u1, u2, u4);
-      inv256_twiddles(Ln & 7, w2, w1);
-      inv256_p2(a, u1, u2, u4, w2);
-    });
-    check("inv256 pass 2", L256, in256, out, ref_inv2);
-    run_layout<4>(L256, in256, out, [&](uint64_t(&a)[4], int Ln) {
-      uint64_t u1, u2, u4, w2[4], w1[4];
-      b256(Ln, u1, u2, u4);
-      inv256_twiddles(Ln & 7, w2, w1);
-      inv256_p1(a, u1, u2, u4, w1);
-    });
-    check("inv256 pass 1", L256, in256, out, ref_inv1);
+    for (int pass = 1; pass <= 2; ++pass) {
+      out.assign(8, {});
+      run_wave([&](int Ln) {
+        const int r = Ln >> 3, h = Ln & 7;
+        const uint64_t u1 = (h & 1) ? ~0ull : 0ull, u2 = (h & 2) ? ~0ull : 0ull, u4 = (h & 4) ? ~0ull : 0ull;
+        uint64_t a[4], w[5];
+        inv256_twiddles(pass, h, w);
+        for (int s = 0; s < 4; ++s) a[s] = in256[r][4 * h + s];
+        if (pass == 2) inv256_pass<2>(a, u1, u2, u4, w);
+        else inv256_pass<1>(a, u1, u2, u4, w);
+        for (int s = 0; s < 4; ++s) {
+          if (a[s] > P) fail("inv256 output not reduced", 8, r, h + 8 * (s >> 1) + 16 * (s & 1), a[s], 0);
+          out[r][h + 8 * (s >> 1) + 16 * (s & 1)] = a[s];
+        }
+      });
+      check(pass == 2 ? "inv256 pass 2" : "inv256 pass 1", L256, in256, out, pass == 2 ? ref_inv2 : ref_inv1);
+    }
   }
   std::printf("ok %llu\n", (unsigned long long)checks);
   return 0;
