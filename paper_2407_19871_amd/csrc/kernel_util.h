@@ -44,28 +44,11 @@ __device__ __forceinline__ const gmem_u64* as_global(const uint64_t* p) {
 }
 
 // ---- whole-wave transforms (layout of ntt64.h) ------------------------------
-// 32 x 32 transpose of one polynomial held by a whole wave: on entry lane
-// (h, l) slot s holds element (l, 2s + h) of the matrix; on exit element
-// (2s + h, l).  Two 32-bit passes through a 32 x 33 word block.
-__device__ __forceinline__ void transpose64(uint64_t (&a)[16], uint32_t* buf, int h, int l) {
-  uint32_t lo[16];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)a[s];
-  wave_fence();
-#pragma unroll
-  for (int s = 0; s < 16; ++s) lo[s] = buf[(2 * s + h) * ROW + l];
-  wave_fence();
-#pragma unroll
-  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)(a[s] >> 32);
-  wave_fence();
-#pragma unroll
-  for (int s = 0; s < 16; ++s) a[s] = ((uint64_t)buf[(2 * s + h) * ROW + l] << 32) | lo[s];
-  wave_fence();
-}
-
-// transpose64 from the pair layout of ntt64.h: on entry register r of lane
-// (h, l) holds element (l, 16h + 2(r & 7) + (r >> 3)); on exit slot s holds
-// element (2s + h, l), as for transpose64.
+// 32 x 32 transposes of one polynomial held by a whole wave, through a
+// 32 x 33 word block in two 32-bit passes.  From the pair layout of
+// ntt64.h: on entry register r of lane (h, l) holds element (l, 16h +
+// 2(r & 7) + (r >> 3)) of the matrix; on exit slot s holds element (2s + h,
+// l).
 __device__ __forceinline__ void transpose64_pairs(uint64_t (&a)[16], uint32_t* buf, int h, int l) {
   uint32_t lo[16];
   uint32_t* wr = buf + l * ROW + 16 * h;
@@ -80,6 +63,25 @@ __device__ __forceinline__ void transpose64_pairs(uint64_t (&a)[16], uint32_t* b
   wave_fence();
 #pragma unroll
   for (int s = 0; s < 16; ++s) a[s] = ((uint64_t)buf[(2 * s + h) * ROW + l] << 32) | lo[s];
+  wave_fence();
+}
+
+// Into the pair layout: on entry slot s of lane (h, l) holds element (l,
+// 2s + h); on exit register r holds element (16h + 2(r & 7) + (r >> 3), l).
+__device__ __forceinline__ void transpose64_to_pairs(uint64_t (&a)[16], uint32_t* buf, int h, int l) {
+  uint32_t lo[16];
+  const uint32_t* rd = buf + 16 * h * ROW + l;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)a[s];
+  wave_fence();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) lo[r] = rd[(2 * (r & 7) + (r >> 3)) * ROW];
+  wave_fence();
+#pragma unroll
+  for (int s = 0; s < 16; ++s) buf[l * ROW + 2 * s + h] = (uint32_t)(a[s] >> 32);
+  wave_fence();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a[r] = ((uint64_t)rd[(2 * (r & 7) + (r >> 3)) * ROW] << 32) | lo[r];
   wave_fence();
 }
 

@@ -488,18 +488,19 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
     const gmem_u64* step_key = bsk + (size_t)i * 6 * 2 * RING_N;
     const gmem_u64* twi = as_global(opaque(tw_i)) + lane;  // twist64's reads
     uint64_t qo[16], qx[16];  // terms of output c and of output 1 - c
-    // gadget level j: rows (c, j) of BSK_i, components c and 1 - c, at this
-    // lane's offsets 64 s + 2 l + h
+    // gadget level j: rows (c, j) of BSK_i, components c and 1 - c, at the
+    // offsets of this lane's registers in the pair layout, 512 h + 64 (r & 7)
+    // + 2 l + (r >> 3)
     auto level = [&](int j, auto first) {
       // the rows are loaded before the transform: the compiler keeps loads
       // where they are written, and after it they would be waited on at once
-      const gmem_u64* ko = step_key + (size_t)((c * 3 + j) * 2 + c) * RING_N + 2 * l + h;
-      const gmem_u64* kx = step_key + (size_t)((c * 3 + j) * 2 + (1 - c)) * RING_N + 2 * l + h;
+      const gmem_u64* ko = step_key + (size_t)((c * 3 + j) * 2 + c) * RING_N + 2 * l + 512 * h;
+      const gmem_u64* kx = step_key + (size_t)((c * 3 + j) * 2 + (1 - c)) * RING_N + 2 * l + 512 * h;
       uint64_t k0[16], k1[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        k0[s] = ko[s * 64];
-        k1[s] = kx[s * 64];
+      for (int r = 0; r < 16; ++r) {
+        k0[r] = ko[64 * (r & 7) + (r >> 3)];
+        k1[r] = kx[64 * (r & 7) + (r >> 3)];
       }
       const int sh = 25 - 7 * j;
       int32_t dg[16];
@@ -511,9 +512,8 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
         const uint32_t D = ((e & 1024u) ? (0u - v) : v) - acc[k];
         dg[s] = (int32_t)(((D + 0x81020400u) >> sh) & 127u) - 64;
       }
-      // forward transform: both passes end in the paired distance-1 stage;
-      // the second is swapped back to the interleaved layout of the key rows
-      // and of the inverse
+      // forward transform: both passes end in the paired distance-1 stage,
+      // and the products and the inverse's input stay in the pair layout
       uint64_t f[16];
       fwd64_p1_digits(dg, f);
       fwd64_p1_rest_pairs(f, h6);
@@ -521,7 +521,6 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
       for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
       transpose64_pairs(f, tbuf, h, l);
       fwd64_p2_pairs(f, h6);
-      pairs_to_interleaved(f);
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         if constexpr (decltype(first)::value) {
@@ -547,12 +546,13 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
 #pragma unroll
     for (int s = 0; s < 16; ++s) qo[s] = gl_add(qo[s], inbox[64 * s + lane]);
     wave_fence();  // the inbox is read before it serves as the transpose block
-    // inverse of the forward transform (1/1024 included), twist factors at hand
-    inv64_p2(qo, lane);
+    // inverse of the forward transform (1/1024 included), twist factors at
+    // hand; each pass starts from the pair layout and ends interleaved
+    inv64_p2_pairs(qo, h6);
 #pragma unroll
     for (int s = 0; s < 16; ++s) qo[s] = gl_mul(qo[s], w[s]);
-    transpose64(qo, tbuf, h, l);
-    inv64_p1(qo, lane);
+    transpose64_to_pairs(qo, tbuf, h, l);
+    inv64_p1_pairs(qo, h6);
 #pragma unroll
     for (int s = 0; s < 16; ++s) acc[l + 32 * (2 * s + h)] += gl_lift_u32(qo[s]);
     wave_fence();

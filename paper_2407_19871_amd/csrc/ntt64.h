@@ -9,13 +9,16 @@
 // positions have the lane's parity, so the stage runs inside the lane, and
 // its twiddle depends on the block alone -- the same shift for every lane,
 // as in the 32-lane transform.  Only the LEN = 1 stage pairs the two lanes
-// of a column: a half-wave swap gives both lanes both values, both form
-// w * x_odd (a uniform shift per slot), and lane h keeps x_even + t (h = 0)
-// or x_even - t (h = 1).
+// of a column.  It runs on slot pairs (s, s + 8): one half-wave swap of the
+// two registers gives the lower lane both values of slot s and the upper
+// lane both values of slot s + 8, and each lane forms a whole butterfly.
+// That leaves the "pair layout": register r of lane (h, l) holds position
+// pair_pos(r, h) = 16h + 2(r & 7) + (r >> 3).
 //   forward:  in  lane (h, l), slot s = coefficient l + 32 (2s + h)
-//             out lane (h, l), slot s = A(k), k = brv5(l) + 32 brv5(2s + h),
-//             which sits at offset 64 s + 2 l + h of the 32-lane layout
-//             (ntt_pos), so NTT-domain keys are shared by both layouts.
+//             out lane (h, l), register r = A(k), k = brv5(l) + 32 brv5(q),
+//             q = pair_pos(r, h), which sits at offset 64 (q >> 1) + 2 l +
+//             (q & 1) of the 32-lane layout (ntt_pos), so NTT-domain keys
+//             are shared by both layouts.
 // The inverses below (on one, two or four waves) are Gentleman-Sande
 // stages that undo the merged Cooley-Tukey stages in reverse order,
 // (X, Y) -> (X + Y, (X - Y) w^-1), with the same per-block twiddles; each
@@ -26,17 +29,6 @@
 #include "ntt32.h"
 
 namespace lp {
-
-// Both values of a column pair in both of its lanes: v_permlane32_swap of
-// a register with itself exchanges its upper half-wave with its lower one,
-// returning (lower copy, upper copy) = (value at the even position, value at
-// the odd position) in every lane.  A VALU operation, so no LDS round trip.
-__device__ __forceinline__ void pair_values(uint64_t x, uint64_t& even, uint64_t& odd) {
-  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)x, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(x >> 32), (uint32_t)(x >> 32), false, false);
-  even = ((uint64_t)hi[0] << 32) | lo[0];
-  odd = ((uint64_t)hi[1] << 32) | lo[1];
-}
 
 // hi_lane ? y : x without a branch (the lane's half is fixed, so a mask).
 __device__ __forceinline__ uint64_t lane_select(uint64_t mask, uint64_t x, uint64_t y) {
@@ -84,21 +76,6 @@ __device__ __forceinline__ void ct64_stage(uint64_t (&a)[16], Zf zf) {
   });
 }
 
-// The LEN = 1 stage across the two lanes of a column; Z(s) per slot.  The
-// lower lane keeps x_even + t, the upper one x_even - t, each with one
-// addition (of t or of -t).
-template <typename Zf>
-__device__ __forceinline__ void ct64_cross(uint64_t (&a)[16], Zf zf, int lane) {
-  const uint64_t odd = lane >= 32 ? ~0ull : 0ull;
-  static_for<0, 16>([&](auto ss) {
-    constexpr int s = decltype(ss)::value;
-    constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
-    uint64_t xe, xo;
-    pair_values(a[s], xe, xo);
-    a[s] = gl_add_r(xe, lane_negate(odd, gl_mul_pow2_r<z>(xo)));
-  });
-}
-
 // ---- the distance-1 stage on slot pairs --------------------------------------
 // v_permlane32_swap of two different registers trades the upper half-wave of
 // `a` for the lower half-wave of `b`.  For the slots (s, s + 8) that leaves
@@ -119,13 +96,15 @@ __device__ __forceinline__ void swap_halves(uint64_t& a, uint64_t& b) {
 //   HI < 32:        x 2^S = low + 2^64 w2, w2 = x >> (64 - S) < 2^31 (for
 //                   LO = 0, w2 = (x >> 1) >> (63 - S), which is 0 at S = 0);
 //   1 <= LO, HI < 64: the 128-bit product (x << S, x >> (64 - S)) reduced;
-//   64 < LO:        -xh + w EPS with c = 96 - S in [1, 31], xh = x >> c,
-//                   w = low32(x) << (S - 64), as in gl_mul_pow2;
+//   64 < LO:        -xh + w EPS with c = 96 - S in [0, 31], xh = x >> c,
+//                   w = low32(x) << (S - 64), as in gl_mul_pow2 (w formed as
+//                   low32(x) 2^32 >> c, which is 0 at S = 96; there xh = x,
+//                   so HI = 96 needs a reduced x);
 //   LO < 64 <= HI:  y = x 2^(S - 32) as (lo, hi), then x 2^S = lo 2^32 +
 //                   hi 2^96 = lo 2^32 - hi with hi < 2^63.
 template <int LO, int HI>
 GL_INLINE uint64_t gl_mul_pow2_lane(uint64_t x, uint32_t S) {
-  static_assert(0 <= LO && LO <= HI && HI < 96, "shift range");
+  static_assert(0 <= LO && LO <= HI && (HI < 96 || (HI == 96 && LO > 64)), "shift range");
   if constexpr (HI < 32) {
     const uint64_t low = x << S;
     const uint64_t w2 = LO == 0 ? (x >> 1) >> (63 - S) : x >> (64 - S);
@@ -137,8 +116,9 @@ GL_INLINE uint64_t gl_mul_pow2_lane(uint64_t x, uint32_t S) {
     static_assert(LO >= 1, "shift range");
     return gl_canon(gl_reduce128(x << S, x >> (64 - S)));
   } else if constexpr (LO > 64) {
-    const uint64_t xh = x >> (96 - S);
-    const uint32_t w = (uint32_t)x << (S - 64);
+    const uint32_t c = 96 - S;
+    const uint64_t xh = x >> c;
+    const uint32_t w = (uint32_t)(((uint64_t)(uint32_t)x << 32) >> c);
     return gl_sub_r(((uint64_t)w << 32) - w, xh);
   } else {
     static_assert(LO > 32, "shift range");
@@ -170,14 +150,6 @@ __device__ __forceinline__ void ct64_cross_pairs(uint64_t (&a)[16], Zf zf, uint3
   });
 }
 
-// Back from the pair layout to the interleaved one.
-__device__ __forceinline__ void pairs_to_interleaved(uint64_t (&a)[16]) {
-  static_for<0, 8>([&](auto ss) {
-    constexpr int s = decltype(ss)::value;
-    swap_halves(a[s], a[s + 8]);
-  });
-}
-
 template <int K>
 struct IC {
   static constexpr int value = K;
@@ -202,22 +174,8 @@ struct Z2 {
   }
 };
 
-__device__ __forceinline__ void fwd64_p1_rest(uint64_t (&a)[16], int lane) {
-  ct64_stage<4>(a, Z1<4>{});
-  ct64_stage<2>(a, Z1<2>{});
-  ct64_cross(a, Z1<1>{}, lane);
-}
-
-__device__ __forceinline__ void fwd64_p2(uint64_t (&a)[16], int lane) {
-  ct64_stage<16>(a, Z2<16>{});
-  ct64_stage<8>(a, Z2<8>{});
-  ct64_stage<4>(a, Z2<4>{});
-  ct64_stage<2>(a, Z2<2>{});
-  ct64_cross(a, Z2<1>{}, lane);
-}
-
-// The same passes ending in the paired distance-1 stage: output in the pair
-// layout, h6 = 6 (lane >> 5).
+// Pass 1 after its digit stages, and pass 2, each ending in the paired
+// distance-1 stage: output in the pair layout, h6 = 6 (lane >> 5).
 __device__ __forceinline__ void fwd64_p1_rest_pairs(uint64_t (&a)[16], uint32_t h6) {
   ct64_stage<4>(a, Z1<4>{});
   ct64_stage<2>(a, Z1<2>{});
@@ -250,32 +208,36 @@ __device__ __forceinline__ void gs64_stage(uint64_t (&a)[16], Zf zf) {
   });
 }
 
-// The first stage of a pass, across the two lanes of a column; its inputs
-// may be lazy, its outputs are reduced.  The lower lane keeps X + Y, the
-// upper one (X - Y) w^-1, both from one addition (of Y or of -Y).
+// The first stage of a pass with its input in the pair layout (X in register
+// s, Y in s + 8: positions 2t and 2t + 1 of its row, t = s + 8h), lazy: an
+// in-lane butterfly (X, Y) -> (X + Y, (X - Y) 2^(192 - z(t))), then the swap
+// back to the interleaved layout.  With -1 = 2^96, (X - Y) 2^(192 - z) =
+// (Y - X) 2^(96 - z), and z(t) = z(s) + 6h, so the lane shifts Y - X by
+// 96 - z(s) - 6h, in [0, 96] (96 only at z = 0, on a reduced Y - X).
 template <typename Zf>
-__device__ __forceinline__ void gs64_cross(uint64_t (&a)[16], Zf zf, int lane) {
-  const uint64_t odd = lane >= 32 ? ~0ull : 0ull;
-  static_for<0, 16>([&](auto ss) {
+__device__ __forceinline__ void gs64_cross_pairs(uint64_t (&a)[16], Zf zf, uint32_t h6) {
+  static_for<0, 8>([&](auto ss) {
     constexpr int s = decltype(ss)::value;
     constexpr int z = decltype(zf(std::integral_constant<int, s>{}))::value;
-    uint64_t x, y;
-    pair_values(a[s], x, y);
-    const uint64_t v = gl_add_r(x, lane_negate(odd, gl_canon(y)));
-    a[s] = lane_select(odd, gl_canon(v), gl_mul_pow2_r<192 - z>(v));
+    static_assert(decltype(zf(std::integral_constant<int, s + 8>{}))::value == z + 6, "pair twiddles");
+    const uint64_t x = gl_canon(a[s]), y = gl_canon(a[s + 8]);
+    a[s] = gl_canon(gl_add_r(x, y));
+    a[s + 8] = gl_mul_pow2_lane<90 - z, 96 - z>(gl_sub_r(y, x), (uint32_t)(96 - z) - h6);
+    swap_halves(a[s], a[s + 8]);
   });
 }
 
-__device__ __forceinline__ void inv64_p2(uint64_t (&a)[16], int lane) {
-  gs64_cross(a, Z2<1>{}, lane);
+// The one-wave inverse passes, input in the pair layout, output interleaved.
+__device__ __forceinline__ void inv64_p2_pairs(uint64_t (&a)[16], uint32_t h6) {
+  gs64_cross_pairs(a, Z2<1>{}, h6);
   gs64_stage<2>(a, Z2<2>{});
   gs64_stage<4>(a, Z2<4>{});
   gs64_stage<8>(a, Z2<8>{});
   gs64_stage<16>(a, Z2<16>{});
 }
 
-__device__ __forceinline__ void inv64_p1(uint64_t (&a)[16], int lane) {
-  gs64_cross(a, Z1<1>{}, lane);
+__device__ __forceinline__ void inv64_p1_pairs(uint64_t (&a)[16], uint32_t h6) {
+  gs64_cross_pairs(a, Z1<1>{}, h6);
   gs64_stage<2>(a, Z1<2>{});
   gs64_stage<4>(a, Z1<4>{});
   gs64_stage<8>(a, Z1<8>{});
