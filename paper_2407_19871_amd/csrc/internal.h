@@ -108,9 +108,8 @@ bool est_br_launch_us(size_t njobs, double* us);
 // table has no timed row.
 uint32_t throughput_knee(float tol);
 // Waves per bootstrap; the built-in rule: 6 (split over two workgroups) up
-// to kSplitMaxJobs, 4 (levels summed, two-wave inverses) up to 256, 5 (the
-// same, two per CU) up to 768, 2 (one accumulator component per wave) up to
-// 1024, 5 up to 1280, else 1.
+// to kSplitMaxJobs, 5 (levels summed, two-wave inverses, two rotations per
+// CU) up to 768, 2 (one accumulator component per wave) up to 1280, else 1.
 int pick_br_wpb(size_t njobs);
 // Built-in defaults (no environment, no table).
 int default_ks_tile(size_t njobs);

@@ -516,11 +516,15 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
       // and the products and the inverse's input stay in the pair layout
       uint64_t f[16];
       fwd64_p1_digits(dg, f);
-      fwd64_p1_rest_pairs(f, h6);
+      // the lane's shift counts are formed here from h6, not held across
+      // the step loop (which spills)
+      uint32_t h6l = h6;
+      asm volatile("" : "+v"(h6l));
+      fwd64_p1_rest_pairs(f, h6l);
 #pragma unroll
       for (int s = 0; s < 16; ++s) f[s] = gl_mul(f[s], s_twf[64 * s + lane]);
       transpose64_pairs(f, tbuf, h, l);
-      fwd64_p2_pairs(f, h6);
+      fwd64_p2_pairs(f, h6l);
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         if constexpr (decltype(first)::value) {
@@ -548,11 +552,13 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
     wave_fence();  // the inbox is read before it serves as the transpose block
     // inverse of the forward transform (1/1024 included), twist factors at
     // hand; each pass starts from the pair layout and ends interleaved
-    inv64_p2_pairs(qo, h6);
+    uint32_t h6i = h6;
+    asm volatile("" : "+v"(h6i));
+    inv64_p2_pairs(qo, h6i);
 #pragma unroll
     for (int s = 0; s < 16; ++s) qo[s] = gl_mul(qo[s], w[s]);
     transpose64_to_pairs(qo, tbuf, h, l);
-    inv64_p1_pairs(qo, h6);
+    inv64_p1_pairs(qo, h6i);
 #pragma unroll
     for (int s = 0; s < 16; ++s) acc[l + 32 * (2 * s + h)] += gl_lift_u32(qo[s]);
     wave_fence();

@@ -88,18 +88,16 @@ int default_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   return sp;
 }
 
-// MI355X, n = 630: split 7.0-7.2 ms per launch up to 128 rotations; four
-// waves 13.1 ms up to 256 (one rotation per CU); four waves two per CU
-// 19.5 ms at 384-512 and 29.7 ms at 768 (three waves: 24.8 and 37.1); two
-// waves, one per component, 34.8 ms at 1024 (one wave 38.2, four waves
-// 38.0); four waves again at 1280 (47.2 ms, one wave 54.5); one wave from
-// 1536 (54-55 ms up to 2048).
+// MI355X, n = 630, gate batches with their key switch: split 6.2 ms up to
+// 128 rotations; four waves two per CU 12.8-13.0 ms at 129-256 (four waves
+// one per CU 13.6-13.9), 20.0-20.5 ms at 384-512 and 30.0-30.1 ms at
+// 640-768 (two waves 28.9-30.2); two waves, one per component, 33.9 ms at
+// 1024 (four waves 39.0, one wave 41.9) and 47.1 ms at 1280 (48.4, 58.5);
+// one wave from 1536, where two waves per rotation need a second round.
 int default_br_wpb(size_t njobs) {
   if (njobs <= (size_t)kSplitMaxJobs) return 6;
-  if (njobs <= 256) return 4;
   if (njobs <= 768) return 5;
-  if (njobs <= 1024) return 2;
-  return njobs <= 1280 ? 5 : 1;
+  return njobs <= 1280 ? 2 : 1;
 }
 
 int pick_ks_tile(size_t njobs) {

@@ -22,7 +22,7 @@ def clean_table(monkeypatch):
 def test_defaults_without_table():
     assert lp.tune_table() == []
     assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129, 256, 257, 768, 769, 1024, 1025, 1280, 1281)] == \
-        [6, 6, 4, 4, 5, 5, 2, 2, 5, 5, 1]
+        [6, 6, 5, 5, 5, 5, 2, 2, 2, 2, 1]
     assert [lp.tune_pick(j)["ks_tile"] for j in (1, 16, 256, 4096)] == [1, 4, 8, 16]
     # the default split grows until the key switch has >= 2048 blocks
     assert lp.tune_pick(1)["ks_split"] == 16
