@@ -42,6 +42,10 @@ typedef __attribute__((address_space(1))) const uint64_t gmem_u64;
 __device__ __forceinline__ const gmem_u64* as_global(const uint64_t* p) {
   return (const gmem_u64*)(const void*)p;
 }
+typedef __attribute__((address_space(1))) const uint32_t gmem_u32;
+__device__ __forceinline__ const gmem_u32* as_global(const uint32_t* p) {
+  return (const gmem_u32*)(const void*)p;
+}
 
 // ---- whole-wave transforms (layout of ntt64.h) ------------------------------
 // 32 x 32 transposes of one polynomial held by a whole wave, through a

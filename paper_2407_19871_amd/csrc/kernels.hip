@@ -581,7 +581,10 @@ __global__ __launch_bounds__(128, 2) void blind_rotate_pair_kernel(
   }
 }
 
-template <int T, int BB>
+// KT > 0: the digit count t fixed at compile time; the KT x NROWS candidate
+// rows of ring index i + 1 are requested while index i is applied, so a
+// wave waits on the key-switching key once per index pair, not per digit.
+template <int T, int BB, int KT>
 __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__ jobs, int njobs,
                                                        const uint32_t* __restrict__ ex, DstBases dst,
                                                        const uint32_t* const* __restrict__ ksk_tab,
@@ -592,8 +595,16 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
   const int col = blockIdx.x * 64 + lane;
   const int j0 = blockIdx.y * T;
   const bool colok = col <= n_lwe;
+  // lanes past the last column read column n_lwe (their sums are never
+  // stored), so every key load is unconditional
+  const uint32_t kcol = colok ? (uint32_t)col : (uint32_t)n_lwe;
   const int w = n_lwe + 1;
-  const uint32_t* __restrict__ ksk = ksk_tab[jobs[j0].key];
+  // the tile's key (one per tile), made uniform so that row addresses are
+  // scalar
+  const uint64_t kp = (uint64_t)ksk_tab[jobs[j0].key];
+  const uint32_t* __restrict__ ksk = (const uint32_t*)(
+      ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(kp >> 32)) << 32) |
+      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)kp));
   const uint32_t prec = 1u << (31 - BB * ks_t);
   const int isplit = gridDim.z;
   const int i_lo = (int)blockIdx.z * (N / isplit), i_hi = i_lo + N / isplit;
@@ -623,17 +634,56 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
       if (e0[t]) v = e0[t][i0 + lane] + (e1[t] ? e1[t][i0 + lane] : 0u) + prec;
       av[t] = v;
     }
+    if constexpr (KT > 0) {
+      constexpr int R = KT * NROWS;  // candidate rows of one ring index
+      // a uniform row pointer plus the lane's column, so that the loads take
+      // a scalar base and share one offset register
+      const gmem_u32* base = as_global(ksk) + (size_t)i0 * R * w;
+      auto fetch = [&](uint32_t(&r)[R], int ii) {
+        const gmem_u32* q = base + (size_t)ii * R * w;
+#pragma unroll
+        for (int k = 0; k < R; ++k) r[k] = (q + (size_t)k * w)[kcol];
+      };
+      auto apply = [&](const uint32_t(&r)[R], int ii) {
+        uint32_t asc[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) asc[t] = (uint32_t)__builtin_amdgcn_readlane((int)av[t], ii);
+#pragma unroll
+        for (int j = 0; j < KT; ++j) {
+          const int shift = 32 - (j + 1) * BB;
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            // d is uniform: the row it selects is picked with scalar masks,
+            // not a branch per digit
+            const uint32_t d = (asc[t] >> shift) & (uint32_t)NROWS;
+            uint32_t sub = 0u;
+#pragma unroll
+            for (int v = 1; v <= NROWS; ++v) sub |= r[j * NROWS + v - 1] & (0u - (uint32_t)(d == (uint32_t)v));
+            accv[t] -= sub;
+          }
+        }
+      };
+      uint32_t ra[R], rb[R];
+      fetch(ra, 0);
+      for (int ii = 0; ii < 64; ii += 2) {
+        fetch(rb, ii + 1);
+        apply(ra, ii);
+        if (ii + 2 < 64) fetch(ra, ii + 2);
+        apply(rb, ii + 1);
+      }
+      continue;
+    }
     for (int ii = 0; ii < 64; ++ii) {
       const int i = i0 + ii;
       uint32_t asc[T];
 #pragma unroll
       for (int t = 0; t < T; ++t) asc[t] = (uint32_t)__builtin_amdgcn_readlane((int)av[t], ii);
       for (int j = 0; j < ks_t; ++j) {
-        const uint32_t* rowp = ksk + ((size_t)(i * ks_t + j) * NROWS) * w + col;
+        const uint32_t* rowp = ksk + ((size_t)(i * ks_t + j) * NROWS) * w + kcol;
         uint32_t r[NROWS + 1];
         r[0] = 0u;
 #pragma unroll
-        for (int v = 0; v < NROWS; ++v) r[v + 1] = colok ? rowp[(size_t)v * w] : 0u;
+        for (int v = 0; v < NROWS; ++v) r[v + 1] = rowp[(size_t)v * w];
         const int shift = 32 - (j + 1) * BB;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -790,11 +840,17 @@ static hipError_t launch_ks_t(const KsJob* d_jobs, int njobs, const uint32_t* d_
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  // both parameter sets use base 2^2 with t = 8: that shape is compiled with
+  // the digit count fixed; any other keeps the runtime loop
+  if (bb == 2 && ks_t == 8) {
+    hipLaunchKernelGGL((keyswitch_kernel<T, 2, 8>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t);
+    return hipGetLastError();
+  }
   switch (bb) {
-    case 1: hipLaunchKernelGGL((keyswitch_kernel<T, 1>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
-    case 2: hipLaunchKernelGGL((keyswitch_kernel<T, 2>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
-    case 3: hipLaunchKernelGGL((keyswitch_kernel<T, 3>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
-    case 4: hipLaunchKernelGGL((keyswitch_kernel<T, 4>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
+    case 1: hipLaunchKernelGGL((keyswitch_kernel<T, 1, 0>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
+    case 2: hipLaunchKernelGGL((keyswitch_kernel<T, 2, 0>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
+    case 3: hipLaunchKernelGGL((keyswitch_kernel<T, 3, 0>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
+    case 4: hipLaunchKernelGGL((keyswitch_kernel<T, 4, 0>), grid, dim3(64), 0, s, d_jobs, njobs, d_ex, dst, d_ksk_tab, pt, n_lwe, N, ks_t); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
