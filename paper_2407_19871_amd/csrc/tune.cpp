@@ -79,12 +79,18 @@ lp_status install(int dev, std::vector<lp_tune_entry> rows) {
 
 }  // namespace
 
-int default_ks_tile(size_t njobs) { return njobs >= 4096 ? 16 : njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1; }
+// The key switch with t = 8 compiled in (its rows requested one ring index
+// ahead) is fastest, on MI355X, at 4 jobs per wave from 16 jobs and 8 from
+// 256 (16 needs 209 VGPRs), and with the ring split until a launch has
+// 64 k blocks, at most 16 ways: 33 us for one job, 1.47 us per job at 128,
+// 1.15 at 1024, 1.10 at 16384 (autotuner, split 16 up to 4096 and 4 at
+// 16384).
+int default_ks_tile(size_t njobs) { return njobs >= 256 ? 8 : njobs >= 16 ? 4 : 1; }
 
 int default_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   const size_t blocks = ((n_lwe + 64) / 64) * ((njobs + tile - 1) / tile);
   int sp = 1;
-  while (sp < 16 && blocks * sp < 2048) sp *= 2;
+  while (sp < 16 && blocks * sp < 65536) sp *= 2;
   return sp;
 }
 

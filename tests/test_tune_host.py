@@ -23,10 +23,10 @@ def test_defaults_without_table():
     assert lp.tune_table() == []
     assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129, 256, 257, 768, 769, 1024, 1025, 1280, 1281)] == \
         [6, 6, 5, 5, 5, 5, 2, 2, 2, 2, 1]
-    assert [lp.tune_pick(j)["ks_tile"] for j in (1, 16, 256, 4096)] == [1, 4, 8, 16]
-    # the default split grows until the key switch has >= 2048 blocks
+    assert [lp.tune_pick(j)["ks_tile"] for j in (1, 16, 256, 4096)] == [1, 4, 8, 8]
+    # the default split grows until the key switch has >= 65536 blocks
     assert lp.tune_pick(1)["ks_split"] == 16
-    assert lp.tune_pick(16384)["ks_split"] == 1
+    assert lp.tune_pick(16384)["ks_split"] == 4
 
 
 def test_row_lookup_first_bound_not_below_count():
