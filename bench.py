@@ -71,7 +71,8 @@ KERNEL_SOURCES = ["paper_2407_19871_amd/csrc/kernels.hip", "paper_2407_19871_amd
                   "paper_2407_19871_amd/_build.py"]
 # blind-rotation kernel of each launch shape (waves per bootstrap)
 SHAPE_KERNEL = {1: "blind_rotate_kernel<1>", 2: "blind_rotate_pair_kernel", 3: "blind_rotate_kernel<3>",
-                4: "blind_rotate_kernel<4>", 5: "blind_rotate_kernel<5>", 6: "blind_rotate_split_kernel"}
+                4: "blind_rotate_kernel<4>", 5: "blind_rotate_kernel<5>", 6: "blind_rotate_split_kernel",
+                7: "blind_rotate_split_kernel<dual>"}
 TUNE_BUCKETS = (1, 16, 32, 64, 128, 256, 384, 512, 768, 1024, 2048, 4096, 16384)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_bbox16x16_traffic.txt")
 VALU_SUMMARY = os.path.join(ROOT, "profiles", "blind_rotate_valu_busy.txt")
@@ -204,8 +205,9 @@ def summarize_launches(launches, depth: int, l: int):
         t["jobs"] += r["jobs"]
         t["total_ms"] += r["ms"]
         if r["name"] == "blind_rotate":
-            # SIMDs holding a rotation's waves (the split: 2 CUs x 4)
-            per = 8 if r["shape"] == 6 else r["shape"]
+            # SIMDs holding a rotation's waves (the split: 2 CUs x 4; two
+            # per CU: half of that)
+            per = {6: 8, 7: 4}.get(r["shape"], r["shape"])
             busy += r["ms"] * min(r["jobs"] * per, 1024) / 1024
             level = n_rot % depth
             n_rot += 1

@@ -423,10 +423,10 @@ lp_status lp_debug_external_product_mfma(const uint32_t* d_key_step, const uint3
 #define LP_OPRATE_COUNT 7
 lp_status lp_debug_field_op_rates(double target_ms, double* rates, double* ms, void* stream);
 
-/* Where a split blind rotation's time goes (br_waves 6): the blind
- * rotation of cnt (1..128) LWE_n samples d_in (device, cnt*(n+1) words) in
- * the shape's profiling build, which reads the shader clock at the phase
- * boundaries of every step.  waves must be 6.  cycles (host, 4 x 12
+/* Where a split blind rotation's time goes (br_waves 6 or 7): the blind
+ * rotation of cnt (1..128 for 6, 1..256 for 7) LWE_n samples d_in (device,
+ * cnt*(n+1) words) in the shape's profiling build, which reads the shader
+ * clock at the phase boundaries of every step.  waves must be 6 or 7.  cycles (host, 4 x 12
  * doubles) receives, per wave index of a workgroup and phase, the clock
  * cycles per executed step averaged over the launch's workgroups: [0]
  * digits and key requests, [1] the barrier after them, [2] the forward
@@ -471,7 +471,7 @@ typedef struct {
   double ms;
 } lp_launch_record;
 lp_status lp_profile_collect_launches(lp_launch_record* recs, int* count);
-/* Split blind rotations (br_waves 6) pair two workgroups that wait for each
+/* Split blind rotations (br_waves 6 and 7) pair two workgroups that wait for each
  * other's transforms every step; each wait is bounded (about a second of
  * polling), so a partner that never arrives cannot hang the device.  Such a
  * wait ends the job's exchange, its output is then undefined, and the
@@ -500,12 +500,14 @@ lp_status lp_split_stall_count(uint32_t* count);
  *             (three level waves,
  *             then the levels summed in the NTT domain and each component
  *             inverted once on two waves; one rotation per CU), 5 (the
- *             same, sized for two rotations per CU) or 6 (the rotation split
+ *             same, sized for two rotations per CU), 6 (the rotation split
  *             over two workgroups, normally two CUs, each owning one
  *             accumulator component and trading its key products for the
  *             other component with the other every step; lower latency
- *             again, for launches of at most 128 rotations -- a wider
- *             launch that looks up 6 runs 3);
+ *             again, for launches of at most 128 rotations) or 7 (the same
+ *             split sized for two workgroups per CU, for launches of at
+ *             most 256) -- a wider launch that looks up a split shape runs
+ *             7 when it fits, else 5;
  *   ks_tile:  key switches per wave tile, 1, 4, 8 or 16;
  *   ks_split: ranges the ring index of a key switch is split into (partial
  *             sums added atomically), 1, 2, 4, 8 or 16;

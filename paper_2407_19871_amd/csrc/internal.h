@@ -108,7 +108,8 @@ bool est_br_launch_us(size_t njobs, double* us);
 // table has no timed row.
 uint32_t throughput_knee(float tol);
 // Waves per bootstrap; the built-in rule: 6 (split over two workgroups) up
-// to kSplitMaxJobs, 5 (levels summed, two-wave inverses, two rotations per
+// to kSplitMaxJobs, 7 (the same, two workgroups per CU) up to
+// kSplitDualMaxJobs, 5 (levels summed, two-wave inverses, two rotations per
 // CU) up to 768, 2 (one accumulator component per wave) up to 1280, else 1.
 int pick_br_wpb(size_t njobs);
 // Built-in defaults (no environment, no table).

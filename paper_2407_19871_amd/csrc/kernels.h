@@ -21,8 +21,10 @@ struct Twiddles {
 hipError_t launch_bsk_to_ntt(const uint32_t* d_src, uint64_t* d_dst, int npoly, Twiddles tw,
                              hipStream_t s);
 
-// Split shape: one bootstrap on two workgroups of four waves.
-inline bool is_split(int waves_per_job) { return waves_per_job == 6; }
+// Split shapes: one bootstrap on two workgroups of four waves; 6 sized for
+// one workgroup per CU (launches of up to kSplitMaxJobs jobs), 7 for two
+// (up to kSplitDualMaxJobs).
+inline bool is_split(int waves_per_job) { return waves_per_job == 6 || waves_per_job == 7; }
 
 // Exchange area of split blind rotations (waves_per_job = 6: one bootstrap
 // on two workgroups, one per accumulator component, that trade their key
@@ -32,6 +34,11 @@ inline bool is_split(int waves_per_job) { return waves_per_job == 6; }
 // (the step flags are cleared by the launch that uses them, at its start).
 // One launch at a time may use an area.
 constexpr int kSplitMaxJobs = 128;
+constexpr int kSplitDualMaxJobs = 256;
+// The widest launch of a split shape (0 for any other).
+inline int split_max_jobs(int waves_per_job) {
+  return waves_per_job == 7 ? kSplitDualMaxJobs : waves_per_job == 6 ? kSplitMaxJobs : 0;
+}
 struct SplitArea {
   uint64_t* xbuf = nullptr;  // [job][role 2][step parity 2][1024] u64
   uint32_t* sync = nullptr;  // 8 ticket counters, finish count, status; 16 flag words per job; give-up marks
@@ -39,7 +46,8 @@ struct SplitArea {
 };
 size_t split_xbuf_bytes(int max_jobs);
 size_t split_sync_bytes(int max_jobs);
-// Synchronous allocation (hipMalloc, zeroed); split_area_free releases it.
+// Synchronous allocation (hipMalloc, zeroed), for 1..kSplitDualMaxJobs
+// jobs; split_area_free releases it.
 hipError_t split_area_alloc(SplitArea* a, int max_jobs);
 void split_area_free(SplitArea* a);
 // Stream-ordered allocation (hipMallocAsync, cleared by a kernel) and release.
@@ -83,7 +91,7 @@ hipError_t split_area_take_stalls(const SplitArea* a, hipStream_t s, uint32_t* c
 // 4 (three level waves, the levels' NTT-domain sum inverted once per
 // component on two waves each; one bootstrap per CU), 5 (the same, two
 // bootstraps per CU), 6 (split over two workgroups of four waves; needs
-// `split` with room for njobs).
+// `split` with room for njobs) or 7 (the same, two workgroups per CU).
 // d_pool_tab (may be null) resolves operands with base KEY_POOL_BASE to the
 // pool of the job's key.
 hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
@@ -91,11 +99,11 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
                                int steps, int raw_acc, Twiddles tw, int waves_per_job, hipStream_t s,
                                const SplitArea* split = nullptr);
 
-// The split rotation's launch (waves_per_job 6), in split.hip; `split`
-// must have room for njobs.
+// The split rotation's launch (waves_per_job 6 or 7), in split.hip; `split`
+// must have room for njobs, and njobs is at most split_max_jobs(waves).
 hipError_t launch_split(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                         const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
-                        int raw_acc, Twiddles tw, const SplitArea* split, hipStream_t s);
+                        int raw_acc, Twiddles tw, int waves_per_job, const SplitArea* split, hipStream_t s);
 
 // The split rotation's profiling instantiation (waves_per_job 6, raw
 // accumulators into d_ex): every wave of every workgroup writes, at

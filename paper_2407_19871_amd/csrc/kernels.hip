@@ -823,7 +823,9 @@ hipError_t launch_blind_rotate(const BrJob* d_jobs, int njobs, const SrcBases& s
                          d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv);
       break;
     case 6:
-      return launch_split(d_jobs, njobs, src, d_ex, d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw, split, s);
+    case 7:
+      return launch_split(d_jobs, njobs, src, d_ex, d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw, waves_per_job,
+                          split, s);
     default:
       return hipErrorInvalidValue;
   }

@@ -690,7 +690,10 @@ lp_status bootstrap_batch(const char* who, const lp_device_key* dk, lp_gate gate
   const bool direct = !with_ks && gc.nbr == 1;
   const size_t ex_bytes = direct ? 0 : nbr * (N + 1) * 4, br_bytes = nbr * sizeof(BrJob),
                ks_bytes = cnt * sizeof(KsJob);
-  const int waves = pick_br_wpb(nbr);
+  int waves = pick_br_wpb(nbr);
+  // the static scratch's split area holds kNoAllocSplitJobs jobs; a wider
+  // split launch there takes four waves two per CU instead
+  if (pre && lp::is_split(waves) && nbr > (size_t)pre->split.max_jobs) waves = 5;
   char* scratch = nullptr;
   uint32_t* ex = d_out;
   BrJob* br = nullptr;
@@ -860,9 +863,9 @@ extern "C" lp_status lp_debug_field_op_rates(double target_ms, double* rates, do
 extern "C" lp_status lp_debug_split_profile(const lp_device_key* dk, const uint32_t* d_in, size_t cnt, int waves,
                                            double* cycles, double* ms, void* stream) {
   if (!dk || !d_in || !cycles) return fail(LP_EINVAL, "lp_debug_split_profile: null argument");
-  if (cnt == 0 || cnt > (size_t)lp::kSplitMaxJobs)
-    return fail(LP_EINVAL, "lp_debug_split_profile: 1..%d rotations", lp::kSplitMaxJobs);
-  if (!lp::is_split(waves)) return fail(LP_EINVAL, "lp_debug_split_profile: waves must be 6");
+  if (!lp::is_split(waves)) return fail(LP_EINVAL, "lp_debug_split_profile: waves must be 6 or 7");
+  if (cnt == 0 || cnt > (size_t)lp::split_max_jobs(waves))
+    return fail(LP_EINVAL, "lp_debug_split_profile: 1..%d rotations", lp::split_max_jobs(waves));
   ScopedDevice sd(dk->device);
   hipStream_t s = as_stream(stream);
   const int N = (int)dk->P.N, wpw = 4;

@@ -277,7 +277,7 @@ bool choose_xnor_early(const std::vector<std::tuple<uint32_t, uint32_t, uint32_t
   if (shapes.size() != 1) return false;
   const uint32_t l = std::get<0>(shapes[0]);
   const size_t comparators = 4 * (size_t)std::get<1>(shapes[0]);
-  return l >= 2 && is_split(pick_br_wpb(2 * comparators)) && !is_split(pick_br_wpb(3 * comparators));
+  return l >= 2 && pick_br_wpb(2 * comparators) == 6 && pick_br_wpb(3 * comparators) != 6;
 }
 
 namespace {

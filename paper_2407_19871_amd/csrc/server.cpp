@@ -315,7 +315,7 @@ lp_status tick(lp_server* S, const std::vector<std::shared_ptr<Request>>& act, c
     e = hipStreamSynchronize(S->stream);
     if (e == hipSuccess) {
       lp::split_area_free(&S->split);
-      e = lp::split_area_alloc(&S->split, lp::kSplitMaxJobs);
+      e = lp::split_area_alloc(&S->split, lp::kSplitDualMaxJobs);
     }
   }
   if (e == hipSuccess) {

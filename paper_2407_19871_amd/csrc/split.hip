@@ -158,26 +158,36 @@ struct PhaseClock {
   }
 };
 
-template <bool PROF>
-__global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
+// DUAL: the same rotation sized for two workgroups per CU (launches of up to
+// kSplitDualMaxJobs jobs), in at most half the CU's LDS: the fourth wave
+// stages only the partner's three key rows and each wave loads its own-sum
+// rows from global memory while it waits for the partner; the inverse
+// twist comes from global memory; the forward transposes use the wave's
+// partial-sum row, and D uses the inverse's transpose block (each read
+// before the next write of the aliased space, at the step's barriers).
+template <bool PROF, bool DUAL>
+__global__ __launch_bounds__(256, DUAL ? 2 : 1) void blind_rotate_split_kernel(
     const BrJob* __restrict__ jobs, int njobs, SrcBases src, uint32_t* __restrict__ ex_out,
     const uint64_t* const* __restrict__ bsk_tab, uint32_t* const* __restrict__ pool_tab, int n_lwe, int steps,
     int raw_acc, const uint64_t* __restrict__ tw_f, const uint64_t* __restrict__ tw_i, uint64_t* __restrict__ xbuf,
     uint32_t* __restrict__ sync, uint32_t* __restrict__ marks, int spin_limit, int allow_l2,
     uint64_t* __restrict__ prof) {
   __shared__ uint32_t s_acc[RING_N];
-  __shared__ __align__(16) uint32_t s_tr[3][LDS_HALF];
+  __shared__ __align__(16) uint32_t s_tr[DUAL ? 1 : 3][DUAL ? 1 : LDS_HALF];
   // the levels' forward transforms and the step's key rows (c, j), both
-  // output components, NTT domain, rows padded (kpad) for conflict-free
-  // reads at the inverse's positions
+  // output components (DUAL: the partner's only), NTT domain, rows padded
+  // (kpad) for conflict-free reads at the inverse's positions
   __shared__ __align__(16) uint64_t s_part[3][KROW];
-  __shared__ __align__(16) uint64_t s_key[6][KROW];
-  __shared__ uint32_t s_D[RING_N];                          // X^a ACC_c - ACC_c
+  __shared__ __align__(16) uint64_t s_key[DUAL ? 3 : 6][KROW];
+  __shared__ uint32_t s_Dn[DUAL ? 1 : RING_N];
   __shared__ __align__(16) uint64_t s_t128[32 * T128_ROW];  // two-wave transpose
-  // both twist tables, read every step at LDS latency instead of L2's
-  __shared__ __align__(16) uint64_t s_twf[RING_N], s_twi[RING_N];
+  // the twist tables, read every step at LDS latency instead of L2's (DUAL:
+  // the forward one)
+  __shared__ __align__(16) uint64_t s_twf[RING_N], s_twi[DUAL ? 1 : RING_N];
   __shared__ uint16_t s_abar[MAX_LWE + 4];
   __shared__ uint32_t s_ticket, s_last, s_local;
+  // X^a ACC_c - ACC_c
+  uint32_t* const s_D = DUAL ? reinterpret_cast<uint32_t*>(s_t128) : s_Dn;
 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
@@ -194,7 +204,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     // forward entry 64 r + lane: the factor of register r of that lane in
     // the pair layout that the forward's first pass leaves
     s_twf[k] = tw_f[pair_pos(k >> 6, (k >> 5) & 1) * 32 + (k & 31)];
-    s_twi[k] = tw_i[k];
+    if constexpr (!DUAL) s_twi[k] = tw_i[k];
   }
   const int cls = (int)(blockIdx.x & 7u);
   if (threadIdx.x == 0) s_ticket = atomicAdd(sync + cls, 1u);
@@ -205,7 +215,7 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
 
   if (job < njobs) {
     const BrJob J = jobs[job];
-    uint32_t* buf = s_tr[lvl ? wave : 0];
+    uint32_t* buf = DUAL ? reinterpret_cast<uint32_t*>(s_part[lvl ? wave : 0]) : s_tr[lvl ? wave : 0];
     {
       auto operand = [&](uint32_t r) -> const uint32_t* {
         if (r == REF_NONE) return nullptr;
@@ -266,9 +276,12 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
     const uint32_t my_fo = (uint32_t)(my_flag - sync) * 4u, peer_fo = (uint32_t)(peer_flag - sync) * 4u;
     // this lane's four inverse positions (row `row`, q = 4 h8 + s): their
     // NTT-domain offsets 64 (q >> 1) + 2 row + (q & 1) in the padded rows
-    int po[4];
+    int po[4], og[4];  // og: the same offsets in an unpadded key row (DUAL's own rows)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) po[s] = kpad(128 * h8 + 64 * (s >> 1) + 2 * row + (s & 1));
+    for (int s = 0; s < 4; ++s) {
+      og[s] = 128 * h8 + 64 * (s >> 1) + 2 * row + (s & 1);
+      po[s] = kpad(og[s]);
+    }
 
     for (int i = 0; i < nsteps; ++i) {
       const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_abar[i]);
@@ -309,10 +322,11 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
         for (int r = 0; r < 16; ++r) s_part[wave][kpad(512 * h + 64 * (r & 7) + 2 * l + (r >> 3))] = f[r];
       } else {
         // meanwhile the fourth wave stages the step's key rows (c, j) in
-        // LDS: row 2 j + 0 for output component c, 2 j + 1 for 1 - c
+        // LDS: row 2 j + 0 for output component c, 2 j + 1 for 1 - c (DUAL:
+        // row j for 1 - c only)
 #pragma unroll 1
-        for (int r = 0; r < 6; ++r) {
-          const int j = r >> 1, comp = (r & 1) ? 1 - c : c;
+        for (int r = 0; r < (DUAL ? 3 : 6); ++r) {
+          const int j = DUAL ? r : r >> 1, comp = (DUAL || (r & 1)) ? 1 - c : c;
           const gmem_u64* src_row = step_key + (size_t)((c * 3 + j) * 2 + comp) * RING_N;
           uint64_t t[16];
 #pragma unroll
@@ -329,12 +343,27 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       // with one reduction, goes out first; this half's own follows while
       // the partner's is on its way
       uint64_t F[3][4], oth[4];
+      // DUAL: this half's own key rows at the same positions, from global
+      // memory, requested first: they arrive while the partner's sums are
+      // formed, so the wait that orders the exchange stores does not also
+      // wait for them
+      uint64_t kown[3][4];
+      if constexpr (DUAL) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const gmem_u64* kr = step_key + (size_t)((c * 3 + j) * 2 + c) * RING_N;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) kown[j][s] = kr[og[s]];
+        }
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) F[j][s] = s_part[j][po[s]];
-        oth[s] = gl_mul_sum3(F[0][s], s_key[1][po[s]], F[1][s], s_key[3][po[s]], F[2][s], s_key[5][po[s]]);
+        oth[s] = gl_mul_sum3(F[0][s], s_key[DUAL ? 0 : 1][po[s]], F[1][s], s_key[DUAL ? 1 : 3][po[s]], F[2][s],
+                             s_key[DUAL ? 2 : 5][po[s]]);
       }
+
       const uint32_t par = (done & 1u) * RING_N;
       const uint32_t slot = par + 64 * wave + lane;  // + 256 s
       if (local) {
@@ -378,7 +407,10 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       }
       uint64_t own[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) own[s] = gl_mul_sum3(F[0][s], s_key[0][po[s]], F[1][s], s_key[2][po[s]], F[2][s], s_key[4][po[s]]);
+      for (int s = 0; s < 4; ++s) {
+        if constexpr (DUAL) own[s] = gl_mul_sum3(F[0][s], kown[0][s], F[1][s], kown[1][s], F[2][s], kown[2][s]);
+        else own[s] = gl_mul_sum3(F[0][s], s_key[0][po[s]], F[1][s], s_key[2][po[s]], F[2][s], s_key[4][po[s]]);
+      }
       // every own product before the first wait for the partner's (ordered
       // empty asm statements that the sums depend on)
 #pragma unroll
@@ -391,11 +423,16 @@ __global__ __launch_bounds__(256, 1) void blind_rotate_split_kernel(
       // eight lanes per row; each pass leaves register s at position
       // h8 + 8 (s >> 1) + 16 (s & 1)
       {
+        uint64_t twv[4];  // DUAL: the inverse twist factors, requested ahead of the pass
+        if constexpr (DUAL) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) twv[s] = as_global(tw_i)[(h8 + 8 * (s >> 1) + 16 * (s & 1)) * 32 + row];
+        }
         inv256_pass<2>(v, upper1, upper2, upper4, tw2);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int j = h8 + 8 * (s >> 1) + 16 * (s & 1);
-          s_t128[row * T128_ROW + j] = gl_mul(v[s], s_twi[j * 32 + row]);
+          s_t128[row * T128_ROW + j] = gl_mul(v[s], DUAL ? twv[s] : s_twi[j * 32 + row]);
         }
         pc.template mark<8>();
         __syncthreads();
@@ -453,12 +490,7 @@ __global__ void split_area_clear_kernel(uint32_t* sync, int words) {
 }
 
 // ---------------------------------------------------------------------------
-// Key switching: a tile of T jobs x 64 output columns per wave.  For every
-// (i, j) the wave reads the base-1 KSK rows of that digit position once and
-// each job of the tile subtracts the row its digit selects.  With
-// gridDim.z > 1 the ring index i is split into gridDim.z ranges; each block
-// subtracts its partial sum atomically from an output that ks_init_kernel
-// set to (0, b') (u32 wrap-around addition is exact and order-free).
+// Host side: launches, the exchange area and its give-up record.
 int split_spin_limit();
 static int split_allow_l2();
 static int split_jobs_padded(int max_jobs) { return (max_jobs + 7) / 8 * 8; }
@@ -469,12 +501,15 @@ static size_t split_marks_offset(int max_jobs) {
 
 hipError_t launch_split(const BrJob* d_jobs, int njobs, const SrcBases& src, uint32_t* d_ex,
                         const uint64_t* const* d_bsk_tab, uint32_t* const* d_pool_tab, int n_lwe, int steps,
-                        int raw_acc, Twiddles tw, const SplitArea* split, hipStream_t s) {
+                        int raw_acc, Twiddles tw, int waves_per_job, const SplitArea* split, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  if (!split || !split->xbuf || !split->sync || njobs > split->max_jobs) return hipErrorInvalidValue;
+  if (!is_split(waves_per_job) || njobs > split_max_jobs(waves_per_job) || !split || !split->xbuf ||
+      !split->sync || njobs > split->max_jobs)
+    return hipErrorInvalidValue;
   const int grid = 16 * ((njobs + 7) / 8);
-  hipLaunchKernelGGL(blind_rotate_split_kernel<false>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
-                     d_bsk_tab, d_pool_tab, n_lwe, steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
+  auto kernel = waves_per_job == 7 ? blind_rotate_split_kernel<false, true> : blind_rotate_split_kernel<false, false>;
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab, d_pool_tab, n_lwe,
+                     steps, raw_acc, tw.fwd, tw.inv, split->xbuf, split->sync,
                      split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), split_allow_l2(),
                      nullptr);
   return hipGetLastError();
@@ -484,11 +519,13 @@ hipError_t launch_split_profiled(const BrJob* d_jobs, int njobs, const SrcBases&
                                  const uint64_t* const* d_bsk_tab, int n_lwe, int steps, Twiddles tw,
                                  int waves_per_job, const SplitArea* split, uint64_t* d_prof, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  if (!is_split(waves_per_job) || !split || !split->xbuf || !split->sync || njobs > split->max_jobs || !d_prof)
+  if (!is_split(waves_per_job) || njobs > split_max_jobs(waves_per_job) || !split || !split->xbuf ||
+      !split->sync || njobs > split->max_jobs || !d_prof)
     return hipErrorInvalidValue;
   const int grid = 16 * ((njobs + 7) / 8);
-  hipLaunchKernelGGL(blind_rotate_split_kernel<true>, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex,
-                     d_bsk_tab, nullptr, n_lwe, steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
+  auto kernel = waves_per_job == 7 ? blind_rotate_split_kernel<true, true> : blind_rotate_split_kernel<true, false>;
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, s, d_jobs, njobs, src, d_ex, d_bsk_tab, nullptr, n_lwe,
+                     steps, 1, tw.fwd, tw.inv, split->xbuf, split->sync,
                      split->sync + split_marks_offset(split->max_jobs), split_spin_limit(), split_allow_l2(),
                      d_prof);
   return hipGetLastError();
@@ -551,7 +588,7 @@ hipError_t launch_clear_words(uint32_t* d, size_t words, hipStream_t s) {
 }
 
 hipError_t split_area_alloc(SplitArea* a, int max_jobs) {
-  if (!a || max_jobs < 1 || max_jobs > kSplitMaxJobs) return hipErrorInvalidValue;
+  if (!a || max_jobs < 1 || max_jobs > kSplitDualMaxJobs) return hipErrorInvalidValue;
   *a = SplitArea{};
   hipError_t e = hipMalloc((void**)&a->xbuf, split_xbuf_bytes(max_jobs));
   if (e == hipSuccess) e = hipMalloc((void**)&a->sync, split_sync_bytes(max_jobs));
@@ -572,7 +609,7 @@ void split_area_free(SplitArea* a) {
 }
 
 hipError_t split_area_alloc_async(SplitArea* a, int max_jobs, hipStream_t s) {
-  if (!a || max_jobs < 1 || max_jobs > kSplitMaxJobs) return hipErrorInvalidValue;
+  if (!a || max_jobs < 1 || max_jobs > kSplitDualMaxJobs) return hipErrorInvalidValue;
   *a = SplitArea{};
   hipError_t e = hipMallocAsync((void**)&a->xbuf, split_xbuf_bytes(max_jobs), s);
   if (e == hipSuccess) e = hipMallocAsync((void**)&a->sync, split_sync_bytes(max_jobs), s);

@@ -28,7 +28,7 @@ std::map<int, std::vector<lp_tune_entry>> g_tune;  // device -> rows sorted by j
 
 constexpr uint32_t kMaxTuneJobs = 1u << 22;      // row bound
 constexpr uint32_t kMaxTuneBucket = 1u << 16;    // batch size the autotuner times
-const int kWaves[] = {1, 2, 3, 4, 5, 6};
+const int kWaves[] = {1, 2, 3, 4, 5, 6, 7};
 constexpr int kNumWaves = sizeof(kWaves) / sizeof(kWaves[0]);
 const int kTiles[] = {1, 4, 8, 16};
 const int kSplits[] = {1, 2, 4, 8, 16};
@@ -94,14 +94,16 @@ int default_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   return sp;
 }
 
-// MI355X, n = 630, gate batches with their key switch: split 6.2 ms up to
-// 128 rotations; four waves two per CU 12.8-13.0 ms at 129-256 (four waves
-// one per CU 13.6-13.9), 20.0-20.5 ms at 384-512 and 30.0-30.1 ms at
-// 640-768 (two waves 28.9-30.2); two waves, one per component, 33.9 ms at
-// 1024 (four waves 39.0, one wave 41.9) and 47.1 ms at 1280 (48.4, 58.5);
-// one wave from 1536, where two waves per rotation need a second round.
+// MI355X, n = 630, gate batches with their key switch: split 5.9 ms up to
+// 128 rotations; the split two workgroups per CU 10.1-10.7 ms at 129-256
+// (four waves two per CU 12.5-12.6, one per CU 13.6-13.9); four waves two
+// per CU 19.4-20.5 ms at 384-512 and 30.0-30.1 ms at 640-768 (two waves
+// 28.9-30.2); two waves, one per component, 33.9 ms at 1024 (four waves
+// 39.0, one wave 41.9) and 47.1 ms at 1280 (48.4, 58.5); one wave from 1536,
+// where two waves per rotation need a second round.
 int default_br_wpb(size_t njobs) {
   if (njobs <= (size_t)kSplitMaxJobs) return 6;
+  if (njobs <= (size_t)kSplitDualMaxJobs) return 7;
   if (njobs <= 768) return 5;
   return njobs <= 1280 ? 2 : 1;
 }
@@ -124,10 +126,15 @@ int pick_ks_split(size_t njobs, int tile, uint32_t n_lwe) {
   return default_ks_split(njobs, tile, n_lwe);
 }
 
-// A split shape (6) applies up to kSplitMaxJobs jobs; a wider launch that
-// looks it up (the table's last row, or a forced shape) takes 3 instead.
+// A split shape applies up to split_max_jobs(w) jobs; a wider launch that
+// looks it up (the table's last row, or a forced shape) takes the split
+// sized for two workgroups per CU (7) where that fits, else four waves two
+// per CU (5).
 int pick_br_wpb(size_t njobs) {
-  auto fit = [&](int w) { return is_split(w) && njobs > (size_t)kSplitMaxJobs ? 3 : w; };
+  auto fit = [&](int w) {
+    if (!is_split(w) || njobs <= (size_t)split_max_jobs(w)) return w;
+    return njobs <= (size_t)kSplitDualMaxJobs ? 7 : 5;
+  };
   const int forced = env_int("LOCPIR_BR_WAVES", 0);
   if (one_of(forced, kWaves, kNumWaves)) return fit(forced);
   lp_tune_entry r;
@@ -253,8 +260,8 @@ extern "C" lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket
   LP_HIP_TRY(hipMalloc(&B.ks, maxB * sizeof(lp::KsJob)));
   LP_HIP_TRY(hipEventCreate(&B.t0));
   LP_HIP_TRY(hipEventCreate(&B.t1));
-  if (sizes.front() <= (uint32_t)lp::kSplitMaxJobs)
-    LP_HIP_TRY(lp::split_area_alloc(&B.split, (int)std::min<size_t>(maxB, lp::kSplitMaxJobs)));
+  if (sizes.front() <= (uint32_t)lp::kSplitDualMaxJobs)
+    LP_HIP_TRY(lp::split_area_alloc(&B.split, (int)std::min<size_t>(maxB, lp::kSplitDualMaxJobs)));
   {
     std::vector<uint32_t> h(2 * maxB * w);
     uint64_t st = 0x5EED0F7A11ull;
@@ -289,7 +296,7 @@ extern "C" lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket
     r.jobs = jobs;
     float best = -1.f;
     for (int W : lp::kWaves) {
-      if (lp::is_split(W) && jobs > (uint32_t)lp::kSplitMaxJobs) continue;
+      if (lp::is_split(W) && jobs > (uint32_t)lp::split_max_jobs(W)) continue;
       float ms = 0.f;
       lp_status st = time(
           [&] {

@@ -42,7 +42,12 @@ def test_rotation_launches_by_shape():
     want = (2 * (10 * 64 + 11 * 512) / 1024 + 2 * 10 * 1.0) / 62.0
     assert busy == pytest.approx(want)
     assert bench.SHAPE_KERNEL[6] == "blind_rotate_split_kernel"
-    assert set(bench.SHAPE_KERNEL) == {1, 2, 3, 4, 5, 6}  # every shape the library launches
+    assert set(bench.SHAPE_KERNEL) == {1, 2, 3, 4, 5, 6, 7}  # every shape the library launches
+    # the split sized for two workgroups per CU: its eight waves share their
+    # SIMDs with another rotation's, four SIMDs each
+    tot, busy, _ = bench.summarize_launches(records([200], 2, waves=7), 1, 1)
+    assert tot["blind_rotate_by_shape"][7]["jobs"] == 400
+    assert busy == pytest.approx(min(200 * 4, 1024) / 1024)
 
 
 def test_missing_key_switch_record_keeps_levels_aligned():

@@ -29,7 +29,7 @@ def inputs(okeys, octx):
     return c1, c2, exp
 
 
-@pytest.mark.parametrize("waves", ["1", "2", "3", "4", "5", "6"])
+@pytest.mark.parametrize("waves", ["1", "2", "3", "4", "5", "6", "7"])
 def test_blind_rotation_waves_per_bootstrap(monkeypatch, okeys, octx, dkey, waves):
     monkeypatch.setenv("LOCPIR_BR_WAVES", waves)
     ct = O.encrypt_bits(okeys, [1, 0, 1], seed=88)
@@ -38,7 +38,7 @@ def test_blind_rotation_waves_per_bootstrap(monkeypatch, okeys, octx, dkey, wave
         assert (acc[k] == octx.blind_rotate(ct[k], 20)).all(), k
 
 
-@pytest.mark.parametrize("waves", ["1", "2", "3", "4", "5", "6"])
+@pytest.mark.parametrize("waves", ["1", "2", "3", "4", "5", "6", "7"])
 def test_gate_waves_per_bootstrap(monkeypatch, dkey, inputs, waves):
     monkeypatch.setenv("LOCPIR_BR_WAVES", waves)
     monkeypatch.setenv("LOCPIR_KS_SPLIT", "1")
@@ -58,7 +58,7 @@ def test_keyswitch_shapes(monkeypatch, octx, dkey, tile, split):
         assert (got[k] == octx.keyswitch(big[k])).all(), k
 
 
-@pytest.mark.parametrize("waves", ["1", "2", "3", "4", "5", "6"])
+@pytest.mark.parametrize("waves", ["1", "2", "3", "4", "5", "6", "7"])
 def test_query_under_each_rotation_shape(monkeypatch, okeys, octx, dkey, waves):
     """An 8-bit one-box query (107 bootstraps, 12 levels) with every level
     forced to one rotation shape equals the oracle."""

@@ -1,6 +1,7 @@
 """Split blind rotation (br_waves 6: one bootstrap on two workgroups of four
 waves, each owning one accumulator component and trading its key products
-for the other component every step): bit-exact against the oracle for the
+for the other component every step; br_waves 7: the same sized for two
+workgroups per CU, up to 256 jobs): bit-exact against the oracle for the
 accumulator after all n steps, for gates at one, ragged and maximal launch
 widths, and for whole queries whose narrow levels run split, with the
 exchange area reused launch after launch; a forced give-up fails the call
@@ -17,7 +18,7 @@ from gpu_common import as_u32, cuda_or_skip, device_key_from_oracle
 
 pytestmark = pytest.mark.gpu
 
-SPLIT_MAX = 128  # widest split launch
+SPLIT_MAX = {6: 128, 7: 256}  # widest launch of each split shape
 
 
 @pytest.fixture(scope="module")
@@ -33,17 +34,23 @@ def stalls_before(dkey):
     return lp.split_stall_count()
 
 
-@pytest.fixture
-def split_w():
+@pytest.fixture(params=[6, 7])
+def split_w(request):
     """The split shape under test."""
-    return 6
+    return request.param
 
 
 @pytest.fixture
-def split_table(split_w):
-    """Split rotations up to 128 jobs, one gadget level per wave above."""
+def split_max(split_w):
+    return SPLIT_MAX[split_w]
+
+
+@pytest.fixture
+def split_table(split_w, split_max):
+    """Split rotations up to the shape's widest launch, one gadget level per
+    wave above."""
     old = lp.tune_table()
-    lp.set_tune_table([{"jobs": SPLIT_MAX, "br_waves": split_w, "ks_tile": 4, "ks_split": 8},
+    lp.set_tune_table([{"jobs": split_max, "br_waves": split_w, "ks_tile": 4, "ks_split": 8},
                        {"jobs": 1 << 22, "br_waves": 3, "ks_tile": 8, "ks_split": 8}])
     yield
     lp.set_tune_table(old)
@@ -72,10 +79,30 @@ def test_gates_at_launch_widths(monkeypatch, okeys, octx, dkey, split_w, cnt):
     assert (d == (1 - (a ^ b))).all()
 
 
-def test_mux_at_widest_split_launch(monkeypatch, okeys, octx, dkey, split_w):
-    """64 MUX gates are 128 rotations, the widest split launch."""
+@pytest.mark.parametrize("cnt", [129, 200, 256])
+def test_gates_at_two_per_cu_widths(monkeypatch, okeys, octx, dkey, cnt):
+    """The split sized for two workgroups per CU past the one-per-CU width:
+    ragged and full."""
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "7")
+    a, b = W.random_bits(1200 + cnt, cnt), W.random_bits(1300 + cnt, cnt)
+    c1 = O.encrypt_bits(okeys, a, seed=1400 + cnt)
+    c2 = O.encrypt_bits(okeys, b, seed=1500 + cnt)
+    lp.profile_enable(True)
+    try:
+        got = as_u32(lp.bootstrap_batch(dkey, "NOR", lp.to_device(c1), lp.to_device(c2)))
+        recs = lp.profile_collect_launches()
+    finally:
+        lp.profile_enable(False)
+    assert [r["shape"] for r in recs if r["name"] == "blind_rotate"] == [7]
+    exp, _ = octx.gate_batch("NOR", c1, c2)
+    assert (got == exp).all()
+
+
+def test_mux_at_widest_split_launch(monkeypatch, okeys, octx, dkey, split_w, split_max):
+    """64 (128) MUX gates are 128 (256) rotations, the widest launch of the
+    shape."""
     monkeypatch.setenv("LOCPIR_BR_WAVES", str(split_w))
-    cnt = SPLIT_MAX // 2
+    cnt = split_max // 2
     s, t, f = (W.random_bits(600 + k, cnt) for k in range(3))
     cts = [O.encrypt_bits(okeys, v, seed=700 + k) for k, v in enumerate((s, t, f))]
     got = as_u32(lp.bootstrap_batch(dkey, "MUX", *[lp.to_device(c) for c in cts]))
@@ -83,13 +110,15 @@ def test_mux_at_widest_split_launch(monkeypatch, okeys, octx, dkey, split_w):
     assert (got == exp).all()
 
 
-def test_wider_launch_falls_back(monkeypatch, okeys, octx, dkey, split_w):
-    """A forced split shape on more than 128 rotations runs one gadget level
-    per wave instead (and is still exact)."""
+def test_wider_launch_falls_back(monkeypatch, okeys, octx, dkey, split_w, split_max):
+    """A forced split shape on a launch wider than it takes runs the split
+    sized for two workgroups per CU where that fits, else four waves two per
+    CU (and is still exact)."""
     monkeypatch.setenv("LOCPIR_BR_WAVES", str(split_w))
-    assert lp.tune_pick(SPLIT_MAX)["br_waves"] == split_w
-    assert lp.tune_pick(SPLIT_MAX + 1)["br_waves"] == 3
-    cnt = SPLIT_MAX + 3
+    fallback = 7 if split_max < SPLIT_MAX[7] else 5
+    assert lp.tune_pick(split_max)["br_waves"] == split_w
+    assert lp.tune_pick(split_max + 1)["br_waves"] == fallback
+    cnt = split_max + 3
     a, b = W.random_bits(801, cnt), W.random_bits(802, cnt)
     c1, c2 = O.encrypt_bits(okeys, a, seed=803), O.encrypt_bits(okeys, b, seed=804)
     lp.profile_enable(True)
@@ -98,7 +127,7 @@ def test_wider_launch_falls_back(monkeypatch, okeys, octx, dkey, split_w):
         recs = lp.profile_collect_launches()
     finally:
         lp.profile_enable(False)
-    assert [r["shape"] for r in recs if r["name"] == "blind_rotate"] == [3]
+    assert [r["shape"] for r in recs if r["name"] == "blind_rotate"] == [fallback]
     exp, _ = octx.gate_batch("AND", c1, c2)
     assert (got == exp).all()
 
@@ -111,7 +140,7 @@ def _query_parts(okeys, q, seed):
 
 
 @pytest.mark.parametrize("graphs", ["1", "0"])
-def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_w, split_table, graphs):
+def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_w, split_max, split_table, graphs):
     """An 8-bit one-box query (12 levels, every one at most 32 rotations
     wide, so all of them split), run twice: the exchange area is reused by
     every level and every replay."""
@@ -119,7 +148,7 @@ def test_query_with_split_levels(monkeypatch, okeys, octx, dkey, split_w, split_
     q = W.random_query_u8(31, force_inside=True)
     parts = _query_parts(okeys, q, seed=32)
     l, N, m = q.l, q.n_boxes, q.m
-    assert max(lp.bbox_level_widths(l, N, m)) <= SPLIT_MAX
+    assert max(lp.bbox_level_widths(l, N, m)) <= split_max
     exp = octx.bbox_query(l, N, m, False, *parts)
     lp.profile_enable(True)
     try:
@@ -235,13 +264,13 @@ def test_give_up_fails_the_server_request_only(monkeypatch, okeys, octx, split_t
     assert (out == octx.bbox_query(l, N, m, False, *parts)).all()
 
 
-def test_split_profile_reports_every_phase(okeys, dkey):
+def test_split_profile_reports_every_phase(okeys, dkey, split_w):
     """The profiling build of the split rotation: every wave reports every
     phase; the fourth wave stages the step's key while the level waves run
     their forward transforms, which take longer, so it then waits for them;
     all four meet at the barriers, so their step totals agree."""
     ct = lp.to_device(O.encrypt_bits(okeys, [1, 0, 1, 1, 0, 0, 1, 0], seed=5))
-    r = lp.debug_split_profile(dkey, ct)
+    r = lp.debug_split_profile(dkey, ct, split_w)
     assert r["ms"] > 0
     assert len(r["waves"]) == 4
     for w in r["waves"]:

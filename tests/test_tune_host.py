@@ -22,7 +22,7 @@ def clean_table(monkeypatch):
 def test_defaults_without_table():
     assert lp.tune_table() == []
     assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129, 256, 257, 768, 769, 1024, 1025, 1280, 1281)] == \
-        [6, 6, 5, 5, 5, 5, 2, 2, 2, 2, 1]
+        [6, 6, 7, 7, 5, 5, 2, 2, 2, 2, 1]
     assert [lp.tune_pick(j)["ks_tile"] for j in (1, 16, 256, 4096)] == [1, 4, 8, 8]
     # the default split grows until the key switch has >= 65536 blocks
     assert lp.tune_pick(1)["ks_split"] == 16
@@ -46,25 +46,28 @@ def test_environment_overrides_table(monkeypatch):
     assert g["br_waves"] == 1 and g["ks_tile"] == 8
     # the row's split belongs to tile 16, so tile 8 takes the default rule
     assert g["ks_split"] == lp.tune_pick(1024, 630)["ks_split"]
-    monkeypatch.setenv("LOCPIR_BR_WAVES", "7")  # invalid values are ignored
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "8")  # invalid values are ignored
     assert lp.tune_pick(1024)["br_waves"] == 3
 
 
-def test_split_shape_applies_up_to_128_jobs(monkeypatch):
-    """A row of split rotations (6) serves launches of at most 128 jobs; a
-    wider launch that looks it up (the last row, or the environment) gets one
-    gadget level per wave (3)."""
+def test_split_shapes_apply_up_to_their_widths(monkeypatch):
+    """A row of split rotations serves launches of at most 128 jobs (6) or
+    256 (7, two workgroups per CU); a wider launch that looks it up (the last
+    row, or the environment) takes 7 where that fits, else four waves two
+    per CU (5)."""
     lp.set_tune_table([{"jobs": 32, "br_waves": 1, "ks_tile": 4, "ks_split": 8},
                        {"jobs": 200, "br_waves": 6, "ks_tile": 8, "ks_split": 8}])
     got = [lp.tune_pick(j)["br_waves"] for j in (32, 33, 128, 129, 200, 5000)]
-    assert got == [1, 6, 6, 3, 3, 3]
+    assert got == [1, 6, 6, 7, 7, 5]
     monkeypatch.setenv("LOCPIR_BR_WAVES", "6")
-    assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129)] == [6, 6, 3]
+    assert [lp.tune_pick(j)["br_waves"] for j in (1, 128, 129, 256, 257)] == [6, 6, 7, 7, 5]
+    monkeypatch.setenv("LOCPIR_BR_WAVES", "7")
+    assert [lp.tune_pick(j)["br_waves"] for j in (1, 256, 257)] == [7, 7, 5]
 
 
 @pytest.mark.parametrize("bad", [
     {"jobs": 0, "br_waves": 1, "ks_tile": 4, "ks_split": 1},
-    {"jobs": 8, "br_waves": 7, "ks_tile": 4, "ks_split": 1},
+    {"jobs": 8, "br_waves": 8, "ks_tile": 4, "ks_split": 1},
     {"jobs": 8, "br_waves": 0, "ks_tile": 4, "ks_split": 1},
     {"jobs": 8, "br_waves": 1, "ks_tile": 3, "ks_split": 1},
     {"jobs": 8, "br_waves": 1, "ks_tile": 4, "ks_split": 32},
