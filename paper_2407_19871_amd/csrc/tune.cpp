@@ -297,6 +297,11 @@ extern "C" lp_status lp_autotune(const lp_device_key* dk, const uint32_t* bucket
     float best = -1.f;
     for (int W : lp::kWaves) {
       if (lp::is_split(W) && jobs > (uint32_t)lp::split_max_jobs(W)) continue;
+      // the split sized for two workgroups per CU serves launches too wide
+      // for the one-per-CU split; up to that width the two tie within the
+      // timing's noise over the timed steps, and over a whole rotation the
+      // one-per-CU split is faster (5.45 against 5.65 ms at 128 in a query)
+      if (W == 7 && jobs <= (uint32_t)lp::kSplitMaxJobs) continue;
       float ms = 0.f;
       lp_status st = time(
           [&] {
