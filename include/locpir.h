@@ -160,7 +160,7 @@ lp_status lp_device_key_bytes(const lp_device_key* dk, size_t* bytes);
  * bootstrapped gate runs the blind rotation, sample extraction and key
  * switching (MUX: two blind rotations, one key switch).  d_out may be one of
  * the inputs (it is written by the key switch, after every input was read).
- * cnt = 0 is a no-op.  A batch of at most 128 blind rotations runs them
+ * cnt = 0 is a no-op.  A batch of at most 256 blind rotations runs them
  * split over two workgroups each (lp_split_stall_count); the call then waits
  * for the stream and returns LP_EDEVICE if one of their bounded waits ran
  * out (the outputs are then undefined). */
@@ -292,9 +292,9 @@ lp_status lp_bbox_counts(uint32_t l, uint32_t n_boxes, uint32_t m, uint64_t* n_b
  * shape table (lp_autotune) a program, one query or many fused by
  * lp_eval_bbox_batch, takes early when the summed launch times the table
  * predicts are at least 2 % lower; without one, a lone query takes early
- * exactly when that lets its MUX levels run as split rotations (br_waves
- * 6, see lp_tune_entry) and a level holding MUXes and XNORs together could
- * not, and fused queries take late.  The server always takes late.  The
+ * exactly when that lets its MUX levels run as split rotations one
+ * workgroup per CU (br_waves 6, see lp_tune_entry) and a level holding
+ * MUXes and XNORs together could not, and fused queries take late.  The server always takes late.  The
  * environment variable LOCPIR_XNOR_EARLY = 0 or 1 overrides the choice.
  * The depth is the same either way.  widths: host array of *n_levels
  * entries on input; *n_levels receives the depth (entries beyond the array
