@@ -598,6 +598,7 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
   // lanes past the last column read column n_lwe (their sums are never
   // stored), so every key load is unconditional
   const uint32_t kcol = colok ? (uint32_t)col : (uint32_t)n_lwe;
+  const uint32_t kbyte = kcol * 4u;  // a 32-bit offset, as the loads' scalar-base form takes
   const int w = n_lwe + 1;
   // the tile's key (one per tile), made uniform so that row addresses are
   // scalar
@@ -636,13 +637,27 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
     }
     if constexpr (KT > 0) {
       constexpr int R = KT * NROWS;  // candidate rows of one ring index
+      uint32_t picked[T];            // sums of the rows picked in this block
+#pragma unroll
+      for (int t = 0; t < T; ++t) picked[t] = 0u;
       // a uniform row pointer plus the lane's column, so that the loads take
       // a scalar base and share one offset register
       const gmem_u32* base = as_global(ksk) + (size_t)i0 * R * w;
       auto fetch = [&](uint32_t(&r)[R], int ii) {
         const gmem_u32* q = base + (size_t)ii * R * w;
+        // the column offset re-enters here as a 32-bit value, so that its
+        // widening is visible next to the loads
+        uint32_t kb = kbyte;
+        asm("" : "+v"(kb));
 #pragma unroll
-        for (int k = 0; k < R; ++k) r[k] = (q + (size_t)k * w)[kcol];
+        for (int k = 0; k < R; ++k) {
+          // each row's address stays a scalar pair (scalar adds), and the
+          // load takes it as its base with the lane's column as offset,
+          // instead of a chain of 64-bit vector adds
+          const gmem_u32* row = q + (size_t)k * w;
+          asm("" : "+s"(row));
+          r[k] = *(const gmem_u32*)((__attribute__((address_space(1))) const char*)row + kb);
+        }
       };
       auto apply = [&](const uint32_t(&r)[R], int ii) {
         uint32_t asc[T];
@@ -653,24 +668,52 @@ __global__ __launch_bounds__(64) void keyswitch_kernel(const KsJob* __restrict__
           const int shift = 32 - (j + 1) * BB;
 #pragma unroll
           for (int t = 0; t < T; ++t) {
-            // d is uniform: the row it selects is picked with scalar masks,
-            // not a branch per digit
-            const uint32_t d = (asc[t] >> shift) & (uint32_t)NROWS;
-            uint32_t sub = 0u;
+            if constexpr (BB == 2) {
+              // d = 2 b1 + b0 is uniform: each bit becomes an all-ones or
+              // all-zero scalar word (one signed field extract), and two
+              // bit-field selects of the rows pick row d (none for d = 0).
+              // The picked rows are summed, and the sum subtracted at the end.
+              // The masks are hidden from the optimizer, which would
+              // otherwise turn them back into compares and lane masks.
+              uint32_t m0 = (uint32_t)__builtin_amdgcn_sbfe((int)asc[t], shift, 1);
+              uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)asc[t], shift + 1, 1);
+              asm("" : "+s"(m0), "+s"(m1));
+              const uint32_t r1 = r[j * 3], r2 = r[j * 3 + 1], r3 = r[j * 3 + 2];
+              uint32_t lo = r1 & m0;
+              // kept apart from the last select, which could otherwise
+              // fold it in and read two scalar masks in one instruction
+              asm("" : "+v"(lo));
+              const uint32_t hi = (r3 & m0) | (r2 & ~m0);
+              picked[t] += (hi & m1) | (lo & ~m1);
+            } else {
+              // d is uniform: the row it selects is picked with scalar
+              // masks, not a branch per digit
+              const uint32_t d = (asc[t] >> shift) & (uint32_t)NROWS;
+              uint32_t sub = 0u;
 #pragma unroll
-            for (int v = 1; v <= NROWS; ++v) sub |= r[j * NROWS + v - 1] & (0u - (uint32_t)(d == (uint32_t)v));
-            accv[t] -= sub;
+              for (int v = 1; v <= NROWS; ++v) sub |= r[j * NROWS + v - 1] & (0u - (uint32_t)(d == (uint32_t)v));
+              picked[t] += sub;
+            }
           }
+          // one digit's masks at a time: hoisting them all ahead of the
+          // selects spills scalar registers
+          __builtin_amdgcn_sched_barrier(0);
         }
       };
       uint32_t ra[R], rb[R];
       fetch(ra, 0);
-      for (int ii = 0; ii < 64; ii += 2) {
+      // the last pair is peeled so that the loop body has no branch
+      for (int ii = 0; ii < 62; ii += 2) {
         fetch(rb, ii + 1);
         apply(ra, ii);
-        if (ii + 2 < 64) fetch(ra, ii + 2);
+        fetch(ra, ii + 2);
         apply(rb, ii + 1);
       }
+      fetch(rb, 63);
+      apply(ra, 62);
+      apply(rb, 63);
+#pragma unroll
+      for (int t = 0; t < T; ++t) accv[t] -= picked[t];
       continue;
     }
     for (int ii = 0; ii < 64; ++ii) {
