@@ -47,7 +47,8 @@ def test_gate_waves_per_bootstrap(monkeypatch, dkey, inputs, waves):
     assert (got == exp).all()
 
 
-@pytest.mark.parametrize("tile,split", [("1", "1"), ("4", "1"), ("1", "16"), ("4", "2"), ("16", "8")])
+@pytest.mark.parametrize("tile,split", [("1", "1"), ("4", "1"), ("1", "16"), ("4", "2"), ("8", "1"), ("8", "16"),
+                                        ("16", "8")])
 def test_keyswitch_shapes(monkeypatch, octx, dkey, tile, split):
     monkeypatch.setenv("LOCPIR_KS_TILE", tile)
     monkeypatch.setenv("LOCPIR_KS_SPLIT", split)

@@ -31,7 +31,7 @@ def test_autotune_rows_and_parity(okeys, octx, dkey, clean_table):
     rows = lp.autotune(dkey, buckets=buckets, br_steps=8)
     assert [r["jobs"] for r in rows] == list(buckets)
     for r in rows:
-        assert r["br_waves"] in (1, 2, 3, 4, 5, 6) and r["ks_tile"] in (1, 4, 8, 16) and r["ks_split"] in (1, 2, 4, 8, 16)
+        assert r["br_waves"] in (1, 2, 3, 4, 5, 6, 7) and r["ks_tile"] in (1, 4, 8, 16) and r["ks_split"] in (1, 2, 4, 8, 16)
         assert r["br_us"] > 0 and r["ks_us"] > 0
     assert lp.tune_table() == rows
     for B in (1, 48, 300):
